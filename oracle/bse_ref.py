@@ -1,0 +1,374 @@
+"""Plain FP64 reference of the dual-k-mesh TDA-BSE path (test infrastructure only).
+
+Conventions (shared with the paper):
+* simple cubic lattice, a = 1, V = 1; R integer triples; k, q fractional;
+  Fourier phases exp(+2 pi i k.R) as in the definition of C^mu(k) (Sec. III.A);
+* dense Gamma-centred mesh, k index (i1*n2 + i2)*n3 + i3;
+* q(k, k') = k' - k reduced into the mesh (the phase exp(i(k2 - k1).R) of
+  Eq. (W_LRI), with k1 the row and k2 the column of A);
+* bands per k: nv valence (ascending) then nc conduction (ascending);
+* transition index I = (k*nc + c)*nv + v; blocks of vectors X[I][b].
+
+Every function restates a definition and is deliberately unoptimised.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "kmesh", "q_index", "q_index_table", "interpolate_W", "coarse_to_R", "coarse_mesh",
+    "pair_density", "hamiltonian_block", "build_H", "apply_H", "apply_H_rows",
+    "transition_energies", "velocity_start", "spectrum_exact", "eig_spectrum",
+    "haydock", "continued_fraction", "haydock_spectrum", "lowest_exciton",
+    "binding_energy", "grad_apply", "grad_WR_from_Wq", "grad_lowest", "grad_spectrum",
+]
+
+
+# ----------------------------------------------------------------------------
+# meshes
+# ----------------------------------------------------------------------------
+def kmesh(nk):
+    """Gamma-centred mesh of fractional k (Sec. IV.A.3 uses Gamma-centred meshes)."""
+    n1, n2, n3 = nk
+    out = np.empty((n1 * n2 * n3, 3))
+    i = 0
+    for a in range(n1):
+        for b in range(n2):
+            for c in range(n3):
+                out[i] = (a / n1, b / n2, c / n3)
+                i += 1
+    return out
+
+
+def coarse_mesh(nc3):
+    return kmesh(nc3)
+
+
+def q_index(nk, ik, jk):
+    """Mesh index of k_j - k_i (mod the mesh): the momentum transfer of the pair (k_i, k_j)."""
+    n1, n2, n3 = nk
+    a1, a2, a3 = ik // (n2 * n3), (ik // n3) % n2, ik % n3
+    b1, b2, b3 = jk // (n2 * n3), (jk // n3) % n2, jk % n3
+    return (((b1 - a1) % n1) * n2 + (b2 - a2) % n2) * n3 + (b3 - a3) % n3
+
+
+def q_index_table(nk):
+    Nk = int(np.prod(nk))
+    return np.array([[q_index(nk, i, j) for j in range(Nk)] for i in range(Nk)], dtype=np.int64)
+
+
+# ----------------------------------------------------------------------------
+# dual-k-mesh interpolation of W (Sec. III.B)
+# ----------------------------------------------------------------------------
+def interpolate_W(W_R, R, w_R, q_frac):
+    """W_munu(q) = sum_R w_R W_munu(R) exp(+2 pi i q.R)   (Sec. III.B, Eq. (W_LRI)).
+
+    Direct discrete Fourier sum over the (weighted, possibly truncated)
+    R set of the coarse Born-von-Karman supercell, evaluated at any list
+    of fractional q.
+    """
+    W_R = np.asarray(W_R, dtype=np.complex128)
+    q_frac = np.atleast_2d(np.asarray(q_frac, dtype=np.float64))
+    out = np.zeros((len(q_frac),) + W_R.shape[1:], dtype=np.complex128)
+    for iq, q in enumerate(q_frac):
+        for r in range(len(R)):
+            out[iq] += w_R[r] * np.exp(2j * np.pi * np.dot(q, R[r])) * W_R[r]
+    return out
+
+
+def coarse_to_R(W_qc, coarse, R):
+    """W(R) = (1/N_c) sum_{q_c} W(q_c) exp(-2 pi i q_c.R): inverse transform of the coarse-mesh W (Sec. III.B)."""
+    qc = coarse_mesh(coarse)
+    Nc = len(qc)
+    out = np.zeros((len(R),) + W_qc.shape[1:], dtype=np.complex128)
+    for r in range(len(R)):
+        for iq in range(Nc):
+            out[r] += np.exp(-2j * np.pi * np.dot(qc[iq], R[r])) * W_qc[iq]
+    return out / Nc
+
+
+# ----------------------------------------------------------------------------
+# LRI pair densities (Sec. III.A, definition of C-tilde)
+# ----------------------------------------------------------------------------
+def pair_density(psi, C, ki, bi, kj, bj):
+    """M^mu_{ij}(k_i, k_j) = sum_st conj(c^{k_i}_{s i}) C^mu_{st} c^{k_j}_{t j}.
+
+    This is the paper's C-tilde^mu_{i k_i, j k_j} for k-independent LRI
+    coefficients.  Returns [n_aux][len(bi)][len(bj)].
+    """
+    a = psi[ki][list(bi)]          # [ni][nao]
+    b = psi[kj][list(bj)]          # [nj][nao]
+    Cb = np.matmul(C, b.T)         # [mu][s][j] = sum_t C^mu_st b_jt
+    return np.matmul(a.conj()[None], Cb)   # [mu][i][j]
+
+
+def _bands(prob):
+    return list(range(prob.nv)), list(range(prob.nv, prob.nv + prob.nc))
+
+
+def hamiltonian_block(prob, W_q, alpha, k, kp, cache=None):
+    """Block A[(k, c, v), (k', c', v')] of the TDA Hamiltonian (Eq. (Hamiltonian)).
+
+    diagonal : (E^GW_{c k} - E^GW_{v k}) delta
+    exchange : + alpha (c k*, v k | V | v' k'*, c' k')
+             = + (alpha/N_k) sum_munu M^mu_{cv}(k,k) Vbar_munu M^nu_{v'c'}(k',k')
+    direct   : - (v' k'*, v k | W | c k*, c' k')
+             = - (1/N_k) sum_munu M^mu_{v'v}(k',k) W_munu(k'-k) M^nu_{cc'}(k,k')
+    (kernel integrals of Eq. (W_LRI) and the exchange line below it,
+    with a = c, i = v, k1 = k, b = c', j = v', k2 = k').
+    Returned as [nc*nv][nc*nv] with row (c, v) and column (c', v').
+    """
+    val, con = _bands(prob)
+    Nk = prob.Nk
+    nc, nv = prob.nc, prob.nv
+    Mcv = pair_density(prob.psi, prob.C, k, con, k, val)        # [mu][c][v]
+    Mvc = pair_density(prob.psi, prob.C, kp, val, kp, con)      # [nu][v'][c']
+    Mvv = pair_density(prob.psi, prob.C, kp, val, k, val)       # [mu][v'][v]
+    Mcc = pair_density(prob.psi, prob.C, k, con, kp, con)       # [nu][c][c']
+    Wq = W_q[q_index(prob.nk, k, kp)]
+    # exchange: sum_mu sum_nu Mcv[mu,c,v] Vbar[mu,nu] Mvc[nu,v',c']
+    t1 = np.einsum("mcv,mn->ncv", Mcv, prob.Vbar)
+    Xb = (alpha / Nk) * np.einsum("ncv,npd->cvdp", t1, Mvc)
+    # direct: sum_mu sum_nu Mvv[mu,v',v] W[mu,nu] Mcc[nu,c,c']
+    t2 = np.einsum("mpv,mn->npv", Mvv, Wq)
+    Db = -(1.0 / Nk) * np.einsum("npv,ncd->cvdp", t2, Mcc)
+    blk = (Xb + Db).reshape(nc * nv, nc * nv)
+    if k == kp:
+        blk = blk + np.diag(transition_energies(prob)[k])
+    return blk
+
+
+def transition_energies(prob, eps=None):
+    """(E_{c k} - E_{v k}) per k as [Nk][nc*nv] with (c, v) order (diagonal of Eq. (Hamiltonian))."""
+    e = prob.eps_qp if eps is None else eps
+    nv, nc = prob.nv, prob.nc
+    out = np.empty((len(e), nc * nv))
+    for k in range(len(e)):
+        for c in range(nc):
+            for v in range(nv):
+                out[k, c * nv + v] = e[k, nv + c] - e[k, v]
+    return out
+
+
+def build_H(prob, W_q, alpha=None):
+    """Explicit TDA Hamiltonian A [N][N] (Eq. (Hamiltonian), TDA as in Sec. II.C)."""
+    alpha = prob.alpha if alpha is None else alpha
+    Nk, nt = prob.Nk, prob.nc * prob.nv
+    H = np.zeros((Nk * nt, Nk * nt), dtype=np.complex128)
+    for k in range(Nk):
+        for kp in range(Nk):
+            H[k * nt:(k + 1) * nt, kp * nt:(kp + 1) * nt] = hamiltonian_block(prob, W_q, alpha, k, kp)
+    return H
+
+
+def apply_H_rows(prob, W_q, X, rows, alpha=None):
+    """Rows k in `rows` of H X, each row block built from Eq. (Hamiltonian) and multiplied by X.
+
+    Returns [len(rows)*nc*nv][nb].  Used where the full H does not fit.
+    """
+    alpha = prob.alpha if alpha is None else alpha
+    nt = prob.nc * prob.nv
+    X = np.asarray(X).reshape(prob.Nk * nt, -1)
+    out = np.zeros((len(rows) * nt, X.shape[1]), dtype=np.complex128)
+    for i, k in enumerate(rows):
+        for kp in range(prob.Nk):
+            out[i * nt:(i + 1) * nt] += hamiltonian_block(prob, W_q, alpha, k, kp) @ X[kp * nt:(kp + 1) * nt]
+    return out
+
+
+def apply_H(prob, W_q, X, alpha=None):
+    return apply_H_rows(prob, W_q, X, list(range(prob.Nk)), alpha)
+
+
+# ----------------------------------------------------------------------------
+# spectrum (Eq. (abs_vel)) and lowest exciton (E_B, Sec. IV.C)
+# ----------------------------------------------------------------------------
+def velocity_start(prob, pol):
+    """p_{cvk} = e.<c k| v |v k> / (E^KS_{ck} - E^KS_{vk})  for each polarisation e (rows of pol).
+
+    The velocity-form oscillator strength of Eq. (abs_vel): for an exciton
+    X^S the amplitude is |sum_I conj(p_I) X^S_I|^2.  Returns [N][n_pol].
+    """
+    pol = np.atleast_2d(pol)
+    nv, nc = prob.nv, prob.nc
+    out = np.zeros((prob.N, len(pol)), dtype=np.complex128)
+    for b, e in enumerate(pol):
+        for k in range(prob.Nk):
+            for c in range(nc):
+                for v in range(nv):
+                    d = prob.eps_ks[k, nv + c] - prob.eps_ks[k, v]
+                    amp = sum(e[a] * prob.vel[a, k, c, v] for a in range(3))
+                    out[(k * nc + c) * nv + v, b] = amp / d
+    return out
+
+
+def lorentzian(x, eta):
+    """L_eta(x) = (eta/pi) / (x^2 + eta^2): eta is the half width at half maximum."""
+    return (eta / np.pi) / (x * x + eta * eta)
+
+
+def spectrum_exact(Omega, Z, P, omega, eta, Nk):
+    """S_e(omega) = (1/N_k) sum_S |<X^S|p_e>|^2 L_eta(omega - Omega_S) (Eq. (abs_vel) without 4 pi^2/(3V)).
+
+    Omega [n_S], Z [N][n_S] eigenvectors, P [N][n_pol]; returns [n_pol][n_omega].
+    """
+    amp = np.abs(Z.conj().T @ P) ** 2      # [S][pol]
+    L = lorentzian(np.asarray(omega)[None, :] - np.asarray(Omega)[:, None], eta)   # [S][w]
+    return (amp.T @ L) / Nk
+
+
+def eig_spectrum(H, P, omega, eta, Nk):
+    Om, Z = np.linalg.eigh(H)
+    return spectrum_exact(Om, Z, P, omega, eta, Nk), Om, Z
+
+
+def lowest_exciton(H):
+    Om, Z = np.linalg.eigh(H)
+    return Om[0], Z[:, 0]
+
+
+def binding_energy(prob, Omega1):
+    """E_B = min_k [E_{c1 k} - E_{v_top k}] - Omega_1 (Sec. IV.C)."""
+    return (prob.eps_qp[:, prob.nv] - prob.eps_qp[:, prob.nv - 1]).min() - Omega1
+
+
+# ----------------------------------------------------------------------------
+# Haydock recurrence (not in the paper; Haydock-Heine-Kelly, Benedict-Shirley)
+# ----------------------------------------------------------------------------
+def haydock(apply, p, m, tol=1e-12):
+    """Lanczos tridiagonalisation of a Hermitian operator from start vector p.
+
+    b_0 = |p|, q_1 = p / b_0, q_0 = 0.  For j = 1..m:
+      w = H q_j;  a_j = Re q_j^H w;  w -= a_j q_j + b_{j-1} q_{j-1};
+      full re-orthogonalisation against q_1..q_j, done twice (classical Gram-Schmidt);
+      b_j = |w|;  stop (breakdown) if b_j <= tol * b_0;  q_{j+1} = w / b_j.
+    Returns a [m] (a_1..a_m), b [m+1] (b_0..b_m), steps done, basis [steps][N].
+    """
+    p = np.asarray(p, dtype=np.complex128)
+    b0 = np.linalg.norm(p)
+    a = np.zeros(m)
+    b = np.zeros(m + 1)
+    b[0] = b0
+    Q = [p / b0]
+    qprev = np.zeros_like(p)
+    steps = m
+    for j in range(1, m + 1):
+        qj = Q[-1]
+        w = apply(qj)
+        a[j - 1] = np.real(np.vdot(qj, w))
+        w = w - a[j - 1] * qj - (b[j - 1] if j > 1 else 0.0) * qprev
+        Qm = np.array(Q)
+        for _ in range(2):
+            w = w - Qm.T @ (Qm.conj() @ w)
+        b[j] = np.linalg.norm(w)
+        if b[j] <= tol * b0:
+            steps = j
+            break
+        qprev = qj
+        if j < m:
+            Q.append(w / b[j])
+    return a, b, steps, np.array(Q[:steps])
+
+
+def continued_fraction(a, b, steps, omega, eta, Nk):
+    """S(omega) = -(1/(pi N_k)) Im f(omega + i eta),
+    f(z) = b_0^2 / (z - a_1 - b_1^2 / (z - a_2 - ... - b_{m-1}^2 / (z - a_m))), no terminator.
+    """
+    z = np.asarray(omega, dtype=np.float64) + 1j * eta
+    g = z - a[steps - 1]
+    for j in range(steps - 1, 0, -1):
+        g = z - a[j - 1] - b[j] ** 2 / g
+    f = b[0] ** 2 / g
+    return -np.imag(f) / (np.pi * Nk)
+
+
+def haydock_spectrum(apply, P, m, omega, eta, Nk, tol=1e-12):
+    """Independent chains for the columns of P; returns S [n_pol][n_omega], a, b, steps."""
+    S, A, B, st = [], [], [], []
+    for col in range(P.shape[1]):
+        a, b, s, _ = haydock(apply, P[:, col], m, tol)
+        S.append(continued_fraction(a, b, s, omega, eta, Nk))
+        A.append(a)
+        B.append(b)
+        st.append(s)
+    return np.array(S), np.array(A), np.array(B), np.array(st)
+
+
+# ----------------------------------------------------------------------------
+# gradients (PyTorch convention: dL = Re sum conj(g) d theta)
+# ----------------------------------------------------------------------------
+def grad_apply(prob, W_q, Ybar, X, alpha=None):
+    """Gradients of L = Re sum_{I,b} conj(Ybar_Ib) (H X)_Ib.
+
+    g_eps[k][v]   = -Re sum_{c,b} conj(Ybar_{cvk,b}) X_{cvk,b}
+    g_eps[k][nv+c]=  Re sum_{v,b} conj(Ybar_{cvk,b}) X_{cvk,b}
+    g_Wq[q]_munu  = -(1/N_k) sum_{k, k' = k+q} sum_b sum_{cvc'v'}
+                     Ybar_{cvk,b} conj(M^mu_{v'v}(k',k) M^nu_{cc'}(k,k') X_{c'v'k',b})
+    (derivative of the direct term of Eq. (Hamiltonian) through Eq. (W_LRI)).
+    """
+    nv, nc, Nk = prob.nv, prob.nc, prob.Nk
+    nt = nc * nv
+    val, con = _bands(prob)
+    Ybar = np.asarray(Ybar).reshape(prob.N, -1)
+    X = np.asarray(X).reshape(prob.N, -1)
+    g_eps = np.zeros((Nk, nv + nc))
+    for k in range(Nk):
+        for c in range(nc):
+            for v in range(nv):
+                I = (k * nc + c) * nv + v
+                s = np.real(np.vdot(Ybar[I], X[I]))
+                g_eps[k, nv + c] += s
+                g_eps[k, v] -= s
+    g_Wq = np.zeros((Nk, prob.n_aux, prob.n_aux), dtype=np.complex128)
+    for k in range(Nk):
+        for kp in range(Nk):
+            Mvv = pair_density(prob.psi, prob.C, kp, val, k, val)   # [mu][v'][v]
+            Mcc = pair_density(prob.psi, prob.C, k, con, kp, con)   # [nu][c][c']
+            G = Ybar[k * nt:(k + 1) * nt] @ X[kp * nt:(kp + 1) * nt].conj().T   # [(c v)][(c' v')]
+            G = G.reshape(nc, nv, nc, nv)
+            g_Wq[q_index(prob.nk, k, kp)] += -(1.0 / Nk) * np.einsum(
+                "mpv,ncd,cvdp->mn", Mvv.conj(), Mcc.conj(), G)
+    return g_eps, g_Wq
+
+
+def grad_WR_from_Wq(g_Wq, R, w_R, q_frac):
+    """g_WR[R] = w_R sum_q exp(-2 pi i q.R) g_Wq[q]: the adjoint of interpolate_W."""
+    out = np.zeros((len(R),) + g_Wq.shape[1:], dtype=np.complex128)
+    for r in range(len(R)):
+        for iq, q in enumerate(q_frac):
+            out[r] += np.exp(-2j * np.pi * np.dot(q, R[r])) * g_Wq[iq]
+        out[r] *= w_R[r]
+    return out
+
+
+def grad_lowest(prob, W_q, H=None, alpha=None):
+    """dOmega_1/d(eps, W_q): Hellmann-Feynman, dOmega_1 = x^H dH x with x the lowest eigenvector."""
+    if H is None:
+        H = build_H(prob, W_q, alpha)
+    Om, Z = np.linalg.eigh(H)
+    x = Z[:, :1]
+    g_eps, g_Wq = grad_apply(prob, W_q, x, x, alpha)
+    return Om[0], g_eps, g_Wq
+
+
+def grad_spectrum(prob, W_q, P, omega, eta, gamma, H=None, alpha=None):
+    """Gradient of L = sum_{e, w} gamma[e][w] S_e(w) through the exact resolvent.
+
+    dS_e(w) = -(1/(pi N_k)) Im( yt^H dH y ), y = (z - H)^-1 p_e, yt = (conj z - H)^-1 p_e,
+    z = w + i eta, so L's gradient is grad_apply with the pairs
+    Ybar = -(i gamma / (pi N_k)) yt and X = y, summed over (e, w).
+    """
+    if H is None:
+        H = build_H(prob, W_q, alpha)
+    Om, U = np.linalg.eigh(H)
+    Nk = prob.Nk
+    Ys, Xs = [], []
+    for e in range(P.shape[1]):
+        c = U.conj().T @ P[:, e]
+        for iw, w in enumerate(omega):
+            z = w + 1j * eta
+            y = U @ (c / (z - Om))
+            yt = U @ (c / (np.conj(z) - Om))
+            Ys.append(-(1j * gamma[e][iw] / (np.pi * Nk)) * yt)
+            Xs.append(y)
+    return grad_apply(prob, W_q, np.array(Ys).T, np.array(Xs).T, alpha)
