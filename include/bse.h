@@ -1,0 +1,213 @@
+/*
+ * bse.h - C ABI of the MI355X (gfx950) dual-k-mesh Tamm-Dancoff BSE hot path.
+ *
+ * The operations follow the paper's statement of the problem:
+ *   inputs  : quasiparticle energies E^GW_nk and Kohn-Sham coefficients c^k_sn
+ *             (Sec. II.A), LRI coefficients C^mu (Sec. III.A), the truncated bare
+ *             Coulomb matrix Vbar (Sec. III.A) and the static screened interaction
+ *             W_munu(R) on a small Born-von-Karman R set (Sec. III.B, workflow);
+ *   outputs : the action of the TDA Hamiltonian A (Eq. (Hamiltonian) with the
+ *             LRI kernel of Eq. (W_LRI)), the absorption spectrum (Eq. (abs_vel))
+ *             and the lowest exciton (binding energy, Sec. IV.C).
+ *
+ * Conventions shared by every call
+ *   - all arrays row-major; complex = interleaved {re, im} doubles ("c128") or
+ *     floats ("c64"); "device" pointers point to HIP device memory of the current
+ *     device, "host" pointers to ordinary host memory;
+ *   - lattice: simple cubic, a = 1, cell volume 1; R integer triples; k and q in
+ *     fractional coordinates; Fourier phases exp(+2 pi i k.R);
+ *   - dense Gamma-centred k mesh n1 x n2 x n3, k index (i1*n2 + i2)*n3 + i3;
+ *     q(k, k') = k' - k reduced into the mesh;
+ *   - bands per k: nv valence (ascending) then nc conduction (ascending);
+ *   - transition index I = (k*nc + c)*nv + v, vector index b fastest: X[I][nb].
+ *
+ * Ownership: the caller owns every argument buffer; the library never frees or
+ * keeps a caller pointer beyond the call.  A plan owns copies of what it needs.
+ * Streams: every call is asynchronous on the HIP stream passed as `hip_stream`
+ * (NULL = default stream); device results are valid after a stream sync.  Host
+ * outputs are written before the call returns.  A plan is not thread-safe;
+ * distinct plans may be used concurrently.
+ * Errors: no exception or abort crosses this ABI.  Argument validation happens
+ * before any HIP call.  HIP failures map to BSE_EDEVICE and the hipError text is
+ * available from bse_last_error() (thread-local).
+ */
+#ifndef BSE_H
+#define BSE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BSE_OK = 0,
+    BSE_EINVAL = 1,      /* null pointer, non-positive size, unknown enum        */
+    BSE_ESHAPE = 2,      /* sizes inconsistent with each other or with the plan   */
+    BSE_ENOMEM = 3,      /* device allocation failed                              */
+    BSE_EDEVICE = 4,     /* a HIP call failed                                     */
+    BSE_ENOTHERM = 5,    /* BSE_CHECK_HERMITIAN found a non-Hermitian input       */
+    BSE_INFO_BREAKDOWN = 100  /* a Haydock chain stopped early (not an error)      */
+} bse_status;
+
+/* Arithmetic of the pair-density / screened-interaction contractions.
+ * BSE_F64    : complex128 storage and FP64 MFMA.
+ * BSE_F32    : complex64 storage and FP32 MFMA, FP32 accumulation inside a tile.
+ * BSE_BF16X3 : complex64 storage; each operand split as hi = bf16(x),
+ *              lo = bf16(x - hi) and multiplied as hi*hi + hi*lo + lo*hi on BF16
+ *              MFMA with FP32 accumulation (Henry, Tang & Heinecke, ARITH 2019).
+ * For every precision the diagonal, the exchange term, accumulation across k'
+ * and the Lanczos recurrence run in FP64. */
+typedef enum { BSE_F64 = 0, BSE_F32 = 1, BSE_BF16X3 = 2 } bse_prec;
+
+#define BSE_CHECK_HERMITIAN 1u   /* plan_create: verify C^mu and Vbar Hermitian */
+
+typedef struct {
+    int32_t nk[3];       /* dense Gamma-centred mesh n1, n2, n3 (Sec. IV.A.3)                */
+    int32_t n_ao;        /* NAO basis functions per cell                                    */
+    int32_t nv, nc;      /* valence / conduction bands in the transition space              */
+    int32_t n_aux;       /* auxiliary basis functions per cell                              */
+    double alpha;        /* exchange factor: 2 singlet, 0 triplet (Eq. (Hamiltonian))       */
+} bse_dims;
+
+typedef struct bse_plan bse_plan;  /* opaque */
+
+/* ---------------------------------------------------------------------------
+ * Dual-k-mesh interpolation of the screened interaction (Sec. III.B: W(k) on
+ * the coarse mesh -> W(R) on the BvK supercell, truncated -> W(q) on the dense
+ * mesh; phase of Eq. (W_LRI)):
+ *     W_q[q] = sum_R w_R W_R[R] exp(+2 pi i q.R)
+ * W_R     device c128 [n_R][n_aux][n_aux]
+ * R       host int32 [n_R][3]; w_R host f64 [n_R] (Wigner-Seitz face weights)
+ * q_frac  host f64 [n_q][3] (any list of fractional q)
+ * W_q     device [n_q][n_aux][n_aux], c128 if out_prec == BSE_F64 else c64
+ * The sum is evaluated in FP64 on the matrix cores whatever out_prec is.
+ * ------------------------------------------------------------------------- */
+bse_status bse_interpolate_W(int32_t n_aux, int32_t n_R, const void* W_R,
+                             const int32_t* R, const double* w_R,
+                             int32_t n_q, const double* q_frac,
+                             void* W_q, bse_prec out_prec, void* hip_stream);
+
+/* Conjugate transpose of the map above (the adjoint used for gradients):
+ *     g_WR[R] = w_R sum_q exp(-2 pi i q.R) g_Wq[q]
+ * With q the coarse mesh and w_R = 1/N_coarse this is also the coarse -> R
+ * inverse transform of the workflow.  g_Wq, g_WR device c128. */
+bse_status bse_interpolate_W_adjoint(int32_t n_aux, int32_t n_R, const int32_t* R,
+                                     const double* w_R, int32_t n_q, const double* q_frac,
+                                     const void* g_Wq, void* g_WR, void* hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Plan: copies the inputs of Eq. (Hamiltonian) and precomputes the halves of
+ * the LRI pair densities (Sec. III.A, C-tilde in the Kohn-Sham basis):
+ *     B^mu_n(k) = psi_n(k)^dagger C^mu            (n valence or conduction)
+ *     rho^mu_{cvk} = B^mu_c(k) psi_v(k) = M^mu_cv(k, k)
+ * so that M^mu_ij(k, k') = psi_i(k)^dagger C^mu psi_j(k') = B^mu_i(k) psi_j(k').
+ * eps_qp  device f64 [Nk][nv+nc]   E^GW (valence first)
+ * psi     device c128 [Nk][nv+nc][n_ao]   row n = c^k_{s n}
+ * C       device c128 [n_aux][n_ao][n_ao], each C^mu Hermitian (the k-independent
+ *         form of the two-centre relation of Sec. III.A); the direct term uses
+ *         conj M^mu_ij(k,k') = M^mu_ji(k',k), which holds only then
+ * Vbar    device c128 [n_aux][n_aux]  (V_munu(0) of Sec. III.A)
+ * W_q     device c128 [Nk][n_aux][n_aux], q = dense-mesh index
+ * prec    arithmetic of the direct term; max_nb the largest block size later used
+ * flags   BSE_CHECK_HERMITIAN (synchronises the stream)
+ * On success *out receives the plan (destroy with bse_plan_destroy).
+ * ------------------------------------------------------------------------- */
+bse_status bse_plan_create(const bse_dims* d, const double* eps_qp, const void* psi,
+                           const void* C, const void* Vbar, const void* W_q,
+                           bse_prec prec, int32_t max_nb, uint32_t flags,
+                           void* hip_stream, bse_plan** out);
+bse_status bse_plan_destroy(bse_plan* plan);
+
+/* Register the R set (host int32 [n_R][3], host f64 weights) used by
+ * bse_apply_adjoint to return g_WR. */
+bse_status bse_plan_set_R(bse_plan* plan, int32_t n_R, const int32_t* R, const double* w_R);
+
+/* Replace the quasiparticle energies (device f64 [Nk][nv+nc]) of a plan. */
+bse_status bse_plan_set_eps(bse_plan* plan, const double* eps_qp, void* hip_stream);
+
+/* Device bytes held by the plan (copies, halves and workspaces). */
+bse_status bse_plan_bytes(const bse_plan* plan, uint64_t* bytes);
+
+/* ---------------------------------------------------------------------------
+ * Y = A X with A the TDA block of Eq. (Hamiltonian):
+ *   A_{cvk,c'v'k'} = (E_ck - E_vk) delta
+ *                  + (alpha/N_k) sum_munu M^mu_cv(k,k) Vbar_munu M^nu_v'c'(k',k')
+ *                  - (1/N_k) sum_munu M^mu_v'v(k',k) W_munu(k'-k) M^nu_cc'(k,k')
+ * applied matrix-free: pair densities are formed on the fly every call.
+ * X, Y device c128 [N][nb], N = Nk*nc*nv, 1 <= nb <= max_nb; X and Y must not
+ * overlap.
+ * ------------------------------------------------------------------------- */
+bse_status bse_apply(bse_plan* plan, const void* X, void* Y, int32_t nb, void* hip_stream);
+
+/* Vector-Jacobian product of L = Re sum_{I,b} conj(Ybar_Ib) (A X)_Ib with
+ * respect to the screened interaction and the energies (PyTorch convention
+ * dL = Re sum conj(g) d theta):
+ *   g_Wq[q]_munu = -(1/N_k) sum_{k, k'=k+q} sum_b sum_{cvc'v'}
+ *                  Ybar_{cvk,b} conj(M^mu_v'v(k',k) M^nu_cc'(k,k') X_{c'v'k',b})
+ *   g_WR[R]      = w_R sum_q exp(-2 pi i q.R) g_Wq[q]     (needs bse_plan_set_R)
+ *   g_eps[k][nv+c] = Re sum_{v,b} conj(Ybar) X,  g_eps[k][v] = -Re sum_{c,b} conj(Ybar) X
+ * Ybar, X device c128 [N][nb]; g_WR device c128 [n_R][n_aux][n_aux];
+ * g_Wq device c128 [Nk][n_aux][n_aux]; g_eps device f64 [Nk][nv+nc].
+ * Each output pointer may be NULL (not computed); outputs are overwritten.
+ * The gradient with respect to X is A Ybar (A is Hermitian): use bse_apply.
+ * ------------------------------------------------------------------------- */
+bse_status bse_apply_adjoint(bse_plan* plan, const void* Ybar, const void* X, int32_t nb,
+                             void* g_WR, void* g_Wq, double* g_eps, void* hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Velocity-form start vectors of Eq. (abs_vel):
+ *   P[I][b] = sum_alpha e_b[alpha] vel[alpha][k][c][v] / (E^KS_ck - E^KS_vk)
+ * vel     device c128 [3][Nk][nc][nv]  (<c k| dH/dk_alpha |v k>)
+ * eps_ks  device f64 [Nk][nv+nc]
+ * pol     host f64 [nb][3] polarisation vectors
+ * P       device c128 [N][nb]
+ * ------------------------------------------------------------------------- */
+bse_status bse_velocity_start(const bse_plan* plan, const void* vel, const double* eps_ks,
+                              int32_t nb, const double* pol, void* P, void* hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * nb independent Haydock chains (Lanczos with full re-orthogonalisation by
+ * classical Gram-Schmidt done twice) from the start vectors P, in FP64:
+ *   b_0 = |p|, q_1 = p / b_0;  w = A q_j;  a_j = Re q_j^H w;
+ *   w -= a_j q_j + b_{j-1} q_{j-1};  w -= Q (Q^H w) twice;  b_j = |w|;
+ *   breakdown when b_j <= 1e-12 b_0 (chain stops, steps_done = j);
+ * then the continued fraction
+ *   S_b(w) = -(1/(pi N_k)) Im  b_0^2 / (z - a_1 - b_1^2 / (z - a_2 - ... - b_{m-1}^2/(z - a_m))),
+ *   z = w + i eta
+ * (the velocity-form spectrum of Eq. (abs_vel) per polarisation, without the
+ * constant 4 pi^2 / (3 V), Lorentzian half width eta).
+ * P device c128 [N][nb]; omega host f64 [n_w]; S host f64 [nb][n_w];
+ * a host f64 [nb][n_steps] (a_1..a_m); b host f64 [nb][n_steps+1] (b_0..b_m);
+ * steps_done host int32 [nb]; basis_out NULL or device c128 [nb][n_steps][N]
+ * (the Lanczos vectors q_1..q_m, e.g. for the spectrum's VJP).  Synchronises
+ * the stream once at the end.  Returns BSE_INFO_BREAKDOWN if any chain broke
+ * down (its results are still valid).
+ * ------------------------------------------------------------------------- */
+bse_status bse_haydock_spectrum(bse_plan* plan, const void* P, int32_t nb, int32_t n_steps,
+                                const double* omega, int32_t n_w, double eta,
+                                double* S, double* a, double* b, int32_t* steps_done,
+                                void* basis_out, void* hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Lowest exciton by block LOBPCG (Knyazev 2001) on the FP64 apply, with
+ * Rayleigh-Ritz in FP64 on the host:  Omega_1 and its eigenvector (Sec. IV.C:
+ * E_B = min_k (E_c1k - E_vtop k) - Omega_1).
+ * n_block >= 1 (block size), max_iter, tol (relative residual |r| <= tol |Omega|).
+ * X0 device c128 [N][n_block] start block (NULL: deterministic pseudo-random);
+ * omega host f64 [n_block] ascending Ritz values; x_out device c128 [N][n_block]
+ * (NULL allowed); iters host int32 (NULL allowed).
+ * ------------------------------------------------------------------------- */
+bse_status bse_lowest_excitons(bse_plan* plan, int32_t n_block, int32_t max_iter, double tol,
+                               const void* X0, double* omega, void* x_out, int32_t* iters,
+                               void* hip_stream);
+
+const char* bse_status_string(bse_status s);
+const char* bse_last_error(void);
+/* Library version string. */
+const char* bse_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BSE_H */

@@ -1,0 +1,278 @@
+"""ctypes binding of libbse.so, the gfx950 dual-k-mesh TDA-BSE library.
+
+Argument marshalling only: tensors are checked for device, dtype, shape and
+contiguity, their device pointers and torch's current HIP stream are passed
+to the C ABI, and status codes become exceptions.  Every step of the
+computation runs in the library's HIP kernels; there is no CPU fallback, and
+importing this module fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("BSE_LIB", os.path.join(_HERE, "libbse.so"))
+
+PREC = {"f64": 0, "f32": 1, "bf16x3": 2}
+BSE_OK, BSE_INFO_BREAKDOWN = 0, 100
+CHECK_HERMITIAN = 1
+
+
+class BSEError(RuntimeError):
+    def __init__(self, where, status, msg):
+        super().__init__("%s: status %d (%s): %s" % (where, status, _status_string(status), msg))
+        self.status = status
+
+
+class _Dims(ctypes.Structure):
+    _fields_ = [("nk", ctypes.c_int32 * 3), ("n_ao", ctypes.c_int32), ("nv", ctypes.c_int32),
+                ("nc", ctypes.c_int32), ("n_aux", ctypes.c_int32), ("alpha", ctypes.c_double)]
+
+
+_lib = None
+_vp, _i32, _f64p, _i32p = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)
+
+_SIGS = {
+    "bse_interpolate_W": [_i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, ctypes.c_int, _vp],
+    "bse_interpolate_W_adjoint": [_i32, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _vp],
+    "bse_plan_create": [ctypes.POINTER(_Dims), _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _i32, ctypes.c_uint32, _vp,
+                        ctypes.POINTER(_vp)],
+    "bse_plan_destroy": [_vp],
+    "bse_plan_set_R": [_vp, _i32, _vp, _vp],
+    "bse_plan_set_eps": [_vp, _vp, _vp],
+    "bse_plan_bytes": [_vp, ctypes.POINTER(ctypes.c_uint64)],
+    "bse_apply": [_vp, _vp, _vp, _i32, _vp],
+    "bse_apply_adjoint": [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp],
+    "bse_velocity_start": [_vp, _vp, _vp, _i32, _vp, _vp, _vp],
+    "bse_haydock_spectrum": [_vp, _vp, _i32, _i32, _vp, _i32, ctypes.c_double, _vp, _vp, _vp, _vp, _vp, _vp],
+    "bse_lowest_excitons": [_vp, _i32, _i32, ctypes.c_double, _vp, _vp, _vp, _vp, _vp],
+    "bse_status_string": [ctypes.c_int],
+    "bse_last_error": [],
+    "bse_version": [],
+}
+EXPORTS = tuple(_SIGS)
+
+
+def lib():
+    """Load libbse.so once; raise if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libbse.so not built at %s: run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_char_p if name in ("bse_status_string", "bse_last_error", "bse_version") else ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _status_string(s):
+    try:
+        return lib().bse_status_string(int(s)).decode()
+    except Exception:
+        return "?"
+
+
+def _check(where, s, allow_breakdown=False):
+    if s == BSE_OK or (allow_breakdown and s == BSE_INFO_BREAKDOWN):
+        return s
+    raise BSEError(where, s, lib().bse_last_error().decode())
+
+
+def _stream(dev):
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _dev(t, dtype, shape, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _host(a, dtype, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=dtype))
+    if shape is not None and a.shape != tuple(shape):
+        raise ValueError("expected shape %s, got %s" % (tuple(shape), a.shape))
+    return a
+
+
+def version():
+    return lib().bse_version().decode()
+
+
+def interpolate_W(W_R, R, w_R, q_frac, out_prec="f64"):
+    """W_q[q] = sum_R w_R W_R[R] exp(+2 pi i q.R) on the device (c128 or c64 output)."""
+    n_R, na, _ = W_R.shape
+    R = _host(R, np.int32, (n_R, 3))
+    w_R = _host(w_R, np.float64, (n_R,))
+    q = _host(q_frac, np.float64)
+    q = q.reshape(-1, 3)
+    out = torch.empty((len(q), na, na), dtype=torch.complex128 if out_prec == "f64" else torch.complex64,
+                      device=W_R.device)
+    s = lib().bse_interpolate_W(na, n_R, _dev(W_R, torch.complex128, (n_R, na, na), "W_R"),
+                                R.ctypes.data, w_R.ctypes.data, len(q), q.ctypes.data,
+                                _dev(out, out.dtype, None, "W_q"), PREC[out_prec], _stream(W_R.device))
+    _check("bse_interpolate_W", s)
+    return out
+
+
+def interpolate_W_adjoint(g_Wq, R, w_R, q_frac):
+    """g_WR[R] = w_R sum_q exp(-2 pi i q.R) g_Wq[q] on the device."""
+    n_q, na, _ = g_Wq.shape
+    R = _host(R, np.int32)
+    R = R.reshape(-1, 3)
+    w_R = _host(w_R, np.float64, (len(R),))
+    q = _host(q_frac, np.float64, (n_q, 3))
+    out = torch.empty((len(R), na, na), dtype=torch.complex128, device=g_Wq.device)
+    s = lib().bse_interpolate_W_adjoint(na, len(R), R.ctypes.data, w_R.ctypes.data, n_q, q.ctypes.data,
+                                        _dev(g_Wq, torch.complex128, None, "g_Wq"),
+                                        _dev(out, torch.complex128, None, "g_WR"), _stream(g_Wq.device))
+    _check("bse_interpolate_W_adjoint", s)
+    return out
+
+
+class Plan:
+    """A TDA-BSE problem resident on one GPU (halves, rho, W_q and workspaces)."""
+
+    def __init__(self, nk, n_ao, nv, nc, n_aux, eps_qp, psi, C, Vbar, W_q, alpha=2.0, prec="f64",
+                 max_nb=8, check_hermitian=False):
+        self.nk = tuple(int(x) for x in nk)
+        self.Nk = int(np.prod(self.nk))
+        self.n_ao, self.nv, self.nc, self.n_aux = int(n_ao), int(nv), int(nc), int(n_aux)
+        self.N = self.Nk * self.nv * self.nc
+        self.prec, self.max_nb, self.alpha = prec, int(max_nb), float(alpha)
+        self.device = psi.device
+        d = _Dims((ctypes.c_int32 * 3)(*self.nk), self.n_ao, self.nv, self.nc, self.n_aux, self.alpha)
+        nb_ = self.nv + self.nc
+        h = ctypes.c_void_p()
+        self._ptr = None
+        s = lib().bse_plan_create(
+            ctypes.byref(d),
+            _dev(eps_qp, torch.float64, (self.Nk, nb_), "eps_qp"),
+            _dev(psi, torch.complex128, (self.Nk, nb_, self.n_ao), "psi"),
+            _dev(C, torch.complex128, (self.n_aux, self.n_ao, self.n_ao), "C"),
+            _dev(Vbar, torch.complex128, (self.n_aux, self.n_aux), "Vbar"),
+            _dev(W_q, torch.complex128, (self.Nk, self.n_aux, self.n_aux), "W_q"),
+            PREC[prec], self.max_nb, CHECK_HERMITIAN if check_hermitian else 0, _stream(self.device),
+            ctypes.byref(h))
+        _check("bse_plan_create", s)
+        self._ptr = h
+
+    def close(self):
+        if self._ptr is not None and _lib is not None:
+            _lib.bse_plan_destroy(self._ptr)
+        self._ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def bytes(self):
+        v = ctypes.c_uint64()
+        _check("bse_plan_bytes", lib().bse_plan_bytes(self._ptr, ctypes.byref(v)))
+        return int(v.value)
+
+    def set_R(self, R, w_R):
+        R = _host(R, np.int32).reshape(-1, 3)
+        w_R = _host(w_R, np.float64, (len(R),))
+        self._R, self._wR = R, w_R
+        _check("bse_plan_set_R", lib().bse_plan_set_R(self._ptr, len(R), R.ctypes.data, w_R.ctypes.data))
+
+    def set_eps(self, eps_qp):
+        _check("bse_plan_set_eps", lib().bse_plan_set_eps(
+            self._ptr, _dev(eps_qp, torch.float64, (self.Nk, self.nv + self.nc), "eps_qp"), _stream(self.device)))
+
+    def apply(self, X, out=None):
+        """Y = A X for X [N][nb] complex128 on the device."""
+        nb = X.shape[1]
+        Y = torch.empty_like(X) if out is None else out
+        s = lib().bse_apply(self._ptr, _dev(X, torch.complex128, (self.N, nb), "X"),
+                            _dev(Y, torch.complex128, (self.N, nb), "Y"), nb, _stream(self.device))
+        _check("bse_apply", s)
+        return Y
+
+    def apply_adjoint(self, Ybar, X, want_WR=True, want_Wq=False, want_eps=True):
+        """Gradients of Re <Ybar, A X> w.r.t. W(R) (or W(q)) and the energies."""
+        nb = X.shape[1]
+        gWR = torch.empty((len(self._wR), self.n_aux, self.n_aux), dtype=torch.complex128,
+                          device=self.device) if want_WR else None
+        gWq = torch.empty((self.Nk, self.n_aux, self.n_aux), dtype=torch.complex128,
+                          device=self.device) if want_Wq else None
+        geps = torch.empty((self.Nk, self.nv + self.nc), dtype=torch.float64,
+                           device=self.device) if want_eps else None
+        s = lib().bse_apply_adjoint(
+            self._ptr, _dev(Ybar, torch.complex128, (self.N, nb), "Ybar"),
+            _dev(X, torch.complex128, (self.N, nb), "X"), nb,
+            _dev(gWR, torch.complex128, None, "g_WR") if want_WR else None,
+            _dev(gWq, torch.complex128, None, "g_Wq") if want_Wq else None,
+            _dev(geps, torch.float64, None, "g_eps") if want_eps else None, _stream(self.device))
+        _check("bse_apply_adjoint", s)
+        return {"W_R": gWR, "W_q": gWq, "eps": geps}
+
+    def velocity_start(self, vel, eps_ks, pol):
+        pol = _host(pol, np.float64).reshape(-1, 3)
+        nb = len(pol)
+        P = torch.empty((self.N, nb), dtype=torch.complex128, device=self.device)
+        s = lib().bse_velocity_start(self._ptr, _dev(vel, torch.complex128, (3, self.Nk, self.nc, self.nv), "vel"),
+                                     _dev(eps_ks, torch.float64, (self.Nk, self.nv + self.nc), "eps_ks"), nb,
+                                     pol.ctypes.data, _dev(P, torch.complex128, None, "P"), _stream(self.device))
+        _check("bse_velocity_start", s)
+        return P
+
+    def haydock(self, P, n_steps, omega, eta, keep_basis=False):
+        nb = P.shape[1]
+        omega = _host(omega, np.float64).ravel()
+        S = np.zeros((nb, len(omega)))
+        a = np.zeros((nb, n_steps))
+        b = np.zeros((nb, n_steps + 1))
+        steps = np.zeros(nb, dtype=np.int32)
+        basis = torch.empty((nb, n_steps, self.N), dtype=torch.complex128, device=self.device) if keep_basis else None
+        s = lib().bse_haydock_spectrum(self._ptr, _dev(P, torch.complex128, (self.N, nb), "P"), nb, int(n_steps),
+                                       omega.ctypes.data, len(omega), float(eta), S.ctypes.data, a.ctypes.data,
+                                       b.ctypes.data, steps.ctypes.data,
+                                       _dev(basis, torch.complex128, None, "basis") if keep_basis else None,
+                                       _stream(self.device))
+        _check("bse_haydock_spectrum", s, allow_breakdown=True)
+        return {"S": S, "a": a, "b": b, "steps": steps, "basis": basis, "breakdown": s == BSE_INFO_BREAKDOWN}
+
+    def lowest_excitons(self, n_block=4, max_iter=200, tol=1e-10, X0=None, want_vectors=True):
+        omega = np.zeros(n_block)
+        iters = np.zeros(1, dtype=np.int32)
+        x = torch.empty((self.N, n_block), dtype=torch.complex128, device=self.device) if want_vectors else None
+        s = lib().bse_lowest_excitons(self._ptr, n_block, max_iter, tol,
+                                      _dev(X0, torch.complex128, (self.N, n_block), "X0") if X0 is not None else None,
+                                      omega.ctypes.data, _dev(x, torch.complex128, None, "x") if want_vectors else None,
+                                      iters.ctypes.data, _stream(self.device))
+        _check("bse_lowest_excitons", s)
+        return omega, x, int(iters[0])
+
+
+def plan_from_problem(prob, W_q, prec="f64", max_nb=8, device="cuda:0", check_hermitian=False):
+    """Build a Plan from a synthetic crystal (inputs copied host -> device)."""
+    dev = torch.device(device)
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)
+    return Plan(prob.nk, prob.n_ao, prob.nv, prob.nc, prob.n_aux, t(prob.eps_qp, torch.float64),
+                t(prob.psi, torch.complex128), t(prob.C, torch.complex128), t(prob.Vbar, torch.complex128),
+                W_q, alpha=prob.alpha, prec=prec, max_nb=max_nb, check_hermitian=check_hermitian)

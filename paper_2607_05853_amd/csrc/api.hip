@@ -1,0 +1,594 @@
+// C ABI of the BSE library: argument validation (before any HIP call), plan
+// construction and the apply / adjoint / start-vector entry points.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <new>
+
+#include "bse_internal.h"
+
+namespace bse {
+
+namespace {
+thread_local std::string g_err;
+int g_alloc_count = 0;
+}  // namespace
+
+void set_error(const std::string& msg) { g_err = msg; }
+const char* last_error() { return g_err.c_str(); }
+
+bse_status dmalloc(void** p, size_t bytes) {
+  *p = nullptr;
+  const char* f = std::getenv("BSE_TEST_FAIL_ALLOC");
+  ++g_alloc_count;
+  if (f && std::atoi(f) == g_alloc_count) {
+    set_error("device allocation failed (BSE_TEST_FAIL_ALLOC)");
+    return BSE_ENOMEM;
+  }
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    set_error(std::string("hipMalloc of ") + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
+    return BSE_ENOMEM;
+  }
+  return BSE_OK;
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+bse_status plan_alloc(Plan* p, void** ptr, size_t bytes) {
+  BSE_TRY(dmalloc(ptr, bytes));
+  p->owned.push_back(DevBuf{*ptr, bytes});
+  p->bytes += bytes;
+  return BSE_OK;
+}
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// plan-construction kernels
+// ---------------------------------------------------------------------------
+// rho[k][c][v][mu] = sum_t Bc[k][c][mu][t] psi[k][v][t]   (chunk of k, FP64)
+__global__ void rho_kernel(int kcount, int k0, int nv, int nc, int nbnd, int n_ao, int n_aux,
+                           const double* __restrict__ Bc, const double* __restrict__ psi,
+                           double* __restrict__ rho) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long total = (long long)kcount * nc * n_aux;
+  if (t >= total) return;
+  const int mu = (int)(t % n_aux);
+  const long long kc = t / n_aux;
+  const int c = (int)(kc % nc);
+  const int kl = (int)(kc / nc);
+  const int k = k0 + kl;
+  const double* brow = Bc + 2 * (((long long)kl * nc + c) * n_aux + mu) * n_ao;
+  for (int v = 0; v < nv; ++v) {
+    const double* pv = psi + 2 * ((long long)k * nbnd + v) * n_ao;
+    double sr = 0, si = 0;
+    for (int s = 0; s < n_ao; ++s) {
+      const double ar = brow[2 * s], ai = brow[2 * s + 1], br = pv[2 * s], bi = pv[2 * s + 1];
+      sr += ar * br - ai * bi;
+      si += ar * bi + ai * br;
+    }
+    double* o = rho + 2 * ((((long long)k * nc + c) * nv + v) * n_aux + mu);
+    o[0] = sr;
+    o[1] = si;
+  }
+}
+
+__global__ void velocity_kernel(long long N, int nv, int nc, int nb, long long Nk, const double* __restrict__ vel,
+                                const double* __restrict__ eks, const double* __restrict__ pol,
+                                double* __restrict__ P) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * nb) return;
+  const int b = (int)(t % nb);
+  const long long I = t / nb;
+  const int v = (int)(I % nv);
+  const long long kc = I / nv;
+  const int c = (int)(kc % nc);
+  const long long k = kc / nc;
+  const double de = eks[k * (nv + nc) + nv + c] - eks[k * (nv + nc) + v];
+  double sr = 0, si = 0;
+  for (int a = 0; a < 3; ++a) {
+    const double* e = vel + 2 * (((a * Nk + k) * nc + c) * nv + v);
+    sr += pol[3 * b + a] * e[0];
+    si += pol[3 * b + a] * e[1];
+  }
+  P[2 * t] = sr / de;
+  P[2 * t + 1] = si / de;
+}
+
+bool bad_ptr(const void* p) { return p == nullptr; }
+
+bse_status validate_dims(const bse_dims* d) {
+  if (!d) {
+    set_error("dims is NULL");
+    return BSE_EINVAL;
+  }
+  for (int i = 0; i < 3; ++i)
+    if (d->nk[i] <= 0) {
+      set_error("nk must be positive");
+      return BSE_EINVAL;
+    }
+  if (d->n_ao <= 0 || d->nv <= 0 || d->nc <= 0 || d->n_aux <= 0) {
+    set_error("n_ao, nv, nc, n_aux must be positive");
+    return BSE_EINVAL;
+  }
+  if (!std::isfinite(d->alpha)) {
+    set_error("alpha must be finite");
+    return BSE_EINVAL;
+  }
+  const long long Nk = (long long)d->nk[0] * d->nk[1] * d->nk[2];
+  if (Nk > (1 << 20) || (long long)d->nv * d->nc > 4096 || d->n_aux > 16384 || d->n_ao > 16384) {
+    set_error("dimensions exceed the supported range");
+    return BSE_ESHAPE;
+  }
+  const long long N = Nk * d->nv * d->nc;
+  if (N > std::numeric_limits<int>::max() / 2) {
+    set_error("transition space too large");
+    return BSE_ESHAPE;
+  }
+  return BSE_OK;
+}
+
+bool valid_prec(int p) { return p == BSE_F64 || p == BSE_F32 || p == BSE_BF16X3; }
+
+hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+size_t per_q_bytes(const Plan* p) {
+  const long long Nk = p->Nk, nv = p->d.nv, nc = p->d.nc, na = p->d.n_aux;
+  return p->esz * (size_t)(Nk * nv * nv * na * 2 + Nk * nc * nc * na + Nk * nc * nc * nv * nv);
+}
+
+bse_status check_hermitian(const void* C, const void* Vbar, const bse_dims* d, hipStream_t st) {
+  const size_t na = d->n_aux, no = d->n_ao;
+  std::vector<double> hc(2 * na * no * no), hv(2 * na * na);
+  BSE_HIP(hipMemcpyAsync(hc.data(), C, hc.size() * 8, hipMemcpyDeviceToHost, st));
+  BSE_HIP(hipMemcpyAsync(hv.data(), Vbar, hv.size() * 8, hipMemcpyDeviceToHost, st));
+  BSE_HIP(hipStreamSynchronize(st));
+  auto herm = [](const double* m, size_t n) {
+    double mx = 0, dev = 0;
+    for (size_t i = 0; i < n; ++i)
+      for (size_t j = 0; j < n; ++j) {
+        const double ar = m[2 * (i * n + j)], ai = m[2 * (i * n + j) + 1];
+        const double br = m[2 * (j * n + i)], bi = -m[2 * (j * n + i) + 1];
+        mx = std::fmax(mx, std::hypot(ar, ai));
+        dev = std::fmax(dev, std::hypot(ar - br, ai - bi));
+      }
+    return dev <= 1e-12 * std::fmax(mx, 1e-300);
+  };
+  for (size_t m = 0; m < na; ++m)
+    if (!herm(hc.data() + 2 * m * no * no, no)) {
+      set_error("C^mu is not Hermitian for mu = " + std::to_string(m));
+      return BSE_ENOTHERM;
+    }
+  if (!herm(hv.data(), na)) {
+    set_error("Vbar is not Hermitian");
+    return BSE_ENOTHERM;
+  }
+  return BSE_OK;
+}
+
+void destroy_plan(Plan* p) {
+  for (auto& b : p->owned) dfree(b.p);
+  p->owned.clear();
+}
+
+bse_status build_plan(Plan* p, const bse_dims* d, const double* eps_qp, const void* psi, const void* C,
+                      const void* Vbar, const void* W_q, bse_prec prec, int max_nb, hipStream_t st) {
+  p->d = *d;
+  p->Nk = d->nk[0] * d->nk[1] * d->nk[2];
+  p->nbnd = d->nv + d->nc;
+  p->nt = d->nv * d->nc;
+  p->N = (long long)p->Nk * p->nt;
+  p->prec = prec;
+  p->max_nb = max_nb;
+  p->esz = prec == BSE_F64 ? 16 : 8;
+  BSE_HIP(hipGetDevice(&p->device));
+  const int Nk = p->Nk, nv = d->nv, nc = d->nc, na = d->n_aux, no = d->n_ao, nbnd = p->nbnd;
+  const bool f64 = prec == BSE_F64;
+
+  // copies of the inputs
+  BSE_TRY(plan_alloc(p, (void**)&p->eps, sizeof(double) * Nk * nbnd));
+  BSE_HIP(hipMemcpyAsync(p->eps, eps_qp, sizeof(double) * Nk * nbnd, hipMemcpyDeviceToDevice, st));
+  const long long npsi = (long long)Nk * nbnd * no;
+  BSE_TRY(plan_alloc(p, (void**)&p->psi64, 16 * npsi));
+  BSE_HIP(hipMemcpyAsync(p->psi64, psi, 16 * npsi, hipMemcpyDeviceToDevice, st));
+  BSE_TRY(plan_alloc(p, (void**)&p->vbar, 16 * (size_t)na * na));
+  BSE_HIP(hipMemcpyAsync(p->vbar, Vbar, 16 * (size_t)na * na, hipMemcpyDeviceToDevice, st));
+  const long long nw = (long long)Nk * na * na;
+  if (f64) {
+    p->psi = p->psi64;
+    BSE_TRY(plan_alloc(p, &p->Wq, 16 * nw));
+    BSE_HIP(hipMemcpyAsync(p->Wq, W_q, 16 * nw, hipMemcpyDeviceToDevice, st));
+  } else {
+    BSE_TRY(plan_alloc(p, &p->psi, 8 * npsi));
+    BSE_TRY(convert_c128_to_c64(p->psi64, (float*)p->psi, npsi, st));
+    BSE_TRY(plan_alloc(p, &p->Wq, 8 * nw));
+    BSE_TRY(convert_c128_to_c64((const double*)W_q, (float*)p->Wq, nw, st));
+  }
+
+  // halves B^mu_n(k) = psi_n(k)^H C^mu, computed in FP64; rho from the FP64 halves
+  const long long hv = (long long)Nk * nv * na * no, hc = (long long)Nk * nc * na * no;
+  BSE_TRY(plan_alloc(p, &p->Bv, p->esz * hv));
+  BSE_TRY(plan_alloc(p, &p->Bc, p->esz * hc));
+  BSE_TRY(plan_alloc(p, (void**)&p->rho, 16 * (size_t)p->N * na));
+  long long* colt = nullptr;
+  {
+    std::vector<long long> h((size_t)na * no);
+    for (int m = 0; m < na; ++m)
+      for (int t = 0; t < no; ++t) h[(size_t)m * no + t] = (long long)m * no * no + t;
+    BSE_TRY(dmalloc((void**)&colt, sizeof(long long) * h.size()));
+    hipError_t e = hipMemcpyAsync(colt, h.data(), sizeof(long long) * h.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      dfree(colt);
+      set_error(std::string("plan tables: ") + hipGetErrorString(e));
+      return BSE_EDEVICE;
+    }
+  }
+  bse_status s = BSE_OK;
+  double* tmp = nullptr;
+  const long long per_k = (long long)nbnd * na * no;  // complex elements of both halves at one k
+  int kc = Nk;
+  if (!f64) {
+    const long long budget = 1LL << 31;  // 2 GiB of FP64 staging
+    kc = (int)std::max(1LL, std::min<long long>(Nk, budget / (16 * per_k)));
+    s = dmalloc((void**)&tmp, 16 * (size_t)kc * per_k);
+  }
+  for (int k0 = 0; s == BSE_OK && k0 < Nk; k0 += kc) {
+    const int kn = std::min(kc, Nk - k0);
+    double* dv = f64 ? (double*)p->Bv + 2LL * k0 * nv * na * no : tmp;
+    double* dc = f64 ? (double*)p->Bc + 2LL * k0 * nc * na * no : tmp + 2LL * kn * nv * na * no;
+    for (int part = 0; part < 2 && s == BSE_OK; ++part) {
+      const int nb_ = part == 0 ? nv : nc;
+      GemmArgs g;
+      g.batch = kn;
+      g.M = nb_;
+      g.N = na * no;
+      g.K = no;
+      g.A = (const double*)p->psi64 + 2 * ((long long)k0 * nbnd + (part == 0 ? 0 : nv)) * no;
+      g.a_sb = (long long)nbnd * no;
+      g.a_si = no;
+      g.a_sk = 1;
+      g.conjA = 1;
+      g.B = C;
+      g.b_tab = colt;
+      g.b_sk = no;
+      g.C = part == 0 ? dv : dc;
+      g.c_sb = (long long)nb_ * na * no;
+      g.c_si = (long long)na * no;
+      g.c_sj = 1;
+      s = cgemm(g, AR_F64, true, true, st);
+    }
+    if (s != BSE_OK) break;
+    {
+      const long long tot = (long long)kn * nc * na;
+      hipLaunchKernelGGL(rho_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, kn, k0, nv, nc, nbnd,
+                         no, na, dc, p->psi64, p->rho);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) {
+        set_error(std::string("rho kernel: ") + hipGetErrorString(e));
+        s = BSE_EDEVICE;
+        break;
+      }
+    }
+    if (!f64) {
+      s = convert_c128_to_c64(dv, (float*)p->Bv + 2LL * k0 * nv * na * no, (long long)kn * nv * na * no, st);
+      if (s == BSE_OK)
+        s = convert_c128_to_c64(dc, (float*)p->Bc + 2LL * k0 * nc * na * no, (long long)kn * nc * na * no, st);
+      if (s == BSE_OK) {
+        hipError_t e = hipStreamSynchronize(st);  // tmp is reused by the next chunk
+        if (e != hipSuccess) {
+          set_error(std::string("plan halves: ") + hipGetErrorString(e));
+          s = BSE_EDEVICE;
+        }
+      }
+    }
+  }
+  {
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess && s == BSE_OK) {
+      set_error(std::string("plan halves: ") + hipGetErrorString(e));
+      s = BSE_EDEVICE;
+    }
+  }
+  dfree(tmp);
+  dfree(colt);
+  if (s != BSE_OK) return s;
+
+  // k + q table
+  {
+    std::vector<int> h((size_t)Nk * Nk);
+    const int n1 = d->nk[0], n2 = d->nk[1], n3 = d->nk[2];
+    for (int k = 0; k < Nk; ++k) {
+      const int a1 = k / (n2 * n3), a2 = (k / n3) % n2, a3 = k % n3;
+      for (int q = 0; q < Nk; ++q) {
+        const int b1 = q / (n2 * n3), b2 = (q / n3) % n2, b3 = q % n3;
+        h[(size_t)k * Nk + q] = (((a1 + b1) % n1) * n2 + (a2 + b2) % n2) * n3 + (a3 + b3) % n3;
+      }
+    }
+    BSE_TRY(plan_alloc(p, (void**)&p->kq, sizeof(int) * h.size()));
+    BSE_HIP(hipMemcpyAsync(p->kq, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice, st));
+    BSE_HIP(hipStreamSynchronize(st));
+  }
+
+  // direct-term workspaces
+  {
+    double gb = 12.0;
+    if (const char* e = std::getenv("BSE_WORKSPACE_GB")) gb = std::atof(e);
+    const size_t budget = (size_t)(gb * (1ull << 30));
+    const size_t pq = per_q_bytes(p);
+    long long qb = (long long)(budget / std::max<size_t>(pq, 1));
+    if (const char* e = std::getenv("BSE_QBATCH")) qb = std::atoll(e);
+    qb = std::max(1LL, std::min<long long>(qb, Nk));
+    p->qb = (int)qb;
+    const long long nq = qb;
+    BSE_TRY(plan_alloc(p, &p->Mv, p->esz * (size_t)(nq * Nk * nv * nv * na)));
+    BSE_TRY(plan_alloc(p, &p->P, p->esz * (size_t)(nq * Nk * nv * nv * na)));
+    BSE_TRY(plan_alloc(p, &p->Mc, p->esz * (size_t)(nq * Nk * nc * nc * na)));
+    BSE_TRY(plan_alloc(p, &p->T, p->esz * (size_t)(nq * Nk * nc * nc * nv * nv)));
+    BSE_TRY(plan_alloc(p, (void**)&p->tab_psi_v, sizeof(long long) * (size_t)(nq * Nk * nv)));
+    BSE_TRY(plan_alloc(p, (void**)&p->tab_mv, sizeof(long long) * (size_t)(nq * Nk * nv)));
+    BSE_TRY(plan_alloc(p, (void**)&p->tab_psi_c, sizeof(long long) * (size_t)(nq * Nk * nc)));
+    BSE_TRY(plan_alloc(p, (void**)&p->tab_mc, sizeof(long long) * (size_t)(nq * Nk * nc)));
+  }
+  // exchange split-K: chunks of whole k points
+  {
+    int gk = 1;
+    while (gk < Nk && (long long)(Nk / gk) > 512) {
+      ++gk;
+      while (Nk % gk) ++gk;
+    }
+    p->xsplit = Nk / gk;
+    BSE_TRY(plan_alloc(p, (void**)&p->xt, 16 * (size_t)(p->xsplit + 1) * na * max_nb));
+    BSE_TRY(plan_alloc(p, (void**)&p->xu, 16 * (size_t)na * max_nb));
+  }
+  return BSE_OK;
+}
+
+}  // namespace
+}  // namespace bse
+
+using namespace bse;
+
+extern "C" {
+
+const char* bse_version(void) { return "bse-gfx950 0.1"; }
+
+const char* bse_status_string(bse_status s) {
+  switch (s) {
+    case BSE_OK: return "ok";
+    case BSE_EINVAL: return "invalid argument";
+    case BSE_ESHAPE: return "inconsistent shape";
+    case BSE_ENOMEM: return "out of device memory";
+    case BSE_EDEVICE: return "HIP device error";
+    case BSE_ENOTHERM: return "input not Hermitian";
+    case BSE_INFO_BREAKDOWN: return "Lanczos breakdown (information)";
+  }
+  return "unknown status";
+}
+
+const char* bse_last_error(void) { return last_error(); }
+
+bse_status bse_interpolate_W(int32_t n_aux, int32_t n_R, const void* W_R, const int32_t* R, const double* w_R,
+                             int32_t n_q, const double* q_frac, void* W_q, bse_prec out_prec, void* hip_stream) {
+  set_error("");
+  if (n_aux <= 0 || n_R <= 0 || n_q <= 0) {
+    set_error("bse_interpolate_W: sizes must be positive");
+    return BSE_EINVAL;
+  }
+  if (bad_ptr(W_R) || bad_ptr(R) || bad_ptr(w_R) || bad_ptr(q_frac) || bad_ptr(W_q)) {
+    set_error("bse_interpolate_W: NULL pointer");
+    return BSE_EINVAL;
+  }
+  if (!valid_prec(out_prec)) {
+    set_error("bse_interpolate_W: unknown precision");
+    return BSE_EINVAL;
+  }
+  if ((long long)n_aux * n_aux > std::numeric_limits<int>::max()) {
+    set_error("bse_interpolate_W: n_aux too large");
+    return BSE_ESHAPE;
+  }
+  return interp_forward(n_aux, n_R, (const double*)W_R, R, w_R, n_q, q_frac, W_q, out_prec == BSE_F64,
+                        S(hip_stream));
+}
+
+bse_status bse_interpolate_W_adjoint(int32_t n_aux, int32_t n_R, const int32_t* R, const double* w_R, int32_t n_q,
+                                     const double* q_frac, const void* g_Wq, void* g_WR, void* hip_stream) {
+  set_error("");
+  if (n_aux <= 0 || n_R <= 0 || n_q <= 0) {
+    set_error("bse_interpolate_W_adjoint: sizes must be positive");
+    return BSE_EINVAL;
+  }
+  if (bad_ptr(R) || bad_ptr(w_R) || bad_ptr(q_frac) || bad_ptr(g_Wq) || bad_ptr(g_WR)) {
+    set_error("bse_interpolate_W_adjoint: NULL pointer");
+    return BSE_EINVAL;
+  }
+  return interp_adjoint(n_aux, n_R, R, w_R, n_q, q_frac, (const double*)g_Wq, (double*)g_WR, S(hip_stream));
+}
+
+bse_status bse_plan_create(const bse_dims* d, const double* eps_qp, const void* psi, const void* C,
+                           const void* Vbar, const void* W_q, bse_prec prec, int32_t max_nb, uint32_t flags,
+                           void* hip_stream, bse_plan** out) {
+  set_error("");
+  if (!out) {
+    set_error("bse_plan_create: out is NULL");
+    return BSE_EINVAL;
+  }
+  *out = nullptr;
+  BSE_TRY(validate_dims(d));
+  if (bad_ptr(eps_qp) || bad_ptr(psi) || bad_ptr(C) || bad_ptr(Vbar) || bad_ptr(W_q)) {
+    set_error("bse_plan_create: NULL input pointer");
+    return BSE_EINVAL;
+  }
+  if (!valid_prec(prec)) {
+    set_error("bse_plan_create: unknown precision");
+    return BSE_EINVAL;
+  }
+  if (max_nb <= 0) {
+    set_error("bse_plan_create: max_nb must be positive");
+    return BSE_EINVAL;
+  }
+  if ((long long)d->nv * d->nc * max_nb > 2048) {
+    set_error("bse_plan_create: nv*nc*max_nb must not exceed 2048");
+    return BSE_ESHAPE;
+  }
+  {
+    // the direct term stages one (nc nv)^2 block and one X slice per pair in LDS
+    const long long nt = (long long)d->nv * d->nc;
+    if (nt * nt * 16 + nt * max_nb * 16 > 150 * 1024) {
+      set_error("bse_plan_create: (nv*nc)^2 + nv*nc*max_nb too large for the LDS-staged pair block");
+      return BSE_ESHAPE;
+    }
+  }
+  if (flags & ~BSE_CHECK_HERMITIAN) {
+    set_error("bse_plan_create: unknown flags");
+    return BSE_EINVAL;
+  }
+  if (flags & BSE_CHECK_HERMITIAN) BSE_TRY(check_hermitian(C, Vbar, d, S(hip_stream)));
+  bse_plan* h = new (std::nothrow) bse_plan();
+  if (!h) {
+    set_error("bse_plan_create: host allocation failed");
+    return BSE_ENOMEM;
+  }
+  bse_status s = build_plan(&h->impl, d, eps_qp, psi, C, Vbar, W_q, prec, max_nb, S(hip_stream));
+  if (s != BSE_OK) {
+    destroy_plan(&h->impl);
+    delete h;
+    return s;
+  }
+  *out = h;
+  return BSE_OK;
+}
+
+bse_status bse_plan_destroy(bse_plan* plan) {
+  if (!plan) return BSE_OK;
+  destroy_plan(&plan->impl);
+  delete plan;
+  return BSE_OK;
+}
+
+bse_status bse_plan_set_R(bse_plan* plan, int32_t n_R, const int32_t* R, const double* w_R) {
+  set_error("");
+  if (!plan || n_R <= 0 || bad_ptr(R) || bad_ptr(w_R)) {
+    set_error("bse_plan_set_R: invalid argument");
+    return BSE_EINVAL;
+  }
+  plan->impl.R.assign(R, R + 3 * (size_t)n_R);
+  plan->impl.wR.assign(w_R, w_R + n_R);
+  return BSE_OK;
+}
+
+bse_status bse_plan_set_eps(bse_plan* plan, const double* eps_qp, void* hip_stream) {
+  set_error("");
+  if (!plan || bad_ptr(eps_qp)) {
+    set_error("bse_plan_set_eps: invalid argument");
+    return BSE_EINVAL;
+  }
+  Plan* p = &plan->impl;
+  BSE_HIP(hipMemcpyAsync(p->eps, eps_qp, sizeof(double) * p->Nk * p->nbnd, hipMemcpyDeviceToDevice,
+                         S(hip_stream)));
+  return BSE_OK;
+}
+
+bse_status bse_plan_bytes(const bse_plan* plan, uint64_t* bytes) {
+  if (!plan || !bytes) {
+    set_error("bse_plan_bytes: invalid argument");
+    return BSE_EINVAL;
+  }
+  *bytes = plan->impl.bytes;
+  return BSE_OK;
+}
+
+bse_status bse_apply(bse_plan* plan, const void* X, void* Y, int32_t nb, void* hip_stream) {
+  set_error("");
+  if (!plan || bad_ptr(X) || bad_ptr(Y)) {
+    set_error("bse_apply: NULL argument");
+    return BSE_EINVAL;
+  }
+  Plan* p = &plan->impl;
+  if (nb <= 0 || nb > p->max_nb) {
+    set_error("bse_apply: nb must be in [1, max_nb]");
+    return BSE_EINVAL;
+  }
+  if (X == Y) {
+    set_error("bse_apply: X and Y must not alias");
+    return BSE_EINVAL;
+  }
+  hipStream_t st = S(hip_stream);
+  BSE_TRY(apply_diag(p, (const double*)X, (double*)Y, nb, st));
+  BSE_TRY(apply_exchange(p, (const double*)X, (double*)Y, nb, st));
+  BSE_TRY(apply_direct(p, (const double*)X, (double*)Y, nb, st));
+  return BSE_OK;
+}
+
+bse_status bse_apply_adjoint(bse_plan* plan, const void* Ybar, const void* X, int32_t nb, void* g_WR, void* g_Wq,
+                             double* g_eps, void* hip_stream) {
+  set_error("");
+  if (!plan || bad_ptr(Ybar) || bad_ptr(X)) {
+    set_error("bse_apply_adjoint: NULL argument");
+    return BSE_EINVAL;
+  }
+  Plan* p = &plan->impl;
+  if (nb <= 0 || nb > p->max_nb) {
+    set_error("bse_apply_adjoint: nb must be in [1, max_nb]");
+    return BSE_EINVAL;
+  }
+  if (g_WR && p->R.empty()) {
+    set_error("bse_apply_adjoint: g_WR requested but bse_plan_set_R was not called");
+    return BSE_EINVAL;
+  }
+  hipStream_t st = S(hip_stream);
+  if (g_eps) BSE_TRY(adjoint_eps(p, (const double*)Ybar, (const double*)X, nb, g_eps, st));
+  if (!g_WR && !g_Wq) return BSE_OK;
+  const int na = p->d.n_aux;
+  double* gq = (double*)g_Wq;
+  if (!gq) {
+    if (!p->gq_acc) BSE_TRY(plan_alloc(p, (void**)&p->gq_acc, 16 * (size_t)p->Nk * na * na));
+    gq = p->gq_acc;
+  }
+  BSE_TRY(adjoint_direct(p, (const double*)Ybar, (const double*)X, nb, gq, st));
+  if (g_WR) {
+    const int nR = (int)p->wR.size();
+    std::vector<double> q(3 * (size_t)p->Nk);
+    const int n1 = p->d.nk[0], n2 = p->d.nk[1], n3 = p->d.nk[2];
+    for (int k = 0; k < p->Nk; ++k) {
+      q[3 * k] = (double)(k / (n2 * n3)) / n1;
+      q[3 * k + 1] = (double)((k / n3) % n2) / n2;
+      q[3 * k + 2] = (double)(k % n3) / n3;
+    }
+    BSE_TRY(interp_adjoint(na, nR, p->R.data(), p->wR.data(), p->Nk, q.data(), gq, (double*)g_WR, st));
+  }
+  return BSE_OK;
+}
+
+bse_status bse_velocity_start(const bse_plan* plan, const void* vel, const double* eps_ks, int32_t nb,
+                              const double* pol, void* P, void* hip_stream) {
+  set_error("");
+  if (!plan || bad_ptr(vel) || bad_ptr(eps_ks) || bad_ptr(pol) || bad_ptr(P) || nb <= 0) {
+    set_error("bse_velocity_start: invalid argument");
+    return BSE_EINVAL;
+  }
+  const Plan* p = &plan->impl;
+  hipStream_t st = S(hip_stream);
+  double* dpol = nullptr;
+  BSE_HIP(hipMallocAsync((void**)&dpol, sizeof(double) * 3 * nb, st));
+  BSE_HIP(hipMemcpyAsync(dpol, pol, sizeof(double) * 3 * nb, hipMemcpyHostToDevice, st));
+  const long long n = p->N * nb;
+  hipLaunchKernelGGL(velocity_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p->N, p->d.nv, p->d.nc,
+                     nb, (long long)p->Nk, (const double*)vel, eps_ks, dpol, (double*)P);
+  hipError_t e = hipGetLastError();
+  (void)hipFreeAsync(dpol, st);
+  if (e != hipSuccess) {
+    set_error(std::string("bse_velocity_start: ") + hipGetErrorString(e));
+    return BSE_EDEVICE;
+  }
+  return BSE_OK;
+}
+
+}  // extern "C"

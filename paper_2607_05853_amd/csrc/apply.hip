@@ -1,0 +1,446 @@
+// Matrix-free action of the TDA Hamiltonian A (Eq. (Hamiltonian) with the LRI
+// kernel of Eq. (W_LRI)) and its vector-Jacobian product.
+//
+// Direct term, per pair (k, k' = k + q), with the halves B^mu_n(k) = psi_n(k)^H C^mu:
+//   Gv[v'][v][mu]   = sum_t psi_v'(k')_t B^mu_vt(k)        = conj M^mu_{v'v}(k', k)
+//   Mc[c'][c][nu]   = sum_t psi_c'(k')_t B^nu_ct(k)        = M^nu_{cc'}(k, k')
+//   P[v'v][nu]      = sum_mu conj(Gv[v'v][mu]) W_munu(q)   (W on the smaller band side)
+//   T[c'c][v'v]     = sum_nu Mc[c'c][nu] P[v'v][nu]        = -N_k * direct block
+//   Y(k)           -= (1/N_k) sum_q T(k, q) X(k + q)
+// All four contractions are batched complex GEMMs on the matrix cores; pairs are
+// processed in batches of qb momentum transfers q so that W(q) is read once per
+// batch and the per-pair intermediates stay within a fixed workspace.
+#include "bse_internal.h"
+
+namespace bse {
+namespace {
+
+// tables of one q batch (q0 .. q0+nq-1), per-batch layout [k][nq*nband]
+__global__ void tables_kernel(int Nk, int nq, int q0, int nv, int nc, int nbnd, int n_ao, int n_aux,
+                              const int* __restrict__ kq, long long* __restrict__ tpv,
+                              long long* __restrict__ tpc, long long* __restrict__ tmv,
+                              long long* __restrict__ tmc) {
+  const int k = blockIdx.x;
+  for (int t = threadIdx.x; t < nq * (nv + nc); t += blockDim.x) {
+    if (t < nq * nv) {
+      const int qi = t / nv, v = t % nv;
+      const int kp = kq[(long long)k * Nk + q0 + qi];
+      tpv[(long long)k * nq * nv + t] = ((long long)kp * nbnd + v) * n_ao;
+      tmv[(long long)k * nq * nv + t] = ((long long)qi * Nk + k) * nv * nv * n_aux + (long long)v * nv * n_aux;
+    } else {
+      const int u = t - nq * nv;
+      const int qi = u / nc, c = u % nc;
+      const int kp = kq[(long long)k * Nk + q0 + qi];
+      tpc[(long long)k * nq * nc + u] = ((long long)kp * nbnd + nv + c) * n_ao;
+      tmc[(long long)k * nq * nc + u] = ((long long)qi * Nk + k) * nc * nc * n_aux + (long long)c * nc * n_aux;
+    }
+  }
+}
+
+// Y[k][(c v)][b] += scale * sum_qi sum_{c'v'} T[qi][k][(c' c)][(v' v)] X[k'][(c' v')][b]
+template <typename TT>
+__global__ void direct_tx_kernel(int Nk, int nq, int q0, int nv, int nc, int nb, double scale,
+                                 const int* __restrict__ kq, const TT* __restrict__ T,
+                                 const double* __restrict__ X, double* __restrict__ Y) {
+  extern __shared__ double smem[];
+  const int k = blockIdx.x;
+  const int nt = nc * nv, nt2 = nt * nt;
+  TT* Ts = reinterpret_cast<TT*>(smem);                       // [nt2] complex
+  double* Xs = reinterpret_cast<double*>(Ts + 2 * (size_t)nt2);  // [nt*nb] complex
+  const int nout = nt * nb;
+  constexpr int SLOTS = 8;  // outputs per thread: nt * nb <= 8 * 256
+  double accr[SLOTS], acci[SLOTS];
+#pragma unroll
+  for (int r = 0; r < SLOTS; ++r) accr[r] = acci[r] = 0.0;
+  for (int qi = 0; qi < nq; ++qi) {
+    const int kp = kq[(long long)k * Nk + q0 + qi];
+    const TT* Tg = T + 2 * ((long long)qi * Nk + k) * nt2;
+    const double* Xg = X + 2 * (long long)kp * nt * nb;
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2 * nt2; i += blockDim.x) Ts[i] = Tg[i];
+    for (int i = threadIdx.x; i < 2 * nout; i += blockDim.x) Xs[i] = Xg[i];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < SLOTS; ++r) {
+      const int o = threadIdx.x + r * blockDim.x;
+      if (o >= nout) break;
+      const int cv = o / nb, b = o % nb;
+      const int c = cv / nv, v = cv % nv;
+      double sr = 0, si = 0;
+      for (int cp = 0; cp < nc; ++cp) {
+        const TT* trow = Ts + 2 * ((cp * nc + c) * (nv * nv) + v);
+        const double* xrow = Xs + 2 * ((cp * nv) * nb + b);
+        for (int vp = 0; vp < nv; ++vp) {
+          const double tr = (double)trow[2 * vp * nv], ti = (double)trow[2 * vp * nv + 1];
+          const double xr = xrow[2 * vp * nb], xi = xrow[2 * vp * nb + 1];
+          sr += tr * xr - ti * xi;
+          si += tr * xi + ti * xr;
+        }
+      }
+      accr[r] += sr;
+      acci[r] += si;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < SLOTS; ++r) {
+    const int o = threadIdx.x + r * blockDim.x;
+    if (o >= nout) break;
+    double* y = Y + 2 * ((long long)k * nout + o);
+    y[0] += scale * accr[r];
+    y[1] += scale * acci[r];
+  }
+}
+
+__global__ void diag_kernel(long long N, int nv, int nc, int nb, const double* __restrict__ eps,
+                            const double* __restrict__ X, double* __restrict__ Y) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * nb) return;
+  const long long I = t / nb;
+  const int v = (int)(I % nv);
+  const long long kc = I / nv;
+  const int c = (int)(kc % nc);
+  const long long k = kc / nc;
+  const double d = eps[k * (nv + nc) + nv + c] - eps[k * (nv + nc) + v];
+  Y[2 * t] = d * X[2 * t];
+  Y[2 * t + 1] = d * X[2 * t + 1];
+}
+
+// t[m][b] = sum_s part[s][m][b]
+__global__ void splitk_reduce(int nsplit, int n, const double* __restrict__ part, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double sr = 0, si = 0;
+  for (int s = 0; s < nsplit; ++s) {
+    sr += part[2 * ((long long)s * n + i)];
+    si += part[2 * ((long long)s * n + i) + 1];
+  }
+  out[2 * i] = sr;
+  out[2 * i + 1] = si;
+}
+
+// Gm[qi][k][(v' v)][(c' c)] = sum_b Ybar[k][(c v)][b] conj(X[k'][(c' v')][b])
+template <typename TT>
+__global__ void adj_gm_kernel(int Nk, int nq, int q0, int nv, int nc, int nb, const int* __restrict__ kq,
+                              const double* __restrict__ Yb, const double* __restrict__ X, TT* __restrict__ Gm) {
+  const int k = blockIdx.x % Nk, qi = blockIdx.x / Nk;
+  const int nt = nc * nv, nt2 = nt * nt;
+  const int kp = kq[(long long)k * Nk + q0 + qi];
+  const double* y = Yb + 2 * (long long)k * nt * nb;
+  const double* x = X + 2 * (long long)kp * nt * nb;
+  TT* out = Gm + 2 * ((long long)qi * Nk + k) * nt2;
+  for (int e = threadIdx.x; e < nt2; e += blockDim.x) {
+    const int row = e / (nc * nc), col = e % (nc * nc);
+    const int vp = row / nv, v = row % nv, cp = col / nc, c = col % nc;
+    const double* yr = y + 2 * (long long)(c * nv + v) * nb;
+    const double* xr = x + 2 * (long long)(cp * nv + vp) * nb;
+    double sr = 0, si = 0;
+    for (int b = 0; b < nb; ++b) {
+      const double ar = yr[2 * b], ai = yr[2 * b + 1], br = xr[2 * b], bi = -xr[2 * b + 1];
+      sr += ar * br - ai * bi;
+      si += ar * bi + ai * br;
+    }
+    out[2 * e] = (TT)sr;
+    out[2 * e + 1] = (TT)si;
+  }
+}
+
+__global__ void adj_eps_kernel(int nv, int nc, int nb, const double* __restrict__ Yb,
+                               const double* __restrict__ X, double* __restrict__ g) {
+  const int k = blockIdx.x;
+  const int nt = nc * nv;
+  // one thread per band of this k
+  for (int n = threadIdx.x; n < nv + nc; n += blockDim.x) {
+    double s = 0;
+    if (n < nv) {
+      for (int c = 0; c < nc; ++c)
+        for (int b = 0; b < nb; ++b) {
+          const long long o = 2 * (((long long)k * nt + c * nv + n) * nb + b);
+          s -= Yb[o] * X[o] + Yb[o + 1] * X[o + 1];
+        }
+    } else {
+      const int c = n - nv;
+      for (int v = 0; v < nv; ++v)
+        for (int b = 0; b < nb; ++b) {
+          const long long o = 2 * (((long long)k * nt + c * nv + v) * nb + b);
+          s += Yb[o] * X[o] + Yb[o + 1] * X[o + 1];
+        }
+    }
+    g[(long long)k * (nv + nc) + n] = s;
+  }
+}
+
+Arith arith_of(bse_prec p) { return p == BSE_F64 ? AR_F64 : (p == BSE_F32 ? AR_F32 : AR_BF16X3); }
+
+char* off_bytes(void* base, long long elems, size_t esz) { return (char*)base + elems * (long long)esz; }
+
+// S1: pair-density halves -> Gv and Mc for one q batch
+bse_status form_pair_densities(Plan* p, int q0, int nq, hipStream_t st) {
+  const bse_dims& d = p->d;
+  const int Nk = p->Nk, nv = d.nv, nc = d.nc, na = d.n_aux, no = d.n_ao;
+  hipLaunchKernelGGL(tables_kernel, dim3(Nk), dim3(256), 0, st, Nk, nq, q0, nv, nc, p->nbnd, no, na, p->kq,
+                     p->tab_psi_v, p->tab_psi_c, p->tab_mv, p->tab_mc);
+  BSE_CHECK_LAUNCH();
+  const Arith ar = arith_of(p->prec);
+  const bool f64 = p->prec == BSE_F64;
+  {
+    GemmArgs g;
+    g.batch = Nk;
+    g.M = nq * nv;
+    g.N = nv * na;
+    g.K = no;
+    g.A = p->psi;
+    g.a_tab = p->tab_psi_v;
+    g.a_tab_pb = 1;
+    g.a_sk = 1;
+    g.B = p->Bv;
+    g.b_sb = (long long)nv * na * no;
+    g.b_sj = no;
+    g.b_sk = 1;
+    g.C = p->Mv;
+    g.c_tab = p->tab_mv;
+    g.c_tab_pb = 1;
+    g.c_sj = 1;
+    BSE_TRY(cgemm(g, ar, f64, f64, st));
+  }
+  {
+    GemmArgs g;
+    g.batch = Nk;
+    g.M = nq * nc;
+    g.N = nc * na;
+    g.K = no;
+    g.A = p->psi;
+    g.a_tab = p->tab_psi_c;
+    g.a_tab_pb = 1;
+    g.a_sk = 1;
+    g.B = p->Bc;
+    g.b_sb = (long long)nc * na * no;
+    g.b_sj = no;
+    g.b_sk = 1;
+    g.C = p->Mc;
+    g.c_tab = p->tab_mc;
+    g.c_tab_pb = 1;
+    g.c_sj = 1;
+    BSE_TRY(cgemm(g, ar, f64, f64, st));
+  }
+  return BSE_OK;
+}
+
+}  // namespace
+
+bse_status apply_diag(Plan* p, const double* X, double* Y, int nb, hipStream_t st) {
+  const long long n = p->N * nb;
+  hipLaunchKernelGGL(diag_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p->N, p->d.nv, p->d.nc,
+                     nb, p->eps, X, Y);
+  BSE_CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+bse_status apply_exchange(Plan* p, const double* X, double* Y, int nb, hipStream_t st) {
+  if (p->d.alpha == 0.0) return BSE_OK;
+  const int na = p->d.n_aux;
+  const long long Ks = p->N / p->xsplit;
+  {  // partial t_s = rho_s^H X_s
+    GemmArgs g;
+    g.batch = p->xsplit;
+    g.M = na;
+    g.N = nb;
+    g.K = (int)Ks;
+    g.A = p->rho;
+    g.a_sb = Ks * na;
+    g.a_si = 1;
+    g.a_sk = na;
+    g.conjA = 1;
+    g.B = X;
+    g.b_sb = Ks * nb;
+    g.b_sk = nb;
+    g.b_sj = 1;
+    g.C = p->xt;
+    g.c_sb = (long long)na * nb;
+    g.c_si = nb;
+    g.c_sj = 1;
+    BSE_TRY(cgemm(g, AR_F64, true, true, st));
+  }
+  double* t = p->xt + 2 * (long long)p->xsplit * na * p->max_nb;  // reduced t after the partials
+  {
+    const int n = na * nb;
+    hipLaunchKernelGGL(splitk_reduce, dim3((n + 255) / 256), dim3(256), 0, st, p->xsplit, n, p->xt, t);
+    BSE_CHECK_LAUNCH();
+  }
+  {  // u = Vbar t
+    GemmArgs g;
+    g.M = na;
+    g.N = nb;
+    g.K = na;
+    g.A = p->vbar;
+    g.a_si = na;
+    g.a_sk = 1;
+    g.B = t;
+    g.b_sk = nb;
+    g.b_sj = 1;
+    g.C = p->xu;
+    g.c_si = nb;
+    g.c_sj = 1;
+    BSE_TRY(cgemm(g, AR_F64, true, true, st));
+  }
+  {  // Y += (alpha / N_k) rho u
+    GemmArgs g;
+    g.M = (int)p->N;
+    g.N = nb;
+    g.K = na;
+    g.A = p->rho;
+    g.a_si = na;
+    g.a_sk = 1;
+    g.B = p->xu;
+    g.b_sk = nb;
+    g.b_sj = 1;
+    g.C = Y;
+    g.c_si = nb;
+    g.c_sj = 1;
+    g.alpha = p->d.alpha / (double)p->Nk;
+    g.beta = 1;
+    BSE_TRY(cgemm(g, AR_F64, true, true, st));
+  }
+  return BSE_OK;
+}
+
+bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t st) {
+  const bse_dims& d = p->d;
+  const int Nk = p->Nk, nv = d.nv, nc = d.nc, na = d.n_aux;
+  const Arith ar = arith_of(p->prec);
+  const bool f64 = p->prec == BSE_F64;
+  const int nt = nc * nv;
+  for (int q0 = 0; q0 < Nk; q0 += p->qb) {
+    const int nq = (Nk - q0) < p->qb ? (Nk - q0) : p->qb;
+    BSE_TRY(form_pair_densities(p, q0, nq, st));
+    {  // P = conj(Gv) W(q)
+      GemmArgs g;
+      g.batch = nq;
+      g.M = Nk * nv * nv;
+      g.N = na;
+      g.K = na;
+      g.A = p->Mv;
+      g.a_sb = (long long)Nk * nv * nv * na;
+      g.a_si = na;
+      g.a_sk = 1;
+      g.conjA = 1;
+      g.B = off_bytes(p->Wq, (long long)q0 * na * na, p->esz);
+      g.b_sb = (long long)na * na;
+      g.b_sk = na;
+      g.b_sj = 1;
+      g.C = p->P;
+      g.c_sb = (long long)Nk * nv * nv * na;
+      g.c_si = na;
+      g.c_sj = 1;
+      BSE_TRY(cgemm(g, ar, f64, f64, st));
+    }
+    {  // T = Mc P^T over nu
+      GemmArgs g;
+      g.batch = nq * Nk;
+      g.M = nc * nc;
+      g.N = nv * nv;
+      g.K = na;
+      g.A = p->Mc;
+      g.a_sb = (long long)nc * nc * na;
+      g.a_si = na;
+      g.a_sk = 1;
+      g.B = p->P;
+      g.b_sb = (long long)nv * nv * na;
+      g.b_sj = na;
+      g.b_sk = 1;
+      g.C = p->T;
+      g.c_sb = (long long)nc * nc * nv * nv;
+      g.c_si = nv * nv;
+      g.c_sj = 1;
+      BSE_TRY(cgemm(g, ar, f64, f64, st));
+    }
+    {
+      const size_t sh = (size_t)nt * nt * p->esz + (size_t)nt * nb * 16;
+      const double scale = -1.0 / (double)Nk;
+      static bool attr_set = false;
+      if (!attr_set) {
+        BSE_HIP(hipFuncSetAttribute((const void*)direct_tx_kernel<double>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        BSE_HIP(hipFuncSetAttribute((const void*)direct_tx_kernel<float>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        attr_set = true;
+      }
+      if (f64)
+        hipLaunchKernelGGL(direct_tx_kernel<double>, dim3(Nk), dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, scale,
+                           p->kq, (const double*)p->T, X, Y);
+      else
+        hipLaunchKernelGGL(direct_tx_kernel<float>, dim3(Nk), dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, scale,
+                           p->kq, (const float*)p->T, X, Y);
+      BSE_CHECK_LAUNCH();
+    }
+  }
+  return BSE_OK;
+}
+
+bse_status adjoint_direct(Plan* p, const double* Ybar, const double* X, int nb, double* gWq, hipStream_t st) {
+  const bse_dims& d = p->d;
+  const int Nk = p->Nk, nv = d.nv, nc = d.nc, na = d.n_aux;
+  const Arith ar = arith_of(p->prec);
+  const bool f64 = p->prec == BSE_F64;
+  for (int q0 = 0; q0 < Nk; q0 += p->qb) {
+    const int nq = (Nk - q0) < p->qb ? (Nk - q0) : p->qb;
+    BSE_TRY(form_pair_densities(p, q0, nq, st));
+    if (f64)
+      hipLaunchKernelGGL(adj_gm_kernel<double>, dim3(nq * Nk), dim3(256), 0, st, Nk, nq, q0, nv, nc, nb, p->kq,
+                         Ybar, X, (double*)p->T);
+    else
+      hipLaunchKernelGGL(adj_gm_kernel<float>, dim3(nq * Nk), dim3(256), 0, st, Nk, nq, q0, nv, nc, nb, p->kq,
+                         Ybar, X, (float*)p->T);
+    BSE_CHECK_LAUNCH();
+    {  // Z[(v'v)][nu] = sum_{c'c} Gm[(v'v)][(c'c)] conj(Mc[(c'c)][nu])   (stored in P)
+      GemmArgs g;
+      g.batch = nq * Nk;
+      g.M = nv * nv;
+      g.N = na;
+      g.K = nc * nc;
+      g.A = p->T;
+      g.a_sb = (long long)nc * nc * nv * nv;
+      g.a_si = nc * nc;
+      g.a_sk = 1;
+      g.B = p->Mc;
+      g.b_sb = (long long)nc * nc * na;
+      g.b_sk = na;
+      g.b_sj = 1;
+      g.conjB = 1;
+      g.C = p->P;
+      g.c_sb = (long long)nv * nv * na;
+      g.c_si = na;
+      g.c_sj = 1;
+      BSE_TRY(cgemm(g, ar, f64, f64, st));
+    }
+    {  // gWq[q][mu][nu] = -(1/N_k) sum_{(k v' v)} Gv[(k v' v)][mu] Z[(k v' v)][nu]
+      GemmArgs g;
+      g.batch = nq;
+      g.M = na;
+      g.N = na;
+      g.K = Nk * nv * nv;
+      g.A = p->Mv;
+      g.a_sb = (long long)Nk * nv * nv * na;
+      g.a_si = 1;
+      g.a_sk = na;
+      g.B = p->P;
+      g.b_sb = (long long)Nk * nv * nv * na;
+      g.b_sk = na;
+      g.b_sj = 1;
+      g.C = gWq + 2 * (long long)q0 * na * na;
+      g.c_sb = (long long)na * na;
+      g.c_si = na;
+      g.c_sj = 1;
+      g.alpha = -1.0 / (double)Nk;
+      BSE_TRY(cgemm(g, ar, f64, true, st));
+    }
+  }
+  return BSE_OK;
+}
+
+bse_status adjoint_eps(Plan* p, const double* Ybar, const double* X, int nb, double* geps, hipStream_t st) {
+  hipLaunchKernelGGL(adj_eps_kernel, dim3(p->Nk), dim3(64), 0, st, p->d.nv, p->d.nc, nb, Ybar, X, geps);
+  BSE_CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+}  // namespace bse

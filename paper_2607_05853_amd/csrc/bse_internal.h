@@ -1,0 +1,160 @@
+// Internal declarations of the gfx950 BSE library: plan layout, error
+// plumbing and the batched complex GEMM engine shared by the stages.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/bse.h"
+
+namespace bse {
+
+// ---------------------------------------------------------------------------
+// error handling: a thread-local message, status codes, no exceptions across
+// the C ABI
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+const char* last_error();
+
+#define BSE_HIP(call)                                                          \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      ::bse::set_error(std::string(#call) + ": " + hipGetErrorString(e_));     \
+      return BSE_EDEVICE;                                                      \
+    }                                                                          \
+  } while (0)
+
+#define BSE_CHECK_LAUNCH()                                                     \
+  do {                                                                         \
+    hipError_t e_ = hipGetLastError();                                         \
+    if (e_ != hipSuccess) {                                                    \
+      ::bse::set_error(std::string("kernel launch: ") + hipGetErrorString(e_));\
+      return BSE_EDEVICE;                                                      \
+    }                                                                          \
+  } while (0)
+
+#define BSE_TRY(expr)                                                          \
+  do {                                                                         \
+    bse_status s_ = (expr);                                                    \
+    if (s_ != BSE_OK) return s_;                                               \
+  } while (0)
+
+// device allocation with a test hook: BSE_TEST_FAIL_ALLOC=n makes the n-th
+// allocation of the process fail (n >= 1), so ENOMEM paths are testable.
+bse_status dmalloc(void** p, size_t bytes);
+void dfree(void* p);
+
+// ---------------------------------------------------------------------------
+// batched complex GEMM on the matrix cores
+//   C_b[i][j] = alpha * sum_k opA(A_b[i][k]) opB(B_b[k][j])  (+ C_b[i][j] if beta)
+// Offsets are in complex elements.  Row offsets of A and C and column offsets
+// of B are either affine (b*sb + i*si) or read from a device table indexed by
+// i (tab_pb = 0) or by b*M + i (tab_pb = 1); the K strides are uniform.
+// ---------------------------------------------------------------------------
+enum Arith { AR_F64 = 0, AR_F32 = 1, AR_BF16X3 = 2 };
+
+struct GemmArgs {
+  int M = 0, N = 0, K = 0, batch = 1;
+  const void* A = nullptr;
+  long long a_sb = 0, a_si = 0, a_sk = 0;
+  const long long* a_tab = nullptr;
+  int a_tab_pb = 0, conjA = 0;
+  const void* B = nullptr;
+  long long b_sb = 0, b_sj = 0, b_sk = 0;
+  const long long* b_tab = nullptr;
+  int b_tab_pb = 0, conjB = 0;
+  void* C = nullptr;
+  long long c_sb = 0, c_si = 0, c_sj = 0;
+  const long long* c_tab = nullptr;
+  int c_tab_pb = 0;
+  double alpha = 1.0;
+  int beta = 0;
+};
+
+// in_f64: A and B are c128 (else c64); out_f64: C is c128 (else c64).
+// AR_F64 requires in_f64.  AR_F32 / AR_BF16X3 require c64 inputs.
+bse_status cgemm(const GemmArgs& g, Arith ar, bool in_f64, bool out_f64, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Plan {
+  bse_dims d{};
+  int Nk = 0, nt = 0, nbnd = 0;
+  long long N = 0;
+  bse_prec prec = BSE_F64;
+  int max_nb = 0;
+  int device = 0;
+  size_t esz = 16;  // bytes per complex element of the plan precision
+
+  // FP64 data
+  double* eps = nullptr;      // [Nk][nv+nc]
+  double* psi64 = nullptr;    // c128 [Nk][nv+nc][n_ao]
+  double* rho = nullptr;      // c128 [N][n_aux]   rho[I][mu] = M^mu_cv(k,k)
+  double* vbar = nullptr;     // c128 [n_aux][n_aux]
+  // plan-precision data (c128 for F64, c64 otherwise)
+  void* psi = nullptr;        // [Nk][nv+nc][n_ao]
+  void* Bv = nullptr;         // [Nk][nv][n_aux][n_ao]   B^mu_v(k)
+  void* Bc = nullptr;         // [Nk][nc][n_aux][n_ao]   B^mu_c(k)
+  void* Wq = nullptr;         // [Nk][n_aux][n_aux]
+
+  // q-batch workspaces of the direct term (plan precision)
+  int qb = 0;                 // q values per batch
+  void* Mv = nullptr;         // [qb][Nk][nv][nv][n_aux]  M^mu_{v v'}(k, k+q)  (row (v', v) after conj)
+  void* Mc = nullptr;         // [qb][Nk][nc][nc][n_aux]  M^nu_{c c'}(k, k+q)
+  void* P = nullptr;          // [qb][Nk][nv][nv][n_aux]
+  void* T = nullptr;          // [qb][Nk][nc*nc][nv*nv]   direct block per pair
+  long long* tab_psi_v = nullptr;   // [Nk][qb*nv]  row offsets of psi_v(k+q)
+  long long* tab_psi_c = nullptr;   // [Nk][qb*nc]
+  long long* tab_mv = nullptr;      // [Nk][qb*nv]  row offsets into Mv
+  long long* tab_mc = nullptr;      // [Nk][qb*nc]
+  int* kq = nullptr;                // [Nk][Nk] k + q index table (k, q) -> k'
+
+  // exchange / misc workspaces (FP64)
+  double* xt = nullptr;       // c128 split-K partials [nsplit][n_aux][max_nb]
+  double* xu = nullptr;       // c128 [n_aux][max_nb]
+  int xsplit = 1;
+
+  // adjoint
+  std::vector<int32_t> R;
+  std::vector<double> wR;
+  double* gq_acc = nullptr;   // c128 [Nk][n_aux][n_aux]
+  double* gw_tmp = nullptr;   // c128 [qb][Nk][nv][nv][n_aux]
+
+  std::vector<DevBuf> owned;
+  size_t bytes = 0;
+};
+
+bse_status plan_alloc(Plan* p, void** ptr, size_t bytes);
+
+// stage launchers (apply.hip)
+bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t st);
+bse_status apply_exchange(Plan* p, const double* X, double* Y, int nb, hipStream_t st);
+bse_status apply_diag(Plan* p, const double* X, double* Y, int nb, hipStream_t st);
+bse_status adjoint_direct(Plan* p, const double* Ybar, const double* X, int nb, double* gWq, hipStream_t st);
+bse_status adjoint_eps(Plan* p, const double* Ybar, const double* X, int nb, double* geps, hipStream_t st);
+
+// interpolation (interp.hip)
+bse_status interp_forward(int n_aux, int n_R, const double* W_R, const int32_t* R, const double* w_R,
+                          int n_q, const double* q, void* W_q, bool out_f64, hipStream_t st);
+bse_status interp_adjoint(int n_aux, int n_R, const int32_t* R, const double* w_R, int n_q,
+                          const double* q, const double* g_Wq, double* g_WR, hipStream_t st);
+
+// small streaming kernels (util.hip)
+bse_status convert_c128_to_c64(const double* in, float* out, long long n, hipStream_t st);
+bse_status zero_fill(void* p, size_t bytes, hipStream_t st);
+
+}  // namespace bse
+
+struct bse_plan {
+  bse::Plan impl;
+};

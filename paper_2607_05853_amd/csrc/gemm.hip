@@ -1,0 +1,489 @@
+// Batched complex GEMM on the gfx950 matrix cores.
+//
+// A complex product C = A B is evaluated as one real GEMM of doubled depth and
+// width:  A is read as the real M x 2K matrix its interleaved storage already is
+// (column 2k = Re A_ik, 2k+1 = Im A_ik) and B is expanded on the fly to the real
+// 2K x 2N matrix  [[Re B, Im B], [-Im B, Re B]]  (row 2k / 2k+1, column 2j / 2j+1),
+// so the real output is the interleaved complex C.  That is the 4-real-product
+// form of the complex product (8 real flops per complex MAC), with no separate
+// real/imaginary accumulators and a natural interleaved store.
+//
+//  FP64 : v_mfma_f64_16x16x4f64, FP32 : v_mfma_f32_16x16x4f32.  Each wave owns a
+//         TM x TN grid of 16 x 16 real output tiles; A and B tiles are staged in
+//         LDS with a one-tile register prefetch of the next K slice.
+//  BF16X3: v_mfma_f32_16x16x32_bf16.  Operands are split once when staged into
+//         LDS (hi = bf16(x), lo = bf16(x - hi)); every tile step issues
+//         hi*hi + hi*lo + lo*hi with FP32 accumulation.
+#include "bse_internal.h"
+
+#include <hip/hip_bf16.h>
+
+namespace bse {
+namespace {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+template <typename T>
+struct V4;
+template <>
+struct V4<double> {
+  using t = d4v;
+};
+template <>
+struct V4<float> {
+  using t = f4v;
+};
+
+__device__ __forceinline__ d4v mma16(double a, double b, d4v c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4v mma16(float a, float b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ long long off_of(const long long* tab, int pb, long long sb, long long si,
+                                            int b, int M, int i) {
+  long long o = (long long)b * sb;
+  if (tab) return o + tab[(pb ? (long long)b * M : 0LL) + i];
+  return o + (long long)i * si;
+}
+
+template <typename T>
+struct C2 {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ C2<T> ldc(const T* p, long long off) {
+  C2<T> r;
+  if constexpr (sizeof(T) == 8) {
+    const double2 v = *reinterpret_cast<const double2*>(p + 2 * off);
+    r.x = v.x;
+    r.y = v.y;
+  } else {
+    const float2 v = *reinterpret_cast<const float2*>(p + 2 * off);
+    r.x = v.x;
+    r.y = v.y;
+  }
+  return r;
+}
+
+// ----------------------------------------------------------------------------
+// FP64 / FP32 kernel
+// ----------------------------------------------------------------------------
+template <typename T, typename TC, int WM, int WN, int TM, int TN, int BK>
+__global__ __launch_bounds__(256) void cgemm_real(GemmArgs g) {
+  static_assert(WM * WN == 4, "4 waves");
+  constexpr int BM = WM * TM * 16;   // complex rows per block
+  constexpr int BNR = WN * TN * 16;  // real output columns per block
+  constexpr int BN = BNR / 2;        // complex columns per block
+  constexpr int AE = (BM * BK + 255) / 256;
+  constexpr int BE = (BK * BN + 255) / 256;
+  constexpr int PA = (sizeof(T) == 8) ? 1 : 1;
+  constexpr int PB = (sizeof(T) == 8) ? 2 : 4;
+  __shared__ T As[BM][2 * BK + PA];
+  __shared__ T Bs[BK][BNR + PB];
+  using acc_t = typename V4<T>::t;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int n0 = blockIdx.x * BN, m0 = blockIdx.y * BM;
+  const T* __restrict__ A = (const T*)g.A;
+  const T* __restrict__ B = (const T*)g.B;
+  TC* __restrict__ C = (TC*)g.C;
+  const bool a_kf = (g.a_sk == 1);
+  const bool b_kf = (g.b_sk == 1);
+  const int r = (lane >> 4) & 1, s = lane & 1;
+  const int bcomp = (r != s) ? 1 : 0;
+  const T bsgn = (r == 1 && s == 0) ? T(-1) : T(1);
+  const T asg = g.conjA ? T(-1) : T(1);
+  const T bsg = g.conjB ? T(-1) : T(1);
+
+  for (int b = blockIdx.z; b < g.batch; b += gridDim.z) {
+    long long aoff[AE];
+    int ai[AE], ak[AE];
+    bool aok[AE];
+#pragma unroll
+    for (int e = 0; e < AE; ++e) {
+      const int idx = tid + 256 * e;
+      if (a_kf) {
+        ak[e] = idx % BK;
+        ai[e] = idx / BK;
+      } else {
+        ai[e] = idx % BM;
+        ak[e] = idx / BM;
+      }
+      const int row = m0 + ai[e];
+      aok[e] = (idx < BM * BK) && (row < g.M);
+      aoff[e] = aok[e] ? off_of(g.a_tab, g.a_tab_pb, g.a_sb, g.a_si, b, g.M, row) : 0;
+    }
+    long long boff[BE];
+    int bj[BE], bk[BE];
+    bool bok[BE];
+#pragma unroll
+    for (int e = 0; e < BE; ++e) {
+      const int idx = tid + 256 * e;
+      if (b_kf) {
+        bk[e] = idx % BK;
+        bj[e] = idx / BK;
+      } else {
+        bj[e] = idx % BN;
+        bk[e] = idx / BN;
+      }
+      const int col = n0 + bj[e];
+      bok[e] = (idx < BK * BN) && (col < g.N);
+      boff[e] = bok[e] ? off_of(g.b_tab, g.b_tab_pb, g.b_sb, g.b_sj, b, g.N, col) : 0;
+    }
+
+    acc_t acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+
+    C2<T> ra[AE], rb[BE];
+    auto gload = [&](int k0) {
+#pragma unroll
+      for (int e = 0; e < AE; ++e) {
+        const int kk = k0 + ak[e];
+        if (aok[e] && kk < g.K) {
+          ra[e] = ldc<T>(A, aoff[e] + (long long)kk * g.a_sk);
+          ra[e].y *= asg;
+        } else {
+          ra[e].x = T(0);
+          ra[e].y = T(0);
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < BE; ++e) {
+        const int kk = k0 + bk[e];
+        if (bok[e] && kk < g.K) {
+          rb[e] = ldc<T>(B, boff[e] + (long long)kk * g.b_sk);
+          rb[e].y *= bsg;
+        } else {
+          rb[e].x = T(0);
+          rb[e].y = T(0);
+        }
+      }
+    };
+    gload(0);
+    for (int k0 = 0; k0 < g.K; k0 += BK) {
+#pragma unroll
+      for (int e = 0; e < AE; ++e) {
+        if (tid + 256 * e < BM * BK) {
+          As[ai[e]][2 * ak[e]] = ra[e].x;
+          As[ai[e]][2 * ak[e] + 1] = ra[e].y;
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < BE; ++e) {
+        if (tid + 256 * e < BK * BN) {
+          Bs[bk[e]][2 * bj[e]] = rb[e].x;
+          Bs[bk[e]][2 * bj[e] + 1] = rb[e].y;
+        }
+      }
+      __syncthreads();
+      if (k0 + BK < g.K) gload(k0 + BK);
+#pragma unroll
+      for (int kk4 = 0; kk4 < (2 * BK) / 4; ++kk4) {
+        const int kk = kk4 * 4 + (lane >> 4);
+        const int kc = kk >> 1;
+        T av[TM], bv[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) av[i] = As[wm * TM * 16 + i * 16 + (lane & 15)][kk];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const int jj = wn * TN * 16 + j * 16 + (lane & 15);
+          bv[j] = bsgn * Bs[kc][(jj & ~1) + bcomp];
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) acc[i][j] = mma16(av[i], bv[j], acc[i][j]);
+      }
+      __syncthreads();
+    }
+
+    // epilogue: register q of a lane holds real column lane%16 of row
+    //   4*(lane/16) + q  (f32 16x16x4)   or   4*q + lane/16  (f64 16x16x4)
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int rin = (sizeof(T) == 8) ? (4 * q + (lane >> 4)) : (4 * (lane >> 4) + q);
+        const int row = m0 + wm * TM * 16 + i * 16 + rin;
+        if (row >= g.M) continue;
+        const long long ro = off_of(g.c_tab, g.c_tab_pb, g.c_sb, g.c_si, b, g.M, row);
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const int jj = wn * TN * 16 + j * 16 + (lane & 15);
+          const int col = n0 + (jj >> 1);
+          if (col >= g.N) continue;
+          const long long o = 2 * (ro + (long long)col * g.c_sj) + (jj & 1);
+          double v = g.alpha * (double)acc[i][j][q];
+          if (g.beta) v += (double)C[o];
+          C[o] = (TC)v;
+        }
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// BF16x3 kernel (c64 inputs, split into bf16 hi/lo when staged to LDS)
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+template <typename TC, int WM, int WN, int TM, int TN, int BK>
+__global__ __launch_bounds__(256) void cgemm_bf16x3(GemmArgs g) {
+  static_assert(WM * WN == 4, "4 waves");
+  static_assert(BK % 16 == 0, "BK multiple of 16 complex (32 real)");
+  constexpr int BM = WM * TM * 16;
+  constexpr int BNR = WN * TN * 16;
+  constexpr int BN = BNR / 2;
+  constexpr int KR = 2 * BK;        // real depth of a tile
+  constexpr int LD = KR + 8;        // bf16 row length in LDS (16 B aligned rows)
+  constexpr int AE = (BM * BK + 255) / 256;
+  constexpr int BE = (BK * BN + 255) / 256;
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[BM * LD];
+  __shared__ __attribute__((aligned(16))) __bf16 Al[BM * LD];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[BNR * LD];   // expanded B, transposed: [jj][kk]
+  __shared__ __attribute__((aligned(16))) __bf16 Bl[BNR * LD];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int n0 = blockIdx.x * BN, m0 = blockIdx.y * BM;
+  const float* __restrict__ A = (const float*)g.A;
+  const float* __restrict__ B = (const float*)g.B;
+  TC* __restrict__ C = (TC*)g.C;
+  const bool a_kf = (g.a_sk == 1);
+  const bool b_kf = (g.b_sk == 1);
+  const float asg = g.conjA ? -1.f : 1.f;
+  const float bsg = g.conjB ? -1.f : 1.f;
+
+  for (int b = blockIdx.z; b < g.batch; b += gridDim.z) {
+    long long aoff[AE];
+    int ai[AE], ak[AE];
+    bool aok[AE];
+#pragma unroll
+    for (int e = 0; e < AE; ++e) {
+      const int idx = tid + 256 * e;
+      if (a_kf) {
+        ak[e] = idx % BK;
+        ai[e] = idx / BK;
+      } else {
+        ai[e] = idx % BM;
+        ak[e] = idx / BM;
+      }
+      const int row = m0 + ai[e];
+      aok[e] = (idx < BM * BK) && (row < g.M);
+      aoff[e] = aok[e] ? off_of(g.a_tab, g.a_tab_pb, g.a_sb, g.a_si, b, g.M, row) : 0;
+    }
+    long long boff[BE];
+    int bj[BE], bk[BE];
+    bool bok[BE];
+#pragma unroll
+    for (int e = 0; e < BE; ++e) {
+      const int idx = tid + 256 * e;
+      if (b_kf) {
+        bk[e] = idx % BK;
+        bj[e] = idx / BK;
+      } else {
+        bj[e] = idx % BN;
+        bk[e] = idx / BN;
+      }
+      const int col = n0 + bj[e];
+      bok[e] = (idx < BK * BN) && (col < g.N);
+      boff[e] = bok[e] ? off_of(g.b_tab, g.b_tab_pb, g.b_sb, g.b_sj, b, g.N, col) : 0;
+    }
+    f4v acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = f4v{0, 0, 0, 0};
+
+    C2<float> ra[AE], rb[BE];
+    auto gload = [&](int k0) {
+#pragma unroll
+      for (int e = 0; e < AE; ++e) {
+        const int kk = k0 + ak[e];
+        if (aok[e] && kk < g.K) {
+          ra[e] = ldc<float>(A, aoff[e] + (long long)kk * g.a_sk);
+          ra[e].y *= asg;
+        } else {
+          ra[e].x = 0.f;
+          ra[e].y = 0.f;
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < BE; ++e) {
+        const int kk = k0 + bk[e];
+        if (bok[e] && kk < g.K) {
+          rb[e] = ldc<float>(B, boff[e] + (long long)kk * g.b_sk);
+          rb[e].y *= bsg;
+        } else {
+          rb[e].x = 0.f;
+          rb[e].y = 0.f;
+        }
+      }
+    };
+    gload(0);
+    for (int k0 = 0; k0 < g.K; k0 += BK) {
+#pragma unroll
+      for (int e = 0; e < AE; ++e) {
+        if (tid + 256 * e < BM * BK) {
+          __bf16 h, l;
+          split_bf16(ra[e].x, h, l);
+          Ah[ai[e] * LD + 2 * ak[e]] = h;
+          Al[ai[e] * LD + 2 * ak[e]] = l;
+          split_bf16(ra[e].y, h, l);
+          Ah[ai[e] * LD + 2 * ak[e] + 1] = h;
+          Al[ai[e] * LD + 2 * ak[e] + 1] = l;
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < BE; ++e) {
+        if (tid + 256 * e < BK * BN) {
+          // real rows 2k, 2k+1 and columns 2j, 2j+1 of [[Br, Bi], [-Bi, Br]]
+          __bf16 rh, rl, ih, il, nh, nl;
+          split_bf16(rb[e].x, rh, rl);
+          split_bf16(rb[e].y, ih, il);
+          split_bf16(-rb[e].y, nh, nl);
+          const int c0 = (2 * bj[e]) * LD + 2 * bk[e];
+          const int c1 = (2 * bj[e] + 1) * LD + 2 * bk[e];
+          Bh[c0] = rh;
+          Bl[c0] = rl;
+          Bh[c0 + 1] = nh;
+          Bl[c0 + 1] = nl;
+          Bh[c1] = ih;
+          Bl[c1] = il;
+          Bh[c1 + 1] = rh;
+          Bl[c1 + 1] = rl;
+        }
+      }
+      __syncthreads();
+      if (k0 + BK < g.K) gload(k0 + BK);
+#pragma unroll
+      for (int ks = 0; ks < KR / 32; ++ks) {
+        const int kb = ks * 32 + 8 * (lane >> 4);
+        bf8v ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          const int row = wm * TM * 16 + i * 16 + (lane & 15);
+          ah[i] = *reinterpret_cast<const bf8v*>(&Ah[row * LD + kb]);
+          al[i] = *reinterpret_cast<const bf8v*>(&Al[row * LD + kb]);
+        }
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const int jj = wn * TN * 16 + j * 16 + (lane & 15);
+          bh[j] = *reinterpret_cast<const bf8v*>(&Bh[jj * LD + kb]);
+          bl[j] = *reinterpret_cast<const bf8v*>(&Bl[jj * LD + kb]);
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+          }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = m0 + wm * TM * 16 + i * 16 + 4 * (lane >> 4) + q;
+        if (row >= g.M) continue;
+        const long long ro = off_of(g.c_tab, g.c_tab_pb, g.c_sb, g.c_si, b, g.M, row);
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const int jj = wn * TN * 16 + j * 16 + (lane & 15);
+          const int col = n0 + (jj >> 1);
+          if (col >= g.N) continue;
+          const long long o = 2 * (ro + (long long)col * g.c_sj) + (jj & 1);
+          double v = g.alpha * (double)acc[i][j][q];
+          if (g.beta) v += (double)C[o];
+          C[o] = (TC)v;
+        }
+      }
+    }
+  }
+}
+
+template <typename K>
+bse_status launch(K kern, const GemmArgs& g, int BM, int BN, hipStream_t st) {
+  const long long gx = (g.N + BN - 1) / BN, gy = (g.M + BM - 1) / BM;
+  if (gy > 65535) {
+    set_error("cgemm: too many row tiles");
+    return BSE_ESHAPE;
+  }
+  const int gz = g.batch < 65535 ? g.batch : 65535;
+  hipLaunchKernelGGL(kern, dim3((unsigned)gx, (unsigned)gy, (unsigned)gz), dim3(256), 0, st, g);
+  BSE_CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+// shape classes: wide (64 x 64), narrow-N (64 x 16), narrow-M (16 x 64)
+enum Shape { SH_WIDE, SH_NARROW_N, SH_NARROW_M };
+Shape pick(const GemmArgs& g) {
+  if (g.N <= 16 && g.M > 16) return SH_NARROW_N;
+  if (g.M <= 16 && g.N > 16) return SH_NARROW_M;
+  return SH_WIDE;
+}
+
+template <typename T, typename TC>
+bse_status run_real(const GemmArgs& g, hipStream_t st) {
+  constexpr int BK = (sizeof(T) == 8) ? 16 : 32;
+  switch (pick(g)) {
+    case SH_NARROW_N:
+      return launch(cgemm_real<T, TC, 4, 1, 1, 2, BK>, g, 64, 16, st);
+    case SH_NARROW_M:
+      return launch(cgemm_real<T, TC, 1, 4, 1, 2, BK>, g, 16, 64, st);
+    default:
+      return launch(cgemm_real<T, TC, 2, 2, 2, 4, BK>, g, 64, 64, st);
+  }
+}
+
+template <typename TC>
+bse_status run_bf16(const GemmArgs& g, hipStream_t st) {
+  switch (pick(g)) {
+    case SH_NARROW_N:
+      return launch(cgemm_bf16x3<TC, 4, 1, 1, 2, 32>, g, 64, 16, st);
+    case SH_NARROW_M:
+      return launch(cgemm_bf16x3<TC, 1, 4, 1, 2, 32>, g, 16, 64, st);
+    default:
+      return launch(cgemm_bf16x3<TC, 2, 2, 2, 4, 32>, g, 64, 64, st);
+  }
+}
+
+}  // namespace
+
+bse_status cgemm(const GemmArgs& g, Arith ar, bool in_f64, bool out_f64, hipStream_t st) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return BSE_OK;
+  if (g.K <= 0) {
+    set_error("cgemm: K must be positive");
+    return BSE_ESHAPE;
+  }
+  if (ar == AR_F64) {
+    if (!in_f64) {
+      set_error("cgemm: FP64 arithmetic needs c128 operands");
+      return BSE_EINVAL;
+    }
+    return out_f64 ? run_real<double, double>(g, st) : run_real<double, float>(g, st);
+  }
+  if (in_f64) {
+    set_error("cgemm: reduced-precision arithmetic needs c64 operands");
+    return BSE_EINVAL;
+  }
+  if (ar == AR_F32) return out_f64 ? run_real<float, double>(g, st) : run_real<float, float>(g, st);
+  return out_f64 ? run_bf16<double>(g, st) : run_bf16<float>(g, st);
+}
+
+}  // namespace bse

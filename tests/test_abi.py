@@ -1,0 +1,94 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol of
+include/bse.h, and validates arguments before any HIP call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HDR = os.path.join(ROOT, "include", "bse.h")
+
+
+def _header_symbols():
+    txt = open(HDR).read()
+    return sorted(set(re.findall(r"^(?:const char\*|bse_status)\s+(bse_\w+)\s*\(", txt, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2607_05853_amd import bse
+    return bse.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    syms = _header_symbols()
+    assert len(syms) >= 15
+    for s in syms:
+        assert hasattr(L, s), s
+    from paper_2607_05853_amd import bse
+    assert sorted(bse.EXPORTS) == syms
+
+
+def test_status_strings(L):
+    assert L.bse_status_string(0) == b"ok"
+    assert b"invalid" in L.bse_status_string(1)
+    assert b"breakdown" in L.bse_status_string(100).lower()
+    assert L.bse_version().startswith(b"bse-gfx950")
+
+
+def test_interpolate_validation_before_hip(L):
+    R = np.zeros((1, 3), np.int32)
+    w = np.ones(1)
+    q = np.zeros((1, 3))
+    dummy = ctypes.c_void_p(16)  # never dereferenced: validation fails first
+    assert L.bse_interpolate_W(0, 1, dummy, R.ctypes.data, w.ctypes.data, 1, q.ctypes.data, dummy, 0, None) == 1
+    assert L.bse_interpolate_W(4, 1, None, R.ctypes.data, w.ctypes.data, 1, q.ctypes.data, dummy, 0, None) == 1
+    assert L.bse_interpolate_W(4, 1, dummy, R.ctypes.data, w.ctypes.data, 1, q.ctypes.data, dummy, 7, None) == 1
+    assert b"precision" in L.bse_last_error()
+    assert L.bse_interpolate_W_adjoint(4, 1, None, w.ctypes.data, 1, q.ctypes.data, dummy, dummy, None) == 1
+
+
+def _dims(**kw):
+    from paper_2607_05853_amd.bse import _Dims
+    d = dict(nk=(2, 2, 2), n_ao=8, nv=2, nc=2, n_aux=12, alpha=2.0)
+    d.update(kw)
+    return _Dims((ctypes.c_int32 * 3)(*d["nk"]), d["n_ao"], d["nv"], d["nc"], d["n_aux"], d["alpha"])
+
+
+def test_plan_create_validation_before_hip(L):
+    dummy = ctypes.c_void_p(16)
+    out = ctypes.c_void_p()
+    args = lambda d, prec=0, nb=4, flags=0, ptr=dummy: L.bse_plan_create(
+        ctypes.byref(d), ptr, dummy, dummy, dummy, dummy, prec, nb, flags, None, ctypes.byref(out))
+    assert args(_dims(nk=(0, 2, 2))) == 1
+    assert args(_dims(nv=0)) == 1
+    assert args(_dims(alpha=float("nan"))) == 1
+    assert args(_dims(), ptr=None) == 1
+    assert args(_dims(), prec=5) == 1
+    assert args(_dims(), nb=0) == 1
+    assert args(_dims(), flags=8) == 1
+    assert args(_dims(nv=32, nc=32), nb=4) == 2          # nv*nc*max_nb above the limit
+    assert args(_dims(nk=(2048, 2048, 2))) == 2          # too many k points
+    assert L.bse_plan_create(None, dummy, dummy, dummy, dummy, dummy, 0, 4, 0, None, ctypes.byref(out)) == 1
+    assert out.value is None
+
+
+def test_null_plan_calls(L):
+    dummy = ctypes.c_void_p(16)
+    assert L.bse_apply(None, dummy, dummy, 1, None) == 1
+    assert L.bse_apply_adjoint(None, dummy, dummy, 1, None, None, None, None) == 1
+    assert L.bse_haydock_spectrum(None, dummy, 1, 1, dummy, 1, 0.1, dummy, dummy, dummy, dummy, None, None) == 1
+    assert L.bse_plan_set_R(None, 1, dummy, dummy) == 1
+    assert L.bse_plan_destroy(None) == 0
+    assert L.bse_lowest_excitons(None, 4, 10, 1e-8, None, dummy, None, None, None) == 1
+    assert L.bse_velocity_start(None, dummy, dummy, 1, dummy, dummy, None) == 1
+
+
+def test_binding_rejects_cpu_tensors():
+    import torch
+    from paper_2607_05853_amd import bse
+    with pytest.raises(TypeError):
+        bse.interpolate_W(torch.zeros((1, 2, 2), dtype=torch.complex128), np.zeros((1, 3)), np.ones(1),
+                          np.zeros((1, 3)))

@@ -1,0 +1,255 @@
+"""GPU parity: every C-ABI entry point against the FP64 oracle on seeded inputs.
+
+Tolerances (relative to the largest reference element):
+* FP64 paths: 1e-12 (rounding-order differences of FP64 sums of <= 10^5 terms);
+* FP32 contractions: 2e-5 (FP32 unit roundoff 6e-8 times sqrt of the
+  contraction depth, with margin);
+* BF16x3 contractions: 5e-4 (two-term bf16 split keeps ~16 significant bits,
+  2^-16 = 1.5e-5 per product, times the depth's random-walk growth).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from synth import dense_kmesh, make_problem, polarisations, random_block
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 2e-5, "bf16x3": 5e-4}
+RAGGED = dict(cfg_id=93, coarse=(3, 3, 3), dense=(3, 2, 5), n_ao=12, nv=3, nc=5, n_aux=40)
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def T(a, dt=torch.complex128):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(dev(), dt)
+
+
+def H_(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2607_05853_amd import bse
+    print("\n[gpu] libbse", bse.version(), flush=True)
+    return bse
+
+
+# ---------------------------------------------------------------------------
+# interpolation
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n_aux,n_R,n_q", [(5, 3, 7), (17, 27, 64), (64, 125, 33)])
+def test_interpolate_small(B, n_aux, n_R, n_q):
+    rng = np.random.default_rng(n_aux)
+    W_R = rng.standard_normal((n_R, n_aux, n_aux)) + 1j * rng.standard_normal((n_R, n_aux, n_aux))
+    R = rng.integers(-3, 4, size=(n_R, 3)).astype(np.int32)
+    w = rng.random(n_R)
+    q = rng.random((n_q, 3))
+    ref = O.interpolate_W(W_R, R, w, q)
+    out = H_(B.interpolate_W(T(W_R), R, w, q))
+    assert rel(out, ref) < TOL["f64"]
+    out32 = H_(B.interpolate_W(T(W_R), R, w, q, out_prec="f32"))
+    assert rel(out32, ref) < 1e-6
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c2"])
+def test_interpolate_configs(B, cfg):
+    p = make_problem(cfg, 0, "G2")
+    kq = dense_kmesh(p.nk)
+    got = H_(B.interpolate_W(T(p.W_R), p.R, p.w_R, kq))
+    idx = np.arange(len(kq)) if cfg == "c1" else np.array([0, 1, 7, 63, 64, 200, 511])
+    ref = O.interpolate_W(p.W_R, p.R, p.w_R, kq[idx])
+    assert rel(got[idx], ref) < TOL["f64"]
+    # Hermitian W(q) for the G2 generator, at every q
+    assert np.abs(got - np.conj(np.transpose(got, (0, 2, 1)))).max() < 1e-13 * np.abs(got).max()
+
+
+def test_interpolate_large_sampled(B):
+    # the largest workload's table: 4096 q x 512^2, checked on sampled q against the oracle
+    p = make_problem("c5", 0, "G1")
+    kq = dense_kmesh(p.nk)
+    got = B.interpolate_W(T(p.W_R), p.R, p.w_R, kq)
+    idx = np.array([0, 1, 255, 1000, 4095])
+    ref = O.interpolate_W(p.W_R, p.R, p.w_R, kq[idx])
+    assert rel(H_(got[torch.as_tensor(idx, device=dev())]), ref) < TOL["f64"]
+    del got
+
+
+def test_coarse_round_trip_on_gpu(B):
+    # coarse W(k) -> R (adjoint with weights 1/N_c) -> back onto the coarse points: exact
+    from synth import ws_rset
+    coarse = (4, 4, 4)
+    R, w = ws_rset(coarse)
+    qc = dense_kmesh(coarse)
+    rng = np.random.default_rng(11)
+    Wqc = rng.standard_normal((len(qc), 6, 6)) + 1j * rng.standard_normal((len(qc), 6, 6))
+    W_R = B.interpolate_W_adjoint(T(Wqc), R, np.full(len(R), 1.0 / len(qc)), qc)
+    assert rel(H_(W_R), O.coarse_to_R(Wqc, coarse, R)) < TOL["f64"]
+    back = H_(B.interpolate_W(W_R, R, w, qc))
+    assert rel(back, Wqc) < TOL["f64"]
+
+
+def test_interpolate_adjoint_matches_oracle(B):
+    p = make_problem("c1", 0, "G2", coarse=(3, 3, 2))
+    kq = dense_kmesh(p.nk)
+    rng = np.random.default_rng(4)
+    g = rng.standard_normal((len(kq), p.n_aux, p.n_aux)) + 1j * rng.standard_normal((len(kq), p.n_aux, p.n_aux))
+    got = H_(B.interpolate_W_adjoint(T(g), p.R, p.w_R, kq))
+    ref = O.grad_WR_from_Wq(g, p.R, p.w_R, kq)
+    assert rel(got, ref) < TOL["f64"]
+
+
+# ---------------------------------------------------------------------------
+# apply
+# ---------------------------------------------------------------------------
+def _plan(B, p, prec="f64", nb=8, Wq=None):
+    if Wq is None:
+        Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
+    return B.plan_from_problem(p, Wq, prec=prec, max_nb=nb, check_hermitian=True), Wq
+
+
+@pytest.mark.parametrize("wgen", ["G1", "G2"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
+def test_apply_c1(B, wgen, prec):
+    p = make_problem("c1", 0, wgen, coarse=(3, 3, 2) if wgen == "G2" else (2, 2, 2))
+    plan, Wq = _plan(B, p, prec, nb=3)
+    H = O.build_H(p, H_(Wq))
+    X = random_block(p.N, 3, seed=1)
+    Y = H_(plan.apply(T(X)))
+    err = rel(Y, H @ X)
+    print("[c1 %s %s] rel err %.3e" % (wgen, prec, err), flush=True)
+    assert err < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_apply_ragged_and_triplet(B, prec):
+    # sizes that are not multiples of any tile: 30 k, 3+5 bands, 40 aux, 12 AOs, 5 vectors
+    p = make_problem(RAGGED, 2, "G2")
+    plan, Wq = _plan(B, p, prec, nb=5)
+    X = random_block(p.N, 5, seed=3)
+    H = O.build_H(p, H_(Wq))
+    assert rel(H_(plan.apply(T(X))), H @ X) < TOL[prec]
+    p.alpha = 0.0
+    plan0, _ = _plan(B, p, prec, nb=5, Wq=Wq)
+    H0 = O.build_H(p, H_(Wq))
+    assert rel(H_(plan0.apply(T(X))), H0 @ X) < TOL[prec]
+    # nb smaller than max_nb, single vector
+    assert rel(H_(plan.apply(T(X[:, :1].copy()))), H @ X[:, :1]) < TOL[prec]
+
+
+def test_apply_c2_sampled_rows(B):
+    p = make_problem("c2", 0, "G2")
+    plan, Wq = _plan(B, p, "f64", nb=8)
+    X = random_block(p.N, 8, seed=5)
+    Y = H_(plan.apply(T(X)))
+    rows = [0, 301]
+    ref = O.apply_H_rows(p, H_(Wq), X, rows)
+    nt = p.nc * p.nv
+    got = np.concatenate([Y[k * nt:(k + 1) * nt] for k in rows])
+    assert rel(got, ref) < TOL["f64"]
+
+
+def test_apply_hermitian_and_deterministic(B):
+    p = make_problem(RAGGED, 4, "G2")
+    plan, _ = _plan(B, p, "f64", nb=4)
+    X1 = T(random_block(p.N, 4, seed=7))
+    X2 = T(random_block(p.N, 4, seed=8))
+    HX2 = plan.apply(X2)
+    HX1 = plan.apply(X1)
+    lhs = torch.sum(torch.conj(X1) * HX2).item()
+    rhs = torch.sum(torch.conj(HX1) * X2).item()
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    again = plan.apply(X2)
+    assert torch.equal(again, HX2)
+
+
+def test_zero_kernel_is_diagonal(B):
+    p = make_problem(RAGGED, 1)
+    p.Vbar = p.Vbar * 0
+    Wq = torch.zeros((p.Nk, p.n_aux, p.n_aux), dtype=torch.complex128, device=dev())
+    plan, _ = _plan(B, p, "f64", nb=2, Wq=Wq)
+    X = random_block(p.N, 2, seed=2)
+    te = O.transition_energies(p).ravel()
+    assert rel(H_(plan.apply(T(X))), te[:, None] * X) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# start vectors and Haydock
+# ---------------------------------------------------------------------------
+def test_velocity_start(B):
+    p = make_problem(RAGGED, 0)
+    plan, _ = _plan(B, p, "f64", nb=4)
+    pol = polarisations(4)
+    got = H_(plan.velocity_start(T(p.vel), T(p.eps_ks, torch.float64), pol))
+    assert rel(got, O.velocity_start(p, pol)) < 1e-14
+
+
+def test_haydock_c1(B):
+    p = make_problem("c1", 0, "G2", coarse=(3, 3, 2))
+    plan, Wq = _plan(B, p, "f64", nb=3)
+    H = O.build_H(p, H_(Wq))
+    pol = polarisations(3)
+    P = plan.velocity_start(T(p.vel), T(p.eps_ks, torch.float64), pol)
+    te = O.transition_energies(p)
+    w = np.linspace(te.min() - 1, te.max() + 1, 2001)
+    m = 200
+    out = plan.haydock(P, m, w, 0.1)
+    Sa, Aa, Ba, st = O.haydock_spectrum(lambda x: H @ x, H_(P), m, w, 0.1, p.Nk)
+    assert (out["steps"] == m).all()
+    assert np.abs(out["a"][:, :50] - Aa[:, :50]).max() < 1e-10
+    assert np.abs(out["b"][:, :51] - Ba[:, :51]).max() < 1e-10 * Ba[:, 0].max()
+    Sref, _, _ = O.eig_spectrum(H, H_(P), w, 0.1, p.Nk)
+    e_eig = rel(out["S"], Sref)
+    print("[haydock c1] spectrum rel err vs eigh %.3e" % e_eig, flush=True)
+    assert e_eig < 1e-8
+    assert rel(out["S"], Sa) < 1e-8
+
+
+def test_haydock_full_krylov_and_breakdown(B):
+    p = make_problem(dict(cfg_id=94, coarse=(2, 2, 2), dense=(2, 2, 2), n_ao=8, nv=2, nc=2, n_aux=12), 0)
+    plan, Wq = _plan(B, p, "f64", nb=2)
+    H = O.build_H(p, H_(Wq))
+    P = O.velocity_start(p, np.eye(3))[:, :2]
+    w = np.linspace(1.0, 5.0, 101)
+    out = plan.haydock(T(P), p.N, w, 0.1)
+    Sref, _, _ = O.eig_spectrum(H, P, w, 0.1, p.Nk)
+    # m = dim: exact up to rounding unless an invariant subspace ends the chain first
+    assert rel(out["S"], Sref) < 1e-9
+    # W = Vbar = 0 and a one-entry start vector: b_1 = 0, chain stops after one step
+    p.Vbar = p.Vbar * 0
+    plan0, _ = _plan(B, p, "f64", nb=1, Wq=torch.zeros_like(Wq))
+    e = np.zeros((p.N, 1), dtype=complex)
+    e[5, 0] = 0.6 + 0.8j
+    out0 = plan0.haydock(T(e), 10, w, 0.1)
+    assert out0["breakdown"] and out0["steps"][0] == 1
+    te = O.transition_energies(p).ravel()
+    ref = (0.1 / np.pi) / ((w - te[5]) ** 2 + 0.01) / p.Nk
+    assert rel(out0["S"][0], ref) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# adjoint
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_apply_adjoint(B, prec):
+    p = make_problem(RAGGED, 5, "G2")
+    plan, Wq = _plan(B, p, prec, nb=3)
+    plan.set_R(p.R, p.w_R)
+    rng = np.random.default_rng(12)
+    Yb = rng.standard_normal((p.N, 3)) + 1j * rng.standard_normal((p.N, 3))
+    X = rng.standard_normal((p.N, 3)) + 1j * rng.standard_normal((p.N, 3))
+    g = plan.apply_adjoint(T(Yb), T(X), want_WR=True, want_Wq=True, want_eps=True)
+    ge, gq = O.grad_apply(p, H_(Wq), Yb, X)
+    gr = O.grad_WR_from_Wq(gq, p.R, p.w_R, dense_kmesh(p.nk))
+    tol = 1e-11 if prec == "f64" else 5e-5
+    assert rel(H_(g["eps"]), ge) < 1e-13
+    assert rel(H_(g["W_q"]), gq) < tol
+    assert rel(H_(g["W_R"]), gr) < tol
