@@ -202,6 +202,29 @@ bse_status bse_lowest_excitons(bse_plan* plan, int32_t n_block, int32_t max_iter
                                const void* X0, double* omega, void* x_out, int32_t* iters,
                                void* hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * Stage timing (tracing): when enabled, HIP events are recorded on the call's
+ * stream around every stage launched by bse_apply / bse_apply_adjoint /
+ * bse_haydock_spectrum, and bse_plan_stage_times() synchronises on them and
+ * returns accumulated milliseconds and launch counts per stage.
+ * ------------------------------------------------------------------------- */
+typedef enum {
+    BSE_STAGE_PAIRDENS_V = 0, /* valence pair densities M_vv' from the halves (1 kernel)    */
+    BSE_STAGE_WSTEP = 1,      /* P = conj(M_v) W(q) (1 kernel)                             */
+    BSE_STAGE_DBLOCK = 2,     /* direct block T = M_c P (1 kernel)                         */
+    BSE_STAGE_TX = 3,         /* Y(k) -= T X(k') (1 kernel)                                */
+    BSE_STAGE_EXCHANGE = 4,   /* rho Vbar rho^H X                                          */
+    BSE_STAGE_DIAG = 5,       /* transition energies                                       */
+    BSE_STAGE_LANCZOS = 6,    /* recurrence, CGS2 and continued fraction                   */
+    BSE_STAGE_ADJOINT = 7,    /* adjoint-only contractions                                 */
+    BSE_STAGE_PAIRDENS_C = 8, /* conduction pair densities M_cc' from the halves (1 kernel) */
+    BSE_STAGE_TABLES = 9,     /* gather tables of a q batch                                */
+    BSE_NSTAGES = 10
+} bse_stage;
+bse_status bse_plan_set_timing(bse_plan* plan, int enable);
+/* ms, launches: host arrays of BSE_NSTAGES entries; reset != 0 clears the totals */
+bse_status bse_plan_stage_times(bse_plan* plan, double* ms, int64_t* launches, int reset);
+
 const char* bse_status_string(bse_status s);
 const char* bse_last_error(void);
 /* Library version string. */

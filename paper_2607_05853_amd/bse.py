@@ -51,6 +51,8 @@ _SIGS = {
     "bse_velocity_start": [_vp, _vp, _vp, _i32, _vp, _vp, _vp],
     "bse_haydock_spectrum": [_vp, _vp, _i32, _i32, _vp, _i32, ctypes.c_double, _vp, _vp, _vp, _vp, _vp, _vp],
     "bse_lowest_excitons": [_vp, _i32, _i32, ctypes.c_double, _vp, _vp, _vp, _vp, _vp],
+    "bse_plan_set_timing": [_vp, ctypes.c_int],
+    "bse_plan_stage_times": [_vp, _vp, _vp, ctypes.c_int],
     "bse_status_string": [ctypes.c_int],
     "bse_last_error": [],
     "bse_version": [],
@@ -230,6 +232,20 @@ class Plan:
             _dev(geps, torch.float64, None, "g_eps") if want_eps else None, _stream(self.device))
         _check("bse_apply_adjoint", s)
         return {"W_R": gWR, "W_q": gWq, "eps": geps}
+
+    STAGES = ("pairdens_v", "wstep", "dblock", "tx", "exchange", "diag", "lanczos", "adjoint", "pairdens_c",
+              "tables")
+
+    def set_timing(self, enable=True):
+        _check("bse_plan_set_timing", lib().bse_plan_set_timing(self._ptr, 1 if enable else 0))
+
+    def stage_times(self, reset=True):
+        """{stage: (milliseconds, launches)} accumulated since the last reset (synchronises)."""
+        ms = np.zeros(len(self.STAGES))
+        n = np.zeros(len(self.STAGES), dtype=np.int64)
+        _check("bse_plan_stage_times", lib().bse_plan_stage_times(self._ptr, ms.ctypes.data, n.ctypes.data,
+                                                                   1 if reset else 0))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(self.STAGES)}
 
     def velocity_start(self, vel, eps_ks, pol):
         pol = _host(pol, np.float64).reshape(-1, 3)

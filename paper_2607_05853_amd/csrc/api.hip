@@ -41,6 +41,57 @@ void dfree(void* p) {
   if (p) (void)hipFree(p);
 }
 
+namespace {
+bool pool_event(Plan* p, hipEvent_t* e) {
+  if (!p->ev_pool.empty()) {
+    *e = p->ev_pool.back();
+    p->ev_pool.pop_back();
+    return true;
+  }
+  if (hipEventCreate(e) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return true;
+}
+}  // namespace
+
+StageMark::StageMark(Plan* p_, int stage, hipStream_t s) : p(p_), st(s) {
+  if (!p->timing) return;
+  Plan::StageRec r{stage, nullptr, nullptr};
+  if (!pool_event(p, &r.a)) return;
+  if (!pool_event(p, &r.b)) {
+    p->ev_pool.push_back(r.a);
+    return;
+  }
+  (void)hipEventRecord(r.a, st);
+  p->recs.push_back(r);
+  idx = (int)p->recs.size() - 1;
+}
+
+StageMark::~StageMark() {
+  if (idx >= 0) (void)hipEventRecord(p->recs[idx].b, st);
+}
+
+bse_status collect_stage_times(Plan* p) {
+  bse_status s = BSE_OK;
+  for (auto& r : p->recs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      p->stage_ms[r.stage] += ms;
+      p->stage_n[r.stage] += 1;
+    } else {
+      (void)hipGetLastError();
+      set_error("stage timing: event query failed");
+      s = BSE_EDEVICE;
+    }
+    p->ev_pool.push_back(r.a);
+    p->ev_pool.push_back(r.b);
+  }
+  p->recs.clear();
+  return s;
+}
+
 bse_status plan_alloc(Plan* p, void** ptr, size_t bytes) {
   BSE_TRY(dmalloc(ptr, bytes));
   p->owned.push_back(DevBuf{*ptr, bytes});
@@ -174,6 +225,9 @@ bse_status check_hermitian(const void* C, const void* Vbar, const bse_dims* d, h
 }
 
 void destroy_plan(Plan* p) {
+  (void)collect_stage_times(p);
+  for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+  p->ev_pool.clear();
   for (auto& b : p->owned) dfree(b.p);
   p->owned.clear();
 }
@@ -503,6 +557,35 @@ bse_status bse_plan_bytes(const bse_plan* plan, uint64_t* bytes) {
   }
   *bytes = plan->impl.bytes;
   return BSE_OK;
+}
+
+bse_status bse_plan_set_timing(bse_plan* plan, int enable) {
+  set_error("");
+  if (!plan) {
+    set_error("bse_plan_set_timing: NULL plan");
+    return BSE_EINVAL;
+  }
+  plan->impl.timing = enable != 0;
+  return BSE_OK;
+}
+
+bse_status bse_plan_stage_times(bse_plan* plan, double* ms, int64_t* launches, int reset) {
+  set_error("");
+  if (!plan || !ms || !launches) {
+    set_error("bse_plan_stage_times: NULL argument");
+    return BSE_EINVAL;
+  }
+  Plan* p = &plan->impl;
+  bse_status s = collect_stage_times(p);
+  for (int i = 0; i < BSE_NSTAGES; ++i) {
+    ms[i] = p->stage_ms[i];
+    launches[i] = p->stage_n[i];
+    if (reset) {
+      p->stage_ms[i] = 0;
+      p->stage_n[i] = 0;
+    }
+  }
+  return s;
 }
 
 bse_status bse_apply(bse_plan* plan, const void* X, void* Y, int32_t nb, void* hip_stream) {

@@ -177,12 +177,16 @@ char* off_bytes(void* base, long long elems, size_t esz) { return (char*)base + 
 bse_status form_pair_densities(Plan* p, int q0, int nq, hipStream_t st) {
   const bse_dims& d = p->d;
   const int Nk = p->Nk, nv = d.nv, nc = d.nc, na = d.n_aux, no = d.n_ao;
-  hipLaunchKernelGGL(tables_kernel, dim3(Nk), dim3(256), 0, st, Nk, nq, q0, nv, nc, p->nbnd, no, na, p->kq,
+  {
+    StageMark sm_(p, BSE_STAGE_TABLES, st);
+    hipLaunchKernelGGL(tables_kernel, dim3(Nk), dim3(256), 0, st, Nk, nq, q0, nv, nc, p->nbnd, no, na, p->kq,
                      p->tab_psi_v, p->tab_psi_c, p->tab_mv, p->tab_mc);
-  BSE_CHECK_LAUNCH();
+    BSE_CHECK_LAUNCH();
+  }
   const Arith ar = arith_of(p->prec);
   const bool f64 = p->prec == BSE_F64;
   {
+    StageMark sm_(p, BSE_STAGE_PAIRDENS_V, st);
     GemmArgs g;
     g.batch = Nk;
     g.M = nq * nv;
@@ -203,6 +207,7 @@ bse_status form_pair_densities(Plan* p, int q0, int nq, hipStream_t st) {
     BSE_TRY(cgemm(g, ar, f64, f64, st));
   }
   {
+    StageMark sm_(p, BSE_STAGE_PAIRDENS_C, st);
     GemmArgs g;
     g.batch = Nk;
     g.M = nq * nc;
@@ -228,6 +233,7 @@ bse_status form_pair_densities(Plan* p, int q0, int nq, hipStream_t st) {
 }  // namespace
 
 bse_status apply_diag(Plan* p, const double* X, double* Y, int nb, hipStream_t st) {
+  StageMark sm_(p, BSE_STAGE_DIAG, st);
   const long long n = p->N * nb;
   hipLaunchKernelGGL(diag_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p->N, p->d.nv, p->d.nc,
                      nb, p->eps, X, Y);
@@ -237,6 +243,7 @@ bse_status apply_diag(Plan* p, const double* X, double* Y, int nb, hipStream_t s
 
 bse_status apply_exchange(Plan* p, const double* X, double* Y, int nb, hipStream_t st) {
   if (p->d.alpha == 0.0) return BSE_OK;
+  StageMark sm_(p, BSE_STAGE_EXCHANGE, st);
   const int na = p->d.n_aux;
   const long long Ks = p->N / p->xsplit;
   {  // partial t_s = rho_s^H X_s
@@ -313,6 +320,7 @@ bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t
     const int nq = (Nk - q0) < p->qb ? (Nk - q0) : p->qb;
     BSE_TRY(form_pair_densities(p, q0, nq, st));
     {  // P = conj(Gv) W(q)
+    StageMark sm_(p, BSE_STAGE_WSTEP, st);
       GemmArgs g;
       g.batch = nq;
       g.M = Nk * nv * nv;
@@ -334,6 +342,7 @@ bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t
       BSE_TRY(cgemm(g, ar, f64, f64, st));
     }
     {  // T = Mc P^T over nu
+    StageMark sm_(p, BSE_STAGE_DBLOCK, st);
       GemmArgs g;
       g.batch = nq * Nk;
       g.M = nc * nc;
@@ -354,6 +363,7 @@ bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t
       BSE_TRY(cgemm(g, ar, f64, f64, st));
     }
     {
+      StageMark sm_(p, BSE_STAGE_TX, st);
       const size_t sh = (size_t)nt * nt * p->esz + (size_t)nt * nb * 16;
       const double scale = -1.0 / (double)Nk;
       static bool attr_set = false;
@@ -384,6 +394,7 @@ bse_status adjoint_direct(Plan* p, const double* Ybar, const double* X, int nb, 
   for (int q0 = 0; q0 < Nk; q0 += p->qb) {
     const int nq = (Nk - q0) < p->qb ? (Nk - q0) : p->qb;
     BSE_TRY(form_pair_densities(p, q0, nq, st));
+    StageMark sm_(p, BSE_STAGE_ADJOINT, st);
     if (f64)
       hipLaunchKernelGGL(adj_gm_kernel<double>, dim3(nq * Nk), dim3(256), 0, st, Nk, nq, q0, nv, nc, nb, p->kq,
                          Ybar, X, (double*)p->T);

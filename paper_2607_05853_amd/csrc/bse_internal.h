@@ -132,7 +132,29 @@ struct Plan {
 
   std::vector<DevBuf> owned;
   size_t bytes = 0;
+
+  // stage timing
+  struct StageRec {
+    int stage;
+    hipEvent_t a, b;
+  };
+  bool timing = false;
+  std::vector<StageRec> recs;
+  std::vector<hipEvent_t> ev_pool;   // events reused across stages (created once)
+  double stage_ms[BSE_NSTAGES] = {};
+  long long stage_n[BSE_NSTAGES] = {};
 };
+
+// RAII stage marker: records a start event now and the end event on destruction
+// (only when the plan's timing is enabled)
+struct StageMark {
+  Plan* p;
+  int idx = -1;
+  hipStream_t st;
+  StageMark(Plan* p_, int stage, hipStream_t s);
+  ~StageMark();
+};
+bse_status collect_stage_times(Plan* p);
 
 bse_status plan_alloc(Plan* p, void** ptr, size_t bytes);
 

@@ -181,7 +181,7 @@ __global__ void lz_next(long long N, int nb, int m, int j, double tol, const dou
 }
 
 __global__ void lz_mark(int nb, int m, int j, double tol, const double* __restrict__ b, int* __restrict__ active) {
-  const int bi = threadIdx.x;
+  const int bi = blockIdx.x * blockDim.x + threadIdx.x;
   if (bi >= nb) return;
   const double b0 = b[(long long)bi * (m + 1)];
   const double bj = b[(long long)bi * (m + 1) + j];
@@ -297,6 +297,7 @@ extern "C" bse_status bse_haydock_spectrum(bse_plan* plan, const void* P, int32_
   BSE_CHECK_LAUNCH();
   for (int j = 1; j <= m; ++j) {
     BSE_TRY(bse_apply(plan, B.Q, B.Wb, nb, hip_stream));
+    StageMark sm_(p, BSE_STAGE_LANCZOS, st);
     hipLaunchKernelGGL(lz_gather, dim3(gN), dim3(256), 0, st, N, nb, B.Wb, B.w);
     // a_j = Re q_j^H w
     hipLaunchKernelGGL(dotc_partial, dim3(nblk, nb), dim3(RB), 0, st, N, B.basis + 2 * (long long)(j - 1) * N,
@@ -311,7 +312,7 @@ extern "C" bse_status bse_haydock_spectrum(bse_plan* plan, const void* P, int32_
     hipLaunchKernelGGL(dot_finalize, dim3(nb), dim3(RB), 0, st, nblk, B.part, B.db + j, (long long)(m + 1), 1);
     hipLaunchKernelGGL(lz_next, dim3(gN), dim3(256), 0, st, N, nb, m, j, tol, B.db, B.w, B.basis, B.Q, B.act,
                        B.stp);
-    hipLaunchKernelGGL(lz_mark, dim3(1), dim3(64), 0, st, nb, m, j, tol, B.db, B.act);
+    hipLaunchKernelGGL(lz_mark, dim3((nb + 63) / 64), dim3(64), 0, st, nb, m, j, tol, B.db, B.act);
     BSE_CHECK_LAUNCH();
   }
   {
