@@ -47,7 +47,8 @@ typedef enum {
     BSE_ENOMEM = 3,      /* device allocation failed                              */
     BSE_EDEVICE = 4,     /* a HIP call failed                                     */
     BSE_ENOTHERM = 5,    /* BSE_CHECK_HERMITIAN found a non-Hermitian input       */
-    BSE_INFO_BREAKDOWN = 100  /* a Haydock chain stopped early (not an error)      */
+    BSE_INFO_BREAKDOWN = 100, /* a Haydock chain stopped early (not an error)      */
+    BSE_INFO_NOT_CONVERGED = 101 /* an iterative driver hit its iteration limit    */
 } bse_status;
 
 /* Arithmetic of the pair-density / screened-interaction contractions.
@@ -190,13 +191,31 @@ bse_status bse_haydock_spectrum(bse_plan* plan, const void* P, int32_t nb, int32
                                 void* basis_out, void* hip_stream);
 
 /* ---------------------------------------------------------------------------
+ * Vector-Jacobian product of the Haydock spectrum: for L = sum_{b,w} gamma[b][w] S_b(w)
+ * the gradients with respect to W(R) / W(q) and the energies, through
+ *   dS(w) = -(1/(pi N_k)) Im( yt^H dA y ),  y = (z - A)^-1 p,  yt = (conj z - A)^-1 p,
+ * with y ~ b_0 Q (z - T)^-1 e_1 from the chain's Lanczos basis Q and tridiagonal T
+ * (the derivative of the converged spectrum; resolvents solved on the host in FP64,
+ * Krylov recombination and the adjoint contractions on the device).
+ * basis device c128 [nb][n_steps][N] as returned by bse_haydock_spectrum; a, b, steps,
+ * omega, gamma host arrays as there ([nb][n_steps], [nb][n_steps+1], [nb], [n_w],
+ * [nb][n_w]).  Outputs as in bse_apply_adjoint (each may be NULL); overwritten.
+ * ------------------------------------------------------------------------- */
+bse_status bse_haydock_vjp(bse_plan* plan, const void* basis, const double* a, const double* b,
+                           const int32_t* steps, int32_t nb, int32_t n_steps, const double* omega,
+                           int32_t n_w, double eta, const double* gamma, void* g_WR, void* g_Wq,
+                           double* g_eps, void* hip_stream);
+
+/* ---------------------------------------------------------------------------
  * Lowest exciton by block LOBPCG (Knyazev 2001) on the FP64 apply, with
  * Rayleigh-Ritz in FP64 on the host:  Omega_1 and its eigenvector (Sec. IV.C:
  * E_B = min_k (E_c1k - E_vtop k) - Omega_1).
  * n_block >= 1 (block size), max_iter, tol (relative residual |r| <= tol |Omega|).
  * X0 device c128 [N][n_block] start block (NULL: deterministic pseudo-random);
  * omega host f64 [n_block] ascending Ritz values; x_out device c128 [N][n_block]
- * (NULL allowed); iters host int32 (NULL allowed).
+ * (NULL allowed); iters host int32 (NULL allowed).  Converged means every Ritz pair
+ * has |A x - omega x| <= tol |omega|; otherwise the last iterate is returned with
+ * BSE_INFO_NOT_CONVERGED.  Synchronises the stream every iteration.
  * ------------------------------------------------------------------------- */
 bse_status bse_lowest_excitons(bse_plan* plan, int32_t n_block, int32_t max_iter, double tol,
                                const void* X0, double* omega, void* x_out, int32_t* iters,

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("BSE_LIB", os.path.join(_HERE, "libbse.so"))
 
 PREC = {"f64": 0, "f32": 1, "bf16x3": 2}
-BSE_OK, BSE_INFO_BREAKDOWN = 0, 100
+BSE_OK, BSE_INFO_BREAKDOWN, BSE_INFO_NOT_CONVERGED = 0, 100, 101
 CHECK_HERMITIAN = 1
 
 
@@ -51,6 +51,7 @@ _SIGS = {
     "bse_velocity_start": [_vp, _vp, _vp, _i32, _vp, _vp, _vp],
     "bse_haydock_spectrum": [_vp, _vp, _i32, _i32, _vp, _i32, ctypes.c_double, _vp, _vp, _vp, _vp, _vp, _vp],
     "bse_lowest_excitons": [_vp, _i32, _i32, ctypes.c_double, _vp, _vp, _vp, _vp, _vp],
+    "bse_haydock_vjp": [_vp, _vp, _vp, _vp, _vp, _i32, _i32, _vp, _i32, ctypes.c_double, _vp, _vp, _vp, _vp, _vp],
     "bse_plan_set_timing": [_vp, ctypes.c_int],
     "bse_plan_stage_times": [_vp, _vp, _vp, ctypes.c_int],
     "bse_status_string": [ctypes.c_int],
@@ -273,7 +274,9 @@ class Plan:
         _check("bse_haydock_spectrum", s, allow_breakdown=True)
         return {"S": S, "a": a, "b": b, "steps": steps, "basis": basis, "breakdown": s == BSE_INFO_BREAKDOWN}
 
-    def lowest_excitons(self, n_block=4, max_iter=200, tol=1e-10, X0=None, want_vectors=True):
+    def lowest_excitons(self, n_block=4, max_iter=200, tol=1e-10, X0=None, want_vectors=True,
+                        allow_unconverged=False):
+        """Lowest n_block eigenpairs by block LOBPCG: (omega ascending, x [N][n_block], iterations)."""
         omega = np.zeros(n_block)
         iters = np.zeros(1, dtype=np.int32)
         x = torch.empty((self.N, n_block), dtype=torch.complex128, device=self.device) if want_vectors else None
@@ -281,8 +284,35 @@ class Plan:
                                       _dev(X0, torch.complex128, (self.N, n_block), "X0") if X0 is not None else None,
                                       omega.ctypes.data, _dev(x, torch.complex128, None, "x") if want_vectors else None,
                                       iters.ctypes.data, _stream(self.device))
-        _check("bse_lowest_excitons", s)
+        if not (allow_unconverged and s == BSE_INFO_NOT_CONVERGED):
+            _check("bse_lowest_excitons", s)
         return omega, x, int(iters[0])
+
+    def haydock_vjp(self, hay, omega, eta, gamma, want_WR=True, want_Wq=False, want_eps=True):
+        """Gradient of sum gamma[b][w] S_b(w) through a Haydock run made with keep_basis=True."""
+        if hay.get("basis") is None:
+            raise ValueError("haydock_vjp needs the Lanczos basis (haydock(..., keep_basis=True))")
+        basis = hay["basis"]
+        nb, m, _ = basis.shape
+        omega = _host(omega, np.float64).ravel()
+        gamma = _host(gamma, np.float64, (nb, len(omega)))
+        a = _host(hay["a"], np.float64, (nb, m))
+        b = _host(hay["b"], np.float64, (nb, m + 1))
+        steps = _host(hay["steps"], np.int32, (nb,))
+        gWR = torch.empty((len(self._wR), self.n_aux, self.n_aux), dtype=torch.complex128,
+                          device=self.device) if want_WR else None
+        gWq = torch.empty((self.Nk, self.n_aux, self.n_aux), dtype=torch.complex128,
+                          device=self.device) if want_Wq else None
+        geps = torch.empty((self.Nk, self.nv + self.nc), dtype=torch.float64, device=self.device) if want_eps else None
+        s = lib().bse_haydock_vjp(self._ptr, _dev(basis, torch.complex128, None, "basis"), a.ctypes.data,
+                                  b.ctypes.data, steps.ctypes.data, nb, m, omega.ctypes.data, len(omega),
+                                  float(eta), gamma.ctypes.data,
+                                  _dev(gWR, torch.complex128, None, "g_WR") if want_WR else None,
+                                  _dev(gWq, torch.complex128, None, "g_Wq") if want_Wq else None,
+                                  _dev(geps, torch.float64, None, "g_eps") if want_eps else None,
+                                  _stream(self.device))
+        _check("bse_haydock_vjp", s)
+        return {"W_R": gWR, "W_q": gWq, "eps": geps}
 
 
 def plan_from_problem(prob, W_q, prec="f64", max_nb=8, device="cuda:0", check_hermitian=False):

@@ -92,6 +92,17 @@ bse_status collect_stage_times(Plan* p) {
   return s;
 }
 
+std::vector<double> plan_kfrac(const Plan* p) {
+  std::vector<double> q(3 * (size_t)p->Nk);
+  const int n1 = p->d.nk[0], n2 = p->d.nk[1], n3 = p->d.nk[2];
+  for (int k = 0; k < p->Nk; ++k) {
+    q[3 * k] = (double)(k / (n2 * n3)) / n1;
+    q[3 * k + 1] = (double)((k / n3) % n2) / n2;
+    q[3 * k + 2] = (double)(k % n3) / n3;
+  }
+  return q;
+}
+
 bse_status plan_alloc(Plan* p, void** ptr, size_t bytes) {
   BSE_TRY(dmalloc(ptr, bytes));
   p->owned.push_back(DevBuf{*ptr, bytes});
@@ -423,6 +434,7 @@ const char* bse_status_string(bse_status s) {
     case BSE_EDEVICE: return "HIP device error";
     case BSE_ENOTHERM: return "input not Hermitian";
     case BSE_INFO_BREAKDOWN: return "Lanczos breakdown (information)";
+    case BSE_INFO_NOT_CONVERGED: return "iteration limit reached (information)";
   }
   return "unknown status";
 }
@@ -627,7 +639,7 @@ bse_status bse_apply_adjoint(bse_plan* plan, const void* Ybar, const void* X, in
     return BSE_EINVAL;
   }
   hipStream_t st = S(hip_stream);
-  if (g_eps) BSE_TRY(adjoint_eps(p, (const double*)Ybar, (const double*)X, nb, g_eps, st));
+  if (g_eps) BSE_TRY(adjoint_eps(p, (const double*)Ybar, (const double*)X, nb, g_eps, false, st));
   if (!g_WR && !g_Wq) return BSE_OK;
   const int na = p->d.n_aux;
   double* gq = (double*)g_Wq;
@@ -635,16 +647,10 @@ bse_status bse_apply_adjoint(bse_plan* plan, const void* Ybar, const void* X, in
     if (!p->gq_acc) BSE_TRY(plan_alloc(p, (void**)&p->gq_acc, 16 * (size_t)p->Nk * na * na));
     gq = p->gq_acc;
   }
-  BSE_TRY(adjoint_direct(p, (const double*)Ybar, (const double*)X, nb, gq, st));
+  BSE_TRY(adjoint_direct(p, (const double*)Ybar, (const double*)X, nb, gq, false, st));
   if (g_WR) {
     const int nR = (int)p->wR.size();
-    std::vector<double> q(3 * (size_t)p->Nk);
-    const int n1 = p->d.nk[0], n2 = p->d.nk[1], n3 = p->d.nk[2];
-    for (int k = 0; k < p->Nk; ++k) {
-      q[3 * k] = (double)(k / (n2 * n3)) / n1;
-      q[3 * k + 1] = (double)((k / n3) % n2) / n2;
-      q[3 * k + 2] = (double)(k % n3) / n3;
-    }
+    const std::vector<double> q = plan_kfrac(p);
     BSE_TRY(interp_adjoint(na, nR, p->R.data(), p->wR.data(), p->Nk, q.data(), gq, (double*)g_WR, st));
   }
   return BSE_OK;

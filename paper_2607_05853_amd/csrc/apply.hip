@@ -145,7 +145,7 @@ __global__ void adj_gm_kernel(int Nk, int nq, int q0, int nv, int nc, int nb, co
 }
 
 __global__ void adj_eps_kernel(int nv, int nc, int nb, const double* __restrict__ Yb,
-                               const double* __restrict__ X, double* __restrict__ g) {
+                               const double* __restrict__ X, double* __restrict__ g, int acc) {
   const int k = blockIdx.x;
   const int nt = nc * nv;
   // one thread per band of this k
@@ -165,7 +165,10 @@ __global__ void adj_eps_kernel(int nv, int nc, int nb, const double* __restrict_
           s += Yb[o] * X[o] + Yb[o + 1] * X[o + 1];
         }
     }
-    g[(long long)k * (nv + nc) + n] = s;
+    if (acc)
+      g[(long long)k * (nv + nc) + n] += s;
+    else
+      g[(long long)k * (nv + nc) + n] = s;
   }
 }
 
@@ -386,7 +389,8 @@ bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t
   return BSE_OK;
 }
 
-bse_status adjoint_direct(Plan* p, const double* Ybar, const double* X, int nb, double* gWq, hipStream_t st) {
+bse_status adjoint_direct(Plan* p, const double* Ybar, const double* X, int nb, double* gWq, bool acc,
+                          hipStream_t st) {
   const bse_dims& d = p->d;
   const int Nk = p->Nk, nv = d.nv, nc = d.nc, na = d.n_aux;
   const Arith ar = arith_of(p->prec);
@@ -442,14 +446,17 @@ bse_status adjoint_direct(Plan* p, const double* Ybar, const double* X, int nb, 
       g.c_si = na;
       g.c_sj = 1;
       g.alpha = -1.0 / (double)Nk;
+      g.beta = acc ? 1 : 0;
       BSE_TRY(cgemm(g, ar, f64, true, st));
     }
   }
   return BSE_OK;
 }
 
-bse_status adjoint_eps(Plan* p, const double* Ybar, const double* X, int nb, double* geps, hipStream_t st) {
-  hipLaunchKernelGGL(adj_eps_kernel, dim3(p->Nk), dim3(64), 0, st, p->d.nv, p->d.nc, nb, Ybar, X, geps);
+bse_status adjoint_eps(Plan* p, const double* Ybar, const double* X, int nb, double* geps, bool acc,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(adj_eps_kernel, dim3(p->Nk), dim3(64), 0, st, p->d.nv, p->d.nc, nb, Ybar, X, geps,
+                     acc ? 1 : 0);
   BSE_CHECK_LAUNCH();
   return BSE_OK;
 }

@@ -162,8 +162,12 @@ bse_status plan_alloc(Plan* p, void** ptr, size_t bytes);
 bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t st);
 bse_status apply_exchange(Plan* p, const double* X, double* Y, int nb, hipStream_t st);
 bse_status apply_diag(Plan* p, const double* X, double* Y, int nb, hipStream_t st);
-bse_status adjoint_direct(Plan* p, const double* Ybar, const double* X, int nb, double* gWq, hipStream_t st);
-bse_status adjoint_eps(Plan* p, const double* Ybar, const double* X, int nb, double* geps, hipStream_t st);
+bse_status adjoint_direct(Plan* p, const double* Ybar, const double* X, int nb, double* gWq, bool acc,
+                          hipStream_t st);
+bse_status adjoint_eps(Plan* p, const double* Ybar, const double* X, int nb, double* geps, bool acc,
+                       hipStream_t st);
+// the dense-mesh k list of a plan (fractional coordinates, host)
+std::vector<double> plan_kfrac(const Plan* p);
 
 // interpolation (interp.hip)
 bse_status interp_forward(int n_aux, int n_R, const double* W_R, const int32_t* R, const double* w_R,
