@@ -266,10 +266,18 @@ bse_status build_plan(Plan* p, const bse_dims* d, const double* eps_qp, const vo
   BSE_TRY(plan_alloc(p, (void**)&p->vbar, 16 * (size_t)na * na));
   BSE_HIP(hipMemcpyAsync(p->vbar, Vbar, 16 * (size_t)na * na, hipMemcpyDeviceToDevice, st));
   const long long nw = (long long)Nk * na * na;
+  p->split = prec == BSE_BF16X3;
   if (f64) {
     p->psi = p->psi64;
     BSE_TRY(plan_alloc(p, &p->Wq, 16 * nw));
     BSE_HIP(hipMemcpyAsync(p->Wq, W_q, 16 * nw, hipMemcpyDeviceToDevice, st));
+  } else if (p->split) {
+    BSE_TRY(plan_alloc(p, &p->psi, 8 * npsi));
+    BSE_TRY(split_planes(p->psi64, true, (__bf16*)p->psi, npsi, npsi, st));
+    BSE_TRY(plan_alloc(p, &p->Wq, 8 * nw));
+    BSE_TRY(split_planes_T(W_q, true, (__bf16*)p->Wq, Nk, na, na, nw, st));
+    BSE_TRY(plan_alloc(p, (void**)&p->psi32, 8 * npsi));
+    BSE_TRY(convert_c128_to_c64(p->psi64, p->psi32, npsi, st));
   } else {
     BSE_TRY(plan_alloc(p, &p->psi, 8 * npsi));
     BSE_TRY(convert_c128_to_c64(p->psi64, (float*)p->psi, npsi, st));
@@ -279,8 +287,13 @@ bse_status build_plan(Plan* p, const bse_dims* d, const double* eps_qp, const vo
 
   // halves B^mu_n(k) = psi_n(k)^H C^mu, computed in FP64; rho from the FP64 halves
   const long long hv = (long long)Nk * nv * na * no, hc = (long long)Nk * nc * na * no;
+  p->ps_psi = npsi;
+  p->ps_W = nw;
+  p->ps_Bv = hv;
+  p->ps_Bc = hc;
   BSE_TRY(plan_alloc(p, &p->Bv, p->esz * hv));
   BSE_TRY(plan_alloc(p, &p->Bc, p->esz * hc));
+  if (p->split) BSE_TRY(plan_alloc(p, &p->BcT, 8 * hc));
   BSE_TRY(plan_alloc(p, (void**)&p->rho, 16 * (size_t)p->N * na));
   long long* colt = nullptr;
   {
@@ -342,16 +355,23 @@ bse_status build_plan(Plan* p, const bse_dims* d, const double* eps_qp, const vo
         break;
       }
     }
-    if (!f64) {
+    if (p->split) {
+      s = split_planes(dv, true, (__bf16*)p->Bv + (long long)k0 * nv * na * no, (long long)kn * nv * na * no, hv, st);
+      if (s == BSE_OK)
+        s = split_planes(dc, true, (__bf16*)p->Bc + (long long)k0 * nc * na * no, (long long)kn * nc * na * no, hc,
+                         st);
+      if (s == BSE_OK)
+        s = split_planes_T(dc, true, (__bf16*)p->BcT + (long long)k0 * nc * no * na, kn * nc, na, no, hc, st);
+    } else if (!f64) {
       s = convert_c128_to_c64(dv, (float*)p->Bv + 2LL * k0 * nv * na * no, (long long)kn * nv * na * no, st);
       if (s == BSE_OK)
         s = convert_c128_to_c64(dc, (float*)p->Bc + 2LL * k0 * nc * na * no, (long long)kn * nc * na * no, st);
-      if (s == BSE_OK) {
-        hipError_t e = hipStreamSynchronize(st);  // tmp is reused by the next chunk
-        if (e != hipSuccess) {
-          set_error(std::string("plan halves: ") + hipGetErrorString(e));
-          s = BSE_EDEVICE;
-        }
+    }
+    if (!f64 && s == BSE_OK) {
+      hipError_t e = hipStreamSynchronize(st);  // tmp is reused by the next chunk
+      if (e != hipSuccess) {
+        set_error(std::string("plan halves: ") + hipGetErrorString(e));
+        s = BSE_EDEVICE;
       }
     }
   }
@@ -394,6 +414,7 @@ bse_status build_plan(Plan* p, const bse_dims* d, const double* eps_qp, const vo
     p->qb = (int)qb;
     const long long nq = qb;
     BSE_TRY(plan_alloc(p, &p->Mv, p->esz * (size_t)(nq * Nk * nv * nv * na)));
+    p->ps_Mv = nq * Nk * nv * nv * na;
     BSE_TRY(plan_alloc(p, &p->P, p->esz * (size_t)(nq * Nk * nv * nv * na)));
     BSE_TRY(plan_alloc(p, &p->Mc, p->esz * (size_t)(nq * Nk * nc * nc * na)));
     BSE_TRY(plan_alloc(p, &p->T, p->esz * (size_t)(nq * Nk * nc * nc * nv * nv)));

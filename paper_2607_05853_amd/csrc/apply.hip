@@ -177,7 +177,7 @@ Arith arith_of(bse_prec p) { return p == BSE_F64 ? AR_F64 : (p == BSE_F32 ? AR_F
 char* off_bytes(void* base, long long elems, size_t esz) { return (char*)base + elems * (long long)esz; }
 
 // S1: pair-density halves -> Gv and Mc for one q batch
-bse_status form_pair_densities(Plan* p, int q0, int nq, hipStream_t st) {
+bse_status form_pair_densities(Plan* p, int q0, int nq, bool need_c, hipStream_t st) {
   const bse_dims& d = p->d;
   const int Nk = p->Nk, nv = d.nv, nc = d.nc, na = d.n_aux, no = d.n_ao;
   {
@@ -207,9 +207,16 @@ bse_status form_pair_densities(Plan* p, int q0, int nq, hipStream_t st) {
     g.c_tab = p->tab_mv;
     g.c_tab_pb = 1;
     g.c_sj = 1;
-    BSE_TRY(cgemm(g, ar, f64, f64, st));
+    if (p->split) {
+      g.a_ps = p->ps_psi;
+      g.b_ps = p->ps_Bv;
+      g.c_ps = p->ps_Mv;
+      BSE_TRY(cgemm_split(g, true, true, true, false, st));
+    } else {
+      BSE_TRY(cgemm(g, ar, f64, f64, st));
+    }
   }
-  {
+  if (need_c) {
     StageMark sm_(p, BSE_STAGE_PAIRDENS_C, st);
     GemmArgs g;
     g.batch = Nk;
@@ -228,7 +235,13 @@ bse_status form_pair_densities(Plan* p, int q0, int nq, hipStream_t st) {
     g.c_tab = p->tab_mc;
     g.c_tab_pb = 1;
     g.c_sj = 1;
-    BSE_TRY(cgemm(g, ar, f64, f64, st));
+    if (p->split) {
+      g.a_ps = p->ps_psi;
+      g.b_ps = p->ps_Bc;
+      BSE_TRY(cgemm_split(g, true, true, false, false, st));
+    } else {
+      BSE_TRY(cgemm(g, ar, f64, f64, st));
+    }
   }
   return BSE_OK;
 }
@@ -321,7 +334,7 @@ bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t
   const int nt = nc * nv;
   for (int q0 = 0; q0 < Nk; q0 += p->qb) {
     const int nq = (Nk - q0) < p->qb ? (Nk - q0) : p->qb;
-    BSE_TRY(form_pair_densities(p, q0, nq, st));
+    BSE_TRY(form_pair_densities(p, q0, nq, !p->split, st));
     {  // P = conj(Gv) W(q)
     StageMark sm_(p, BSE_STAGE_WSTEP, st);
       GemmArgs g;
@@ -334,18 +347,33 @@ bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t
       g.a_si = na;
       g.a_sk = 1;
       g.conjA = 1;
-      g.B = off_bytes(p->Wq, (long long)q0 * na * na, p->esz);
-      g.b_sb = (long long)na * na;
-      g.b_sk = na;
-      g.b_sj = 1;
       g.C = p->P;
       g.c_sb = (long long)Nk * nv * nv * na;
       g.c_si = na;
       g.c_sj = 1;
-      BSE_TRY(cgemm(g, ar, f64, f64, st));
+      if (p->split) {
+        // W stored transposed per q: B[mu][nu] at q*na^2 + nu*na + mu
+        g.B = (const __bf16*)p->Wq + (long long)q0 * na * na;
+        g.b_sb = (long long)na * na;
+        g.b_sk = 1;
+        g.b_sj = na;
+        g.a_ps = p->ps_Mv;
+        g.b_ps = p->ps_W;
+        g.c_ps = p->ps_Mv;  // P is written pre-split for the conduction-side kernel
+        BSE_TRY(cgemm_split(g, true, true, true, false, st));
+      } else {
+        g.B = off_bytes(p->Wq, (long long)q0 * na * na, p->esz);
+        g.b_sb = (long long)na * na;
+        g.b_sk = na;
+        g.b_sj = 1;
+        BSE_TRY(cgemm(g, ar, f64, f64, st));
+      }
     }
-    {  // T = Mc P^T over nu
-    StageMark sm_(p, BSE_STAGE_DBLOCK, st);
+    if (p->split) {  // T from B_c(k) and P without the conduction pair densities
+      StageMark sm_(p, BSE_STAGE_DBLOCK, st);
+      BSE_TRY(direct_u_b3(p, q0, nq, st));
+    } else {  // T = Mc P^T over nu
+      StageMark sm_(p, BSE_STAGE_DBLOCK, st);
       GemmArgs g;
       g.batch = nq * Nk;
       g.M = nc * nc;
@@ -397,7 +425,7 @@ bse_status adjoint_direct(Plan* p, const double* Ybar, const double* X, int nb, 
   const bool f64 = p->prec == BSE_F64;
   for (int q0 = 0; q0 < Nk; q0 += p->qb) {
     const int nq = (Nk - q0) < p->qb ? (Nk - q0) : p->qb;
-    BSE_TRY(form_pair_densities(p, q0, nq, st));
+    BSE_TRY(form_pair_densities(p, q0, nq, true, st));
     StageMark sm_(p, BSE_STAGE_ADJOINT, st);
     if (f64)
       hipLaunchKernelGGL(adj_gm_kernel<double>, dim3(nq * Nk), dim3(256), 0, st, Nk, nq, q0, nv, nc, nb, p->kq,
@@ -447,7 +475,12 @@ bse_status adjoint_direct(Plan* p, const double* Ybar, const double* X, int nb, 
       g.c_sj = 1;
       g.alpha = -1.0 / (double)Nk;
       g.beta = acc ? 1 : 0;
-      BSE_TRY(cgemm(g, ar, f64, true, st));
+      if (p->split) {
+        g.a_ps = p->ps_Mv;
+        BSE_TRY(cgemm_split(g, true, false, false, true, st));
+      } else {
+        BSE_TRY(cgemm(g, ar, f64, true, st));
+      }
     }
   }
   return BSE_OK;

@@ -73,11 +73,23 @@ struct GemmArgs {
   int c_tab_pb = 0;
   double alpha = 1.0;
   int beta = 0;
+  // plane strides (elements) of operands stored pre-split as four bf16 planes
+  long long a_ps = 0, b_ps = 0, c_ps = 0;
 };
 
 // in_f64: A and B are c128 (else c64); out_f64: C is c128 (else c64).
 // AR_F64 requires in_f64.  AR_F32 / AR_BF16X3 require c64 inputs.
 bse_status cgemm(const GemmArgs& g, Arith ar, bool in_f64, bool out_f64, hipStream_t st);
+// BF16X3 on the large-tile kernel with any of A, B, C pre-split into bf16 planes
+// (Re hi, Re lo, Im hi, Im lo at plane strides a_ps / b_ps / c_ps); non-split
+// operands are c64 (A, B) and c64 / c128 (C, per out_f64).
+bse_status cgemm_split(const GemmArgs& g, bool a_split, bool b_split, bool c_split, bool out_f64, hipStream_t st);
+// split c64 / c128 arrays into four bf16 planes (util.hip); n complex elements,
+// optionally transposing each of `batch` rows x cols matrices
+bse_status split_planes(const void* in, bool in_f64, __bf16* out, long long n, long long plane_stride,
+                        hipStream_t st);
+bse_status split_planes_T(const void* in, bool in_f64, __bf16* out, int batch, int rows, int cols,
+                          long long plane_stride, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // plan
@@ -95,6 +107,9 @@ struct Plan {
   int max_nb = 0;
   int device = 0;
   size_t esz = 16;  // bytes per complex element of the plan precision
+  bool split = false;  // BF16X3: psi, halves, W_q and the valence pair densities are stored as
+                       // four bf16 planes (Re hi, Re lo, Im hi, Im lo); W_q transposed per q
+  long long ps_psi = 0, ps_W = 0, ps_Bv = 0, ps_Bc = 0, ps_Mv = 0;  // plane strides (elements)
 
   // FP64 data
   double* eps = nullptr;      // [Nk][nv+nc]
@@ -106,6 +121,8 @@ struct Plan {
   void* Bv = nullptr;         // [Nk][nv][n_aux][n_ao]   B^mu_v(k)
   void* Bc = nullptr;         // [Nk][nc][n_aux][n_ao]   B^mu_c(k)
   void* Wq = nullptr;         // [Nk][n_aux][n_aux]
+  void* BcT = nullptr;        // BF16X3 only: planes [Nk][nc][n_ao][n_aux] (B^nu_ct(k), t-major)
+  float* psi32 = nullptr;     // BF16X3 only: c64 [Nk][nv+nc][n_ao]
 
   // q-batch workspaces of the direct term (plan precision)
   int qb = 0;                 // q values per batch
@@ -164,6 +181,7 @@ bse_status apply_exchange(Plan* p, const double* X, double* Y, int nb, hipStream
 bse_status apply_diag(Plan* p, const double* X, double* Y, int nb, hipStream_t st);
 bse_status adjoint_direct(Plan* p, const double* Ybar, const double* X, int nb, double* gWq, bool acc,
                           hipStream_t st);
+bse_status direct_u_b3(Plan* p, int q0, int nq, hipStream_t st);
 bse_status adjoint_eps(Plan* p, const double* Ybar, const double* X, int nb, double* geps, bool acc,
                        hipStream_t st);
 // the dense-mesh k list of a plan (fractional coordinates, host)

@@ -1,0 +1,198 @@
+// Conduction side of the direct term on the BF16x3 path, without forming the
+// conduction pair densities.  With M^nu_{cc'}(k,k') = sum_t B^nu_{ct}(k) psi_{c't}(k'):
+//
+//   T(k,k')[(c'c)][(v'v)] = sum_nu M^nu_{cc'}(k,k') P(k,k')[(v'v)][nu]
+//                         = sum_t psi_{c't}(k') U(k,k')[(c,t)][(v'v)],
+//   U(k,k')[(c,t)][(v'v)] = sum_nu B^nu_{ct}(k) P(k,k')[(v'v)][nu].
+//
+// One block owns one k, one conduction band c and a group of q: U is a
+// complex GEMM (rows t, columns (q, v'v), depth nu) on the 32x32x16 BF16 MFMA
+// with pre-split operands; its epilogue stages U in LDS and contracts the AO
+// index t with psi(k+q) on the vector units, writing the direct blocks T.
+// Nothing of size N_k^2 x n_aux leaves the chip.
+#include "bse_internal.h"
+#include "mfma_common.h"
+
+namespace bse {
+namespace {
+
+struct UArgs {
+  int Nk, nq, q0, nv, nc, nbnd, no, na, qg;
+  const __bf16* BcT;   // planes [Nk][nc][no][na] (K = nu contiguous)
+  long long ps_BcT;
+  const __bf16* P;     // planes [nq][Nk][nv*nv][na]
+  long long ps_P;
+  const float* psi;    // c64 [Nk][nbnd][no]
+  const int* kq;       // [Nk][Nk]
+  float* T;            // c64 [nq][Nk][nc*nc][nv*nv]
+};
+
+template <int TMW>
+__global__ __launch_bounds__(256) void u_direct_b3(UArgs u) {
+  constexpr int BM = 2 * TMW * 32, BN = 128, BK = 16, HN = 64;
+  __shared__ __attribute__((aligned(16))) __bf16 sA[2][4][BM * BK];
+  __shared__ __attribute__((aligned(16))) __bf16 sB[2][4][BN * BK];
+  __shared__ float2 Us[BM * HN];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int k = blockIdx.z, c = blockIdx.y;
+  const int nv2 = u.nv * u.nv;
+  const int qbase = blockIdx.x * u.qg;  // batch-local index of the first q of the group
+  const int ncol = min(u.qg, u.nq - qbase) * nv2;
+  const int na = u.na, no = u.no, Nk = u.Nk;
+
+  // staging slices: rows / columns tid/2, k half tid%2
+  const int sr = tid >> 1, sh = tid & 1;
+  const bool a_thread = sr < BM;
+  const bool aok = a_thread && sr < no;
+  const long long aoff = aok ? ((long long)(k * u.nc + c) * no + sr) * na : 0;
+  const bool bok = sr < ncol;
+  long long boff = 0;
+  if (bok) {
+    const int ql = sr / nv2, r = sr % nv2;
+    boff = ((long long)(qbase + ql) * Nk + k) * nv2 * na + (long long)r * na;
+  }
+  const int nK = (na + BK - 1) / BK;
+  bf8v pa[4], pb[4];
+  auto load = [&](const __bf16* base, long long ps, long long off, bool ok, int kb, bf8v* out) {
+    if (ok && ((off + kb) & 7) == 0 && kb + 8 <= na) {
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) out[pl] = *reinterpret_cast<const bf8v*>(base + pl * ps + off + kb);
+    } else {
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) out[pl][e] = (ok && kb + e < na) ? base[pl * ps + off + kb + e] : (__bf16)0.f;
+    }
+  };
+  auto gload = [&](int kt) {
+    const int kb = kt * BK + 8 * sh;
+    if (a_thread) load(u.BcT, u.ps_BcT, aoff, aok, kb, pa);
+    load(u.P, u.ps_P, boff, bok, kb, pb);
+  };
+  auto lstore = [&](int st) {
+    const int o = sr * BK + 8 * sh;
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) {
+      if (a_thread) *reinterpret_cast<bf8v*>(&sA[st][pl][o]) = pa[pl];
+      *reinterpret_cast<bf8v*>(&sB[st][pl][o]) = pb[pl];
+    }
+  };
+
+  f16v accR[TMW][2], accI[TMW][2];
+#pragma unroll
+  for (int i = 0; i < TMW; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        accR[i][j][r] = 0.f;
+        accI[i][j][r] = 0.f;
+      }
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nK; ++kt) {
+    const int st = kt & 1;
+    if (kt + 1 < nK) gload(kt + 1);
+    const int fo = 8 * (lane >> 5);
+    bf8v a[TMW][4], bb[2][4];
+#pragma unroll
+    for (int i = 0; i < TMW; ++i) {
+      const int row = wm * TMW * 32 + i * 32 + (lane & 31);
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) a[i][pl] = *reinterpret_cast<const bf8v*>(&sA[st][pl][row * BK + fo]);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = wn * 64 + j * 32 + (lane & 31);
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) bb[j][pl] = *reinterpret_cast<const bf8v*>(&sB[st][pl][col * BK + fo]);
+    }
+#pragma unroll
+    for (int i = 0; i < TMW; ++i) {
+      const bf8v nih = neg8(a[i][2]), nil = neg8(a[i][3]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) cmma_b3(a[i], nih, nil, bb[j], accR[i][j], accI[i][j]);
+    }
+    if (kt + 1 < nK) lstore(st ^ 1);
+    __syncthreads();
+  }
+
+  // epilogue, one half of the columns at a time: U -> LDS, then T = psi(k+q) U over t
+  const int nc = u.nc;
+  for (int h = 0; h < 2; ++h) {
+    if (wn == h) {
+#pragma unroll
+      for (int i = 0; i < TMW; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int row = wm * TMW * 32 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            const int col = j * 32 + (lane & 31);
+            Us[row * HN + col] = make_float2(accR[i][j][r], accI[i][j][r]);
+          }
+    }
+    __syncthreads();
+    // outputs (c', col) of this half: col -> (q, v'v)
+    for (int o = tid; o < nc * HN; o += 256) {
+      const int col = o % HN, cp = o / HN;
+      const int gcol = h * HN + col;
+      if (gcol >= ncol) continue;
+      const int ql = gcol / nv2, r = gcol % nv2;
+      const int qi = qbase + ql;
+      const int kp = u.kq[(long long)k * Nk + u.q0 + qi];
+      const float* ps = u.psi + 2 * ((long long)kp * u.nbnd + u.nv + cp) * no;
+      float sr_ = 0.f, si_ = 0.f;
+      for (int t = 0; t < no; ++t) {
+        const float2 uv = Us[t * HN + col];
+        const float pr = ps[2 * t], pi = ps[2 * t + 1];
+        sr_ += pr * uv.x - pi * uv.y;
+        si_ += pr * uv.y + pi * uv.x;
+      }
+      float* out = u.T + 2 * ((((long long)qi * Nk + k) * nc * nc + (long long)cp * nc + c) * nv2 + r);
+      out[0] = sr_;
+      out[1] = si_;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+bse_status direct_u_b3(Plan* p, int q0, int nq, hipStream_t st) {
+  const bse_dims& d = p->d;
+  UArgs u;
+  u.Nk = p->Nk;
+  u.nq = nq;
+  u.q0 = q0;
+  u.nv = d.nv;
+  u.nc = d.nc;
+  u.nbnd = p->nbnd;
+  u.no = d.n_ao;
+  u.na = d.n_aux;
+  const int nv2 = d.nv * d.nv;
+  if (nv2 > 128 || d.n_ao > 128) {
+    set_error("direct_u_b3: needs nv^2 <= 128 and n_ao <= 128");
+    return BSE_ESHAPE;
+  }
+  u.qg = 128 / nv2;
+  u.BcT = (const __bf16*)p->BcT;
+  u.ps_BcT = p->ps_Bc;
+  u.P = (const __bf16*)p->P;
+  u.ps_P = p->ps_Mv;
+  u.psi = p->psi32;
+  u.kq = p->kq;
+  u.T = (float*)p->T;
+  const dim3 grid((unsigned)((nq + u.qg - 1) / u.qg), (unsigned)d.nc, (unsigned)p->Nk);
+  if (d.n_ao <= 64)
+    hipLaunchKernelGGL(u_direct_b3<1>, grid, dim3(256), 0, st, u);
+  else
+    hipLaunchKernelGGL(u_direct_b3<2>, grid, dim3(256), 0, st, u);
+  BSE_CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+}  // namespace bse

@@ -15,15 +15,10 @@
 //         LDS (hi = bf16(x), lo = bf16(x - hi)); every tile step issues
 //         hi*hi + hi*lo + lo*hi with FP32 accumulation.
 #include "bse_internal.h"
-
-#include <hip/hip_bf16.h>
+#include "mfma_common.h"
 
 namespace bse {
 namespace {
-
-typedef double d4v __attribute__((ext_vector_type(4)));
-typedef float f4v __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
 template <typename T>
 struct V4;
@@ -43,12 +38,6 @@ __device__ __forceinline__ f4v mma16(float a, float b, f4v c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ long long off_of(const long long* tab, int pb, long long sb, long long si,
-                                            int b, int M, int i) {
-  long long o = (long long)b * sb;
-  if (tab) return o + tab[(pb ? (long long)b * M : 0LL) + i];
-  return o + (long long)i * si;
-}
 
 template <typename T>
 struct C2 {
@@ -234,10 +223,6 @@ __global__ __launch_bounds__(256) void cgemm_real(GemmArgs g) {
 // ----------------------------------------------------------------------------
 // BF16x3 kernel (c64 inputs, split into bf16 hi/lo when staged to LDS)
 // ----------------------------------------------------------------------------
-__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
-  hi = (__bf16)x;
-  lo = (__bf16)(x - (float)hi);
-}
 
 template <typename TC, int WM, int WN, int TM, int TN, int BK>
 __global__ __launch_bounds__(256) void cgemm_bf16x3(GemmArgs g) {
@@ -417,6 +402,189 @@ __global__ __launch_bounds__(256) void cgemm_bf16x3(GemmArgs g) {
   }
 }
 
+
+// ----------------------------------------------------------------------------
+// BF16X3, large tiles: planar hi/lo operands and 32x32x16 MFMA
+//
+// Block tile 128 x 128 complex, K step 16 complex, 4 waves in 2 x 2, each wave
+// 2 x 2 tiles of 32 x 32 complex.  Every thread stages one (row, 8 k) slice of A
+// and of B per K step: the 8 complex values are split once into four bf16 planes
+// (Re hi, Re lo, Im hi, Im lo) and written to LDS as 16-byte vectors, so the
+// MFMA operands are single ds_read_b128 loads.  Complex products use four real
+// products per plane pair with separate Re / Im accumulators:
+//   Cr += Ar Br - Ai Bi,   Ci += Ar Bi + Ai Br,  each as hi*hi + hi*lo + lo*hi.
+// LDS is double buffered with one barrier per K step.
+// ----------------------------------------------------------------------------
+
+// A, B: AS / BS = true when the operand is stored pre-split as four bf16 planes
+// (Re hi, Re lo, Im hi, Im lo; plane p at base + p * ps, same element offsets as
+// the complex array); otherwise complex64 and split while staging.
+// CS = true writes C pre-split the same way (alpha applied, beta ignored).
+template <bool AS, bool BS, bool CS, typename TC>
+__global__ __launch_bounds__(256) void cgemm_b3_big(GemmArgs g) {
+  constexpr int BM = 128, BN = 128, BK = 16;
+  constexpr int PL = BM * BK;  // bf16 elements per plane
+  __shared__ __attribute__((aligned(16))) __bf16 sA[2][4][PL];
+  __shared__ __attribute__((aligned(16))) __bf16 sB[2][4][BN * BK];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int n0 = blockIdx.x * BN, m0 = blockIdx.y * BM;
+  const float asg = g.conjA ? -1.f : 1.f;
+  const float bsg = g.conjB ? -1.f : 1.f;
+  // staging slice of this thread: row / column tid/2, k half tid%2
+  const int sr = tid >> 1, sh = tid & 1;
+  const int nK = (g.K + BK - 1) / BK;
+
+  for (int b = blockIdx.z; b < g.batch; b += gridDim.z) {
+    const bool aok = (m0 + sr) < g.M;
+    const bool bok = (n0 + sr) < g.N;
+    const long long aoff = aok ? off_of(g.a_tab, g.a_tab_pb, g.a_sb, g.a_si, b, g.M, m0 + sr) : 0;
+    const long long boff = bok ? off_of(g.b_tab, g.b_tab_pb, g.b_sb, g.b_sj, b, g.N, n0 + sr) : 0;
+    // staged operand slices: 4 planes x 8 bf16
+    bf8v pa[4], pb[4];
+    auto load_split = [&](const __bf16* base, long long ps, long long off, long long sk, bool ok, int kb,
+                          float sg, bf8v* out) {
+      const bool fast = ok && sk == 1 && ((off + kb) & 7) == 0 && kb + 8 <= g.K;
+      if (fast) {
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl) out[pl] = *reinterpret_cast<const bf8v*>(base + pl * ps + off + kb);
+      } else {
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl)
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            out[pl][e] = (ok && kb + e < g.K) ? base[pl * ps + off + (long long)(kb + e) * sk] : (__bf16)0.f;
+      }
+      if (sg < 0.f) {
+        out[2] = neg8(out[2]);
+        out[3] = neg8(out[3]);
+      }
+    };
+    auto load_c64 = [&](const float* base, long long off, long long sk, bool ok, int kb, float sg, bf8v* out) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        float re = 0.f, im = 0.f;
+        if (ok && kb + e < g.K) {
+          const float2 v = *reinterpret_cast<const float2*>(base + 2 * (off + (long long)(kb + e) * sk));
+          re = v.x;
+          im = sg * v.y;
+        }
+        __bf16 h, l;
+        split_bf16(re, h, l);
+        out[0][e] = h;
+        out[1][e] = l;
+        split_bf16(im, h, l);
+        out[2][e] = h;
+        out[3][e] = l;
+      }
+    };
+    auto gload = [&](int kt) {
+      const int kb = kt * BK + 8 * sh;
+      if constexpr (AS)
+        load_split((const __bf16*)g.A, g.a_ps, aoff, g.a_sk, aok, kb, asg, pa);
+      else
+        load_c64((const float*)g.A, aoff, g.a_sk, aok, kb, asg, pa);
+      if constexpr (BS)
+        load_split((const __bf16*)g.B, g.b_ps, boff, g.b_sk, bok, kb, bsg, pb);
+      else
+        load_c64((const float*)g.B, boff, g.b_sk, bok, kb, bsg, pb);
+    };
+    auto lstore = [&](int st) {
+      const int o = sr * BK + 8 * sh;
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) {
+        *reinterpret_cast<bf8v*>(&sA[st][pl][o]) = pa[pl];
+        *reinterpret_cast<bf8v*>(&sB[st][pl][o]) = pb[pl];
+      }
+    };
+
+    f16v accR[2][2], accI[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          accR[i][j][r] = 0.f;
+          accI[i][j][r] = 0.f;
+        }
+
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nK; ++kt) {
+      const int st = kt & 1;
+      if (kt + 1 < nK) gload(kt + 1);
+      const int fo = 8 * (lane >> 5);
+      bf8v a[2][4], bb[2][4];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int row = wm * 64 + i * 32 + (lane & 31);
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl) a[i][pl] = *reinterpret_cast<const bf8v*>(&sA[st][pl][row * BK + fo]);
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int col = wn * 64 + j * 32 + (lane & 31);
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl) bb[j][pl] = *reinterpret_cast<const bf8v*>(&sB[st][pl][col * BK + fo]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const bf8v nih = neg8(a[i][2]), nil = neg8(a[i][3]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          f16v cr = accR[i][j], ci = accI[i][j];
+          cmma_b3(a[i], nih, nil, bb[j], cr, ci);
+          accR[i][j] = cr;
+          accI[i][j] = ci;
+        }
+      }
+      if (kt + 1 < nK) lstore(st ^ 1);
+      __syncthreads();
+    }
+    // epilogue: register r of a lane holds row 8*(r/4) + 4*(lane/32) + r%4, column lane%32
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (row >= g.M) continue;
+        const long long ro = off_of(g.c_tab, g.c_tab_pb, g.c_sb, g.c_si, b, g.M, row);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int col = n0 + wn * 64 + j * 32 + (lane & 31);
+          if (col >= g.N) continue;
+          const long long co = ro + (long long)col * g.c_sj;
+          if constexpr (CS) {
+            __bf16* o = (__bf16*)g.C + co;
+            const float vr = (float)(g.alpha * (double)accR[i][j][r]);
+            const float vi = (float)(g.alpha * (double)accI[i][j][r]);
+            __bf16 h, l;
+            split_bf16(vr, h, l);
+            o[0] = h;
+            o[g.c_ps] = l;
+            split_bf16(vi, h, l);
+            o[2 * g.c_ps] = h;
+            o[3 * g.c_ps] = l;
+          } else {
+            TC* o = (TC*)g.C + 2 * co;
+            double vr = g.alpha * (double)accR[i][j][r], vi = g.alpha * (double)accI[i][j][r];
+            if (g.beta) {
+              vr += (double)o[0];
+              vi += (double)o[1];
+            }
+            o[0] = (TC)vr;
+            o[1] = (TC)vi;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <typename K>
 bse_status launch(K kern, const GemmArgs& g, int BM, int BN, hipStream_t st) {
   const long long gx = (g.N + BN - 1) / BN, gy = (g.M + BM - 1) / BM;
@@ -453,6 +621,7 @@ bse_status run_real(const GemmArgs& g, hipStream_t st) {
 
 template <typename TC>
 bse_status run_bf16(const GemmArgs& g, hipStream_t st) {
+  if (g.M >= 64 && g.N >= 64) return launch(cgemm_b3_big<false, false, false, TC>, g, 128, 128, st);
   switch (pick(g)) {
     case SH_NARROW_N:
       return launch(cgemm_bf16x3<TC, 4, 1, 1, 2, 32>, g, 64, 16, st);
@@ -464,6 +633,27 @@ bse_status run_bf16(const GemmArgs& g, hipStream_t st) {
 }
 
 }  // namespace
+
+bse_status cgemm_split(const GemmArgs& g, bool a_split, bool b_split, bool c_split, bool out_f64, hipStream_t st) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return BSE_OK;
+  if (g.K <= 0) {
+    set_error("cgemm_split: K must be positive");
+    return BSE_ESHAPE;
+  }
+#define BSE_SPLIT_CASE(AS, BS, CS)                                                              \
+  if (a_split == AS && b_split == BS && c_split == CS)                                           \
+    return out_f64 ? launch(cgemm_b3_big<AS, BS, CS, double>, g, 128, 128, st)                   \
+                   : launch(cgemm_b3_big<AS, BS, CS, float>, g, 128, 128, st);
+  BSE_SPLIT_CASE(true, true, true)
+  BSE_SPLIT_CASE(true, true, false)
+  BSE_SPLIT_CASE(true, false, false)
+  BSE_SPLIT_CASE(false, true, false)
+  BSE_SPLIT_CASE(false, false, false)
+  BSE_SPLIT_CASE(false, true, true)
+#undef BSE_SPLIT_CASE
+  set_error("cgemm_split: unsupported operand combination");
+  return BSE_EINVAL;
+}
 
 bse_status cgemm(const GemmArgs& g, Arith ar, bool in_f64, bool out_f64, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return BSE_OK;

@@ -1,0 +1,55 @@
+// Device helpers shared by the matrix-core kernels: vector types, the bf16
+// hi/lo split and operand-offset lookup.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "bse_internal.h"
+
+namespace bse {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+
+// x = hi + lo + O(2^-16 |x|): hi = bf16_rn(x), lo = bf16_rn(x - hi)
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+// flip the sign of 8 packed bf16 values
+__device__ __forceinline__ bf8v neg8(bf8v x) {
+  u4v u = __builtin_bit_cast(u4v, x);
+  u ^= 0x80008000u;
+  return __builtin_bit_cast(bf8v, u);
+}
+
+__device__ __forceinline__ long long off_of(const long long* tab, int pb, long long sb, long long si, int b, int M,
+                                            int i) {
+  long long o = (long long)b * sb;
+  if (tab) return o + tab[(pb ? (long long)b * M : 0LL) + i];
+  return o + (long long)i * si;
+}
+
+// one complex tile step of the BF16x3 product on 32x32x16 MFMA:
+//   cr += ar br - ai bi,  ci += ar bi + ai br   (each as hi*hi + hi*lo + lo*hi)
+// a[0..3] = (Re hi, Re lo, Im hi, Im lo) of A, b[0..3] likewise; nih / nil = -Im parts of A
+__device__ __forceinline__ void cmma_b3(const bf8v* a, bf8v nih, bf8v nil, const bf8v* b, f16v& cr, f16v& ci) {
+  cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[0], cr, 0, 0, 0);
+  ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[2], ci, 0, 0, 0);
+  cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[1], cr, 0, 0, 0);
+  ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[3], ci, 0, 0, 0);
+  cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nil, b[2], cr, 0, 0, 0);
+  ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[3], b[0], ci, 0, 0, 0);
+  cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nih, b[3], cr, 0, 0, 0);
+  ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[1], ci, 0, 0, 0);
+  cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[0], cr, 0, 0, 0);
+  ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[2], ci, 0, 0, 0);
+  cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nih, b[2], cr, 0, 0, 0);
+  ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[0], ci, 0, 0, 0);
+}
+
+}  // namespace bse

@@ -30,7 +30,66 @@ unsigned grid_for(long long n) {
   return (unsigned)g;
 }
 
+template <typename T>
+__global__ void split_kernel(const T* __restrict__ in, __bf16* __restrict__ out, long long n, long long ps) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const float re = (float)in[2 * i], im = (float)in[2 * i + 1];
+    const __bf16 rh = (__bf16)re, ih = (__bf16)im;
+    out[i] = rh;
+    out[ps + i] = (__bf16)(re - (float)rh);
+    out[2 * ps + i] = ih;
+    out[3 * ps + i] = (__bf16)(im - (float)ih);
+  }
+}
+
+// out[b][c][r] (planes) = split(in[b][r][c])
+template <typename T>
+__global__ void split_T_kernel(const T* __restrict__ in, __bf16* __restrict__ out, int batch, int rows, int cols,
+                               long long ps) {
+  const long long per = (long long)rows * cols, n = per * batch;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long b = i / per, rc = i % per;
+    const int c = (int)(rc / rows), r = (int)(rc % rows);  // output order: consecutive threads -> consecutive r
+    const long long src = b * per + (long long)r * cols + c;
+    const float re = (float)in[2 * src], im = (float)in[2 * src + 1];
+    const __bf16 rh = (__bf16)re, ih = (__bf16)im;
+    out[i] = rh;
+    out[ps + i] = (__bf16)(re - (float)rh);
+    out[2 * ps + i] = ih;
+    out[3 * ps + i] = (__bf16)(im - (float)ih);
+  }
+}
+
 }  // namespace
+
+bse_status split_planes(const void* in, bool in_f64, __bf16* out, long long n, long long plane_stride,
+                        hipStream_t st) {
+  if (n <= 0) return BSE_OK;
+  if (in_f64)
+    hipLaunchKernelGGL(split_kernel<double>, dim3(grid_for(n)), dim3(256), 0, st, (const double*)in, out, n,
+                       plane_stride);
+  else
+    hipLaunchKernelGGL(split_kernel<float>, dim3(grid_for(n)), dim3(256), 0, st, (const float*)in, out, n,
+                       plane_stride);
+  BSE_CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+bse_status split_planes_T(const void* in, bool in_f64, __bf16* out, int batch, int rows, int cols,
+                          long long plane_stride, hipStream_t st) {
+  const long long n = (long long)batch * rows * cols;
+  if (n <= 0) return BSE_OK;
+  if (in_f64)
+    hipLaunchKernelGGL(split_T_kernel<double>, dim3(grid_for(n)), dim3(256), 0, st, (const double*)in, out, batch,
+                       rows, cols, plane_stride);
+  else
+    hipLaunchKernelGGL(split_T_kernel<float>, dim3(grid_for(n)), dim3(256), 0, st, (const float*)in, out, batch,
+                       rows, cols, plane_stride);
+  BSE_CHECK_LAUNCH();
+  return BSE_OK;
+}
 
 // n = number of complex elements
 bse_status convert_c128_to_c64(const double* in, float* out, long long n, hipStream_t st) {
