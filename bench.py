@@ -41,11 +41,44 @@ def f_apply(Nk, n_ao, nv, nc, n_aux, nb):
                  + 2 * Nk * nc * nv * n_aux * nb + n_aux ** 2 * nb) + 2 * N * nb)
 
 
-def kernel_flops_per_pair(p):
-    """Algorithmic flops per (k, k') pair of each single-kernel stage of the direct term."""
+def kernel_flops_per_pair(p, prec):
+    """Algorithmic flops per (k, k') pair of each single-kernel stage of the direct term.
+
+    wstep      P = conj(M_v) W(q)              8 n_aux^2 nv^2
+    pairdens_v M_vv' from the halves            8 n_aux n_ao nv^2
+    pairdens_c M_cc' from the halves            8 n_aux n_ao nc^2      (FP64 / FP32 paths)
+    dblock     FP64 / FP32: T = M_c P^T         8 n_aux nc^2 nv^2
+               BF16x3: U = B_c^T P^T and T = psi U (conduction pair densities never formed)
+                                                8 nc n_ao n_aux nv^2 + 8 nc^2 n_ao nv^2
+    """
     na, no, nv, nc = p.n_aux, p.n_ao, p.nv, p.nc
-    return {"wstep": 8 * na * na * nv * nv, "pairdens_c": 8 * na * no * nc * nc,
-            "pairdens_v": 8 * na * no * nv * nv, "dblock": 8 * na * nc * nc * nv * nv}
+    d = {"wstep": 8 * na * na * nv * nv, "pairdens_c": 8 * na * no * nc * nc,
+         "pairdens_v": 8 * na * no * nv * nv, "dblock": 8 * na * nc * nc * nv * nv}
+    if prec == "bf16x3":
+        d["dblock"] = 8 * nc * no * na * nv * nv + 8 * nc * nc * no * nv * nv
+    return d
+
+
+def kernel_bytes_per_pair(p, prec):
+    """Algorithmic HBM bytes per (k, k') pair of the single-kernel stages (each operand once)."""
+    na, no, nv, nc, Nk = p.n_aux, p.n_ao, p.nv, p.nc, p.Nk
+    e = 16 if prec == "f64" else 8
+    return {"wstep": e * (2 * nv * nv * na) + e * na * na / Nk,
+            "pairdens_v": e * nv * nv * na + e * (nv * na * no) / Nk,
+            "pairdens_c": e * nc * nc * na + e * (nc * na * no) / Nk,
+            "dblock": (e * nv * nv * na + 8 * nc * nc * nv * nv + e * nc * no * na / Nk) if prec == "bf16x3"
+            else e * (nc * nc * na + nv * nv * na) + e * nc * nc * nv * nv}
+
+
+def copy_calibration(nbytes=1 << 30):
+    """One plain device copy of a known size, for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}), flush=True)
 
 
 def main():
@@ -54,16 +87,31 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prec", default="auto", choices=["auto", "f64", "f32", "bf16x3"])
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default="mesh8_ao64")
     ap.add_argument("--haydock-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=2)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run one 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
+    ap.add_argument("--mode", default="spectrum", choices=["spectrum", "precision", "gradients"],
+                    help="spectrum: the timed pipeline (default); precision: per-precision apply and "
+                         "short-Haydock errors on a larger workload; gradients: LOBPCG and spectrum "
+                         "gradients checked by central finite differences")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.mode == "precision":
+        precision_mode(args.config if args.config != "mesh8_ao64" else "mesh12_ao96", args.haydock_steps or 10)
+        return
+    if args.mode == "gradients":
+        gradients_mode(args.config if args.config != "mesh8_ao64" else "mesh8_ao64_grad", args.haydock_steps or 100)
+        return
 
     import torch
     from paper_2607_05853_amd import bse as B
@@ -144,7 +192,7 @@ def main():
     print("[bench] timed: %s %.3f s/step -> %.1f GFLOP/s" % (prec, dt, value), file=sys.stderr, flush=True)
 
     # roofline of the dominant single kernel (event-timed on the library's stream)
-    fpp = kernel_flops_per_pair(p)
+    fpp = kernel_flops_per_pair(p, prec)
     cand = {k: v for k, v in st_all.items() if k in fpp and v[1] > 0}
     dom = max(cand, key=lambda k: cand[k][0])
     ms, n = cand[dom]
@@ -153,8 +201,11 @@ def main():
     passes = m + (1 if dom.startswith("pairdens") else 0)
     pairs_per_launch = passes * p.Nk * p.Nk / n
     achieved = fpp[dom] * pairs_per_launch / (ms / n * 1e-3) / 1e12
+    traffic = measured_traffic(dom, args.config, prec)
     roof = {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[prec],
-            "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[prec], "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[prec],
+            "traffic": traffic["bytes_per_launch"] if traffic else None,
+            "algorithmic_bytes_per_launch": kernel_bytes_per_pair(p, prec)[dom] * pairs_per_launch,
             "avg_launch_ms": ms / n, "launches": n, "pairs_per_launch": pairs_per_launch}
 
     cpu = None
@@ -181,6 +232,170 @@ def main():
         "stage_ms_last_step": stages,
     }
     print(json.dumps(rec), flush=True)
+
+
+def _setup(config, wgen="G1"):
+    import torch
+    from paper_2607_05853_amd import bse as B
+    from synth import dense_kmesh, make_problem
+    dev = torch.device("cuda:0")
+    T = lambda a, dt=torch.complex128: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)
+    p = make_problem(config, 0, wgen)
+    return B, T, p, dense_kmesh(p.nk), torch
+
+
+def precision_mode(config, m):
+    """Apply and short-Haydock spectrum of each precision against the FP64 GPU path on one seed."""
+    from synth import CONFIGS, polarisations, random_block
+    B, T, p, kq, torch = _setup(config)
+    nb = CONFIGS[config]["nb"]
+    Fa = f_apply(p.Nk, p.n_ao, p.nv, p.nc, p.n_aux, nb)
+    W_R, eps = T(p.W_R), T(p.eps_qp, torch.float64)
+    X = T(random_block(p.N, nb, seed=1))
+    te = p.eps_qp[:, p.nv:][:, :, None] - p.eps_qp[:, :p.nv][:, None, :]
+    omega = np.linspace(te.min() - 1.0, te.max() + 1.0, 2001)
+    out = {}
+    Yref = Sref = None
+    for prec in ["f64", "bf16x3", "f32"]:
+        Wq = B.interpolate_W(W_R, p.R, p.w_R, kq)
+        plan = B.Plan(p.nk, p.n_ao, p.nv, p.nc, p.n_aux, eps, T(p.psi), T(p.C), T(p.Vbar), Wq, alpha=p.alpha,
+                      prec=prec, max_nb=nb)
+        del Wq
+        torch.cuda.synchronize()
+        t0 = time.time()
+        Y = plan.apply(X)
+        torch.cuda.synchronize()
+        ta = time.time() - t0
+        P = plan.velocity_start(T(p.vel), T(p.eps_ks, torch.float64), polarisations(nb))
+        t0 = time.time()
+        S = plan.haydock(P, m, omega, 0.1)["S"]
+        th = time.time() - t0
+        if Yref is None:
+            Yref, Sref = Y.clone(), S
+        rec = {"apply_s": ta, "apply_GFLOP_s": Fa / ta / 1e9,
+               "apply_rel_err_vs_f64": float((Y - Yref).abs().max() / Yref.abs().max()),
+               "haydock_s": th, "spectrum_rel_err_vs_f64": float(np.abs(S - Sref).max() / np.abs(Sref).max())}
+        out[prec] = rec
+        print("[precision] %s %s" % (prec, json.dumps(rec)), file=sys.stderr, flush=True)
+        plan.close()
+        del plan, Y, P
+        torch.cuda.empty_cache()
+    print(json.dumps({"mode": "precision", "workload": "%s: dense %s, N_ao=%d, nv=%d, nc=%d, N_aux=%d, BSE dim %d, "
+                                                  "blocks of %d, Haydock %d steps" %
+                      (config, "x".join(map(str, p.nk)), p.n_ao, p.nv, p.nc, p.n_aux, p.N, nb, m),
+                      "F_apply_TFLOP": Fa / 1e12, "results": out}), flush=True)
+
+
+def gradients_mode(config, m):
+    """Gradients of Omega_1 (LOBPCG) and of the Haydock spectrum at 64 frequencies w.r.t. W(R) and eps,
+    against central finite differences of the same GPU path (FP64, h = 1e-6)."""
+    from synth import CONFIGS, polarisations
+    from paper_2607_05853_amd import autograd as AG
+    B, T, p, kq, torch = _setup(config, "G2")
+    nb = CONFIGS[config]["nb"]
+    eta, h = 0.1, 1e-6
+    rng = np.random.default_rng(7)
+    idx = {tuple(r): i for i, r in enumerate(p.R)}
+    dW = np.zeros(p.W_R.shape)
+    for i, r in enumerate(p.R):
+        j = idx[tuple(-r)]
+        if j < i:
+            continue
+        A = rng.standard_normal(p.W_R.shape[1:]) * 1e-2
+        if i == j:
+            A = A + A.T
+        dW[i], dW[j] = A, A.T
+    dW = dW.astype(complex)
+    de = rng.standard_normal(p.eps_qp.shape)
+
+    def build(W_R, eps):
+        Wq = B.interpolate_W(W_R, p.R, p.w_R, kq)
+        pl = B.Plan(p.nk, p.n_ao, p.nv, p.nc, p.n_aux, eps, T(p.psi), T(p.C), T(p.Vbar), Wq, alpha=p.alpha,
+                    prec="f64", max_nb=max(nb, 64))
+        pl.set_R(p.R, p.w_R)
+        return pl
+
+    res = {}
+    W_R = T(p.W_R).requires_grad_(True)
+    eps = T(p.eps_qp, torch.float64).requires_grad_(True)
+    plan = build(W_R.detach(), eps.detach())
+    t0 = time.time()
+    om1 = AG.lowest_exciton_energy(plan, W_R, eps, n_block=nb, tol=1e-12, max_iter=500)
+    om1.backward()
+    torch.cuda.synchronize()
+    res["lowest_s"] = time.time() - t0
+    gW, ge = W_R.grad.detach().cpu().numpy(), eps.grad.detach().cpu().numpy()
+
+    def om(Wr, e):
+        pl = build(T(Wr), T(e, torch.float64))
+        o, _, _ = pl.lowest_excitons(n_block=nb, tol=1e-13, max_iter=800, allow_unconverged=True)
+        pl.close()
+        return o[0]
+
+    fdW = (om(p.W_R + h * dW, p.eps_qp) - om(p.W_R - h * dW, p.eps_qp)) / (2 * h)
+    fde = (om(p.W_R, p.eps_qp + h * de) - om(p.W_R, p.eps_qp - h * de)) / (2 * h)
+    anW, ane = float(np.real(np.vdot(gW, dW))), float(np.sum(ge * de))
+    res["Omega1_eV"] = float(om1.item())
+    res["dOmega1_dW_fd_rel_err"] = abs(fdW - anW) / abs(anW)
+    res["dOmega1_deps_fd_rel_err"] = abs(fde - ane) / abs(ane)
+    print("[gradients] lowest %s" % json.dumps(res), file=sys.stderr, flush=True)
+
+    omega = np.linspace(res["Omega1_eV"] - 0.5, res["Omega1_eV"] + 2.5, 64)
+    gamma = rng.standard_normal((nb, len(omega)))
+    W_R2 = T(p.W_R).requires_grad_(True)
+    eps2 = T(p.eps_qp, torch.float64).requires_grad_(True)
+    P = plan.velocity_start(T(p.vel), T(p.eps_ks, torch.float64), polarisations(nb))
+    t0 = time.time()
+    S = AG.haydock_spectrum(plan, P, W_R2, eps2, m, omega, eta)
+    torch.sum(T(gamma, torch.float64) * S).backward()
+    torch.cuda.synchronize()
+    res["spectrum_grad_s"] = time.time() - t0
+
+    def spec(Wr, e):
+        pl = build(T(Wr), T(e, torch.float64))
+        s = pl.haydock(P, m, omega, eta)["S"]
+        pl.close()
+        return float(np.sum(gamma * s))
+
+    fdW = (spec(p.W_R + h * dW, p.eps_qp) - spec(p.W_R - h * dW, p.eps_qp)) / (2 * h)
+    fde = (spec(p.W_R, p.eps_qp + h * de) - spec(p.W_R, p.eps_qp - h * de)) / (2 * h)
+    anW = float(np.real(np.vdot(W_R2.grad.detach().cpu().numpy(), dW)))
+    ane = float(np.sum(eps2.grad.detach().cpu().numpy() * de))
+    res["dS_dW_fd_rel_err"] = abs(fdW - anW) / abs(anW)
+    res["dS_deps_fd_rel_err"] = abs(fde - ane) / abs(ane)
+    print(json.dumps({"mode": "gradients", "workload": "%s: dense %s, N_ao=%d, nv=%d, nc=%d, N_aux=%d, BSE dim %d, "
+                                                      "LOBPCG block %d, spectrum at 64 frequencies, Haydock %d steps"
+                      % (config, "x".join(map(str, p.nk)), p.n_ao, p.nv, p.nc, p.n_aux, p.N, nb, m),
+                      "fd_step": h, "results": res}), flush=True)
+
+
+def source_digest():
+    """Digest of the HIP sources: counter summaries taken on other sources are stale."""
+    import hashlib
+    h = hashlib.sha256()
+    cdir = os.path.join(ROOT, "paper_2607_05853_amd", "csrc")
+    for f in sorted(os.listdir(cdir)):
+        with open(os.path.join(cdir, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, config, prec):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if it matches these sources."""
+    path = os.path.join(ROOT, "profiles", "pmc_%s_%s_%s.txt" % (kernel, config, prec))
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_digest") != source_digest():
+        return None
+    try:
+        return {"bytes_per_launch": float(vals["hbm_bytes_per_launch"])}
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(p, kq, nb, Fa, rows):

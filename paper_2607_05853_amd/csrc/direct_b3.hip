@@ -36,9 +36,13 @@ __global__ __launch_bounds__(256) void u_direct_b3(UArgs u) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int k = blockIdx.z, c = blockIdx.y;
   const int nv2 = u.nv * u.nv;
-  const int qbase = blockIdx.x * u.qg;  // batch-local index of the first q of the group
+  // 1-D grid over (k, c, q group), XCD-aware: all blocks of one k share B_c(k) and P(k, .)
+  const int nqg = (u.nq + u.qg - 1) / u.qg;
+  long long kl, t;
+  xcd_map(blockIdx.x, (long long)u.nc * nqg, u.Nk, kl, t);
+  const int k = (int)kl, c = (int)(t / nqg);
+  const int qbase = (int)(t % nqg) * u.qg;  // batch-local index of the first q of the group
   const int ncol = min(u.qg, u.nq - qbase) * nv2;
   const int na = u.na, no = u.no, Nk = u.Nk;
 
@@ -186,7 +190,7 @@ bse_status direct_u_b3(Plan* p, int q0, int nq, hipStream_t st) {
   u.psi = p->psi32;
   u.kq = p->kq;
   u.T = (float*)p->T;
-  const dim3 grid((unsigned)((nq + u.qg - 1) / u.qg), (unsigned)d.nc, (unsigned)p->Nk);
+  const dim3 grid((unsigned)((long long)((nq + u.qg - 1) / u.qg) * d.nc * p->Nk));
   if (d.n_ao <= 64)
     hipLaunchKernelGGL(u_direct_b3<1>, grid, dim3(256), 0, st, u);
   else

@@ -429,14 +429,21 @@ __global__ __launch_bounds__(256) void cgemm_b3_big(GemmArgs g) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int n0 = blockIdx.x * BN, m0 = blockIdx.y * BM;
   const float asg = g.conjA ? -1.f : 1.f;
   const float bsg = g.conjB ? -1.f : 1.f;
   // staging slice of this thread: row / column tid/2, k half tid%2
   const int sr = tid >> 1, sh = tid & 1;
   const int nK = (g.K + BK - 1) / BK;
+  // 1-D grid over (batch, row tile, column tile), XCD-aware (one batch entry per XCD)
+  const int gxn = (g.N + BN - 1) / BN, gyn = (g.M + BM - 1) / BM;
+  const long long per_batch = (long long)gxn * gyn;
+  const long long total = per_batch * g.batch;
 
-  for (int b = blockIdx.z; b < g.batch; b += gridDim.z) {
+  for (long long L = blockIdx.x; L < total; L += gridDim.x) {
+    long long bl, t;
+    xcd_map(L, per_batch, g.batch, bl, t);
+    const int b = (int)bl;
+    const int m0 = (int)(t / gxn) * BM, n0 = (int)(t % gxn) * BN;
     const bool aok = (m0 + sr) < g.M;
     const bool bok = (n0 + sr) < g.N;
     const long long aoff = aok ? off_of(g.a_tab, g.a_tab_pb, g.a_sb, g.a_si, b, g.M, m0 + sr) : 0;
@@ -598,6 +605,17 @@ bse_status launch(K kern, const GemmArgs& g, int BM, int BN, hipStream_t st) {
   return BSE_OK;
 }
 
+// 1-D launch of the XCD-aware large-tile kernel (it loops if the grid is capped)
+template <typename K>
+bse_status launch_1d(K kern, const GemmArgs& g, int BM, int BN, hipStream_t st) {
+  const long long tiles = (long long)((g.N + BN - 1) / BN) * ((g.M + BM - 1) / BM) * g.batch;
+  const long long cap = 1LL << 30;
+  const unsigned gx = (unsigned)(tiles < cap ? tiles : cap);
+  hipLaunchKernelGGL(kern, dim3(gx), dim3(256), 0, st, g);
+  BSE_CHECK_LAUNCH();
+  return BSE_OK;
+}
+
 // shape classes: wide (64 x 64), narrow-N (64 x 16), narrow-M (16 x 64)
 enum Shape { SH_WIDE, SH_NARROW_N, SH_NARROW_M };
 Shape pick(const GemmArgs& g) {
@@ -621,7 +639,7 @@ bse_status run_real(const GemmArgs& g, hipStream_t st) {
 
 template <typename TC>
 bse_status run_bf16(const GemmArgs& g, hipStream_t st) {
-  if (g.M >= 64 && g.N >= 64) return launch(cgemm_b3_big<false, false, false, TC>, g, 128, 128, st);
+  if (g.M >= 64 && g.N >= 64) return launch_1d(cgemm_b3_big<false, false, false, TC>, g, 128, 128, st);
   switch (pick(g)) {
     case SH_NARROW_N:
       return launch(cgemm_bf16x3<TC, 4, 1, 1, 2, 32>, g, 64, 16, st);
@@ -642,8 +660,8 @@ bse_status cgemm_split(const GemmArgs& g, bool a_split, bool b_split, bool c_spl
   }
 #define BSE_SPLIT_CASE(AS, BS, CS)                                                              \
   if (a_split == AS && b_split == BS && c_split == CS)                                           \
-    return out_f64 ? launch(cgemm_b3_big<AS, BS, CS, double>, g, 128, 128, st)                   \
-                   : launch(cgemm_b3_big<AS, BS, CS, float>, g, 128, 128, st);
+    return out_f64 ? launch_1d(cgemm_b3_big<AS, BS, CS, double>, g, 128, 128, st)                \
+                   : launch_1d(cgemm_b3_big<AS, BS, CS, float>, g, 128, 128, st);
   BSE_SPLIT_CASE(true, true, true)
   BSE_SPLIT_CASE(true, true, false)
   BSE_SPLIT_CASE(true, false, false)

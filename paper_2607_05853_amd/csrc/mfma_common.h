@@ -34,6 +34,23 @@ __device__ __forceinline__ long long off_of(const long long* tab, int pb, long l
   return o + (long long)i * si;
 }
 
+// XCD-aware block order for a 1-D grid of nbatch * per_batch blocks.  Hardware
+// deals consecutive workgroups round-robin to the 8 XCDs (each with its own
+// L2); this maps the j-th block landing on XCD x to batch x + 8 (j / per_batch)
+// so every block of one batch entry (which share operand panels) runs on the
+// same XCD, back to back.  Falls back to the identity when nbatch % 8 != 0.
+__device__ __forceinline__ void xcd_map(long long L, long long per_batch, long long nbatch, long long& bt,
+                                        long long& t) {
+  if ((nbatch & 7) == 0) {
+    const long long x = L & 7, j = L >> 3;
+    bt = x + 8 * (j / per_batch);
+    t = j % per_batch;
+  } else {
+    bt = L / per_batch;
+    t = L % per_batch;
+  }
+}
+
 // one complex tile step of the BF16x3 product on 32x32x16 MFMA:
 //   cr += ar br - ai bi,  ci += ar bi + ai br   (each as hi*hi + hi*lo + lo*hi)
 // a[0..3] = (Re hi, Re lo, Im hi, Im lo) of A, b[0..3] likewise; nih / nil = -Im parts of A

@@ -45,19 +45,19 @@ W_KERNEL = 0.4          # eV, target spectral norm of the direct block (random-m
 
 CONFIGS = {
     # tiny: full diagonalisation + Haydock 200
-    "c1": dict(cfg_id=0, coarse=(2, 2, 2), dense=(4, 4, 4), n_ao=16, nv=4, nc=4,
+    "mesh4_ao16": dict(cfg_id=0, coarse=(2, 2, 2), dense=(4, 4, 4), n_ao=16, nv=4, nc=4,
                n_aux=64, r_cut=None, nb=3, haydock_steps=200),
     # plain FP64 on the GPU: matrix-free apply on blocks of 8, Haydock 300
-    "c2": dict(cfg_id=1, coarse=(4, 4, 4), dense=(8, 8, 8), n_ao=64, nv=4, nc=8,
+    "mesh8_ao64": dict(cfg_id=1, coarse=(4, 4, 4), dense=(8, 8, 8), n_ao=64, nv=4, nc=8,
                n_aux=256, r_cut=None, nb=8, haydock_steps=300),
     # precision form
-    "c3": dict(cfg_id=2, coarse=(4, 4, 4), dense=(12, 12, 12), n_ao=96, nv=6, nc=10,
+    "mesh12_ao96": dict(cfg_id=2, coarse=(4, 4, 4), dense=(12, 12, 12), n_ao=96, nv=6, nc=10,
                n_aux=384, r_cut=None, nb=8, haydock_steps=300),
     # differentiation form
-    "c4": dict(cfg_id=3, coarse=(4, 4, 4), dense=(8, 8, 8), n_ao=64, nv=4, nc=8,
+    "mesh8_ao64_grad": dict(cfg_id=3, coarse=(4, 4, 4), dense=(8, 8, 8), n_ao=64, nv=4, nc=8,
                n_aux=256, r_cut=None, nb=4, haydock_steps=300),
     # largest
-    "c5": dict(cfg_id=4, coarse=(6, 6, 6), dense=(16, 16, 16), n_ao=128, nv=8, nc=8,
+    "mesh16_ao128": dict(cfg_id=4, coarse=(6, 6, 6), dense=(16, 16, 16), n_ao=128, nv=8, nc=8,
                n_aux=512, r_cut=3.0, nb=16, haydock_steps=100),
 }
 
@@ -194,7 +194,7 @@ def _bands(HR, kfrac, n_ao, nv, nc):
     return eps, psi, vel
 
 
-def make_problem(cfg="c1", seed=0, wgen="G1", **over) -> Problem:
+def make_problem(cfg="mesh4_ao16", seed=0, wgen="G1", **over) -> Problem:
     """Draw the synthetic crystal of a named workload (or a dict), with overrides.
 
     Overrides: dense, coarse, n_ao, nv, nc, n_aux, r_cut, alpha.

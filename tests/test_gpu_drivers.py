@@ -61,9 +61,9 @@ def _admissible(p, seed, scale=1e-2):
     return d.astype(complex)
 
 
-@pytest.mark.parametrize("cfg,wgen", [("c1", "G1"), (SMALL, "G2")])
+@pytest.mark.parametrize("cfg,wgen", [("mesh4_ao16", "G1"), (SMALL, "G2")])
 def test_lobpcg_lowest(B, cfg, wgen):
-    p = make_problem(cfg, 0, wgen) if cfg == "c1" else make_problem(cfg, 0, wgen)
+    p = make_problem(cfg, 0, wgen) if cfg == "mesh4_ao16" else make_problem(cfg, 0, wgen)
     plan, Wq = _plan(B, p, nb=4)
     H = O.build_H(p, H_(Wq))
     ev, Z = np.linalg.eigh(H)

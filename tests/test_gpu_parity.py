@@ -60,12 +60,12 @@ def test_interpolate_small(B, n_aux, n_R, n_q):
     assert rel(out32, ref) < 1e-6
 
 
-@pytest.mark.parametrize("cfg", ["c1", "c2"])
+@pytest.mark.parametrize("cfg", ["mesh4_ao16", "mesh8_ao64"])
 def test_interpolate_configs(B, cfg):
     p = make_problem(cfg, 0, "G2")
     kq = dense_kmesh(p.nk)
     got = H_(B.interpolate_W(T(p.W_R), p.R, p.w_R, kq))
-    idx = np.arange(len(kq)) if cfg == "c1" else np.array([0, 1, 7, 63, 64, 200, 511])
+    idx = np.arange(len(kq)) if cfg == "mesh4_ao16" else np.array([0, 1, 7, 63, 64, 200, 511])
     ref = O.interpolate_W(p.W_R, p.R, p.w_R, kq[idx])
     assert rel(got[idx], ref) < TOL["f64"]
     # Hermitian W(q) for the G2 generator, at every q
@@ -74,7 +74,7 @@ def test_interpolate_configs(B, cfg):
 
 def test_interpolate_large_sampled(B):
     # the largest workload's table: 4096 q x 512^2, checked on sampled q against the oracle
-    p = make_problem("c5", 0, "G1")
+    p = make_problem("mesh16_ao128", 0, "G1")
     kq = dense_kmesh(p.nk)
     got = B.interpolate_W(T(p.W_R), p.R, p.w_R, kq)
     idx = np.array([0, 1, 255, 1000, 4095])
@@ -98,7 +98,7 @@ def test_coarse_round_trip_on_gpu(B):
 
 
 def test_interpolate_adjoint_matches_oracle(B):
-    p = make_problem("c1", 0, "G2", coarse=(3, 3, 2))
+    p = make_problem("mesh4_ao16", 0, "G2", coarse=(3, 3, 2))
     kq = dense_kmesh(p.nk)
     rng = np.random.default_rng(4)
     g = rng.standard_normal((len(kq), p.n_aux, p.n_aux)) + 1j * rng.standard_normal((len(kq), p.n_aux, p.n_aux))
@@ -119,7 +119,7 @@ def _plan(B, p, prec="f64", nb=8, Wq=None):
 @pytest.mark.parametrize("wgen", ["G1", "G2"])
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
 def test_apply_c1(B, wgen, prec):
-    p = make_problem("c1", 0, wgen, coarse=(3, 3, 2) if wgen == "G2" else (2, 2, 2))
+    p = make_problem("mesh4_ao16", 0, wgen, coarse=(3, 3, 2) if wgen == "G2" else (2, 2, 2))
     plan, Wq = _plan(B, p, prec, nb=3)
     H = O.build_H(p, H_(Wq))
     X = random_block(p.N, 3, seed=1)
@@ -146,7 +146,7 @@ def test_apply_ragged_and_triplet(B, prec):
 
 
 def test_apply_c2_sampled_rows(B):
-    p = make_problem("c2", 0, "G2")
+    p = make_problem("mesh8_ao64", 0, "G2")
     plan, Wq = _plan(B, p, "f64", nb=8)
     X = random_block(p.N, 8, seed=5)
     Y = H_(plan.apply(T(X)))
@@ -193,7 +193,7 @@ def test_velocity_start(B):
 
 
 def test_haydock_c1(B):
-    p = make_problem("c1", 0, "G2", coarse=(3, 3, 2))
+    p = make_problem("mesh4_ao16", 0, "G2", coarse=(3, 3, 2))
     plan, Wq = _plan(B, p, "f64", nb=3)
     H = O.build_H(p, H_(Wq))
     pol = polarisations(3)

@@ -68,7 +68,7 @@ def test_diagonal_closed_form_and_breakdown(small_cfg):
 @pytest.mark.slow
 def test_c1_convergence_in_m():
     # at the tiny benchmark workload (dim 1024) 200 steps are converged on the eta = 0.1 eV scale
-    p = make_problem("c1", 0)
+    p = make_problem("mesh4_ao16", 0)
     Wq = O.interpolate_W(p.W_R, p.R, p.w_R, dense_kmesh(p.nk))
     H = O.build_H(p, Wq)
     P = O.velocity_start(p, np.eye(3))
