@@ -207,6 +207,7 @@ bse_status form_pair_densities(Plan* p, int q0, int nq, bool need_c, hipStream_t
     g.c_tab = p->tab_mv;
     g.c_tab_pb = 1;
     g.c_sj = 1;
+    g.tab_aligned = (no % 8 == 0);
     if (p->split) {
       g.a_ps = p->ps_psi;
       g.b_ps = p->ps_Bv;
@@ -235,6 +236,7 @@ bse_status form_pair_densities(Plan* p, int q0, int nq, bool need_c, hipStream_t
     g.c_tab = p->tab_mc;
     g.c_tab_pb = 1;
     g.c_sj = 1;
+    g.tab_aligned = (no % 8 == 0);
     if (p->split) {
       g.a_ps = p->ps_psi;
       g.b_ps = p->ps_Bc;

@@ -75,6 +75,8 @@ struct GemmArgs {
   int beta = 0;
   // plane strides (elements) of operands stored pre-split as four bf16 planes
   long long a_ps = 0, b_ps = 0, c_ps = 0;
+  // set by the caller when every table offset (a_tab, b_tab) is a multiple of 8 elements
+  int tab_aligned = 0;
 };
 
 // in_f64: A and B are c128 (else c64); out_f64: C is c128 (else c64).

@@ -16,6 +16,9 @@
 namespace bse {
 namespace {
 
+__device__ __forceinline__ void vm_wait_barrier0() { asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+__device__ __forceinline__ void lds_wait_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 struct UArgs {
   int Nk, nq, q0, nv, nc, nbnd, no, na, qg;
   const __bf16* BcT;   // planes [Nk][nc][no][na] (K = nu contiguous)
@@ -164,6 +167,193 @@ __global__ __launch_bounds__(256) void u_direct_b3(UArgs u) {
   }
 }
 
+
+// Same computation with direct-to-LDS staging of both operands (global_load_lds_dwordx4,
+// two stages, XOR-swizzled 16-byte k chunks as in the split GEMM); needs N_aux % 16 == 0.
+template <int TMW>
+__global__ __launch_bounds__(256) void u_direct_b3_dma(UArgs u) {
+  constexpr int BM = 2 * TMW * 32, BN = 128, BK = 16, HN = 64;
+  constexpr int PA = BM * BK, PB = BN * BK;  // bf16 per plane per stage
+  constexpr int STAGE = 4 * (PA + PB);
+  constexpr int RBA = BM / 32, RB = (BM + BN) / 32;  // 32-row blocks of A, of A and B together
+  __shared__ __attribute__((aligned(1024))) __bf16 smem[2 * STAGE];
+  constexpr int PSI_LDS = 4096;  // complex elements
+  __shared__ float2 psiS[PSI_LDS];
+  float2* Us = reinterpret_cast<float2*>(smem);  // epilogue: [BM][HN] (reuses the stages)
+  static_assert(BM * HN * 8 <= 2 * STAGE * 2, "epilogue staging must fit in the stages");
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int nv2 = u.nv * u.nv;
+  const int nqg = (u.nq + u.qg - 1) / u.qg;
+  long long kl, t;
+  xcd_map(blockIdx.x, (long long)u.nc * nqg, u.Nk, kl, t);
+  const int k = (int)kl, c = (int)(t / nqg);
+  const int qbase = (int)(t % nqg) * u.qg;
+  const int ncol = min(u.qg, u.nq - qbase) * nv2;
+  const int na = u.na, no = u.no, Nk = u.Nk;
+  const int nK = na / BK;
+
+  // DMA slots: 32-row block rb (A rows first, then B columns) is loaded by wave rb % 4, so a wave owns
+  // row blocks wave and wave + 4; lane -> row 32 rb' + lane / 2, 16-byte chunk (lane % 2) ^ bit 3 of the row
+  auto slot = [&](int rb, const __bf16*& src, int& lo, long long& ps, int& pstride) {
+    const bool isA = rb < RBA;
+    const int r = 32 * (isA ? rb : rb - RBA) + (lane >> 1);
+    const int chunk = (lane & 1) ^ ((r >> 3) & 1);
+    if (isA) {
+      const int tr = r < no ? r : 0;  // rows past N_ao re-load row 0; those U rows are never used
+      src = u.BcT + ((long long)(k * u.nc + c) * no + tr) * na + 8 * chunk;
+      lo = 32 * rb * BK;
+      ps = u.ps_BcT;
+      pstride = PA;
+    } else {
+      const int cc = r < ncol ? r : 0;  // columns past the group re-load column 0; never stored
+      const int ql = cc / nv2, rr = cc % nv2;
+      src = u.P + ((long long)(qbase + ql) * Nk + k) * nv2 * na + (long long)rr * na + 8 * chunk;
+      lo = 4 * PA + 32 * (rb - RBA) * BK;
+      ps = u.ps_P;
+      pstride = PB;
+    }
+  };
+  const __bf16 *src0 = nullptr, *src1 = nullptr;
+  int lo0 = 0, lo1 = 0, pst0 = 0, pst1 = 0;
+  long long ps0 = 0, ps1 = 0;
+  slot(wave, src0, lo0, ps0, pst0);  // RB >= 6 > wave always
+  const bool two = wave + 4 < RB;
+  if (two) slot(wave + 4, src1, lo1, ps1, pst1);
+  auto issue = [&](int kt) {
+    __bf16* st = smem + (kt & 1) * STAGE;
+    const int kb = kt * BK;
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl)
+      __builtin_amdgcn_global_load_lds((const void*)(src0 + pl * ps0 + kb),
+                                       (__attribute__((address_space(3))) void*)(st + lo0 + pl * pst0), 16, 0, 0);
+    if (two) {
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl)
+        __builtin_amdgcn_global_load_lds((const void*)(src1 + pl * ps1 + kb),
+                                         (__attribute__((address_space(3))) void*)(st + lo1 + pl * pst1), 16, 0, 0);
+    }
+  };
+
+  f16v accR[TMW][2], accI[TMW][2];
+#pragma unroll
+  for (int i = 0; i < TMW; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        accR[i][j][r] = 0.f;
+        accI[i][j][r] = 0.f;
+      }
+  issue(0);
+  const int ch = lane >> 5;
+  for (int kt = 0; kt < nK; ++kt) {
+    vm_wait_barrier0();
+    if (kt + 1 < nK) issue(kt + 1);
+    const __bf16* sa = smem + (kt & 1) * STAGE;
+    const __bf16* sb = sa + 4 * PA;
+    bf8v a[TMW][4], bb[2][4];
+#pragma unroll
+    for (int i = 0; i < TMW; ++i) {
+      const int row = wm * TMW * 32 + i * 32 + (lane & 31);
+      const int o = row * BK + 8 * (ch ^ ((row >> 3) & 1));
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) a[i][pl] = *reinterpret_cast<const bf8v*>(sa + pl * PA + o);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = wn * 64 + j * 32 + (lane & 31);
+      const int o = col * BK + 8 * (ch ^ ((col >> 3) & 1));
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) bb[j][pl] = *reinterpret_cast<const bf8v*>(sb + pl * PB + o);
+    }
+#pragma unroll
+    for (int i = 0; i < TMW; ++i) {
+      const bf8v nih = neg8(a[i][2]), nil = neg8(a[i][3]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) cmma_b3(a[i], nih, nil, bb[j], accR[i][j], accI[i][j]);
+    }
+  }
+  vm_wait_barrier0();
+
+  const int nc = u.nc;
+  // psi(k+q) of the conduction bands of this block's q group, staged once in LDS when it fits
+  // ([ql][c'][t], row stride no + 1 complex so the q groups of one wave fall in different banks)
+  const int nql = min(u.qg, u.nq - qbase);
+  const int pstr = no + 1;
+  const bool stage_psi = nql * nc * pstr <= PSI_LDS;
+  if (stage_psi) {
+    for (int e = tid; e < nql * nc * no; e += 256) {
+      const int tt = e % no, rest = e / no, cp = rest % nc, ql = rest / nc;
+      const int kp = u.kq[(long long)k * Nk + u.q0 + qbase + ql];
+      psiS[(ql * nc + cp) * pstr + tt] = reinterpret_cast<const float2*>(u.psi)[((long long)kp * u.nbnd + u.nv + cp) * no + tt];
+    }
+  }
+  // outputs of one column half: thread -> column tid % 64, conduction bands c' = tid / 64 + 4 i
+  const int col = tid & 63, cg = tid >> 6;
+  for (int h = 0; h < 2; ++h) {
+    if (wn == h) {
+#pragma unroll
+      for (int i = 0; i < TMW; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int row = wm * TMW * 32 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            const int cl = j * 32 + (lane & 31);
+            Us[row * HN + cl] = make_float2(accR[i][j][r], accI[i][j][r]);
+          }
+    }
+    lds_wait_barrier();
+    const int gcol = h * HN + col;
+    if (gcol < ncol) {
+      const int ql = gcol / nv2, r = gcol % nv2;
+      const int qi = qbase + ql;
+      const int kp = u.kq[(long long)k * Nk + u.q0 + qi];
+      for (int cp0 = cg; cp0 < nc; cp0 += 8) {
+        // two conduction bands per pass: cp0 and cp0 + 4
+        const int cp1 = cp0 + 4;
+        const bool two = cp1 < nc;
+        float s0r = 0.f, s0i = 0.f, s1r = 0.f, s1i = 0.f;
+        if (stage_psi) {
+          const float2* p0 = psiS + (ql * nc + cp0) * pstr;
+          const float2* p1 = psiS + (ql * nc + (two ? cp1 : cp0)) * pstr;
+          for (int tt = 0; tt < no; ++tt) {
+            const float2 uv = Us[tt * HN + col];
+            const float2 a0 = p0[tt], a1 = p1[tt];
+            s0r += a0.x * uv.x - a0.y * uv.y;
+            s0i += a0.x * uv.y + a0.y * uv.x;
+            s1r += a1.x * uv.x - a1.y * uv.y;
+            s1i += a1.x * uv.y + a1.y * uv.x;
+          }
+        } else {
+          const float2* p0 = reinterpret_cast<const float2*>(u.psi) + ((long long)kp * u.nbnd + u.nv + cp0) * no;
+          const float2* p1 = reinterpret_cast<const float2*>(u.psi) + ((long long)kp * u.nbnd + u.nv + (two ? cp1 : cp0)) * no;
+          for (int tt = 0; tt < no; ++tt) {
+            const float2 uv = Us[tt * HN + col];
+            const float2 a0 = p0[tt], a1 = p1[tt];
+            s0r += a0.x * uv.x - a0.y * uv.y;
+            s0i += a0.x * uv.y + a0.y * uv.x;
+            s1r += a1.x * uv.x - a1.y * uv.y;
+            s1i += a1.x * uv.y + a1.y * uv.x;
+          }
+        }
+        const long long ob = (((long long)qi * Nk + k) * nc * nc + c) * nv2 + r;
+        float* o0 = u.T + 2 * (ob + (long long)cp0 * nc * nv2);
+        o0[0] = s0r;
+        o0[1] = s0i;
+        if (two) {
+          float* o1 = u.T + 2 * (ob + (long long)cp1 * nc * nv2);
+          o1[0] = s1r;
+          o1[1] = s1i;
+        }
+      }
+    }
+    lds_wait_barrier();
+  }
+}
+
 }  // namespace
 
 bse_status direct_u_b3(Plan* p, int q0, int nq, hipStream_t st) {
@@ -191,6 +381,16 @@ bse_status direct_u_b3(Plan* p, int q0, int nq, hipStream_t st) {
   u.kq = p->kq;
   u.T = (float*)p->T;
   const dim3 grid((unsigned)((long long)((nq + u.qg - 1) / u.qg) * d.nc * p->Nk));
+  const bool dma = d.n_aux % 16 == 0 && u.ps_BcT % 8 == 0 && u.ps_P % 8 == 0 &&
+                   (reinterpret_cast<uintptr_t>(u.BcT) & 15) == 0 && (reinterpret_cast<uintptr_t>(u.P) & 15) == 0;
+  if (dma) {
+    if (d.n_ao <= 64)
+      hipLaunchKernelGGL(u_direct_b3_dma<1>, grid, dim3(256), 0, st, u);
+    else
+      hipLaunchKernelGGL(u_direct_b3_dma<2>, grid, dim3(256), 0, st, u);
+    BSE_CHECK_LAUNCH();
+    return BSE_OK;
+  }
   if (d.n_ao <= 64)
     hipLaunchKernelGGL(u_direct_b3<1>, grid, dim3(256), 0, st, u);
   else

@@ -592,6 +592,194 @@ __global__ __launch_bounds__(256) void cgemm_b3_big(GemmArgs g) {
   }
 }
 
+// ----------------------------------------------------------------------------
+// BF16X3 with both operands pre-split: direct-to-LDS staging
+//
+// Same tile (128 x 128 complex, K step 16, 4 waves of 2 x 2 32x32 tiles) and the
+// same per-accumulator MFMA order as cgemm_b3_big, so results are identical.
+// Operands go from global memory straight into LDS with global_load_lds_dwordx4
+// (no register staging): wave w fills rows 32w .. 32w+31 of every plane, one
+// 16-byte k chunk per lane, and the two chunks of a row are XOR-swizzled by bit 3
+// of the row so the ds_read_b128 fragment loads are free of bank conflicts.  Two
+// LDS stages; the loads of stage kt+1 are in flight while stage kt is multiplied.
+// A split C is staged through LDS and written with 16-byte stores.
+// ----------------------------------------------------------------------------
+
+// wait until at most N vector-memory ops of this wave are outstanding and its LDS
+// ops are done, then barrier
+template <int N>
+__device__ __forceinline__ void vm_lds_barrier() {
+  asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
+template <int CJA, int CJB, bool CS, typename TC>
+__global__ __launch_bounds__(256) void cgemm_b3_dma(GemmArgs g) {
+  constexpr int BM = 128, BN = 128, BK = 16, NS = 2;
+  constexpr int PL = BM * BK;    // bf16 per plane per operand per stage
+  constexpr int STAGE = 8 * PL;  // A planes 0..3, B planes 4..7
+  __shared__ __attribute__((aligned(1024))) __bf16 smem[NS * STAGE];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int nK = g.K / BK;
+  const int gxn = (g.N + BN - 1) / BN, gyn = (g.M + BM - 1) / BM;
+  const long long per_batch = (long long)gxn * gyn;
+  long long bl, t;
+  xcd_map(blockIdx.x, per_batch, g.batch, bl, t);
+  const int b = (int)bl;
+  const int m0 = (int)(t / gxn) * BM, n0 = (int)(t % gxn) * BN;
+  // this lane's DMA slot: row 32*wave + lane/2, stored chunk position lane%2 holds k chunk
+  // (lane%2) ^ ((row >> 3) & 1).  Rows past the matrix edge re-load a valid row: those
+  // products only reach output rows / columns that are never stored.
+  const int drow = 32 * wave + (lane >> 1);
+  const int dch = (lane & 1) ^ ((drow >> 3) & 1);
+  const int arow = (m0 + drow < g.M) ? m0 + drow : m0;
+  const int bcol = (n0 + drow < g.N) ? n0 + drow : n0;
+  const __bf16* ga = (const __bf16*)g.A + off_of(g.a_tab, g.a_tab_pb, g.a_sb, g.a_si, b, g.M, arow) + 8 * dch;
+  const __bf16* gb = (const __bf16*)g.B + off_of(g.b_tab, g.b_tab_pb, g.b_sb, g.b_sj, b, g.N, bcol) + 8 * dch;
+  auto issue = [&](int kt) {
+    __bf16* st = smem + (kt % NS) * STAGE + 32 * wave * BK;
+    const int kb = kt * BK;
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) {
+      __builtin_amdgcn_global_load_lds((const void*)(ga + pl * g.a_ps + kb),
+                                       (__attribute__((address_space(3))) void*)(st + pl * PL), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void*)(gb + pl * g.b_ps + kb),
+                                       (__attribute__((address_space(3))) void*)(st + (4 + pl) * PL), 16, 0, 0);
+    }
+  };
+  f16v accR[2][2], accI[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        accR[i][j][r] = 0.f;
+        accI[i][j][r] = 0.f;
+      }
+  issue(0);
+  const int ch = lane >> 5;
+  for (int kt = 0; kt < nK; ++kt) {
+    // stage kt has landed once only the 8 loads of stage kt+1 (if issued) may be outstanding; the
+    // barrier also guarantees that every wave has finished reading stage kt-1, whose buffer is refilled next
+    vm_lds_barrier<0>();
+    if (kt + 1 < nK) issue(kt + 1);
+    const __bf16* sa = smem + (kt % NS) * STAGE;
+    const __bf16* sb = sa + 4 * PL;
+    bf8v a[2][4], bb[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int row = wm * 64 + i * 32 + (lane & 31);
+      const int o = row * BK + 8 * (ch ^ ((row >> 3) & 1));
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) a[i][pl] = *reinterpret_cast<const bf8v*>(sa + pl * PL + o);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = wn * 64 + j * 32 + (lane & 31);
+      const int o = col * BK + 8 * (ch ^ ((col >> 3) & 1));
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) bb[j][pl] = *reinterpret_cast<const bf8v*>(sb + pl * PL + o);
+      if (CJB) {
+        bb[j][2] = neg8(bb[j][2]);
+        bb[j][3] = neg8(bb[j][3]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      // Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br, with Ai -> -Ai for conj(A); rh/rl carry the sign of
+      // Im A in the real part, ih/il in the imaginary part
+      const bf8v nih = neg8(a[i][2]), nil = neg8(a[i][3]);
+      const bf8v rh = CJA ? a[i][2] : nih, rl = CJA ? a[i][3] : nil;
+      const bf8v ih = CJA ? nih : a[i][2], il = CJA ? nil : a[i][3];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        f16v& cr = accR[i][j];
+        f16v& ci = accI[i][j];
+        cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], bb[j][0], cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], bb[j][2], ci, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], bb[j][1], cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], bb[j][3], ci, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rl, bb[j][2], cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(il, bb[j][0], ci, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rh, bb[j][3], cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ih, bb[j][1], ci, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], bb[j][0], cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], bb[j][2], ci, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rh, bb[j][2], cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ih, bb[j][0], ci, 0, 0, 0);
+      }
+    }
+  }
+  vm_lds_barrier<0>();  // all waves are done with the stages before the epilogue reuses LDS
+  if constexpr (CS) {
+    // one row half (64 rows) at a time through LDS as planes [4][64][128], then 16-byte stores
+    __bf16* sC = smem;
+    const float al = (float)g.alpha;
+    for (int h = 0; h < 2; ++h) {
+      if (wm == h) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const int row = i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+              const int col = wn * 64 + j * 32 + (lane & 31);
+              __bf16 hh, ll;
+              split_bf16(al * accR[i][j][r], hh, ll);
+              sC[(0 * 64 + row) * 128 + col] = hh;
+              sC[(1 * 64 + row) * 128 + col] = ll;
+              split_bf16(al * accI[i][j][r], hh, ll);
+              sC[(2 * 64 + row) * 128 + col] = hh;
+              sC[(3 * 64 + row) * 128 + col] = ll;
+            }
+      }
+      vm_lds_barrier<63>();
+#pragma unroll 4
+      for (int it = 0; it < 16; ++it) {
+        const int id = tid + 256 * it;
+        const int c8 = id & 15, row = (id >> 4) & 63, pl = id >> 10;
+        const int grow = m0 + h * 64 + row, gcol = n0 + c8 * 8;
+        if (grow < g.M && gcol < g.N) {
+          const long long ro = off_of(g.c_tab, g.c_tab_pb, g.c_sb, g.c_si, b, g.M, grow);
+          __bf16* o = (__bf16*)g.C + pl * g.c_ps + ro + gcol;
+          const bf8v v = *reinterpret_cast<const bf8v*>(&sC[(pl * 64 + row) * 128 + c8 * 8]);
+          if (gcol + 8 <= g.N && ((ro + gcol) & 7) == 0) {
+            *reinterpret_cast<bf8v*>(o) = v;
+          } else {
+            for (int e = 0; e < 8 && gcol + e < g.N; ++e) o[e] = v[e];
+          }
+        }
+      }
+      vm_lds_barrier<63>();
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (row >= g.M) continue;
+        const long long ro = off_of(g.c_tab, g.c_tab_pb, g.c_sb, g.c_si, b, g.M, row);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int col = n0 + wn * 64 + j * 32 + (lane & 31);
+          if (col >= g.N) continue;
+          TC* o = (TC*)g.C + 2 * (ro + (long long)col * g.c_sj);
+          double vr = g.alpha * (double)accR[i][j][r], vi = g.alpha * (double)accI[i][j][r];
+          if (g.beta) {
+            vr += (double)o[0];
+            vi += (double)o[1];
+          }
+          o[0] = (TC)vr;
+          o[1] = (TC)vi;
+        }
+      }
+    }
+  }
+}
+
 template <typename K>
 bse_status launch(K kern, const GemmArgs& g, int BM, int BN, hipStream_t st) {
   const long long gx = (g.N + BN - 1) / BN, gy = (g.M + BM - 1) / BM;
@@ -650,6 +838,33 @@ bse_status run_bf16(const GemmArgs& g, hipStream_t st) {
   }
 }
 
+// the direct-to-LDS kernel needs unit k stride, whole K steps and 16-byte aligned operand rows
+bool dma_ok(const GemmArgs& g) {
+  auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  if (g.a_sk != 1 || g.b_sk != 1 || g.K % 16 != 0) return false;
+  if (!al(g.A) || !al(g.B) || (g.a_ps & 7) || (g.b_ps & 7)) return false;
+  if (g.a_tab ? !g.tab_aligned : ((g.a_sb & 7) || (g.a_si & 7))) return false;
+  if (g.b_tab ? !g.tab_aligned : ((g.b_sb & 7) || (g.b_sj & 7))) return false;
+  const long long tiles = (long long)((g.N + 127) / 128) * ((g.M + 127) / 128) * g.batch;
+  return tiles < (1LL << 31);
+}
+
+template <bool CS, typename TC>
+bse_status launch_dma(const GemmArgs& g, hipStream_t st) {
+  const long long tiles = (long long)((g.N + 127) / 128) * ((g.M + 127) / 128) * g.batch;
+  const dim3 grid((unsigned)tiles), block(256);
+  if (g.conjA && g.conjB)
+    hipLaunchKernelGGL((cgemm_b3_dma<1, 1, CS, TC>), grid, block, 0, st, g);
+  else if (g.conjA)
+    hipLaunchKernelGGL((cgemm_b3_dma<1, 0, CS, TC>), grid, block, 0, st, g);
+  else if (g.conjB)
+    hipLaunchKernelGGL((cgemm_b3_dma<0, 1, CS, TC>), grid, block, 0, st, g);
+  else
+    hipLaunchKernelGGL((cgemm_b3_dma<0, 0, CS, TC>), grid, block, 0, st, g);
+  BSE_CHECK_LAUNCH();
+  return BSE_OK;
+}
+
 }  // namespace
 
 bse_status cgemm_split(const GemmArgs& g, bool a_split, bool b_split, bool c_split, bool out_f64, hipStream_t st) {
@@ -657,6 +872,10 @@ bse_status cgemm_split(const GemmArgs& g, bool a_split, bool b_split, bool c_spl
   if (g.K <= 0) {
     set_error("cgemm_split: K must be positive");
     return BSE_ESHAPE;
+  }
+  if (a_split && b_split && dma_ok(g)) {
+    if (c_split) return launch_dma<true, float>(g, st);
+    return out_f64 ? launch_dma<false, double>(g, st) : launch_dma<false, float>(g, st);
   }
 #define BSE_SPLIT_CASE(AS, BS, CS)                                                              \
   if (a_split == AS && b_split == BS && c_split == CS)                                           \
