@@ -110,7 +110,9 @@ def main():
         precision_mode(args.config if args.config != "mesh8_ao64" else "mesh12_ao96", args.haydock_steps or 10)
         return
     if args.mode == "gradients":
-        gradients_mode(args.config if args.config != "mesh8_ao64" else "mesh8_ao64_grad", args.haydock_steps or 100)
+        from synth import CONFIGS
+        gcfg = args.config if args.config != "mesh8_ao64" else "mesh8_ao64_grad"
+        gradients_mode(gcfg, args.haydock_steps or CONFIGS[gcfg]["haydock_steps"])
         return
 
     import torch

@@ -434,6 +434,7 @@ bse_status build_plan(Plan* p, const bse_dims* d, const double* eps_qp, const vo
     BSE_TRY(plan_alloc(p, (void**)&p->xt, 16 * (size_t)(p->xsplit + 1) * na * max_nb));
     BSE_TRY(plan_alloc(p, (void**)&p->xu, 16 * (size_t)na * max_nb));
   }
+  BSE_TRY(plan_alloc(p, (void**)&p->txp, 16 * (size_t)TX_CHUNKS * p->N * max_nb));
   return BSE_OK;
 }
 

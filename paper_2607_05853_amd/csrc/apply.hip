@@ -37,13 +37,14 @@ __global__ void tables_kernel(int Nk, int nq, int q0, int nv, int nc, int nbnd, 
   }
 }
 
-// Y[k][(c v)][b] += scale * sum_qi sum_{c'v'} T[qi][k][(c' c)][(v' v)] X[k'][(c' v')][b]
+// part[chunk][k][(c v)][b] = sum_{qi in chunk} sum_{c'v'} T[qi][k][(c' c)][(v' v)] X[k'][(c' v')][b],
+// k' = k + q0 + qi; block (k, chunk), chunks of qlen consecutive q
 template <typename TT>
-__global__ void direct_tx_kernel(int Nk, int nq, int q0, int nv, int nc, int nb, double scale,
+__global__ void direct_tx_kernel(int Nk, int nq, int q0, int nv, int nc, int nb, int qlen,
                                  const int* __restrict__ kq, const TT* __restrict__ T,
-                                 const double* __restrict__ X, double* __restrict__ Y) {
+                                 const double* __restrict__ X, double* __restrict__ part) {
   extern __shared__ double smem[];
-  const int k = blockIdx.x;
+  const int k = blockIdx.x, chunk = blockIdx.y;
   const int nt = nc * nv, nt2 = nt * nt;
   TT* Ts = reinterpret_cast<TT*>(smem);                       // [nt2] complex
   double* Xs = reinterpret_cast<double*>(Ts + 2 * (size_t)nt2);  // [nt*nb] complex
@@ -52,7 +53,8 @@ __global__ void direct_tx_kernel(int Nk, int nq, int q0, int nv, int nc, int nb,
   double accr[SLOTS], acci[SLOTS];
 #pragma unroll
   for (int r = 0; r < SLOTS; ++r) accr[r] = acci[r] = 0.0;
-  for (int qi = 0; qi < nq; ++qi) {
+  const int qa = chunk * qlen, qe = min(nq, qa + qlen);
+  for (int qi = qa; qi < qe; ++qi) {
     const int kp = kq[(long long)k * Nk + q0 + qi];
     const TT* Tg = T + 2 * ((long long)qi * Nk + k) * nt2;
     const double* Xg = X + 2 * (long long)kp * nt * nb;
@@ -85,9 +87,23 @@ __global__ void direct_tx_kernel(int Nk, int nq, int q0, int nv, int nc, int nb,
   for (int r = 0; r < SLOTS; ++r) {
     const int o = threadIdx.x + r * blockDim.x;
     if (o >= nout) break;
-    double* y = Y + 2 * ((long long)k * nout + o);
-    y[0] += scale * accr[r];
-    y[1] += scale * acci[r];
+    double* y = part + 2 * (((long long)chunk * Nk + k) * nout + o);
+    y[0] = accr[r];
+    y[1] = acci[r];
+  }
+}
+
+// Y[i] += scale * sum_chunk part[chunk][i] (complex, n = N * nb), chunks added in order
+__global__ void tx_reduce(long long n, int nchunks, double scale, const double* __restrict__ part,
+                          double* __restrict__ Y) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    double sr = 0, si = 0;
+    for (int c = 0; c < nchunks; ++c) {
+      sr += part[2 * (c * n + i)];
+      si += part[2 * (c * n + i) + 1];
+    }
+    Y[2 * i] += scale * sr;
+    Y[2 * i + 1] += scale * si;
   }
 }
 
@@ -407,12 +423,20 @@ bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t
                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
         attr_set = true;
       }
+      // q chunks spread the pairs of one k over several blocks; partial sums are added in chunk order
+      const int nch = std::min(TX_CHUNKS, nq);
+      const int qlen = (nq + nch - 1) / nch;
+      const dim3 grid((unsigned)Nk, (unsigned)nch);
       if (f64)
-        hipLaunchKernelGGL(direct_tx_kernel<double>, dim3(Nk), dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, scale,
-                           p->kq, (const double*)p->T, X, Y);
+        hipLaunchKernelGGL(direct_tx_kernel<double>, grid, dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, qlen, p->kq,
+                           (const double*)p->T, X, p->txp);
       else
-        hipLaunchKernelGGL(direct_tx_kernel<float>, dim3(Nk), dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, scale,
-                           p->kq, (const float*)p->T, X, Y);
+        hipLaunchKernelGGL(direct_tx_kernel<float>, grid, dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, qlen, p->kq,
+                           (const float*)p->T, X, p->txp);
+      BSE_CHECK_LAUNCH();
+      const long long n = p->N * nb;
+      hipLaunchKernelGGL(tx_reduce, dim3((unsigned)std::min<long long>((n + 255) / 256, 65536)), dim3(256), 0, st, n,
+                         nch, scale, p->txp, Y);
       BSE_CHECK_LAUNCH();
     }
   }

@@ -101,6 +101,9 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// q chunks of the T.X stage (each block sums its chunk; a second pass adds the chunks in order)
+constexpr int TX_CHUNKS = 8;
+
 struct Plan {
   bse_dims d{};
   int Nk = 0, nt = 0, nbnd = 0;
@@ -142,6 +145,7 @@ struct Plan {
   double* xt = nullptr;       // c128 split-K partials [nsplit][n_aux][max_nb]
   double* xu = nullptr;       // c128 [n_aux][max_nb]
   int xsplit = 1;
+  double* txp = nullptr;      // c128 T.X partial sums [TX_CHUNKS][N][max_nb] (one per q chunk)
 
   // adjoint
   std::vector<int32_t> R;

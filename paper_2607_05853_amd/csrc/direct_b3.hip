@@ -177,8 +177,6 @@ __global__ __launch_bounds__(256) void u_direct_b3_dma(UArgs u) {
   constexpr int STAGE = 4 * (PA + PB);
   constexpr int RBA = BM / 32, RB = (BM + BN) / 32;  // 32-row blocks of A, of A and B together
   __shared__ __attribute__((aligned(1024))) __bf16 smem[2 * STAGE];
-  constexpr int PSI_LDS = 4096;  // complex elements
-  __shared__ float2 psiS[PSI_LDS];
   float2* Us = reinterpret_cast<float2*>(smem);  // epilogue: [BM][HN] (reuses the stages)
   static_assert(BM * HN * 8 <= 2 * STAGE * 2, "epilogue staging must fit in the stages");
 
@@ -278,20 +276,6 @@ __global__ __launch_bounds__(256) void u_direct_b3_dma(UArgs u) {
   vm_wait_barrier0();
 
   const int nc = u.nc;
-  // psi(k+q) of the conduction bands of this block's q group, staged once in LDS when it fits
-  // ([ql][c'][t], row stride no + 1 complex so the q groups of one wave fall in different banks)
-  const int nql = min(u.qg, u.nq - qbase);
-  const int pstr = no + 1;
-  const bool stage_psi = nql * nc * pstr <= PSI_LDS;
-  if (stage_psi) {
-    for (int e = tid; e < nql * nc * no; e += 256) {
-      const int tt = e % no, rest = e / no, cp = rest % nc, ql = rest / nc;
-      const int kp = u.kq[(long long)k * Nk + u.q0 + qbase + ql];
-      psiS[(ql * nc + cp) * pstr + tt] = reinterpret_cast<const float2*>(u.psi)[((long long)kp * u.nbnd + u.nv + cp) * no + tt];
-    }
-  }
-  // outputs of one column half: thread -> column tid % 64, conduction bands c' = tid / 64 + 4 i
-  const int col = tid & 63, cg = tid >> 6;
   for (int h = 0; h < 2; ++h) {
     if (wn == h) {
 #pragma unroll
@@ -301,54 +285,29 @@ __global__ __launch_bounds__(256) void u_direct_b3_dma(UArgs u) {
 #pragma unroll
           for (int r = 0; r < 16; ++r) {
             const int row = wm * TMW * 32 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            const int cl = j * 32 + (lane & 31);
-            Us[row * HN + cl] = make_float2(accR[i][j][r], accI[i][j][r]);
+            const int col = j * 32 + (lane & 31);
+            Us[row * HN + col] = make_float2(accR[i][j][r], accI[i][j][r]);
           }
     }
     lds_wait_barrier();
-    const int gcol = h * HN + col;
-    if (gcol < ncol) {
+    for (int o = tid; o < nc * HN; o += 256) {
+      const int col = o % HN, cp = o / HN;
+      const int gcol = h * HN + col;
+      if (gcol >= ncol) continue;
       const int ql = gcol / nv2, r = gcol % nv2;
       const int qi = qbase + ql;
       const int kp = u.kq[(long long)k * Nk + u.q0 + qi];
-      for (int cp0 = cg; cp0 < nc; cp0 += 8) {
-        // two conduction bands per pass: cp0 and cp0 + 4
-        const int cp1 = cp0 + 4;
-        const bool two = cp1 < nc;
-        float s0r = 0.f, s0i = 0.f, s1r = 0.f, s1i = 0.f;
-        if (stage_psi) {
-          const float2* p0 = psiS + (ql * nc + cp0) * pstr;
-          const float2* p1 = psiS + (ql * nc + (two ? cp1 : cp0)) * pstr;
-          for (int tt = 0; tt < no; ++tt) {
-            const float2 uv = Us[tt * HN + col];
-            const float2 a0 = p0[tt], a1 = p1[tt];
-            s0r += a0.x * uv.x - a0.y * uv.y;
-            s0i += a0.x * uv.y + a0.y * uv.x;
-            s1r += a1.x * uv.x - a1.y * uv.y;
-            s1i += a1.x * uv.y + a1.y * uv.x;
-          }
-        } else {
-          const float2* p0 = reinterpret_cast<const float2*>(u.psi) + ((long long)kp * u.nbnd + u.nv + cp0) * no;
-          const float2* p1 = reinterpret_cast<const float2*>(u.psi) + ((long long)kp * u.nbnd + u.nv + (two ? cp1 : cp0)) * no;
-          for (int tt = 0; tt < no; ++tt) {
-            const float2 uv = Us[tt * HN + col];
-            const float2 a0 = p0[tt], a1 = p1[tt];
-            s0r += a0.x * uv.x - a0.y * uv.y;
-            s0i += a0.x * uv.y + a0.y * uv.x;
-            s1r += a1.x * uv.x - a1.y * uv.y;
-            s1i += a1.x * uv.y + a1.y * uv.x;
-          }
-        }
-        const long long ob = (((long long)qi * Nk + k) * nc * nc + c) * nv2 + r;
-        float* o0 = u.T + 2 * (ob + (long long)cp0 * nc * nv2);
-        o0[0] = s0r;
-        o0[1] = s0i;
-        if (two) {
-          float* o1 = u.T + 2 * (ob + (long long)cp1 * nc * nv2);
-          o1[0] = s1r;
-          o1[1] = s1i;
-        }
+      const float* ps = u.psi + 2 * ((long long)kp * u.nbnd + u.nv + cp) * no;
+      float sr_ = 0.f, si_ = 0.f;
+      for (int tt = 0; tt < no; ++tt) {
+        const float2 uv = Us[tt * HN + col];
+        const float pr = ps[2 * tt], pi = ps[2 * tt + 1];
+        sr_ += pr * uv.x - pi * uv.y;
+        si_ += pr * uv.y + pi * uv.x;
       }
+      float* out = u.T + 2 * ((((long long)qi * Nk + k) * nc * nc + (long long)cp * nc + c) * nv2 + r);
+      out[0] = sr_;
+      out[1] = si_;
     }
     lds_wait_barrier();
   }
