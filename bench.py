@@ -268,6 +268,7 @@ def precision_mode(config, m):
         Y = plan.apply(X)
         torch.cuda.synchronize()
         ta = time.time() - t0
+        print("[precision] %s apply %.3f s" % (prec, ta), file=sys.stderr, flush=True)
         P = plan.velocity_start(T(p.vel), T(p.eps_ks, torch.float64), polarisations(nb))
         t0 = time.time()
         S = plan.haydock(P, m, omega, 0.1)["S"]
@@ -303,11 +304,13 @@ def gradients_mode(config, m):
         j = idx[tuple(-r)]
         if j < i:
             continue
-        A = rng.standard_normal(p.W_R.shape[1:]) * 1e-2
+        A = rng.standard_normal(p.W_R.shape[1:])
         if i == j:
             A = A + A.T
         dW[i], dW[j] = A, A.T
-    dW = dW.astype(complex)
+    # scale the direction so that h * dW is a 1e-6 relative change of W(R): the directional
+    # derivative is then well above the rounding noise of the difference quotient
+    dW = (dW * (np.abs(p.W_R).max() / np.abs(dW).max())).astype(complex)
     de = rng.standard_normal(p.eps_qp.shape)
 
     def build(W_R, eps):
@@ -322,22 +325,28 @@ def gradients_mode(config, m):
     eps = T(p.eps_qp, torch.float64).requires_grad_(True)
     plan = build(W_R.detach(), eps.detach())
     t0 = time.time()
+    om_all, _, _ = plan.lowest_excitons(n_block=nb, tol=1e-12, max_iter=500)
+    res["Omega2_minus_Omega1_eV"] = float(om_all[1] - om_all[0])
     om1 = AG.lowest_exciton_energy(plan, W_R, eps, n_block=nb, tol=1e-12, max_iter=500)
     om1.backward()
     torch.cuda.synchronize()
     res["lowest_s"] = time.time() - t0
+    print("[gradients] Omega_1 and its gradient: %.1f s" % res["lowest_s"], file=sys.stderr, flush=True)
     gW, ge = W_R.grad.detach().cpu().numpy(), eps.grad.detach().cpu().numpy()
 
     def om(Wr, e):
         pl = build(T(Wr), T(e, torch.float64))
-        o, _, _ = pl.lowest_excitons(n_block=nb, tol=1e-13, max_iter=800, allow_unconverged=True)
+        o, _, it = pl.lowest_excitons(n_block=nb, tol=1e-13, max_iter=800, allow_unconverged=True)
         pl.close()
+        print("[gradients] LOBPCG for finite differences: %d iterations" % it, file=sys.stderr, flush=True)
         return o[0]
 
     fdW = (om(p.W_R + h * dW, p.eps_qp) - om(p.W_R - h * dW, p.eps_qp)) / (2 * h)
     fde = (om(p.W_R, p.eps_qp + h * de) - om(p.W_R, p.eps_qp - h * de)) / (2 * h)
     anW, ane = float(np.real(np.vdot(gW, dW))), float(np.sum(ge * de))
     res["Omega1_eV"] = float(om1.item())
+    res["dOmega1_dW"] = {"adjoint": anW, "fd": fdW}
+    res["dOmega1_deps"] = {"adjoint": ane, "fd": fde}
     res["dOmega1_dW_fd_rel_err"] = abs(fdW - anW) / abs(anW)
     res["dOmega1_deps_fd_rel_err"] = abs(fde - ane) / abs(ane)
     print("[gradients] lowest %s" % json.dumps(res), file=sys.stderr, flush=True)
@@ -357,12 +366,15 @@ def gradients_mode(config, m):
         pl = build(T(Wr), T(e, torch.float64))
         s = pl.haydock(P, m, omega, eta)["S"]
         pl.close()
+        print("[gradients] Haydock for finite differences done", file=sys.stderr, flush=True)
         return float(np.sum(gamma * s))
 
     fdW = (spec(p.W_R + h * dW, p.eps_qp) - spec(p.W_R - h * dW, p.eps_qp)) / (2 * h)
     fde = (spec(p.W_R, p.eps_qp + h * de) - spec(p.W_R, p.eps_qp - h * de)) / (2 * h)
     anW = float(np.real(np.vdot(W_R2.grad.detach().cpu().numpy(), dW)))
     ane = float(np.sum(eps2.grad.detach().cpu().numpy() * de))
+    res["dS_dW"] = {"adjoint": anW, "fd": fdW}
+    res["dS_deps"] = {"adjoint": ane, "fd": fde}
     res["dS_dW_fd_rel_err"] = abs(fdW - anW) / abs(anW)
     res["dS_deps_fd_rel_err"] = abs(fde - ane) / abs(ane)
     print(json.dumps({"mode": "gradients", "workload": "%s: dense %s, N_ao=%d, nv=%d, nc=%d, N_aux=%d, BSE dim %d, "

@@ -145,16 +145,70 @@ def test_apply_ragged_and_triplet(B, prec):
     assert rel(H_(plan.apply(T(X[:, :1].copy()))), H @ X[:, :1]) < TOL[prec]
 
 
-def test_apply_c2_sampled_rows(B):
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
+def test_apply_c2_sampled_rows(B, prec):
+    # the timed workload (8x8x8 dense mesh, N_aux = 256, blocks of 8) in every precision, two k rows
+    # of the oracle's matrix-free apply (one row per q batch boundary region and one interior)
     p = make_problem("mesh8_ao64", 0, "G2")
-    plan, Wq = _plan(B, p, "f64", nb=8)
+    plan, Wq = _plan(B, p, prec, nb=8)
     X = random_block(p.N, 8, seed=5)
     Y = H_(plan.apply(T(X)))
-    rows = [0, 301]
+    rows = [0, 301, 511]
     ref = O.apply_H_rows(p, H_(Wq), X, rows)
     nt = p.nc * p.nv
     got = np.concatenate([Y[k * nt:(k + 1) * nt] for k in rows])
-    assert rel(got, ref) < TOL["f64"]
+    err = rel(got, ref)
+    print("[c2 sampled %s] rel err %.3e" % (prec, err), flush=True)
+    assert err < TOL[prec]
+
+
+# n_aux a multiple of 16 and n_ao a multiple of 8 select the direct-to-LDS kernels; n_ao = 80 > 64 takes
+# the 128-row conduction-side tile with ragged rows, nv = 5 gives 25 columns per q (5 q per column group)
+DMA = dict(cfg_id=94, coarse=(2, 2, 2), dense=(2, 2, 3), n_ao=80, nv=5, nc=3, n_aux=48)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
+def test_apply_dma_shapes(B, prec):
+    p = make_problem(DMA, 0, "G2", coarse=(3, 3, 2))
+    plan, Wq = _plan(B, p, prec, nb=4)
+    X = random_block(p.N, 4, seed=8)
+    H = O.build_H(p, H_(Wq))
+    err = rel(H_(plan.apply(T(X))), H @ X)
+    print("[dma shapes %s] rel err %.3e" % (prec, err), flush=True)
+    assert err < TOL[prec]
+
+
+def test_apply_c3_properties(B):
+    # 12x12x12 dense mesh, N_ao = 96, n_v = 6, n_c = 10, N_aux = 384 (BSE dim 103680): the oracle needs
+    # minutes per k row here, so this size is checked through properties that hold at any size:
+    # Hermiticity of the BF16x3 apply, agreement of BF16x3 with the FP64 path (itself pinned to the
+    # oracle at the smaller sizes), and the closed form of the zero kernel
+    p = make_problem("mesh12_ao96", 0, "G2")
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
+    X1 = T(random_block(p.N, 4, seed=11))
+    X2 = T(random_block(p.N, 4, seed=12))
+    planb = B.plan_from_problem(p, Wq, prec="bf16x3", max_nb=4)
+    Yb1, Yb2 = planb.apply(X1), planb.apply(X2)
+    lhs = torch.sum(torch.conj(X1) * Yb2).item()
+    rhs = torch.sum(torch.conj(Yb1) * X2).item()
+    herm = abs(lhs - rhs) / (torch.linalg.norm(Yb1).item() * torch.linalg.norm(X2).item())
+    planb.close()
+    planf = B.plan_from_problem(p, Wq, prec="f64", max_nb=4)
+    Yf1 = planf.apply(X1)
+    planf.close()
+    err = ((Yb1 - Yf1).abs().max() / Yf1.abs().max()).item()
+    print("[c3] bf16x3 vs f64 %.3e, hermiticity defect %.3e" % (err, herm), flush=True)
+    assert err < TOL["bf16x3"]
+    assert herm < TOL["bf16x3"]
+    # zero screened and bare interaction: H = diag(e_c - e_v) exactly
+    p0 = make_problem("mesh12_ao96", 0, "G2")
+    p0.Vbar = np.zeros_like(p0.Vbar)
+    Wz = torch.zeros_like(Wq)
+    planz = B.plan_from_problem(p0, Wz, prec="bf16x3", max_nb=4)
+    Yz = H_(planz.apply(X1))
+    planz.close()
+    te = O.transition_energies(p0).reshape(-1)
+    assert rel(Yz, te[:, None] * H_(X1)) < 1e-14
 
 
 def test_apply_hermitian_and_deterministic(B):
