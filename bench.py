@@ -341,8 +341,13 @@ def gradients_mode(config, m):
         print("[gradients] LOBPCG for finite differences: %d iterations" % it, file=sys.stderr, flush=True)
         return o[0]
 
-    fdW = (om(p.W_R + h * dW, p.eps_qp) - om(p.W_R - h * dW, p.eps_qp)) / (2 * h)
+    # Omega_1 depends on W only through the weak binding (its W derivative is ~1e-6 of its eps
+    # derivative here), so the W difference quotient takes a larger step to stay above the
+    # ~1e-15 relative rounding of the eigenvalue
+    hW = 1e-4
+    fdW = (om(p.W_R + hW * dW, p.eps_qp) - om(p.W_R - hW * dW, p.eps_qp)) / (2 * hW)
     fde = (om(p.W_R, p.eps_qp + h * de) - om(p.W_R, p.eps_qp - h * de)) / (2 * h)
+    res["fd_step_W_Omega1"] = hW
     anW, ane = float(np.real(np.vdot(gW, dW))), float(np.sum(ge * de))
     res["Omega1_eV"] = float(om1.item())
     res["dOmega1_dW"] = {"adjoint": anW, "fd": fdW}

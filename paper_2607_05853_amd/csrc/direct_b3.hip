@@ -28,7 +28,28 @@ struct UArgs {
   const float* psi;    // c64 [Nk][nbnd][no]
   const int* kq;       // [Nk][Nk]
   float* T;            // c64 [nq][Nk][nc*nc][nv*nv]
+  const __bf16* psis;  // planes [Nk][nbnd][no] (pre-split psi) for the matrix-core epilogue
+  long long ps_psi;
+  int mfma_epi;        // 1: contract t on the matrix cores (needs nv^2 <= 64 and n_ao % 8 == 0)
 };
+
+// one complex step of the BF16x3 product on 16x16x32 MFMA (no conjugation):
+//   cr += ar br - ai bi,  ci += ar bi + ai br   (each as hi*hi + hi*lo + lo*hi)
+__device__ __forceinline__ void cmma16_b3(const bf8v* a, const bf8v* b, f4v& cr, f4v& ci) {
+  const bf8v nih = neg8(a[2]), nil = neg8(a[3]);
+  cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], cr, 0, 0, 0);
+  ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[2], ci, 0, 0, 0);
+  cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1], cr, 0, 0, 0);
+  ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[3], ci, 0, 0, 0);
+  cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nil, b[2], cr, 0, 0, 0);
+  ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[3], b[0], ci, 0, 0, 0);
+  cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nih, b[3], cr, 0, 0, 0);
+  ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[1], ci, 0, 0, 0);
+  cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], cr, 0, 0, 0);
+  ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2], ci, 0, 0, 0);
+  cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nih, b[2], cr, 0, 0, 0);
+  ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0], ci, 0, 0, 0);
+}
 
 template <int TMW>
 __global__ __launch_bounds__(256) void u_direct_b3(UArgs u) {
@@ -171,7 +192,7 @@ __global__ __launch_bounds__(256) void u_direct_b3(UArgs u) {
 // Same computation with direct-to-LDS staging of both operands (global_load_lds_dwordx4,
 // two stages, XOR-swizzled 16-byte k chunks as in the split GEMM); needs N_aux % 16 == 0.
 template <int TMW>
-__global__ __launch_bounds__(256) void u_direct_b3_dma(UArgs u) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMW == 1 ? 2 : 1, TMW == 1 ? 2 : 1))) void u_direct_b3_dma(UArgs u) {
   constexpr int BM = 2 * TMW * 32, BN = 128, BK = 16, HN = 64;
   constexpr int PA = BM * BK, PB = BN * BK;  // bf16 per plane per stage
   constexpr int STAGE = 4 * (PA + PB);
@@ -276,6 +297,87 @@ __global__ __launch_bounds__(256) void u_direct_b3_dma(UArgs u) {
   vm_wait_barrier0();
 
   const int nc = u.nc;
+  if (u.mfma_epi) {
+    // T_q = Psi_q U_q for every q of the group, on 16x16x32 MFMA: U is split into bf16 planes in LDS,
+    // [plane][column][t] with row stride TPAD (zero for t >= n_ao), one pass per PW columns holding whole q
+    constexpr int PW = 64, TPAD = BM + 8, UPL = PW * TPAD;
+    __shared__ __attribute__((aligned(16))) __bf16 ubx[TMW == 2 ? 4 * UPL : 8];
+    __bf16* Ub = TMW == 2 ? ubx : smem;
+    const int qpp = PW / nv2;  // whole q per pass
+    const int nql = min(u.qg, u.nq - qbase);
+    const int NT = (nv2 + 15) / 16, MT = (nc + 15) / 16, KP = (no + 31) / 32 * 32;
+    for (int pq0 = 0; pq0 < nql; pq0 += qpp) {
+      const int qcount = min(qpp, nql - pq0);
+      const int pc0 = pq0 * nv2, pcn = qcount * nv2;  // tile columns [pc0, pc0 + pcn) in this pass
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int pc = wn * 64 + j * 32 + (lane & 31) - pc0;
+        if (pc < 0 || pc >= pcn) continue;
+#pragma unroll
+        for (int i = 0; i < TMW; ++i)
+#pragma unroll
+          for (int r4 = 0; r4 < 4; ++r4) {
+            const int t0 = wm * TMW * 32 + i * 32 + 8 * r4 + 4 * (lane >> 5);
+            typedef __bf16 bf4v __attribute__((ext_vector_type(4)));
+            bf4v rh, rl, ih, il;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const bool ok = t0 + e < no;
+              __bf16 hh, ll;
+              split_bf16(ok ? accR[i][j][4 * r4 + e] : 0.f, hh, ll);
+              rh[e] = hh;
+              rl[e] = ll;
+              split_bf16(ok ? accI[i][j][4 * r4 + e] : 0.f, hh, ll);
+              ih[e] = hh;
+              il[e] = ll;
+            }
+            __bf16* o = Ub + pc * TPAD + t0;
+            *reinterpret_cast<bf4v*>(o) = rh;
+            *reinterpret_cast<bf4v*>(o + UPL) = rl;
+            *reinterpret_cast<bf4v*>(o + 2 * UPL) = ih;
+            *reinterpret_cast<bf4v*>(o + 3 * UPL) = il;
+          }
+      }
+      lds_wait_barrier();
+      const int nunits = qcount * NT * MT;
+      for (int un = wave; un < nunits; un += 4) {
+        const int ql = un / (NT * MT), nt = (un / MT) % NT, mt = un % MT;
+        const int qi = qbase + pq0 + ql;
+        const int kp = u.kq[(long long)k * Nk + u.q0 + qi];
+        const int cpa = mt * 16 + (lane & 15);  // A row (conduction band c') of this lane
+        const int n = nt * 16 + (lane & 15);    // B column (v'v) of this lane
+        const int pcb = min(ql * nv2 + n, PW - 1);
+        const __bf16* pa = u.psis + ((long long)kp * u.nbnd + u.nv + (cpa < nc ? cpa : 0)) * no;
+        f4v cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
+        for (int kk = 0; kk < KP; kk += 32) {
+          const int t = kk + 8 * (lane >> 4);
+          bf8v af[4], bfr[4];
+#pragma unroll
+          for (int pl = 0; pl < 4; ++pl) {
+            if (cpa < nc && t < no)
+              af[pl] = *reinterpret_cast<const bf8v*>(pa + pl * u.ps_psi + t);
+            else
+              af[pl] = bf8v{};
+            bfr[pl] = *reinterpret_cast<const bf8v*>(Ub + pl * UPL + pcb * TPAD + t);
+          }
+          cmma16_b3(af, bfr, cr, ci);
+        }
+        // lane holds rows c' = 16 mt + 4 (lane / 16) + e, column n
+        if (n < nv2) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int cp = mt * 16 + 4 * (lane >> 4) + e;
+            if (cp >= nc) continue;
+            float* out = u.T + 2 * ((((long long)qi * Nk + k) * nc * nc + (long long)cp * nc + c) * nv2 + n);
+            out[0] = cr[e];
+            out[1] = ci[e];
+          }
+        }
+      }
+      lds_wait_barrier();
+    }
+    return;
+  }
   for (int h = 0; h < 2; ++h) {
     if (wn == h) {
 #pragma unroll
@@ -339,6 +441,10 @@ bse_status direct_u_b3(Plan* p, int q0, int nq, hipStream_t st) {
   u.psi = p->psi32;
   u.kq = p->kq;
   u.T = (float*)p->T;
+  u.psis = (const __bf16*)p->psi;
+  u.ps_psi = p->ps_psi;
+  u.mfma_epi = nv2 <= 64 && d.n_ao % 8 == 0 && p->ps_psi % 8 == 0 &&
+               (reinterpret_cast<uintptr_t>(p->psi) & 15) == 0;
   const dim3 grid((unsigned)((long long)((nq + u.qg - 1) / u.qg) * d.nc * p->Nk));
   const bool dma = d.n_aux % 16 == 0 && u.ps_BcT % 8 == 0 && u.ps_P % 8 == 0 &&
                    (reinterpret_cast<uintptr_t>(u.BcT) & 15) == 0 && (reinterpret_cast<uintptr_t>(u.P) & 15) == 0;

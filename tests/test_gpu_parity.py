@@ -162,19 +162,25 @@ def test_apply_c2_sampled_rows(B, prec):
     assert err < TOL[prec]
 
 
-# n_aux a multiple of 16 and n_ao a multiple of 8 select the direct-to-LDS kernels; n_ao = 80 > 64 takes
-# the 128-row conduction-side tile with ragged rows, nv = 5 gives 25 columns per q (5 q per column group)
+# n_aux a multiple of 16 selects the direct-to-LDS kernels.  DMA: n_ao = 80 > 64 takes the 128-row
+# conduction-side tile with ragged rows and the matrix-core epilogue, nv = 5 gives 25 columns per q (5 q
+# per column group, 2 q per epilogue pass).  DMA_MT: nc = 17 needs two 16-row tiles of conduction bands
+# in the matrix-core epilogue, nv = 2 puts 32 q in a column group.  DMA_ODD: n_ao = 20 (not a multiple
+# of 8) keeps the vector-unit epilogue and the register-staged valence pair-density GEMM
 DMA = dict(cfg_id=94, coarse=(2, 2, 2), dense=(2, 2, 3), n_ao=80, nv=5, nc=3, n_aux=48)
+DMA_MT = dict(cfg_id=95, coarse=(2, 2, 2), dense=(2, 3, 1), n_ao=40, nv=2, nc=17, n_aux=32)
+DMA_ODD = dict(cfg_id=98, coarse=(2, 2, 2), dense=(3, 1, 2), n_ao=20, nv=3, nc=4, n_aux=32)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
-def test_apply_dma_shapes(B, prec):
-    p = make_problem(DMA, 0, "G2", coarse=(3, 3, 2))
+@pytest.mark.parametrize("shape", ["DMA", "DMA_MT", "DMA_ODD"])
+def test_apply_dma_shapes(B, prec, shape):
+    p = make_problem({"DMA": DMA, "DMA_MT": DMA_MT, "DMA_ODD": DMA_ODD}[shape], 0, "G2", coarse=(3, 3, 2))
     plan, Wq = _plan(B, p, prec, nb=4)
     X = random_block(p.N, 4, seed=8)
     H = O.build_H(p, H_(Wq))
     err = rel(H_(plan.apply(T(X))), H @ X)
-    print("[dma shapes %s] rel err %.3e" % (prec, err), flush=True)
+    print("[dma shapes %s %s] rel err %.3e" % (shape, prec, err), flush=True)
     assert err < TOL[prec]
 
 
