@@ -39,17 +39,16 @@ __global__ void tables_kernel(int Nk, int nq, int q0, int nv, int nc, int nbnd, 
 
 // part[chunk][k][(c v)][b] = sum_{qi in chunk} sum_{c'v'} T[qi][k][(c' c)][(v' v)] X[k'][(c' v')][b],
 // k' = k + q0 + qi; block (k, chunk), chunks of qlen consecutive q
-template <typename TT>
-__global__ void direct_tx_kernel(int Nk, int nq, int q0, int nv, int nc, int nb, int qlen,
-                                 const int* __restrict__ kq, const TT* __restrict__ T,
-                                 const double* __restrict__ X, double* __restrict__ part) {
+template <typename TT, int SLOTS>
+__global__ __launch_bounds__(256) void direct_tx_kernel(int Nk, int nq, int q0, int nv, int nc, int nb, int qlen,
+                                                        const int* __restrict__ kq, const TT* __restrict__ T,
+                                                        const double* __restrict__ X, double* __restrict__ part) {
   extern __shared__ double smem[];
   const int k = blockIdx.x, chunk = blockIdx.y;
   const int nt = nc * nv, nt2 = nt * nt;
   TT* Ts = reinterpret_cast<TT*>(smem);                       // [nt2] complex
   double* Xs = reinterpret_cast<double*>(Ts + 2 * (size_t)nt2);  // [nt*nb] complex
-  const int nout = nt * nb;
-  constexpr int SLOTS = 8;  // outputs per thread: nt * nb <= 8 * 256
+  const int nout = nt * nb;  // SLOTS outputs per thread: nt * nb <= SLOTS * 256
   double accr[SLOTS], acci[SLOTS];
 #pragma unroll
   for (int r = 0; r < SLOTS; ++r) accr[r] = acci[r] = 0.0;
@@ -105,6 +104,35 @@ __global__ void tx_reduce(long long n, int nchunks, double scale, const double* 
     Y[2 * i] += scale * sr;
     Y[2 * i + 1] += scale * si;
   }
+}
+
+template <typename TT>
+bse_status tx_set_attributes() {
+  BSE_HIP(hipFuncSetAttribute((const void*)direct_tx_kernel<TT, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024));
+  BSE_HIP(hipFuncSetAttribute((const void*)direct_tx_kernel<TT, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024));
+  BSE_HIP(hipFuncSetAttribute((const void*)direct_tx_kernel<TT, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024));
+  BSE_HIP(hipFuncSetAttribute((const void*)direct_tx_kernel<TT, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024));
+  return BSE_OK;
+}
+
+// outputs per thread: the smallest of 1, 2, 4, 8 that covers nt * nb over 256 threads
+template <typename TT>
+bse_status launch_tx(int slots, dim3 grid, size_t sh, hipStream_t st, int Nk, int nq, int q0, int nv, int nc, int nb,
+                     int qlen, const int* kq, const TT* T, const double* X, double* part) {
+  if (slots <= 1)
+    hipLaunchKernelGGL((direct_tx_kernel<TT, 1>), grid, dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, qlen, kq, T, X, part);
+  else if (slots <= 2)
+    hipLaunchKernelGGL((direct_tx_kernel<TT, 2>), grid, dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, qlen, kq, T, X, part);
+  else if (slots <= 4)
+    hipLaunchKernelGGL((direct_tx_kernel<TT, 4>), grid, dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, qlen, kq, T, X, part);
+  else
+    hipLaunchKernelGGL((direct_tx_kernel<TT, 8>), grid, dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, qlen, kq, T, X, part);
+  BSE_CHECK_LAUNCH();
+  return BSE_OK;
 }
 
 __global__ void diag_kernel(long long N, int nv, int nc, int nb, const double* __restrict__ eps,
@@ -417,23 +445,21 @@ bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t
       const double scale = -1.0 / (double)Nk;
       static bool attr_set = false;
       if (!attr_set) {
-        BSE_HIP(hipFuncSetAttribute((const void*)direct_tx_kernel<double>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-        BSE_HIP(hipFuncSetAttribute((const void*)direct_tx_kernel<float>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        BSE_TRY(tx_set_attributes<double>());
+        BSE_TRY(tx_set_attributes<float>());
         attr_set = true;
       }
       // q chunks spread the pairs of one k over several blocks; partial sums are added in chunk order
       const int nch = std::min(TX_CHUNKS, nq);
       const int qlen = (nq + nch - 1) / nch;
       const dim3 grid((unsigned)Nk, (unsigned)nch);
+      const int slots = (nt * nb + 255) / 256;
       if (f64)
-        hipLaunchKernelGGL(direct_tx_kernel<double>, grid, dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, qlen, p->kq,
-                           (const double*)p->T, X, p->txp);
+        BSE_TRY(launch_tx<double>(slots, grid, sh, st, Nk, nq, q0, nv, nc, nb, qlen, p->kq, (const double*)p->T, X,
+                                  p->txp));
       else
-        hipLaunchKernelGGL(direct_tx_kernel<float>, grid, dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, qlen, p->kq,
-                           (const float*)p->T, X, p->txp);
-      BSE_CHECK_LAUNCH();
+        BSE_TRY(launch_tx<float>(slots, grid, sh, st, Nk, nq, q0, nv, nc, nb, qlen, p->kq, (const float*)p->T, X,
+                                 p->txp));
       const long long n = p->N * nb;
       hipLaunchKernelGGL(tx_reduce, dim3((unsigned)std::min<long long>((n + 255) / 256, 65536)), dim3(256), 0, st, n,
                          nch, scale, p->txp, Y);

@@ -102,7 +102,7 @@ struct DevBuf {
 };
 
 // q chunks of the T.X stage (each block sums its chunk; a second pass adds the chunks in order)
-constexpr int TX_CHUNKS = 8;
+constexpr int TX_CHUNKS = 16;
 
 struct Plan {
   bse_dims d{};
