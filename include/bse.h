@@ -62,6 +62,7 @@ typedef enum {
 typedef enum { BSE_F64 = 0, BSE_F32 = 1, BSE_BF16X3 = 2 } bse_prec;
 
 #define BSE_CHECK_HERMITIAN 1u   /* plan_create: verify C^mu and Vbar Hermitian */
+#define BSE_ALL_PAIRS 2u         /* plan_create: form every (k, k') block of the direct term */
 
 typedef struct {
     int32_t nk[3];       /* dense Gamma-centred mesh n1, n2, n3 (Sec. IV.A.3)                */
@@ -111,7 +112,15 @@ bse_status bse_interpolate_W_adjoint(int32_t n_aux, int32_t n_R, const int32_t* 
  * Vbar    device c128 [n_aux][n_aux]  (V_munu(0) of Sec. III.A)
  * W_q     device c128 [Nk][n_aux][n_aux], q = dense-mesh index
  * prec    arithmetic of the direct term; max_nb the largest block size later used
- * flags   BSE_CHECK_HERMITIAN (synchronises the stream)
+ * flags   BSE_CHECK_HERMITIAN (synchronises the stream), BSE_ALL_PAIRS
+ * Pair symmetry: with Hermitian C^mu the direct block of Eq. (Hamiltonian)
+ * obeys D(k, k-q) = D(k-q, k)^dagger as soon as W_q(-q) = conj W_q(q)
+ * elementwise (true for any real W(R) interpolated with Sec. III.B).  Plan
+ * creation tests that relation on the given W_q (to 1e-12 of max |W_q|); when
+ * it holds, bse_apply forms the blocks of one q of each pair {q, -q} (and of
+ * the q equal to their own negative) and takes the others from the relation,
+ * about half of the direct-term work.  BSE_ALL_PAIRS forms every block.
+ * bse_plan_pairs reports which mode a plan uses.
  * On success *out receives the plan (destroy with bse_plan_destroy).
  * ------------------------------------------------------------------------- */
 bse_status bse_plan_create(const bse_dims* d, const double* eps_qp, const void* psi,
@@ -126,6 +135,11 @@ bse_status bse_plan_set_R(bse_plan* plan, int32_t n_R, const int32_t* R, const d
 
 /* Replace the quasiparticle energies (device f64 [Nk][nv+nc]) of a plan. */
 bse_status bse_plan_set_eps(bse_plan* plan, const double* eps_qp, void* hip_stream);
+
+/* Number of q (dense-mesh differences k' - k) whose direct blocks bse_apply
+ * forms (*formed) out of *total = N_k: N_k with BSE_ALL_PAIRS or when the
+ * pair symmetry does not hold, about N_k / 2 otherwise.  Host pointers. */
+bse_status bse_plan_pairs(const bse_plan* plan, int64_t* formed, int64_t* total);
 
 /* Device bytes held by the plan (copies, halves and workspaces). */
 bse_status bse_plan_bytes(const bse_plan* plan, uint64_t* bytes);

@@ -243,8 +243,42 @@ void destroy_plan(Plan* p) {
   p->owned.clear();
 }
 
+// max |W[-q] - conj W[q]| and max |W| over all q and elements (non-negative doubles compared as
+// their bit patterns)
+__global__ void w_pair_check(long long per_q, int Nk, const int* __restrict__ neg, const double* __restrict__ W,
+                             unsigned long long* __restrict__ out) {
+  double dmax = 0.0, wmax = 0.0;
+  const long long n = per_q * Nk;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const long long q = i / per_q, e = i % per_q;
+    const double2 a = reinterpret_cast<const double2*>(W)[i];
+    const double2 b = reinterpret_cast<const double2*>(W)[(long long)neg[q] * per_q + e];
+    dmax = fmax(dmax, fmax(fabs(b.x - a.x), fabs(b.y + a.y)));
+    wmax = fmax(wmax, fmax(fabs(a.x), fabs(a.y)));
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    dmax = fmax(dmax, __shfl_down(dmax, o));
+    wmax = fmax(wmax, __shfl_down(wmax, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(&out[0], (unsigned long long)__double_as_longlong(dmax));
+    atomicMax(&out[1], (unsigned long long)__double_as_longlong(wmax));
+  }
+}
+
+// out block j = in block order[j] for each of nplanes planes (blocks of blk 2-byte units)
+__global__ void permute_blocks(const unsigned short* __restrict__ in, unsigned short* __restrict__ out,
+                               const int* __restrict__ order, int nblk, long long blk, int nplanes, long long plane) {
+  const long long n = (long long)nblk * blk * nplanes;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const long long pl = i / ((long long)nblk * blk), r = i % ((long long)nblk * blk);
+    const long long j = r / blk, e = r % blk;
+    out[pl * plane + j * blk + e] = in[pl * plane + (long long)order[j] * blk + e];
+  }
+}
+
 bse_status build_plan(Plan* p, const bse_dims* d, const double* eps_qp, const void* psi, const void* C,
-                      const void* Vbar, const void* W_q, bse_prec prec, int max_nb, hipStream_t st) {
+                      const void* Vbar, const void* W_q, bse_prec prec, int max_nb, uint32_t flags, hipStream_t st) {
   p->d = *d;
   p->Nk = d->nk[0] * d->nk[1] * d->nk[2];
   p->nbnd = d->nv + d->nc;
@@ -386,9 +420,9 @@ bse_status build_plan(Plan* p, const bse_dims* d, const double* eps_qp, const vo
   dfree(colt);
   if (s != BSE_OK) return s;
 
-  // k + q table
+  // k + q table, and the q order of the pair symmetry
   {
-    std::vector<int> h((size_t)Nk * Nk);
+    std::vector<int> h((size_t)Nk * Nk), neg(Nk);
     const int n1 = d->nk[0], n2 = d->nk[1], n3 = d->nk[2];
     for (int k = 0; k < Nk; ++k) {
       const int a1 = k / (n2 * n3), a2 = (k / n3) % n2, a3 = k % n3;
@@ -396,9 +430,81 @@ bse_status build_plan(Plan* p, const bse_dims* d, const double* eps_qp, const vo
         const int b1 = q / (n2 * n3), b2 = (q / n3) % n2, b3 = q % n3;
         h[(size_t)k * Nk + q] = (((a1 + b1) % n1) * n2 + (a2 + b2) % n2) * n3 + (a3 + b3) % n3;
       }
+      neg[k] = (((n1 - a1) % n1) * n2 + (n2 - a2) % n2) * n3 + (n3 - a3) % n3;
     }
     BSE_TRY(plan_alloc(p, (void**)&p->kq, sizeof(int) * h.size()));
     BSE_HIP(hipMemcpyAsync(p->kq, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice, st));
+    // self-conjugate q (q = -q on the mesh) first, then the smaller index of each pair, then partners
+    std::vector<int> order;
+    order.reserve(Nk);
+    for (int q = 0; q < Nk; ++q)
+      if (neg[q] == q) order.push_back(q);
+    const int nself = (int)order.size();
+    for (int q = 0; q < Nk; ++q)
+      if (q < neg[q]) order.push_back(q);
+    const int nhalf = (int)order.size();
+    for (int j = nself; j < nhalf; ++j) order.push_back(neg[order[j]]);
+    bool use = !(flags & BSE_ALL_PAIRS) && nhalf < Nk;
+    if (use) {
+      // W_q(-q) = conj W_q(q) elementwise, to 1e-12 of the largest element
+      int* dneg = nullptr;
+      unsigned long long* dout = nullptr;
+      BSE_TRY(dmalloc((void**)&dneg, sizeof(int) * Nk));
+      bse_status s = dmalloc((void**)&dout, 16);
+      unsigned long long hout[2] = {0, 0};
+      if (s == BSE_OK) {
+        (void)hipMemcpyAsync(dneg, neg.data(), sizeof(int) * Nk, hipMemcpyHostToDevice, st);
+        (void)hipMemsetAsync(dout, 0, 16, st);
+        hipLaunchKernelGGL(w_pair_check, dim3(1024), dim3(256), 0, st, (long long)na * na, Nk, dneg,
+                           (const double*)W_q, dout);
+        (void)hipMemcpyAsync(hout, dout, 16, hipMemcpyDeviceToHost, st);
+        if (hipStreamSynchronize(st) != hipSuccess) s = BSE_EDEVICE;
+      }
+      dfree(dneg);
+      dfree(dout);
+      BSE_TRY(s);
+      double dmax, wmax;
+      std::memcpy(&dmax, &hout[0], 8);
+      std::memcpy(&wmax, &hout[1], 8);
+      use = dmax <= 1e-12 * wmax;
+    }
+    if (use) {
+      std::vector<int> hp((size_t)Nk * Nk), hm((size_t)Nk * Nk);
+      for (int k = 0; k < Nk; ++k)
+        for (int j = 0; j < Nk; ++j) {
+          hp[(size_t)k * Nk + j] = h[(size_t)k * Nk + order[j]];
+          hm[(size_t)k * Nk + j] = h[(size_t)k * Nk + neg[order[j]]];
+        }
+      BSE_TRY(plan_alloc(p, (void**)&p->kqp, sizeof(int) * hp.size()));
+      BSE_TRY(plan_alloc(p, (void**)&p->kqm, sizeof(int) * hm.size()));
+      BSE_HIP(hipMemcpyAsync(p->kqp, hp.data(), sizeof(int) * hp.size(), hipMemcpyHostToDevice, st));
+      BSE_HIP(hipMemcpyAsync(p->kqm, hm.data(), sizeof(int) * hm.size(), hipMemcpyHostToDevice, st));
+      // the W step reads W(q) in this order: permute the plan's copy once
+      int* dorder = nullptr;
+      void* tmp = nullptr;
+      BSE_TRY(dmalloc((void**)&dorder, sizeof(int) * Nk));
+      const size_t wbytes = (p->split ? 8 : (size_t)p->esz) * (size_t)nw;
+      bse_status s = dmalloc(&tmp, wbytes);
+      if (s == BSE_OK) {
+        (void)hipMemcpyAsync(dorder, order.data(), sizeof(int) * Nk, hipMemcpyHostToDevice, st);
+        (void)hipMemcpyAsync(tmp, p->Wq, wbytes, hipMemcpyDeviceToDevice, st);
+        // bf16 planes: 4 planes of Nk blocks of na^2 * 2 bytes; complex: one plane of na^2 * esz bytes
+        const int nplanes = p->split ? 4 : 1;
+        const long long blk = (long long)na * na * (p->split ? 2 : p->esz) / 2;
+        hipLaunchKernelGGL(permute_blocks, dim3(4096), dim3(256), 0, st, (const unsigned short*)tmp,
+                           (unsigned short*)p->Wq, dorder, Nk, blk, nplanes, blk * Nk);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+          set_error("pair symmetry: permuting W(q) failed");
+          s = BSE_EDEVICE;
+        }
+      }
+      dfree(dorder);
+      dfree(tmp);
+      BSE_TRY(s);
+      p->herm_half = 1;
+      p->nself = nself;
+      p->nhalf = nhalf;
+    }
     BSE_HIP(hipStreamSynchronize(st));
   }
 
@@ -534,7 +640,7 @@ bse_status bse_plan_create(const bse_dims* d, const double* eps_qp, const void* 
       return BSE_ESHAPE;
     }
   }
-  if (flags & ~BSE_CHECK_HERMITIAN) {
+  if (flags & ~(BSE_CHECK_HERMITIAN | BSE_ALL_PAIRS)) {
     set_error("bse_plan_create: unknown flags");
     return BSE_EINVAL;
   }
@@ -544,13 +650,24 @@ bse_status bse_plan_create(const bse_dims* d, const double* eps_qp, const void* 
     set_error("bse_plan_create: host allocation failed");
     return BSE_ENOMEM;
   }
-  bse_status s = build_plan(&h->impl, d, eps_qp, psi, C, Vbar, W_q, prec, max_nb, S(hip_stream));
+  bse_status s = build_plan(&h->impl, d, eps_qp, psi, C, Vbar, W_q, prec, max_nb, flags, S(hip_stream));
   if (s != BSE_OK) {
     destroy_plan(&h->impl);
     delete h;
     return s;
   }
   *out = h;
+  return BSE_OK;
+}
+
+bse_status bse_plan_pairs(const bse_plan* plan, int64_t* formed, int64_t* total) {
+  if (!plan || bad_ptr(formed) || bad_ptr(total)) {
+    set_error("bse_plan_pairs: NULL argument");
+    return BSE_EINVAL;
+  }
+  const Plan& p = plan->impl;
+  *formed = p.herm_half ? p.nhalf : p.Nk;
+  *total = p.Nk;
   return BSE_OK;
 }
 

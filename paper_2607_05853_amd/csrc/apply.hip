@@ -38,10 +38,13 @@ __global__ void tables_kernel(int Nk, int nq, int q0, int nv, int nc, int nbnd, 
 }
 
 // part[chunk][k][(c v)][b] = sum_{qi in chunk} sum_{c'v'} T[qi][k][(c' c)][(v' v)] X[k'][(c' v')][b],
-// k' = k + q0 + qi; block (k, chunk), chunks of qlen consecutive q
+// k' = k + q_j with j = q0 + qi in the order of kqp (block (k, chunk), chunks of qlen consecutive q).
+// For j >= nself the partner block is added too: D(k, k - q) = D(k - q, k)^dagger, i.e.
+//   part += sum_{c'v'} conj(T[qi][k''][(c c')][(v v')]) X[k''][(c' v')][b],   k'' = kqm[k][j] = k - q_j.
 template <typename TT, int SLOTS>
 __global__ __launch_bounds__(256) void direct_tx_kernel(int Nk, int nq, int q0, int nv, int nc, int nb, int qlen,
-                                                        const int* __restrict__ kq, const TT* __restrict__ T,
+                                                        const int* __restrict__ kqp, const int* __restrict__ kqm,
+                                                        int nself, const TT* __restrict__ T,
                                                         const double* __restrict__ X, double* __restrict__ part) {
   extern __shared__ double smem[];
   const int k = blockIdx.x, chunk = blockIdx.y;
@@ -54,32 +57,47 @@ __global__ __launch_bounds__(256) void direct_tx_kernel(int Nk, int nq, int q0, 
   for (int r = 0; r < SLOTS; ++r) accr[r] = acci[r] = 0.0;
   const int qa = chunk * qlen, qe = min(nq, qa + qlen);
   for (int qi = qa; qi < qe; ++qi) {
-    const int kp = kq[(long long)k * Nk + q0 + qi];
-    const TT* Tg = T + 2 * ((long long)qi * Nk + k) * nt2;
-    const double* Xg = X + 2 * (long long)kp * nt * nb;
-    __syncthreads();
-    for (int i = threadIdx.x; i < 2 * nt2; i += blockDim.x) Ts[i] = Tg[i];
-    for (int i = threadIdx.x; i < 2 * nout; i += blockDim.x) Xs[i] = Xg[i];
-    __syncthreads();
+    const int j = q0 + qi;
+    const int npass = j >= nself ? 2 : 1;
+    for (int pass = 0; pass < npass; ++pass) {
+      const int kb = pass == 0 ? k : kqm[(long long)k * Nk + j];   // block row of the stored T
+      const int kx = pass == 0 ? kqp[(long long)k * Nk + j] : kb;  // k-point of the X slice
+      const TT* Tg = T + 2 * ((long long)qi * Nk + kb) * nt2;
+      const double* Xg = X + 2 * (long long)kx * nt * nb;
+      __syncthreads();
+      for (int i = threadIdx.x; i < 2 * nt2; i += blockDim.x) Ts[i] = Tg[i];
+      for (int i = threadIdx.x; i < 2 * nout; i += blockDim.x) Xs[i] = Xg[i];
+      __syncthreads();
 #pragma unroll
-    for (int r = 0; r < SLOTS; ++r) {
-      const int o = threadIdx.x + r * blockDim.x;
-      if (o >= nout) break;
-      const int cv = o / nb, b = o % nb;
-      const int c = cv / nv, v = cv % nv;
-      double sr = 0, si = 0;
-      for (int cp = 0; cp < nc; ++cp) {
-        const TT* trow = Ts + 2 * ((cp * nc + c) * (nv * nv) + v);
-        const double* xrow = Xs + 2 * ((cp * nv) * nb + b);
-        for (int vp = 0; vp < nv; ++vp) {
-          const double tr = (double)trow[2 * vp * nv], ti = (double)trow[2 * vp * nv + 1];
-          const double xr = xrow[2 * vp * nb], xi = xrow[2 * vp * nb + 1];
-          sr += tr * xr - ti * xi;
-          si += tr * xi + ti * xr;
+      for (int r = 0; r < SLOTS; ++r) {
+        const int o = threadIdx.x + r * blockDim.x;
+        if (o >= nout) break;
+        const int cv = o / nb, b = o % nb;
+        const int c = cv / nv, v = cv % nv;
+        double sr = 0, si = 0;
+        for (int cp = 0; cp < nc; ++cp) {
+          const double* xrow = Xs + 2 * ((cp * nv) * nb + b);
+          if (pass == 0) {
+            const TT* trow = Ts + 2 * ((cp * nc + c) * (nv * nv) + v);
+            for (int vp = 0; vp < nv; ++vp) {
+              const double tr = (double)trow[2 * vp * nv], ti = (double)trow[2 * vp * nv + 1];
+              const double xr = xrow[2 * vp * nb], xi = xrow[2 * vp * nb + 1];
+              sr += tr * xr - ti * xi;
+              si += tr * xi + ti * xr;
+            }
+          } else {
+            const TT* trow = Ts + 2 * ((c * nc + cp) * (nv * nv) + v * nv);
+            for (int vp = 0; vp < nv; ++vp) {
+              const double tr = (double)trow[2 * vp], ti = -(double)trow[2 * vp + 1];
+              const double xr = xrow[2 * vp * nb], xi = xrow[2 * vp * nb + 1];
+              sr += tr * xr - ti * xi;
+              si += tr * xi + ti * xr;
+            }
+          }
         }
+        accr[r] += sr;
+        acci[r] += si;
       }
-      accr[r] += sr;
-      acci[r] += si;
     }
   }
 #pragma unroll
@@ -122,15 +140,19 @@ bse_status tx_set_attributes() {
 // outputs per thread: the smallest of 1, 2, 4, 8 that covers nt * nb over 256 threads
 template <typename TT>
 bse_status launch_tx(int slots, dim3 grid, size_t sh, hipStream_t st, int Nk, int nq, int q0, int nv, int nc, int nb,
-                     int qlen, const int* kq, const TT* T, const double* X, double* part) {
+                     int qlen, const int* kqp, const int* kqm, int nself, const TT* T, const double* X, double* part) {
   if (slots <= 1)
-    hipLaunchKernelGGL((direct_tx_kernel<TT, 1>), grid, dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, qlen, kq, T, X, part);
+    hipLaunchKernelGGL((direct_tx_kernel<TT, 1>), grid, dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, qlen, kqp, kqm,
+                       nself, T, X, part);
   else if (slots <= 2)
-    hipLaunchKernelGGL((direct_tx_kernel<TT, 2>), grid, dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, qlen, kq, T, X, part);
+    hipLaunchKernelGGL((direct_tx_kernel<TT, 2>), grid, dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, qlen, kqp, kqm,
+                       nself, T, X, part);
   else if (slots <= 4)
-    hipLaunchKernelGGL((direct_tx_kernel<TT, 4>), grid, dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, qlen, kq, T, X, part);
+    hipLaunchKernelGGL((direct_tx_kernel<TT, 4>), grid, dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, qlen, kqp, kqm,
+                       nself, T, X, part);
   else
-    hipLaunchKernelGGL((direct_tx_kernel<TT, 8>), grid, dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, qlen, kq, T, X, part);
+    hipLaunchKernelGGL((direct_tx_kernel<TT, 8>), grid, dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, qlen, kqp, kqm,
+                       nself, T, X, part);
   BSE_CHECK_LAUNCH();
   return BSE_OK;
 }
@@ -221,12 +243,12 @@ Arith arith_of(bse_prec p) { return p == BSE_F64 ? AR_F64 : (p == BSE_F32 ? AR_F
 char* off_bytes(void* base, long long elems, size_t esz) { return (char*)base + elems * (long long)esz; }
 
 // S1: pair-density halves -> Gv and Mc for one q batch
-bse_status form_pair_densities(Plan* p, int q0, int nq, bool need_c, hipStream_t st) {
+bse_status form_pair_densities(Plan* p, int q0, int nq, bool need_c, const int* kq, hipStream_t st) {
   const bse_dims& d = p->d;
   const int Nk = p->Nk, nv = d.nv, nc = d.nc, na = d.n_aux, no = d.n_ao;
   {
     StageMark sm_(p, BSE_STAGE_TABLES, st);
-    hipLaunchKernelGGL(tables_kernel, dim3(Nk), dim3(256), 0, st, Nk, nq, q0, nv, nc, p->nbnd, no, na, p->kq,
+    hipLaunchKernelGGL(tables_kernel, dim3(Nk), dim3(256), 0, st, Nk, nq, q0, nv, nc, p->nbnd, no, na, kq,
                      p->tab_psi_v, p->tab_psi_c, p->tab_mv, p->tab_mc);
     BSE_CHECK_LAUNCH();
   }
@@ -378,9 +400,13 @@ bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t
   const Arith ar = arith_of(p->prec);
   const bool f64 = p->prec == BSE_F64;
   const int nt = nc * nv;
-  for (int q0 = 0; q0 < Nk; q0 += p->qb) {
-    const int nq = (Nk - q0) < p->qb ? (Nk - q0) : p->qb;
-    BSE_TRY(form_pair_densities(p, q0, nq, !p->split, st));
+  // with the pair symmetry only the first nhalf q of the plan's order are formed (W(q) is stored in
+  // that order); T.X adds the partner blocks D(k, k-q) = D(k-q, k)^dagger
+  const int nqt = p->herm_half ? p->nhalf : Nk;
+  const int* kq = p->herm_half ? p->kqp : p->kq;
+  for (int q0 = 0; q0 < nqt; q0 += p->qb) {
+    const int nq = (nqt - q0) < p->qb ? (nqt - q0) : p->qb;
+    BSE_TRY(form_pair_densities(p, q0, nq, !p->split, kq, st));
     {  // P = conj(Gv) W(q)
     StageMark sm_(p, BSE_STAGE_WSTEP, st);
       GemmArgs g;
@@ -417,7 +443,7 @@ bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t
     }
     if (p->split) {  // T from B_c(k) and P without the conduction pair densities
       StageMark sm_(p, BSE_STAGE_DBLOCK, st);
-      BSE_TRY(direct_u_b3(p, q0, nq, st));
+      BSE_TRY(direct_u_b3(p, q0, nq, kq, st));
     } else {  // T = Mc P^T over nu
       StageMark sm_(p, BSE_STAGE_DBLOCK, st);
       GemmArgs g;
@@ -442,6 +468,7 @@ bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t
     {
       StageMark sm_(p, BSE_STAGE_TX, st);
       const size_t sh = (size_t)nt * nt * p->esz + (size_t)nt * nb * 16;
+      const int nself = p->herm_half ? p->nself : nqt;  // q from index nself on also give partner blocks
       const double scale = -1.0 / (double)Nk;
       static bool attr_set = false;
       if (!attr_set) {
@@ -455,11 +482,11 @@ bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t
       const dim3 grid((unsigned)Nk, (unsigned)nch);
       const int slots = (nt * nb + 255) / 256;
       if (f64)
-        BSE_TRY(launch_tx<double>(slots, grid, sh, st, Nk, nq, q0, nv, nc, nb, qlen, p->kq, (const double*)p->T, X,
-                                  p->txp));
+        BSE_TRY(launch_tx<double>(slots, grid, sh, st, Nk, nq, q0, nv, nc, nb, qlen, kq, p->kqm, nself,
+                                  (const double*)p->T, X, p->txp));
       else
-        BSE_TRY(launch_tx<float>(slots, grid, sh, st, Nk, nq, q0, nv, nc, nb, qlen, p->kq, (const float*)p->T, X,
-                                 p->txp));
+        BSE_TRY(launch_tx<float>(slots, grid, sh, st, Nk, nq, q0, nv, nc, nb, qlen, kq, p->kqm, nself,
+                                 (const float*)p->T, X, p->txp));
       const long long n = p->N * nb;
       hipLaunchKernelGGL(tx_reduce, dim3((unsigned)std::min<long long>((n + 255) / 256, 65536)), dim3(256), 0, st, n,
                          nch, scale, p->txp, Y);
@@ -477,7 +504,7 @@ bse_status adjoint_direct(Plan* p, const double* Ybar, const double* X, int nb, 
   const bool f64 = p->prec == BSE_F64;
   for (int q0 = 0; q0 < Nk; q0 += p->qb) {
     const int nq = (Nk - q0) < p->qb ? (Nk - q0) : p->qb;
-    BSE_TRY(form_pair_densities(p, q0, nq, true, st));
+    BSE_TRY(form_pair_densities(p, q0, nq, true, p->kq, st));
     StageMark sm_(p, BSE_STAGE_ADJOINT, st);
     if (f64)
       hipLaunchKernelGGL(adj_gm_kernel<double>, dim3(nq * Nk), dim3(256), 0, st, Nk, nq, q0, nv, nc, nb, p->kq,

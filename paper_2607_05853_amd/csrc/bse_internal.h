@@ -140,6 +140,11 @@ struct Plan {
   long long* tab_mv = nullptr;      // [Nk][qb*nv]  row offsets into Mv
   long long* tab_mc = nullptr;      // [Nk][qb*nc]
   int* kq = nullptr;                // [Nk][Nk] k + q index table (k, q) -> k'
+  // pair symmetry of the apply: q order with the self-conjugate q first, then one q of each pair
+  // {q, -q}, then their partners; kqp[k][j] = k + q_j, kqm[k][j] = k - q_j in that order
+  int herm_half = 0, nself = 0, nhalf = 0;
+  int* kqp = nullptr;
+  int* kqm = nullptr;
 
   // exchange / misc workspaces (FP64)
   double* xt = nullptr;       // c128 split-K partials [nsplit][n_aux][max_nb]
@@ -187,7 +192,7 @@ bse_status apply_exchange(Plan* p, const double* X, double* Y, int nb, hipStream
 bse_status apply_diag(Plan* p, const double* X, double* Y, int nb, hipStream_t st);
 bse_status adjoint_direct(Plan* p, const double* Ybar, const double* X, int nb, double* gWq, bool acc,
                           hipStream_t st);
-bse_status direct_u_b3(Plan* p, int q0, int nq, hipStream_t st);
+bse_status direct_u_b3(Plan* p, int q0, int nq, const int* kq, hipStream_t st);
 bse_status adjoint_eps(Plan* p, const double* Ybar, const double* X, int nb, double* geps, bool acc,
                        hipStream_t st);
 // the dense-mesh k list of a plan (fractional coordinates, host)

@@ -417,7 +417,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMW == 1 ? 
 
 }  // namespace
 
-bse_status direct_u_b3(Plan* p, int q0, int nq, hipStream_t st) {
+bse_status direct_u_b3(Plan* p, int q0, int nq, const int* kq, hipStream_t st) {
   const bse_dims& d = p->d;
   UArgs u;
   u.Nk = p->Nk;
@@ -439,7 +439,7 @@ bse_status direct_u_b3(Plan* p, int q0, int nq, hipStream_t st) {
   u.P = (const __bf16*)p->P;
   u.ps_P = p->ps_Mv;
   u.psi = p->psi32;
-  u.kq = p->kq;
+  u.kq = kq;
   u.T = (float*)p->T;
   u.psis = (const __bf16*)p->psi;
   u.ps_psi = p->ps_psi;

@@ -313,3 +313,42 @@ def test_apply_adjoint(B, prec):
     assert rel(H_(g["eps"]), ge) < 1e-13
     assert rel(H_(g["W_q"]), gq) < tol
     assert rel(H_(g["W_R"]), gr) < tol
+
+
+@pytest.mark.parametrize("prec", ["f64", "bf16x3"])
+@pytest.mark.parametrize("cfg", ["mesh4_ao16", "RAGGED", "DMA"])
+def test_pair_symmetry_against_all_pairs(B, prec, cfg):
+    # the apply forms the direct blocks of about half of the q and takes the rest from
+    # D(k, k-q) = D(k-q, k)^dagger; both modes must give the oracle's H X
+    conf = {"mesh4_ao16": "mesh4_ao16", "RAGGED": RAGGED, "DMA": DMA}[cfg]
+    p = make_problem(conf, 1, "G2", coarse=(3, 3, 2))
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
+    X = random_block(p.N, 4, seed=21)
+    H = O.build_H(p, H_(Wq))
+    ref = H @ X
+    half = B.plan_from_problem(p, Wq, prec=prec, max_nb=4)
+    full = B.plan_from_problem(p, Wq, prec=prec, max_nb=4, all_pairs=True)
+    formed, total = half.pairs
+    assert total == p.Nk and full.pairs == (p.Nk, p.Nk)
+    neg = [int(np.ravel_multi_index(tuple((-np.array(np.unravel_index(q, p.nk))) % np.array(p.nk)), p.nk))
+           for q in range(p.Nk)]
+    assert formed == sum(1 for q in range(p.Nk) if q <= neg[q])
+    eh, ef = rel(H_(half.apply(T(X))), ref), rel(H_(full.apply(T(X))), ref)
+    print("[pair symmetry %s %s] formed %d of %d, err %.2e (all pairs %.2e)" % (cfg, prec, formed, total, eh, ef),
+          flush=True)
+    assert eh < TOL[prec] and ef < TOL[prec]
+
+
+def test_pair_symmetry_off_for_general_W(B):
+    # a W_q without W(-q) = conj W(q) must fall back to forming every block (and still match the oracle,
+    # whose H is then not Hermitian)
+    p = make_problem("mesh4_ao16", 2, "G2", coarse=(3, 3, 2))
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
+    rng = np.random.default_rng(4)
+    bump = (rng.standard_normal((p.n_aux, p.n_aux)) + 1j * rng.standard_normal((p.n_aux, p.n_aux))) * 1e-3
+    Wq[5] += T(bump)
+    plan = B.plan_from_problem(p, Wq, prec="f64", max_nb=3)
+    assert plan.pairs == (p.Nk, p.Nk)
+    X = random_block(p.N, 3, seed=22)
+    H = O.build_H(p, H_(Wq))
+    assert rel(H_(plan.apply(T(X))), H @ X) < TOL["f64"]
