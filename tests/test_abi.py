@@ -84,6 +84,8 @@ def test_null_plan_calls(L):
     assert L.bse_plan_destroy(None) == 0
     assert L.bse_lowest_excitons(None, 4, 10, 1e-8, None, dummy, None, None, None) == 1
     assert L.bse_velocity_start(None, dummy, dummy, 1, dummy, dummy, None) == 1
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    assert L.bse_plan_pairs(None, ctypes.byref(a), ctypes.byref(b)) == 1
 
 
 def test_binding_rejects_cpu_tensors():
