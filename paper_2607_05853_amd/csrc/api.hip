@@ -201,9 +201,11 @@ bool valid_prec(int p) { return p == BSE_F64 || p == BSE_F32 || p == BSE_BF16X3;
 
 hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// workspace bytes per q of a batch: Gv, P, T, and the conduction pair densities Mc unless the plan is
+// split (the BF16x3 apply never forms them; its adjoint allocates them on first use)
 size_t per_q_bytes(const Plan* p) {
   const long long Nk = p->Nk, nv = p->d.nv, nc = p->d.nc, na = p->d.n_aux;
-  return p->esz * (size_t)(Nk * nv * nv * na * 2 + Nk * nc * nc * na + Nk * nc * nc * nv * nv);
+  return p->esz * (size_t)(Nk * nv * nv * na * 2 + (p->split ? 0 : Nk * nc * nc * na) + Nk * nc * nc * nv * nv);
 }
 
 bse_status check_hermitian(const void* C, const void* Vbar, const bse_dims* d, hipStream_t st) {
@@ -508,12 +510,17 @@ bse_status build_plan(Plan* p, const bse_dims* d, const double* eps_qp, const vo
     BSE_HIP(hipStreamSynchronize(st));
   }
 
-  // direct-term workspaces
+  // direct-term workspaces: at least 12 GiB, more where 16 q per batch need it and 40 % of the free
+  // device memory allows (short q batches leave the pair-density tiles mostly empty)
   {
-    double gb = 12.0;
-    if (const char* e = std::getenv("BSE_WORKSPACE_GB")) gb = std::atof(e);
-    const size_t budget = (size_t)(gb * (1ull << 30));
     const size_t pq = per_q_bytes(p);
+    size_t budget = (size_t)12 << 30;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
+      budget = std::max(budget, std::min<size_t>(16 * pq, (size_t)(0.4 * (double)free_b)));
+    else
+      (void)hipGetLastError();
+    if (const char* e = std::getenv("BSE_WORKSPACE_GB")) budget = (size_t)(std::atof(e) * (double)(1ull << 30));
     long long qb = (long long)(budget / std::max<size_t>(pq, 1));
     if (const char* e = std::getenv("BSE_QBATCH")) qb = std::atoll(e);
     qb = std::max(1LL, std::min<long long>(qb, Nk));
@@ -521,8 +528,10 @@ bse_status build_plan(Plan* p, const bse_dims* d, const double* eps_qp, const vo
     const long long nq = qb;
     BSE_TRY(plan_alloc(p, &p->Mv, p->esz * (size_t)(nq * Nk * nv * nv * na)));
     p->ps_Mv = nq * Nk * nv * nv * na;
+    p->ps_Mc = nq * Nk * nc * nc * na;
+    p->ps_T = nq * Nk * nc * nc * nv * nv;
     BSE_TRY(plan_alloc(p, &p->P, p->esz * (size_t)(nq * Nk * nv * nv * na)));
-    BSE_TRY(plan_alloc(p, &p->Mc, p->esz * (size_t)(nq * Nk * nc * nc * na)));
+    if (!p->split) BSE_TRY(plan_alloc(p, &p->Mc, p->esz * (size_t)(nq * Nk * nc * nc * na)));
     BSE_TRY(plan_alloc(p, &p->T, p->esz * (size_t)(nq * Nk * nc * nc * nv * nv)));
     BSE_TRY(plan_alloc(p, (void**)&p->tab_psi_v, sizeof(long long) * (size_t)(nq * Nk * nv)));
     BSE_TRY(plan_alloc(p, (void**)&p->tab_mv, sizeof(long long) * (size_t)(nq * Nk * nv)));

@@ -11,6 +11,7 @@
 // processed in batches of qb momentum transfers q so that W(q) is read once per
 // batch and the per-pair intermediates stay within a fixed workspace.
 #include "bse_internal.h"
+#include "mfma_common.h"
 
 namespace bse {
 namespace {
@@ -210,6 +211,38 @@ __global__ void adj_gm_kernel(int Nk, int nq, int q0, int nv, int nc, int nb, co
   }
 }
 
+// GmT[qi][k][(c' c)][(v' v)] = sum_b Ybar[k][(c v)][b] conj(X[k'][(c' v')][b]) as four bf16 planes (plane
+// stride ps): the k-major operand of Z = Gm conj(Mc) on the BF16x3 path
+__global__ void adj_gmT_split_kernel(int Nk, int nq, int q0, int nv, int nc, int nb, const int* __restrict__ kq,
+                                     const double* __restrict__ Yb, const double* __restrict__ X,
+                                     __bf16* __restrict__ G, long long ps) {
+  const int k = blockIdx.x % Nk, qi = blockIdx.x / Nk;
+  const int nt = nc * nv, nt2 = nt * nt, nv2 = nv * nv;
+  const int kp = kq[(long long)k * Nk + q0 + qi];
+  const double* y = Yb + 2 * (long long)k * nt * nb;
+  const double* x = X + 2 * (long long)kp * nt * nb;
+  __bf16* out = G + ((long long)qi * Nk + k) * nt2;
+  for (int e = threadIdx.x; e < nt2; e += blockDim.x) {
+    const int col = e / nv2, row = e % nv2;  // col = (c' c), row = (v' v)
+    const int cp = col / nc, c = col % nc, vp = row / nv, v = row % nv;
+    const double* yr = y + 2 * (long long)(c * nv + v) * nb;
+    const double* xr = x + 2 * (long long)(cp * nv + vp) * nb;
+    double sr = 0, si = 0;
+    for (int b = 0; b < nb; ++b) {
+      const double ar = yr[2 * b], ai = yr[2 * b + 1], br = xr[2 * b], bi = -xr[2 * b + 1];
+      sr += ar * br - ai * bi;
+      si += ar * bi + ai * br;
+    }
+    __bf16 h, l;
+    split_bf16((float)sr, h, l);
+    out[e] = h;
+    out[ps + e] = l;
+    split_bf16((float)si, h, l);
+    out[2 * ps + e] = h;
+    out[3 * ps + e] = l;
+  }
+}
+
 __global__ void adj_eps_kernel(int nv, int nc, int nb, const double* __restrict__ Yb,
                                const double* __restrict__ X, double* __restrict__ g, int acc) {
   const int k = blockIdx.x;
@@ -243,7 +276,8 @@ Arith arith_of(bse_prec p) { return p == BSE_F64 ? AR_F64 : (p == BSE_F32 ? AR_F
 char* off_bytes(void* base, long long elems, size_t esz) { return (char*)base + elems * (long long)esz; }
 
 // S1: pair-density halves -> Gv and Mc for one q batch
-bse_status form_pair_densities(Plan* p, int q0, int nq, bool need_c, const int* kq, hipStream_t st) {
+bse_status form_pair_densities(Plan* p, int q0, int nq, bool need_c, const int* kq, hipStream_t st,
+                                 bool c_split = false) {
   const bse_dims& d = p->d;
   const int Nk = p->Nk, nv = d.nv, nc = d.nc, na = d.n_aux, no = d.n_ao;
   {
@@ -306,7 +340,8 @@ bse_status form_pair_densities(Plan* p, int q0, int nq, bool need_c, const int* 
     if (p->split) {
       g.a_ps = p->ps_psi;
       g.b_ps = p->ps_Bc;
-      BSE_TRY(cgemm_split(g, true, true, false, false, st));
+      g.c_ps = p->ps_Mc;
+      BSE_TRY(cgemm_split(g, true, true, c_split, false, st));
     } else {
       BSE_TRY(cgemm(g, ar, f64, f64, st));
     }
@@ -502,11 +537,17 @@ bse_status adjoint_direct(Plan* p, const double* Ybar, const double* X, int nb, 
   const int Nk = p->Nk, nv = d.nv, nc = d.nc, na = d.n_aux;
   const Arith ar = arith_of(p->prec);
   const bool f64 = p->prec == BSE_F64;
+  // BF16x3 with 8-aligned n_v^2 and N_aux: every operand pre-split, both reductions on the k-major kernel
+  const bool tn = p->split && (nv * nv) % 8 == 0 && na % 8 == 0;
+  if (!p->Mc) BSE_TRY(plan_alloc(p, &p->Mc, p->esz * (size_t)p->qb * Nk * nc * nc * na));
   for (int q0 = 0; q0 < Nk; q0 += p->qb) {
     const int nq = (Nk - q0) < p->qb ? (Nk - q0) : p->qb;
-    BSE_TRY(form_pair_densities(p, q0, nq, true, p->kq, st));
+    BSE_TRY(form_pair_densities(p, q0, nq, true, p->kq, st, tn));
     StageMark sm_(p, BSE_STAGE_ADJOINT, st);
-    if (f64)
+    if (tn)
+      hipLaunchKernelGGL(adj_gmT_split_kernel, dim3(nq * Nk), dim3(256), 0, st, Nk, nq, q0, nv, nc, nb, p->kq, Ybar,
+                         X, (__bf16*)p->T, p->ps_T);
+    else if (f64)
       hipLaunchKernelGGL(adj_gm_kernel<double>, dim3(nq * Nk), dim3(256), 0, st, Nk, nq, q0, nv, nc, nb, p->kq,
                          Ybar, X, (double*)p->T);
     else
@@ -520,9 +561,6 @@ bse_status adjoint_direct(Plan* p, const double* Ybar, const double* X, int nb, 
       g.N = na;
       g.K = nc * nc;
       g.A = p->T;
-      g.a_sb = (long long)nc * nc * nv * nv;
-      g.a_si = nc * nc;
-      g.a_sk = 1;
       g.B = p->Mc;
       g.b_sb = (long long)nc * nc * na;
       g.b_sk = na;
@@ -532,7 +570,20 @@ bse_status adjoint_direct(Plan* p, const double* Ybar, const double* X, int nb, 
       g.c_sb = (long long)nv * nv * na;
       g.c_si = na;
       g.c_sj = 1;
-      BSE_TRY(cgemm(g, ar, f64, f64, st));
+      if (tn) {  // A = GmT [(c'c)][(v'v)], Z written pre-split
+        g.a_sb = (long long)nc * nc * nv * nv;
+        g.a_si = 1;
+        g.a_sk = nv * nv;
+        g.a_ps = p->ps_T;
+        g.b_ps = p->ps_Mc;
+        g.c_ps = p->ps_Mv;
+        BSE_TRY(cgemm_split(g, true, true, true, false, st));
+      } else {
+        g.a_sb = (long long)nc * nc * nv * nv;
+        g.a_si = nc * nc;
+        g.a_sk = 1;
+        BSE_TRY(cgemm(g, ar, f64, f64, st));
+      }
     }
     {  // gWq[q][mu][nu] = -(1/N_k) sum_{(k v' v)} Gv[(k v' v)][mu] Z[(k v' v)][nu]
       GemmArgs g;
@@ -556,7 +607,8 @@ bse_status adjoint_direct(Plan* p, const double* Ybar, const double* X, int nb, 
       g.beta = acc ? 1 : 0;
       if (p->split) {
         g.a_ps = p->ps_Mv;
-        BSE_TRY(cgemm_split(g, true, false, false, true, st));
+        g.b_ps = p->ps_Mv;
+        BSE_TRY(cgemm_split(g, true, tn, false, true, st));
       } else {
         BSE_TRY(cgemm(g, ar, f64, true, st));
       }

@@ -114,7 +114,7 @@ struct Plan {
   size_t esz = 16;  // bytes per complex element of the plan precision
   bool split = false;  // BF16X3: psi, halves, W_q and the valence pair densities are stored as
                        // four bf16 planes (Re hi, Re lo, Im hi, Im lo); W_q transposed per q
-  long long ps_psi = 0, ps_W = 0, ps_Bv = 0, ps_Bc = 0, ps_Mv = 0;  // plane strides (elements)
+  long long ps_psi = 0, ps_W = 0, ps_Bv = 0, ps_Bc = 0, ps_Mv = 0, ps_Mc = 0, ps_T = 0;  // plane strides (elements)
 
   // FP64 data
   double* eps = nullptr;      // [Nk][nv+nc]
@@ -156,7 +156,6 @@ struct Plan {
   std::vector<int32_t> R;
   std::vector<double> wR;
   double* gq_acc = nullptr;   // c128 [Nk][n_aux][n_aux]
-  double* gw_tmp = nullptr;   // c128 [qb][Nk][nv][nv][n_aux]
 
   std::vector<DevBuf> owned;
   size_t bytes = 0;

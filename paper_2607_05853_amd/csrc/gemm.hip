@@ -780,6 +780,174 @@ __global__ __launch_bounds__(256) void cgemm_b3_dma(GemmArgs g) {
   }
 }
 
+// ----------------------------------------------------------------------------
+// BF16X3, both operands pre-split and k-major:  C[b][m][n] = sum_k A[b][k][m] B[b][k][n]
+//
+// For reductions over a long row index (the gradient of W(q) sums over every
+// pair of a q).  Rows k of A and B are contiguous in m / n, so the MFMA operand
+// layout (8 consecutive k per lane) needs a transpose: each thread loads an 8 x 8
+// (k x column) block of one plane with eight 16-byte loads, transposes it in
+// registers and writes eight 16-byte column vectors to LDS.  LDS rows are the
+// tile's columns (16 k each, two 8-k halves); within each group of 8 rows the
+// row is XOR-permuted by the group index so that the eight rows a thread writes
+// per instruction, and the rows of different threads, spread over the banks.
+// Same tile and MFMA order as the other BF16x3 kernels.  The K range can be
+// split over blocks (split s covers [s kc, (s+1) kc)): partial sums go to a
+// FP64 buffer part[b][s][m][n] and are added in split order by tn_reduce.
+// CS writes C pre-split instead (one split only).
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ int tn_row(int m) { return (m & ~7) | ((m ^ (m >> 3)) & 7); }
+
+template <bool CS>
+__global__ __launch_bounds__(256) void cgemm_b3_tn(GemmArgs g, int nsplit, int kc, double* __restrict__ part) {
+  constexpr int BM = 128, BN = 128, BK = 16;
+  constexpr int PL = BM * BK;  // bf16 per plane per operand per stage
+  __shared__ __attribute__((aligned(16))) __bf16 smem[2 * 8 * PL];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int gxn = (g.N + BN - 1) / BN, gyn = (g.M + BM - 1) / BM;
+  const long long per = (long long)gxn * gyn;
+  long long bl, t;
+  xcd_map(blockIdx.x, per, (long long)g.batch * nsplit, bl, t);
+  const int b = (int)(bl / nsplit), s = (int)(bl % nsplit);
+  const int m0 = (int)(t / gxn) * BM, n0 = (int)(t % gxn) * BN;
+  const int k_lo = s * kc, k_hi = min(g.K, k_lo + kc);
+  const int nK = (k_hi - k_lo + BK - 1) / BK;
+
+  // staging role (wave-uniform operand): threads 0..127 stage A, 128..255 B; plane pl, k half kh
+  // (rows 8 kh .. 8 kh + 7 of the step), columns 8 cb .. 8 cb + 7 of the tile
+  const int isB = tid >> 7, u = tid & 127;
+  const int pl = u >> 5, kh = (u >> 3) & 1, cb = (u & 7) | ((u >> 1) & 8);  // 16 lanes: 16 distinct bank slots
+  const int c0 = (isB ? n0 : m0) + 8 * cb;
+  const bool cok = c0 < (isB ? g.N : g.M);
+  const long long ld = isB ? g.b_sk : g.a_sk;
+  const __bf16* src = (const __bf16*)(isB ? g.B : g.A) + (isB ? g.b_ps : g.a_ps) * pl +
+                      (long long)b * (isB ? g.b_sb : g.a_sb) + (cok ? c0 : 0);
+  const unsigned flip = ((isB ? g.conjB : g.conjA) && pl >= 2) ? 0x80008000u : 0u;  // conj: -Im planes
+  __bf16* const dst0 = smem + (isB * 4 + pl) * PL + 8 * kh;
+
+  u4v v[8];
+  auto gload = [&](int kt) {
+    const int kb = k_lo + kt * BK + 8 * kh;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      if (cok && kb + r < k_hi)
+        v[r] = *reinterpret_cast<const u4v*>(src + (long long)(kb + r) * ld);
+      else
+        v[r] = u4v{0u, 0u, 0u, 0u};
+    }
+  };
+  auto lstore = [&](int st) {
+    __bf16* dst = dst0 + st * 8 * PL;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      // column c of the 8 x 8 block: dword j holds rows 2j (low half) and 2j + 1 (high half)
+      u4v w;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const unsigned lo = v[2 * j][c >> 1], hi = v[2 * j + 1][c >> 1];
+        w[j] = (c & 1) ? ((lo >> 16) | (hi & 0xffff0000u)) : ((lo & 0xffffu) | (hi << 16));
+      }
+      w ^= flip;
+      *reinterpret_cast<u4v*>(dst + tn_row(8 * cb + c) * BK) = w;
+    }
+  };
+
+  f16v accR[2][2], accI[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        accR[i][j][r] = 0.f;
+        accI[i][j][r] = 0.f;
+      }
+  if (nK > 0) {
+    gload(0);
+    lstore(0);
+  }
+  __syncthreads();
+  const int fo = 8 * (lane >> 5);
+  for (int kt = 0; kt < nK; ++kt) {
+    const int st = kt & 1;
+    if (kt + 1 < nK) gload(kt + 1);
+    const __bf16* sa = smem + st * 8 * PL;
+    const __bf16* sb = sa + 4 * PL;
+    bf8v a[2][4], bb[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int o = tn_row(wm * 64 + i * 32 + (lane & 31)) * BK + fo;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[i][q] = *reinterpret_cast<const bf8v*>(sa + q * PL + o);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int o = tn_row(wn * 64 + j * 32 + (lane & 31)) * BK + fo;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bb[j][q] = *reinterpret_cast<const bf8v*>(sb + q * PL + o);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const bf8v nih = neg8(a[i][2]), nil = neg8(a[i][3]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) cmma_b3(a[i], nih, nil, bb[j], accR[i][j], accI[i][j]);
+    }
+    if (kt + 1 < nK) lstore(st ^ 1);
+    __syncthreads();
+  }
+  // register r of a lane holds row 8 (r / 4) + 4 (lane / 32) + r % 4, column lane % 32 of its 32 x 32 tile
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      if (row >= g.M) continue;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int col = n0 + wn * 64 + j * 32 + (lane & 31);
+        if (col >= g.N) continue;
+        if constexpr (CS) {
+          __bf16* o = (__bf16*)g.C + (long long)b * g.c_sb + (long long)row * g.c_si + (long long)col * g.c_sj;
+          __bf16 h, l;
+          split_bf16((float)(g.alpha * (double)accR[i][j][r]), h, l);
+          o[0] = h;
+          o[g.c_ps] = l;
+          split_bf16((float)(g.alpha * (double)accI[i][j][r]), h, l);
+          o[2 * g.c_ps] = h;
+          o[3 * g.c_ps] = l;
+        } else {
+          double* o = part + 2 * ((((long long)b * nsplit + s) * g.M + row) * g.N + col);
+          *reinterpret_cast<double2*>(o) = make_double2((double)accR[i][j][r], (double)accI[i][j][r]);
+        }
+      }
+    }
+  }
+}
+
+// C[b][m][n] = alpha * sum_s part[b][s][m][n] (+ C if beta), splits added in order; C is c128
+__global__ void tn_reduce(GemmArgs g, int nsplit, const double* __restrict__ part) {
+  const long long mn = (long long)g.M * g.N, n = mn * g.batch;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const long long b = i / mn, e = i % mn;
+    const int row = (int)(e / g.N), col = (int)(e % g.N);
+    double sr = 0.0, si = 0.0;
+    for (int s = 0; s < nsplit; ++s) {
+      const double2 v = reinterpret_cast<const double2*>(part)[(b * nsplit + s) * mn + e];
+      sr += v.x;
+      si += v.y;
+    }
+    double* o = (double*)g.C + 2 * (b * g.c_sb + (long long)row * g.c_si + (long long)col * g.c_sj);
+    double vr = g.alpha * sr, vi = g.alpha * si;
+    if (g.beta) {
+      vr += o[0];
+      vi += o[1];
+    }
+    o[0] = vr;
+    o[1] = vi;
+  }
+}
+
 template <typename K>
 bse_status launch(K kern, const GemmArgs& g, int BM, int BN, hipStream_t st) {
   const long long gx = (g.N + BN - 1) / BN, gy = (g.M + BM - 1) / BM;
@@ -865,6 +1033,47 @@ bse_status launch_dma(const GemmArgs& g, hipStream_t st) {
   return BSE_OK;
 }
 
+// the k-major kernel: unit m / n strides, 16-byte aligned rows of whole 8-column chunks, no tables
+bool tn_ok(const GemmArgs& g) {
+  auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  if (g.a_si != 1 || g.b_sj != 1 || g.a_tab || g.b_tab || g.c_tab) return false;
+  if (!al(g.A) || !al(g.B) || (g.M & 7) || (g.N & 7)) return false;
+  if ((g.a_sk & 7) || (g.b_sk & 7) || (g.a_sb & 7) || (g.b_sb & 7) || (g.a_ps & 7) || (g.b_ps & 7)) return false;
+  const long long tiles = (long long)((g.N + 127) / 128) * ((g.M + 127) / 128) * g.batch;
+  return tiles < (1LL << 24);
+}
+
+// split K over enough blocks to fill the chip (about 2048 blocks, at least 1024 k per split)
+bse_status launch_tn(const GemmArgs& g, bool c_split, hipStream_t st) {
+  const long long tiles = (long long)((g.N + 127) / 128) * ((g.M + 127) / 128) * g.batch;
+  if (c_split) {
+    hipLaunchKernelGGL(cgemm_b3_tn<true>, dim3((unsigned)tiles), dim3(256), 0, st, g, 1, g.K, (double*)nullptr);
+    BSE_CHECK_LAUNCH();
+    return BSE_OK;
+  }
+  long long ns = (2048 + tiles - 1) / tiles;
+  ns = std::max(1LL, std::min<long long>(ns, g.K / 1024));
+  const int kc = (int)(((g.K + ns - 1) / ns + 15) / 16 * 16);
+  const int nsplit = (g.K + kc - 1) / kc;
+  double* part = nullptr;
+  const size_t bytes = 16 * (size_t)g.batch * nsplit * g.M * g.N;
+  BSE_HIP(hipMallocAsync((void**)&part, bytes, st));
+  hipLaunchKernelGGL(cgemm_b3_tn<false>, dim3((unsigned)(tiles * nsplit)), dim3(256), 0, st, g, nsplit, kc, part);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    const long long n = (long long)g.batch * g.M * g.N;
+    hipLaunchKernelGGL(tn_reduce, dim3((unsigned)std::min<long long>((n + 255) / 256, 65536)), dim3(256), 0, st, g,
+                       nsplit, (const double*)part);
+    e = hipGetLastError();
+  }
+  (void)hipFreeAsync(part, st);
+  if (e != hipSuccess) {
+    set_error(std::string("cgemm_b3_tn: ") + hipGetErrorString(e));
+    return BSE_EDEVICE;
+  }
+  return BSE_OK;
+}
+
 }  // namespace
 
 bse_status cgemm_split(const GemmArgs& g, bool a_split, bool b_split, bool c_split, bool out_f64, hipStream_t st) {
@@ -877,6 +1086,7 @@ bse_status cgemm_split(const GemmArgs& g, bool a_split, bool b_split, bool c_spl
     if (c_split) return launch_dma<true, float>(g, st);
     return out_f64 ? launch_dma<false, double>(g, st) : launch_dma<false, float>(g, st);
   }
+  if (a_split && b_split && (c_split || out_f64) && tn_ok(g)) return launch_tn(g, c_split, st);
 #define BSE_SPLIT_CASE(AS, BS, CS)                                                              \
   if (a_split == AS && b_split == BS && c_split == CS)                                           \
     return out_f64 ? launch_1d(cgemm_b3_big<AS, BS, CS, double>, g, 128, 128, st)                \
@@ -887,6 +1097,7 @@ bse_status cgemm_split(const GemmArgs& g, bool a_split, bool b_split, bool c_spl
   BSE_SPLIT_CASE(false, true, false)
   BSE_SPLIT_CASE(false, false, false)
   BSE_SPLIT_CASE(false, true, true)
+  BSE_SPLIT_CASE(false, false, true)
 #undef BSE_SPLIT_CASE
   set_error("cgemm_split: unsupported operand combination");
   return BSE_EINVAL;

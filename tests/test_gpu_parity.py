@@ -315,6 +315,29 @@ def test_apply_adjoint(B, prec):
     assert rel(H_(g["W_R"]), gr) < tol
 
 
+# BF16x3 adjoint on the k-major kernel (n_v^2 and N_aux multiples of 8): ADJ_TN has ragged 40 x 40
+# W-gradient tiles and a 9-deep Z product (one partial k step); ADJ_SPLIT has n_v = 8 and a 2048-deep
+# W-gradient reduction split over two k ranges
+ADJ_TN = dict(cfg_id=80, coarse=(2, 2, 2), dense=(3, 2, 2), n_ao=16, nv=4, nc=3, n_aux=40)
+ADJ_SPLIT = dict(cfg_id=81, coarse=(2, 2, 2), dense=(4, 4, 2), n_ao=16, nv=8, nc=2, n_aux=24)
+
+
+@pytest.mark.parametrize("cfg", ["ADJ_TN", "ADJ_SPLIT"])
+def test_apply_adjoint_kmajor(B, cfg):
+    conf = {"ADJ_TN": ADJ_TN, "ADJ_SPLIT": ADJ_SPLIT}[cfg]
+    p = make_problem(conf, 6, "G2", coarse=(3, 3, 2))
+    plan, Wq = _plan(B, p, "bf16x3", nb=4)
+    plan.set_R(p.R, p.w_R)
+    Yb, X = random_block(p.N, 4, seed=31), random_block(p.N, 4, seed=32)
+    g = plan.apply_adjoint(T(Yb), T(X), want_WR=True, want_Wq=True, want_eps=True)
+    ge, gq = O.grad_apply(p, H_(Wq), Yb, X)
+    gr = O.grad_WR_from_Wq(gq, p.R, p.w_R, dense_kmesh(p.nk))
+    eq, er = rel(H_(g["W_q"]), gq), rel(H_(g["W_R"]), gr)
+    print("[adjoint k-major %s] W_q %.2e W_R %.2e" % (cfg, eq, er), flush=True)
+    assert rel(H_(g["eps"]), ge) < 1e-13
+    assert eq < 5e-4 and er < 5e-4
+
+
 @pytest.mark.parametrize("prec", ["f64", "bf16x3"])
 @pytest.mark.parametrize("cfg", ["mesh4_ao16", "RAGGED", "DMA"])
 def test_pair_symmetry_against_all_pairs(B, prec, cfg):
