@@ -97,10 +97,11 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=2)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
-    ap.add_argument("--mode", default="spectrum", choices=["spectrum", "precision", "gradients"],
+    ap.add_argument("--mode", default="spectrum", choices=["spectrum", "precision", "gradients", "largest"],
                     help="spectrum: the timed pipeline (default); precision: per-precision apply and "
                          "short-Haydock errors on a larger workload; gradients: LOBPCG and spectrum "
-                         "gradients checked by central finite differences")
+                         "gradients checked by central finite differences; largest: one BF16x3 apply and "
+                         "adjoint on the 16x16x16 / N_ao = 128 workload")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -112,6 +113,9 @@ def main():
         return
     if args.mode == "precision":
         precision_mode(args.config if args.config != "mesh8_ao64" else "mesh12_ao96", args.haydock_steps or 10)
+        return
+    if args.mode == "largest":
+        largest_mode(args.config if args.config != "mesh8_ao64" else "mesh16_ao128")
         return
     if args.mode == "gradients":
         from synth import CONFIGS
@@ -301,6 +305,64 @@ def precision_mode(config, m):
                                                   "blocks of %d, Haydock %d steps" %
                       (config, "x".join(map(str, p.nk)), p.n_ao, p.nv, p.nc, p.n_aux, p.N, nb, m),
                       "F_apply_TFLOP": Fa / 1e12, "results": out}), flush=True)
+
+
+def largest_mode(config):
+    """One BF16x3 apply and one adjoint (W(R) and energy gradients) at the largest workload, timed with the
+    stage breakdown; the apply is run once untimed first."""
+    from synth import CONFIGS, random_block
+    B, T, p, kq, torch = _setup(config)
+    nb = CONFIGS[config]["nb"]
+    t0 = time.time()
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, kq)
+    torch.cuda.synchronize()
+    t_interp = time.time() - t0
+    t0 = time.time()
+    plan = B.Plan(p.nk, p.n_ao, p.nv, p.nc, p.n_aux, T(p.eps_qp, torch.float64), T(p.psi), T(p.C), T(p.Vbar), Wq,
+                  alpha=p.alpha, prec="bf16x3", max_nb=nb)
+    plan.set_R(p.R, p.w_R)
+    del Wq
+    torch.cuda.synchronize()
+    t_plan = time.time() - t0
+    print("[largest] interpolation %.2f s, plan %.2f s (%.1f GB)" % (t_interp, t_plan, plan.bytes / 2**30),
+          file=sys.stderr, flush=True)
+    X, Yb = T(random_block(p.N, nb, seed=1)), T(random_block(p.N, nb, seed=2))
+    plan.apply(X)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    plan.stage_times()
+    t0 = time.time()
+    plan.apply(X)
+    torch.cuda.synchronize()
+    ta = time.time() - t0
+    st_apply = {k: round(v[0], 1) for k, v in plan.stage_times().items() if v[1]}
+    print("[largest] apply %.2f s %s" % (ta, st_apply), file=sys.stderr, flush=True)
+    t0 = time.time()
+    plan.apply_adjoint(Yb, X, want_WR=True, want_eps=True)
+    torch.cuda.synchronize()
+    tg = time.time() - t0
+    st_adj = {k: round(v[0], 1) for k, v in plan.stage_times().items() if v[1]}
+    print("[largest] adjoint %.2f s %s" % (tg, st_adj), file=sys.stderr, flush=True)
+    qf, qt = plan.pairs
+    Fa = f_apply(p.Nk, p.n_ao, p.nv, p.nc, p.n_aux, nb)
+    Fx = f_apply(p.Nk, p.n_ao, p.nv, p.nc, p.n_aux, nb, q_formed=qf)
+    # adjoint flops: pair densities (both sides), Z = Gm conj(M_c), g_W = Gv^T Z over every pair, Gm
+    na, no, nv, nc = p.n_aux, p.n_ao, p.nv, p.nc
+    Fg = 8 * p.Nk ** 2 * (na * no * (nv ** 2 + nc ** 2) + nv ** 2 * nc ** 2 * na + na ** 2 * nv ** 2
+                          + nv ** 2 * nc ** 2 * nb)
+    print(json.dumps({
+        "mode": "largest", "workload": "%s: dense %s from coarse %s, N_ao=%d, nv=%d, nc=%d, N_aux=%d, |R|<=%g, "
+                                       "BSE dim %d, blocks of %d" %
+        (config, "x".join(map(str, p.nk)), "x".join(map(str, p.coarse)), p.n_ao, p.nv, p.nc, p.n_aux,
+         CONFIGS[config]["r_cut"], p.N, nb),
+        "prec": "bf16x3", "plan_GB": plan.bytes / 2**30, "interpolate_s": t_interp, "plan_s": t_plan,
+        "apply_s": ta, "F_apply_TFLOP": Fa / 1e12, "apply_GFLOP_s": Fa / ta / 1e9,
+        "pct_mfma_peak_apply_F_apply": Fa / ta / 1e12 / PEAK_TFLOPS["bf16x3"],
+        "direct_pairs": {"q_formed": qf, "q_total": qt, "F_apply_executed_TFLOP": Fx / 1e12},
+        "pct_mfma_peak_apply": Fx / ta / 1e12 / PEAK_TFLOPS["bf16x3"],
+        "apply_stage_ms": st_apply, "adjoint_s": tg, "F_adjoint_TFLOP": Fg / 1e12,
+        "adjoint_GFLOP_s": Fg / tg / 1e9, "adjoint_stage_ms": st_adj}), flush=True)
+    plan.close()
 
 
 def gradients_mode(config, m):

@@ -21,6 +21,7 @@ __all__ = [
     "transition_energies", "velocity_start", "spectrum_exact", "eig_spectrum",
     "haydock", "continued_fraction", "haydock_spectrum", "lowest_exciton",
     "binding_energy", "grad_apply", "grad_WR_from_Wq", "grad_lowest", "grad_spectrum",
+    "interpolate_W_matmul", "apply_H_rows_allpairs", "grad_Wq_at", "grad_eps",
 ]
 
 
@@ -340,6 +341,133 @@ def grad_WR_from_Wq(g_Wq, R, w_R, q_frac):
         out[r] *= w_R[r]
     return out
 
+
+# ----------------------------------------------------------------------------
+# the same definitions evaluated a whole row of pairs at a time (large meshes)
+#
+# These functions compute exactly the quantities of interpolate_W, apply_H_rows
+# and grad_apply; the sums over k' (or k) are evaluated for all pairs of a row
+# at once with matrix products instead of one (k, k') block after another, so
+# that sampled rows stay affordable on a 16x16x16 mesh.  Nothing else changes:
+# the same pair densities, the same W(k' - k), the same terms.
+# ----------------------------------------------------------------------------
+def interpolate_W_matmul(W_R, R, w_R, q_frac):
+    """W_munu(q) = sum_R w_R W_munu(R) exp(+2 pi i q.R) (Sec. III.B) as one matrix product
+    [n_q x n_R] x [n_R x n_aux^2] of the phase table with the stacked W(R)."""
+    W_R = np.asarray(W_R, dtype=np.complex128)
+    q_frac = np.atleast_2d(np.asarray(q_frac, dtype=np.float64))
+    ph = np.asarray(w_R)[None, :] * np.exp(2j * np.pi * (q_frac @ np.asarray(R, dtype=np.float64).T))
+    return (ph @ W_R.reshape(len(R), -1)).reshape((len(q_frac),) + W_R.shape[1:])
+
+
+def _psi_sets(prob):
+    val, con = _bands(prob)
+    return prob.psi[:, val, :], prob.psi[:, con, :]      # [Nk][nv][nao], [Nk][nc][nao]
+
+
+def apply_H_rows_allpairs(prob, W_q, X, rows, alpha=None, chunk=64):
+    """Rows k in `rows` of H X (Eq. (Hamiltonian), kernel of Eq. (W_LRI)), as apply_H_rows.
+
+    For a row k and every k' of a chunk at once:
+      Mvv[k'][mu][v'][v] = M^mu_{v'v}(k', k),  Mcc[k'][nu][c][c'] = M^nu_{cc'}(k, k'),
+      direct block  -(1/N_k) sum_munu Mvv[k'][mu][v'][v] W_munu(k' - k) Mcc[k'][nu][c][c'];
+    the exchange sum over k' is taken inside, (alpha/N_k) M_cv(k,k) Vbar (sum_k' M_v'c'(k',k') X(k')).
+    Returns [len(rows)*nc*nv][nb]."""
+    alpha = prob.alpha if alpha is None else alpha
+    nv, nc, Nk = prob.nv, prob.nc, prob.Nk
+    nt = nc * nv
+    val, con = _bands(prob)
+    pv, pc = _psi_sets(prob)
+    C = prob.C
+    X = np.asarray(X).reshape(Nk, nt, -1)           # [k][(c v)][b]
+    nb = X.shape[2]
+    Xr = X.reshape(Nk, nc, nv, nb)
+    # exchange: t[nu][b] = sum_k' sum_{v'c'} M^nu_{v'c'}(k',k') X[(c' v' k')][b]
+    t = np.zeros((prob.n_aux, nb), dtype=np.complex128)
+    for k0 in range(0, Nk, chunk):
+        ks = slice(k0, min(Nk, k0 + chunk))
+        K = ks.stop - ks.start
+        Cpc = np.tensordot(C, pc[ks], axes=([2], [2]))                            # [nu][s][K][c']  C^nu psi_c'(k')
+        Cpc = np.transpose(Cpc, (2, 1, 0, 3)).reshape(K, prob.n_ao, -1)           # [K][s][(nu c')]
+        Mvc = np.matmul(pv[ks].conj(), Cpc).reshape(K, nv, prob.n_aux, nc)        # [K][v'][nu][c']
+        Mvc = np.transpose(Mvc, (0, 2, 1, 3))                                     # [K][nu][v'][c'] = M^nu_{v'c'}(k',k')
+        # t[nu][b] += sum over (k', v', c') of Mvc[k'][nu][v'][c'] X[k'][c'][v'][b]
+        t += np.transpose(Mvc, (1, 0, 2, 3)).reshape(prob.n_aux, -1) @ \
+            np.transpose(Xr[ks], (0, 2, 1, 3)).reshape(-1, nb)
+    u = prob.Vbar @ t                                                             # u[mu] = sum_nu Vbar[mu][nu] t[nu]
+    qtab = np.array([[q_index(prob.nk, k, kp) for kp in range(Nk)] for k in rows])
+    eps_t = transition_energies(prob)
+    out = np.zeros((len(rows), nt, nb), dtype=np.complex128)
+    for i, k in enumerate(rows):
+        Mcv = pair_density(prob.psi, C, k, con, k, val)                           # [mu][c][v]
+        out[i] += (alpha / Nk) * np.einsum("mcv,mb->cvb", Mcv, u).reshape(nt, nb)
+        out[i] += eps_t[k][:, None] * X[k]
+        Cv = np.matmul(C, pv[k].T)                                                # [mu][s][v]  (C^mu psi_v(k))
+        Bc = np.matmul(pc[k].conj()[None], C)                                     # [nu][c][t]  (psi_c(k)^H C^nu)
+        for k0 in range(0, Nk, chunk):
+            ks = slice(k0, min(Nk, k0 + chunk))
+            K = ks.stop - ks.start
+            Mvv = np.tensordot(pv[ks].conj(), Cv, axes=([2], [1]))                # [K][v'][mu][v]
+            Mvv = np.transpose(Mvv, (0, 2, 1, 3)).reshape(K, prob.n_aux, nv * nv)  # [K][mu][(v' v)]
+            Mcc = np.tensordot(Bc, pc[ks], axes=([2], [2]))                       # [nu][c][K][c']
+            Mcc = np.transpose(Mcc, (2, 1, 3, 0)).reshape(K, nc * nc, prob.n_aux)  # [K][(c c')][nu]
+            W = W_q[qtab[i, ks]]                                                  # [K][mu][nu]
+            t2 = np.matmul(np.transpose(W, (0, 2, 1)), Mvv)                       # [K][nu][(v' v)]
+            D = -(1.0 / Nk) * np.matmul(Mcc, t2)                                  # [K][(c c')][(v' v)]
+            D = np.transpose(D.reshape(K, nc, nc, nv, nv), (0, 1, 4, 2, 3)).reshape(K, nt, nt)  # [(c v)][(c' v')]
+            out[i] += np.transpose(D, (1, 0, 2)).reshape(nt, K * nt) @ X[ks].reshape(K * nt, nb)   # sum_k' D X(k')
+    return out.reshape(len(rows) * nt, nb)
+
+
+def grad_Wq_at(prob, Ybar, X, qs, chunk=64):
+    """g_Wq[q] of L = Re sum conj(Ybar) (H X) for the q in `qs` (the W part of grad_apply), every k of a q
+    at once:  g_Wq[q]_munu = -(1/N_k) sum_{k, k' = k + q} sum_{cvc'v'} conj(M^mu_{v'v}(k',k)) conj(M^nu_{cc'}(k,k'))
+    G[(c v)][(c' v')],  G = Ybar(k) X(k')^H.  Returns [len(qs)][n_aux][n_aux]."""
+    nv, nc, Nk, na = prob.nv, prob.nc, prob.Nk, prob.n_aux
+    nt = nc * nv
+    pv, pc = _psi_sets(prob)
+    C = prob.C
+    Ybar = np.asarray(Ybar).reshape(Nk, nt, -1)
+    X = np.asarray(X).reshape(Nk, nt, -1)
+    out = np.zeros((len(qs), na, na), dtype=np.complex128)
+    n = np.array(prob.nk)
+    kidx = np.array(np.unravel_index(np.arange(Nk), prob.nk)).T                  # [Nk][3] mesh coordinates
+    for i, q in enumerate(qs):
+        # k' = k + q on the mesh, i.e. q_index(k, k') = q
+        kps = np.ravel_multi_index(tuple(((kidx + np.array(np.unravel_index(q, prob.nk))) % n).T), prob.nk)
+        for k0 in range(0, Nk, chunk):
+            ks = np.arange(k0, min(Nk, k0 + chunk))
+            kp = kps[ks]
+            K = len(ks)
+            Cv = np.tensordot(C, pv[ks], axes=([2], [2]))                         # [mu][s][K][v]  C^mu psi_v(k)
+            Cv = np.transpose(Cv, (2, 1, 0, 3)).reshape(K, prob.n_ao, -1)         # [K][s][(mu v)]
+            Mvv = np.matmul(pv[kp].conj(), Cv).reshape(K, nv, na, nv)             # [K][v'][mu][v]
+            Mvv = np.transpose(Mvv, (0, 2, 1, 3))                                 # [K][mu][v'][v]  M^mu_{v'v}(k',k)
+            Cc = np.tensordot(C, pc[kp], axes=([2], [2]))                         # [nu][s][K][c']  C^nu psi_c'(k')
+            Cc = np.transpose(Cc, (2, 1, 0, 3)).reshape(K, prob.n_ao, -1)         # [K][s][(nu c')]
+            Mcc = np.matmul(pc[ks].conj(), Cc).reshape(K, nc, na, nc)             # [K][c][nu][c']
+            Mcc = np.transpose(Mcc, (0, 2, 1, 3))                                 # [K][nu][c][c']  M^nu_{cc'}(k,k')
+            G = np.matmul(Ybar[ks], np.transpose(X[kp].conj(), (0, 2, 1)))        # [K][(c v)][(c' v')]
+            G = np.transpose(G.reshape(K, nc, nv, nc, nv), (0, 1, 3, 4, 2)).reshape(K, nc * nc, nv * nv)  # [(c c')][(v' v)]
+            Z = np.matmul(Mcc.conj().reshape(K, na, nc * nc), G)                  # [K][nu][(v' v)]
+            # sum over (k, v', v) of conj(Mvv[k][mu][(v' v)]) Z[k][nu][(v' v)]
+            A = np.transpose(Mvv.conj().reshape(K, na, nv * nv), (1, 0, 2)).reshape(na, -1)
+            Bz = np.transpose(Z, (1, 0, 2)).reshape(na, -1)
+            out[i] += -(1.0 / Nk) * (A @ Bz.T)
+    return out
+
+
+
+def grad_eps(prob, Ybar, X):
+    """The energy part of grad_apply alone: d/d eps of L = Re sum conj(Ybar) (H X) through the diagonal
+    (E_ck - E_vk) of Eq. (Hamiltonian):  g[k][nv+c] = sum_v s_cvk,  g[k][v] = -sum_c s_cvk,
+    s_cvk = Re sum_b conj(Ybar_{cvk,b}) X_{cvk,b}."""
+    nv, nc, Nk = prob.nv, prob.nc, prob.Nk
+    s = np.real(np.sum(np.conj(np.asarray(Ybar)) * np.asarray(X), axis=1)).reshape(Nk, nc, nv)
+    g = np.zeros((Nk, nv + nc))
+    g[:, nv:] = s.sum(axis=2)
+    g[:, :nv] = -s.sum(axis=1)
+    return g
 
 def grad_lowest(prob, W_q, H=None, alpha=None):
     """dOmega_1/d(eps, W_q): Hellmann-Feynman, dOmega_1 = x^H dH x with x the lowest eigenvector."""

@@ -61,12 +61,13 @@ __global__ __launch_bounds__(256) void u_direct_b3(UArgs u) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int nv2 = u.nv * u.nv;
-  // 1-D grid over (k, c, q group), XCD-aware: all blocks of one k share B_c(k) and P(k, .)
+  // 1-D grid over (k, q group, c), XCD-aware: all blocks of one k share B_c(k) and P(k, .); the n_c
+  // blocks that read one column group of P run back to back
   const int nqg = (u.nq + u.qg - 1) / u.qg;
   long long kl, t;
   xcd_map(blockIdx.x, (long long)u.nc * nqg, u.Nk, kl, t);
-  const int k = (int)kl, c = (int)(t / nqg);
-  const int qbase = (int)(t % nqg) * u.qg;  // batch-local index of the first q of the group
+  const int k = (int)kl, c = (int)(t % u.nc);
+  const int qbase = (int)(t / u.nc) * u.qg;  // batch-local index of the first q of the group
   const int ncol = min(u.qg, u.nq - qbase) * nv2;
   const int na = u.na, no = u.no, Nk = u.Nk;
 
@@ -207,8 +208,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMW == 1 ? 
   const int nqg = (u.nq + u.qg - 1) / u.qg;
   long long kl, t;
   xcd_map(blockIdx.x, (long long)u.nc * nqg, u.Nk, kl, t);
-  const int k = (int)kl, c = (int)(t / nqg);
-  const int qbase = (int)(t % nqg) * u.qg;
+  const int k = (int)kl, c = (int)(t % u.nc);  // c fastest: the n_c blocks of one P column group in a row
+  const int qbase = (int)(t / u.nc) * u.qg;
   const int ncol = min(u.qg, u.nq - qbase) * nv2;
   const int na = u.na, no = u.no, Nk = u.Nk;
   const int nK = na / BK;
