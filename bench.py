@@ -29,6 +29,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+CONDUCTION = None  # BF16x3 conduction route ("mc", "u" or the plan's choice)
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2516.6 / 3.0}
 HBM_PEAK_GBS = 8000.0
 
@@ -45,32 +46,32 @@ def f_apply(Nk, n_ao, nv, nc, n_aux, nb, q_formed=None):
                  + 2 * Nk * nc * nv * n_aux * nb + n_aux ** 2 * nb) + 2 * N * nb)
 
 
-def kernel_flops_per_pair(p, prec):
+def kernel_flops_per_pair(p, prec, route="mc"):
     """Algorithmic flops per (k, k') pair of each single-kernel stage of the direct term.
 
     wstep      P = conj(M_v) W(q)              8 n_aux^2 nv^2
     pairdens_v M_vv' from the halves            8 n_aux n_ao nv^2
-    pairdens_c M_cc' from the halves            8 n_aux n_ao nc^2      (FP64 / FP32 paths)
-    dblock     FP64 / FP32: T = M_c P^T         8 n_aux nc^2 nv^2
-               BF16x3: U = B_c^T P^T and T = psi U (conduction pair densities never formed)
+    pairdens_c M_cc' from the halves            8 n_aux n_ao nc^2      (route "mc")
+    dblock     route "mc": T = M_c P^T          8 n_aux nc^2 nv^2
+               route "u" (BF16x3): U = B_c^T P^T and T = psi U (conduction pair densities never formed)
                                                 8 nc n_ao n_aux nv^2 + 8 nc^2 n_ao nv^2
     """
     na, no, nv, nc = p.n_aux, p.n_ao, p.nv, p.nc
     d = {"wstep": 8 * na * na * nv * nv, "pairdens_c": 8 * na * no * nc * nc,
          "pairdens_v": 8 * na * no * nv * nv, "dblock": 8 * na * nc * nc * nv * nv}
-    if prec == "bf16x3":
+    if route == "u":
         d["dblock"] = 8 * nc * no * na * nv * nv + 8 * nc * nc * no * nv * nv
     return d
 
 
-def kernel_bytes_per_pair(p, prec):
+def kernel_bytes_per_pair(p, prec, route="mc"):
     """Algorithmic HBM bytes per (k, k') pair of the single-kernel stages (each operand once)."""
     na, no, nv, nc, Nk = p.n_aux, p.n_ao, p.nv, p.nc, p.Nk
     e = 16 if prec == "f64" else 8
     return {"wstep": e * (2 * nv * nv * na) + e * na * na / Nk,
             "pairdens_v": e * nv * nv * na + e * (nv * na * no) / Nk,
             "pairdens_c": e * nc * nc * na + e * (nc * na * no) / Nk,
-            "dblock": (e * nv * nv * na + 8 * nc * nc * nv * nv + e * nc * no * na / Nk) if prec == "bf16x3"
+            "dblock": (e * nv * nv * na + 8 * nc * nc * nv * nv + e * nc * no * na / Nk) if route == "u"
             else e * (nc * nc * na + nv * nv * na) + e * nc * nc * nv * nv}
 
 
@@ -97,12 +98,17 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=2)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
+    ap.add_argument("--conduction", default="auto", choices=["auto", "mc", "u"],
+                    help="BF16x3 conduction side of the direct term: the plan's choice (auto), forming the "
+                         "conduction pair densities (mc) or the B_c(k) contraction (u)")
     ap.add_argument("--mode", default="spectrum", choices=["spectrum", "precision", "gradients", "largest"],
                     help="spectrum: the timed pipeline (default); precision: per-precision apply and "
                          "short-Haydock errors on a larger workload; gradients: LOBPCG and spectrum "
                          "gradients checked by central finite differences; largest: one BF16x3 apply and "
                          "adjoint on the 16x16x16 / N_ao = 128 workload")
     args = ap.parse_args()
+    global CONDUCTION
+    CONDUCTION = None if args.conduction == "auto" else args.conduction
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus %d is not supported" % args.gpus,
@@ -150,7 +156,7 @@ def main():
     def step(prec, timing=False):
         Wq = B.interpolate_W(d_WR, p.R, p.w_R, kq)
         plan = B.Plan(p.nk, p.n_ao, p.nv, p.nc, p.n_aux, d_eps, d_psi, d_C, d_V, Wq, alpha=p.alpha,
-                      prec=prec, max_nb=nb)
+                      prec=prec, max_nb=nb, conduction=CONDUCTION if prec == "bf16x3" else None)
         plan.set_R(p.R, p.w_R)
         if timing:
             plan.set_timing(True)
@@ -159,11 +165,12 @@ def main():
         g = plan.apply_adjoint(P, P, want_WR=True, want_eps=True)
         st = plan.stage_times() if timing else None
         pairs[prec] = plan.pairs
+        routes[prec] = plan.conduction
         plan.close()
         del Wq, P, g
         return out, st
 
-    pairs = {}
+    pairs, routes = {}, {}
 
     # FP64 reference (untimed): spectrum and step time
     sync()
@@ -205,7 +212,7 @@ def main():
     print("[bench] timed: %s %.3f s/step -> %.1f GFLOP/s" % (prec, dt, value), file=sys.stderr, flush=True)
 
     # roofline of the dominant single kernel (event-timed on the library's stream)
-    fpp = kernel_flops_per_pair(p, prec)
+    fpp = kernel_flops_per_pair(p, prec, routes[prec])
     cand = {k: v for k, v in st_all.items() if k in fpp and v[1] > 0}
     dom = max(cand, key=lambda k: cand[k][0])
     ms, n = cand[dom]
@@ -219,7 +226,7 @@ def main():
     roof = {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[prec],
             "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[prec],
             "traffic": traffic["bytes_per_launch"] if traffic else None,
-            "algorithmic_bytes_per_launch": kernel_bytes_per_pair(p, prec)[dom] * pairs_per_launch,
+            "algorithmic_bytes_per_launch": kernel_bytes_per_pair(p, prec, routes[prec])[dom] * pairs_per_launch,
             "avg_launch_ms": ms / n, "launches": n, "pairs_per_launch": pairs_per_launch}
 
     cpu = None
@@ -250,6 +257,7 @@ def main():
         "pct_mfma_peak_apply": m * Fx / dt / 1e12 / PEAK_TFLOPS[prec],
         "pct_mfma_peak_apply_F_apply": value / 1e3 / PEAK_TFLOPS[prec],
         "stage_ms_last_step": stages,
+        "conduction": routes[prec],
     }
     print(json.dumps(rec), flush=True)
 
@@ -279,7 +287,7 @@ def precision_mode(config, m):
     for prec in ["f64", "bf16x3", "f32"]:
         Wq = B.interpolate_W(W_R, p.R, p.w_R, kq)
         plan = B.Plan(p.nk, p.n_ao, p.nv, p.nc, p.n_aux, eps, T(p.psi), T(p.C), T(p.Vbar), Wq, alpha=p.alpha,
-                      prec=prec, max_nb=nb)
+                      prec=prec, max_nb=nb, conduction=CONDUCTION if prec == "bf16x3" else None)
         del Wq
         torch.cuda.synchronize()
         t0 = time.time()
@@ -319,7 +327,7 @@ def largest_mode(config):
     t_interp = time.time() - t0
     t0 = time.time()
     plan = B.Plan(p.nk, p.n_ao, p.nv, p.nc, p.n_aux, T(p.eps_qp, torch.float64), T(p.psi), T(p.C), T(p.Vbar), Wq,
-                  alpha=p.alpha, prec="bf16x3", max_nb=nb)
+                  alpha=p.alpha, prec="bf16x3", max_nb=nb, conduction=CONDUCTION)
     plan.set_R(p.R, p.w_R)
     del Wq
     torch.cuda.synchronize()
@@ -355,7 +363,7 @@ def largest_mode(config):
                                        "BSE dim %d, blocks of %d" %
         (config, "x".join(map(str, p.nk)), "x".join(map(str, p.coarse)), p.n_ao, p.nv, p.nc, p.n_aux,
          CONFIGS[config]["r_cut"], p.N, nb),
-        "prec": "bf16x3", "plan_GB": plan.bytes / 2**30, "interpolate_s": t_interp, "plan_s": t_plan,
+        "prec": "bf16x3", "conduction": plan.conduction, "plan_GB": plan.bytes / 2**30, "interpolate_s": t_interp, "plan_s": t_plan,
         "apply_s": ta, "F_apply_TFLOP": Fa / 1e12, "apply_GFLOP_s": Fa / ta / 1e9,
         "pct_mfma_peak_apply_F_apply": Fa / ta / 1e12 / PEAK_TFLOPS["bf16x3"],
         "direct_pairs": {"q_formed": qf, "q_total": qt, "F_apply_executed_TFLOP": Fx / 1e12},

@@ -63,6 +63,8 @@ typedef enum { BSE_F64 = 0, BSE_F32 = 1, BSE_BF16X3 = 2 } bse_prec;
 
 #define BSE_CHECK_HERMITIAN 1u   /* plan_create: verify C^mu and Vbar Hermitian */
 #define BSE_ALL_PAIRS 2u         /* plan_create: form every (k, k') block of the direct term */
+#define BSE_CONDUCTION_MC 4u     /* plan_create, BF16X3: form the conduction pair densities M_cc' */
+#define BSE_CONDUCTION_U 8u      /* plan_create, BF16X3: contract B_c(k) with the W step instead  */
 
 typedef struct {
     int32_t nk[3];       /* dense Gamma-centred mesh n1, n2, n3 (Sec. IV.A.3)                */
@@ -121,6 +123,14 @@ bse_status bse_interpolate_W_adjoint(int32_t n_aux, int32_t n_R, const int32_t* 
  * the q equal to their own negative) and takes the others from the relation,
  * about half of the direct-term work.  BSE_ALL_PAIRS forms every block.
  * bse_plan_pairs reports which mode a plan uses.
+ * Conduction side of the direct term on BF16X3 (FP64 / FP32 always form M_cc'):
+ * either the pair densities M^nu_cc'(k,k') = B^nu_c(k) psi_c'(k') are formed and
+ * the block taken as sum_nu M_cc' P (BSE_CONDUCTION_MC), or B_c(k) is contracted
+ * with P first and psi_c'(k') applied last, so M_cc' never exists
+ * (BSE_CONDUCTION_U; needs n_v^2 <= 128 and n_ao <= 128).  Both compute the same
+ * sums; without either flag the plan takes the one with the smaller estimated
+ * time (matrix-core work against the M_cc' traffic), bse_plan_conduction tells
+ * which.  Giving both flags is BSE_EINVAL.
  * On success *out receives the plan (destroy with bse_plan_destroy).
  * ------------------------------------------------------------------------- */
 bse_status bse_plan_create(const bse_dims* d, const double* eps_qp, const void* psi,
@@ -140,6 +150,11 @@ bse_status bse_plan_set_eps(bse_plan* plan, const double* eps_qp, void* hip_stre
  * forms (*formed) out of *total = N_k: N_k with BSE_ALL_PAIRS or when the
  * pair symmetry does not hold, about N_k / 2 otherwise.  Host pointers. */
 bse_status bse_plan_pairs(const bse_plan* plan, int64_t* formed, int64_t* total);
+
+/* *forms_mc = 1 when the plan's direct term forms the conduction pair densities
+ * M_cc' (always on FP64 / FP32), 0 when it uses the B_c(k) contraction (BF16X3).
+ * Host pointer. */
+bse_status bse_plan_conduction(const bse_plan* plan, int32_t* forms_mc);
 
 /* Device bytes held by the plan (copies, halves and workspaces). */
 bse_status bse_plan_bytes(const bse_plan* plan, uint64_t* bytes);

@@ -22,6 +22,7 @@ PREC = {"f64": 0, "f32": 1, "bf16x3": 2}
 BSE_OK, BSE_INFO_BREAKDOWN, BSE_INFO_NOT_CONVERGED = 0, 100, 101
 CHECK_HERMITIAN = 1
 ALL_PAIRS = 2
+CONDUCTION = {None: 0, "mc": 4, "u": 8}
 
 
 class BSEError(RuntimeError):
@@ -48,6 +49,7 @@ _SIGS = {
     "bse_plan_set_eps": [_vp, _vp, _vp],
     "bse_plan_bytes": [_vp, ctypes.POINTER(ctypes.c_uint64)],
     "bse_plan_pairs": [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
+    "bse_plan_conduction": [_vp, ctypes.POINTER(ctypes.c_int32)],
     "bse_apply": [_vp, _vp, _vp, _i32, _vp],
     "bse_apply_adjoint": [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp],
     "bse_velocity_start": [_vp, _vp, _vp, _i32, _vp, _vp, _vp],
@@ -153,7 +155,7 @@ class Plan:
     """A TDA-BSE problem resident on one GPU (halves, rho, W_q and workspaces)."""
 
     def __init__(self, nk, n_ao, nv, nc, n_aux, eps_qp, psi, C, Vbar, W_q, alpha=2.0, prec="f64",
-                 max_nb=8, check_hermitian=False, all_pairs=False):
+                 max_nb=8, check_hermitian=False, all_pairs=False, conduction=None):
         self.nk = tuple(int(x) for x in nk)
         self.Nk = int(np.prod(self.nk))
         self.n_ao, self.nv, self.nc, self.n_aux = int(n_ao), int(nv), int(nc), int(n_aux)
@@ -171,7 +173,8 @@ class Plan:
             _dev(C, torch.complex128, (self.n_aux, self.n_ao, self.n_ao), "C"),
             _dev(Vbar, torch.complex128, (self.n_aux, self.n_aux), "Vbar"),
             _dev(W_q, torch.complex128, (self.Nk, self.n_aux, self.n_aux), "W_q"),
-            PREC[prec], self.max_nb, (CHECK_HERMITIAN if check_hermitian else 0) | (ALL_PAIRS if all_pairs else 0),
+            PREC[prec], self.max_nb,
+            (CHECK_HERMITIAN if check_hermitian else 0) | (ALL_PAIRS if all_pairs else 0) | CONDUCTION[conduction],
             _stream(self.device), ctypes.byref(h))
         _check("bse_plan_create", s)
         self._ptr = h
@@ -199,6 +202,13 @@ class Plan:
         f, t = ctypes.c_int64(), ctypes.c_int64()
         _check("bse_plan_pairs", lib().bse_plan_pairs(self._ptr, ctypes.byref(f), ctypes.byref(t)))
         return int(f.value), int(t.value)
+
+    @property
+    def conduction(self):
+        """'mc' when the direct term forms the conduction pair densities, 'u' for the B_c(k) contraction."""
+        v = ctypes.c_int32()
+        _check("bse_plan_conduction", lib().bse_plan_conduction(self._ptr, ctypes.byref(v)))
+        return "mc" if v.value else "u"
 
     @property
     def bytes(self):
@@ -324,11 +334,12 @@ class Plan:
         return {"W_R": gWR, "W_q": gWq, "eps": geps}
 
 
-def plan_from_problem(prob, W_q, prec="f64", max_nb=8, device="cuda:0", check_hermitian=False, all_pairs=False):
+def plan_from_problem(prob, W_q, prec="f64", max_nb=8, device="cuda:0", check_hermitian=False, all_pairs=False,
+                      conduction=None):
     """Build a Plan from a synthetic crystal (inputs copied host -> device)."""
     dev = torch.device(device)
     t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)
     return Plan(prob.nk, prob.n_ao, prob.nv, prob.nc, prob.n_aux, t(prob.eps_qp, torch.float64),
                 t(prob.psi, torch.complex128), t(prob.C, torch.complex128), t(prob.Vbar, torch.complex128),
                 W_q, alpha=prob.alpha, prec=prec, max_nb=max_nb, check_hermitian=check_hermitian,
-                all_pairs=all_pairs)
+                all_pairs=all_pairs, conduction=conduction)

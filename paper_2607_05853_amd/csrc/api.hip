@@ -205,7 +205,23 @@ hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 // split (the BF16x3 apply never forms them; its adjoint allocates them on first use)
 size_t per_q_bytes(const Plan* p) {
   const long long Nk = p->Nk, nv = p->d.nv, nc = p->d.nc, na = p->d.n_aux;
-  return p->esz * (size_t)(Nk * nv * nv * na * 2 + (p->split ? 0 : Nk * nc * nc * na) + Nk * nc * nc * nv * nv);
+  return p->esz * (size_t)(Nk * nv * nv * na * 2 + (p->mc_direct ? Nk * nc * nc * na : 0) + Nk * nc * nc * nv * nv);
+}
+
+// BF16X3 conduction side: estimated time per pair of forming M_cc' (pair-density GEMM, T = M_c P^T on
+// 128 x 128 tiles, M_cc' written and read once) against the B_c(k) contraction (U = B_c^T P^T on tiles
+// of 64 or 128 AO rows and 128 columns holding floor(128 / n_v^2) whole q, then psi_c'(k') on the
+// matrix cores), both with the tile padding they execute; 250 TFLOP/s and 4 TB/s are the measured
+// orders of the kernels (16^3 / N_ao = 128: 0.42 against 1.09 us per pair; 12^3 / N_ao = 96: 0.45
+// against 0.65; 8^3 / N_ao = 64: U at 0.075)
+bool prefer_mc(const bse_dims& d) {
+  const double na = d.n_aux, no = d.n_ao, nv = d.nv, nc = d.nc;
+  auto up = [](double x, double t) { return std::ceil(x / t) * t; };
+  const double t_mc = 8.0 * (na * no * nc * nc + up(nc * nc, 128) * up(nv * nv, 128) * na) / 250e12 +
+                      16.0 * nc * nc * na / 4e12;
+  const double cols = 128.0 / std::floor(128.0 / (nv * nv));  // tile columns per pair
+  const double t_u = 8.0 * (nc * up(no, 64) * na * cols + nc * nc * no * nv * nv) / 250e12;
+  return t_mc < t_u;
 }
 
 bse_status check_hermitian(const void* C, const void* Vbar, const bse_dims* d, hipStream_t st) {
@@ -510,6 +526,18 @@ bse_status build_plan(Plan* p, const bse_dims* d, const double* eps_qp, const vo
     BSE_HIP(hipStreamSynchronize(st));
   }
 
+  // conduction side of the direct term
+  if (p->split) {
+    const bool u_ok = (long long)nv * nv <= 128 && no <= 128;
+    if (flags & BSE_CONDUCTION_U) {
+      p->mc_direct = 0;
+    } else if (flags & BSE_CONDUCTION_MC) {
+      p->mc_direct = 1;
+    } else {
+      p->mc_direct = (!u_ok || prefer_mc(*d)) ? 1 : 0;
+    }
+  }
+
   // direct-term workspaces: at least 12 GiB, more where 16 q per batch need it and 40 % of the free
   // device memory allows (short q batches leave the pair-density tiles mostly empty)
   {
@@ -531,7 +559,7 @@ bse_status build_plan(Plan* p, const bse_dims* d, const double* eps_qp, const vo
     p->ps_Mc = nq * Nk * nc * nc * na;
     p->ps_T = nq * Nk * nc * nc * nv * nv;
     BSE_TRY(plan_alloc(p, &p->P, p->esz * (size_t)(nq * Nk * nv * nv * na)));
-    if (!p->split) BSE_TRY(plan_alloc(p, &p->Mc, p->esz * (size_t)(nq * Nk * nc * nc * na)));
+    if (p->mc_direct) BSE_TRY(plan_alloc(p, &p->Mc, p->esz * (size_t)(nq * Nk * nc * nc * na)));
     BSE_TRY(plan_alloc(p, &p->T, p->esz * (size_t)(nq * Nk * nc * nc * nv * nv)));
     BSE_TRY(plan_alloc(p, (void**)&p->tab_psi_v, sizeof(long long) * (size_t)(nq * Nk * nv)));
     BSE_TRY(plan_alloc(p, (void**)&p->tab_mv, sizeof(long long) * (size_t)(nq * Nk * nv)));
@@ -649,9 +677,23 @@ bse_status bse_plan_create(const bse_dims* d, const double* eps_qp, const void* 
       return BSE_ESHAPE;
     }
   }
-  if (flags & ~(BSE_CHECK_HERMITIAN | BSE_ALL_PAIRS)) {
+  if ((flags & BSE_CONDUCTION_MC) && (flags & BSE_CONDUCTION_U)) {
+    set_error("bse_plan_create: BSE_CONDUCTION_MC and BSE_CONDUCTION_U exclude each other");
+    return BSE_EINVAL;
+  }
+  if (flags & ~(BSE_CHECK_HERMITIAN | BSE_ALL_PAIRS | BSE_CONDUCTION_MC | BSE_CONDUCTION_U)) {
     set_error("bse_plan_create: unknown flags");
     return BSE_EINVAL;
+  }
+  if (flags & BSE_CONDUCTION_U) {
+    if (prec != BSE_BF16X3) {
+      set_error("bse_plan_create: BSE_CONDUCTION_U applies to BSE_BF16X3 only");
+      return BSE_EINVAL;
+    }
+    if ((long long)d->nv * d->nv > 128 || d->n_ao > 128) {
+      set_error("bse_plan_create: BSE_CONDUCTION_U needs nv^2 <= 128 and n_ao <= 128");
+      return BSE_ESHAPE;
+    }
   }
   if (flags & BSE_CHECK_HERMITIAN) BSE_TRY(check_hermitian(C, Vbar, d, S(hip_stream)));
   bse_plan* h = new (std::nothrow) bse_plan();
@@ -677,6 +719,15 @@ bse_status bse_plan_pairs(const bse_plan* plan, int64_t* formed, int64_t* total)
   const Plan& p = plan->impl;
   *formed = p.herm_half ? p.nhalf : p.Nk;
   *total = p.Nk;
+  return BSE_OK;
+}
+
+bse_status bse_plan_conduction(const bse_plan* plan, int32_t* forms_mc) {
+  if (!plan || bad_ptr(forms_mc)) {
+    set_error("bse_plan_conduction: NULL argument");
+    return BSE_EINVAL;
+  }
+  *forms_mc = plan->impl.mc_direct;
   return BSE_OK;
 }
 

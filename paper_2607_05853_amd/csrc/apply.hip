@@ -441,7 +441,7 @@ bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t
   const int* kq = p->herm_half ? p->kqp : p->kq;
   for (int q0 = 0; q0 < nqt; q0 += p->qb) {
     const int nq = (nqt - q0) < p->qb ? (nqt - q0) : p->qb;
-    BSE_TRY(form_pair_densities(p, q0, nq, !p->split, kq, st));
+    BSE_TRY(form_pair_densities(p, q0, nq, p->mc_direct, kq, st, p->split));
     {  // P = conj(Gv) W(q)
     StageMark sm_(p, BSE_STAGE_WSTEP, st);
       GemmArgs g;
@@ -476,7 +476,7 @@ bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t
         BSE_TRY(cgemm(g, ar, f64, f64, st));
       }
     }
-    if (p->split) {  // T from B_c(k) and P without the conduction pair densities
+    if (!p->mc_direct) {  // T from B_c(k) and P without the conduction pair densities (BF16X3)
       StageMark sm_(p, BSE_STAGE_DBLOCK, st);
       BSE_TRY(direct_u_b3(p, q0, nq, kq, st));
     } else {  // T = Mc P^T over nu
@@ -498,7 +498,13 @@ bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t
       g.c_sb = (long long)nc * nc * nv * nv;
       g.c_si = nv * nv;
       g.c_sj = 1;
-      BSE_TRY(cgemm(g, ar, f64, f64, st));
+      if (p->split) {  // both operands pre-split, T in c64
+        g.a_ps = p->ps_Mc;
+        g.b_ps = p->ps_Mv;
+        BSE_TRY(cgemm_split(g, true, true, false, false, st));
+      } else {
+        BSE_TRY(cgemm(g, ar, f64, f64, st));
+      }
     }
     {
       StageMark sm_(p, BSE_STAGE_TX, st);

@@ -143,6 +143,8 @@ struct Plan {
   // pair symmetry of the apply: q order with the self-conjugate q first, then one q of each pair
   // {q, -q}, then their partners; kqp[k][j] = k + q_j, kqm[k][j] = k - q_j in that order
   int herm_half = 0, nself = 0, nhalf = 0;
+  // conduction side: 1 = form M_cc' and T = M_c P^T (FP64 / FP32 always), 0 = B_c(k) contraction (BF16X3)
+  int mc_direct = 1;
   int* kqp = nullptr;
   int* kqm = nullptr;
 

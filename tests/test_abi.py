@@ -68,7 +68,11 @@ def test_plan_create_validation_before_hip(L):
     assert args(_dims(), ptr=None) == 1
     assert args(_dims(), prec=5) == 1
     assert args(_dims(), nb=0) == 1
-    assert args(_dims(), flags=8) == 1
+    assert args(_dims(), flags=16) == 1                  # unknown flag
+    assert args(_dims(), prec=2, flags=4 | 8) == 1       # both conduction routes
+    assert args(_dims(), prec=0, flags=8) == 1           # the B_c contraction is a BF16x3 route
+    assert args(_dims(nv=12), prec=2, flags=8) == 2      # nv^2 > 128
+    assert args(_dims(n_ao=136), prec=2, flags=8) == 2   # n_ao > 128
     assert args(_dims(nv=32, nc=32), nb=4) == 2          # nv*nc*max_nb above the limit
     assert args(_dims(nk=(2048, 2048, 2))) == 2          # too many k points
     assert L.bse_plan_create(None, dummy, dummy, dummy, dummy, dummy, 0, 4, 0, None, ctypes.byref(out)) == 1
@@ -86,6 +90,8 @@ def test_null_plan_calls(L):
     assert L.bse_velocity_start(None, dummy, dummy, 1, dummy, dummy, None) == 1
     a, b = ctypes.c_int64(), ctypes.c_int64()
     assert L.bse_plan_pairs(None, ctypes.byref(a), ctypes.byref(b)) == 1
+    c = ctypes.c_int32()
+    assert L.bse_plan_conduction(None, ctypes.byref(c)) == 1
 
 
 def test_binding_rejects_cpu_tensors():

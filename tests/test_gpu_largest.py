@@ -42,8 +42,8 @@ def big():
     plan.set_R(p.R, p.w_R)
     del Wq
     torch.cuda.empty_cache()
-    print("\n[largest] problem and plan %.1f s, plan %.1f GB, pairs %s" % (time.time() - t0, plan.bytes / 2**30,
-                                                                           plan.pairs), flush=True)
+    print("\n[largest] problem and plan %.1f s, plan %.1f GB, pairs %s, conduction route %s" %
+          (time.time() - t0, plan.bytes / 2**30, plan.pairs, plan.conduction), flush=True)
     W = O.interpolate_W_matmul(p.W_R, p.R, p.w_R, kq)
     print("[largest] oracle W(q) %.1f s" % (time.time() - t0), flush=True)
     yield dict(B=B, p=p, plan=plan, W=W, T=T)

@@ -184,6 +184,22 @@ def test_apply_dma_shapes(B, prec, shape):
     assert err < TOL[prec]
 
 
+@pytest.mark.parametrize("route", ["mc", "u"])
+@pytest.mark.parametrize("shape", ["mesh4_ao16", "RAGGED", "DMA", "DMA_MT", "DMA_ODD"])
+def test_bf16x3_conduction_routes(B, shape, route):
+    # the two BF16x3 routes of the conduction side: forming M_cc' and T = M_c P^T (the split GEMM; N_aux = 40
+    # in RAGGED takes its register-staged fallback) or the B_c(k) contraction of direct_b3
+    conf = {"mesh4_ao16": "mesh4_ao16", "RAGGED": RAGGED, "DMA": DMA, "DMA_MT": DMA_MT, "DMA_ODD": DMA_ODD}[shape]
+    p = make_problem(conf, 2, "G2", coarse=(3, 3, 2))
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
+    plan = B.plan_from_problem(p, Wq, prec="bf16x3", max_nb=4, conduction=route)
+    assert plan.conduction == route
+    X = random_block(p.N, 4, seed=9)
+    err = rel(H_(plan.apply(T(X))), O.build_H(p, H_(Wq)) @ X)
+    print("[conduction %s %s] rel err %.3e" % (shape, route, err), flush=True)
+    assert err < TOL["bf16x3"]
+
+
 def test_apply_c3_properties(B):
     # 12x12x12 dense mesh, N_ao = 96, n_v = 6, n_c = 10, N_aux = 384 (BSE dim 103680): the oracle needs
     # minutes per k row here, so this size is checked through properties that hold at any size:
