@@ -780,6 +780,113 @@ __global__ __launch_bounds__(256) void cgemm_b3_dma(GemmArgs g) {
   }
 }
 
+// 64 x 64 tiles of the same product for small per-pair matrices (the direct block T = M_c P^T has
+// n_c^2 x n_v^2 entries, 64 x 64 at n_c = n_v = 8, where a 128 x 128 tile would be three quarters
+// empty): four waves of one 32 x 32 tile each, waves 0 and 1 stage the A rows, 2 and 3 the B columns.
+// Each accumulator receives the same MFMA sequence as in cgemm_b3_dma, so the results are identical.
+template <typename TC>
+__global__ __launch_bounds__(256) void cgemm_b3_dma64(GemmArgs g) {
+  constexpr int BM = 64, BN = 64, BK = 16, NS = 2;
+  constexpr int PL = BM * BK;
+  constexpr int STAGE = 8 * PL;
+  __shared__ __attribute__((aligned(1024))) __bf16 smem[NS * STAGE];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int nK = g.K / BK;
+  const int gxn = (g.N + BN - 1) / BN, gyn = (g.M + BM - 1) / BM;
+  const long long per_batch = (long long)gxn * gyn;
+  long long bl, t;
+  xcd_map(blockIdx.x, per_batch, g.batch, bl, t);
+  const int b = (int)bl;
+  const int m0 = (int)(t / gxn) * BM, n0 = (int)(t % gxn) * BN;
+  // DMA slot: row 32 (wave % 2) + lane / 2 of A (waves 0, 1) or of B (waves 2, 3), 16-byte chunk as above
+  const bool isB = wave >= 2;
+  const int drow = 32 * (wave & 1) + (lane >> 1);
+  const int dch = (lane & 1) ^ ((drow >> 3) & 1);
+  const __bf16* src;
+  long long ps;
+  if (!isB) {
+    const int arow = (m0 + drow < g.M) ? m0 + drow : m0;
+    src = (const __bf16*)g.A + off_of(g.a_tab, g.a_tab_pb, g.a_sb, g.a_si, b, g.M, arow) + 8 * dch;
+    ps = g.a_ps;
+  } else {
+    const int bcol = (n0 + drow < g.N) ? n0 + drow : n0;
+    src = (const __bf16*)g.B + off_of(g.b_tab, g.b_tab_pb, g.b_sb, g.b_sj, b, g.N, bcol) + 8 * dch;
+    ps = g.b_ps;
+  }
+  const int loff = (isB ? 4 * PL : 0) + 32 * (wave & 1) * BK;
+  auto issue = [&](int kt) {
+    __bf16* st = smem + (kt % NS) * STAGE + loff;
+    const int kb = kt * BK;
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl)
+      __builtin_amdgcn_global_load_lds((const void*)(src + pl * ps + kb),
+                                       (__attribute__((address_space(3))) void*)(st + pl * PL), 16, 0, 0);
+  };
+  f16v accR, accI;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    accR[r] = 0.f;
+    accI[r] = 0.f;
+  }
+  issue(0);
+  const int ch = lane >> 5;
+  for (int kt = 0; kt < nK; ++kt) {
+    vm_lds_barrier<0>();
+    if (kt + 1 < nK) issue(kt + 1);
+    const __bf16* sa = smem + (kt % NS) * STAGE;
+    const __bf16* sb = sa + 4 * PL;
+    bf8v a[4], bb[4];
+    {
+      const int row = wm * 32 + (lane & 31);
+      const int o = row * BK + 8 * (ch ^ ((row >> 3) & 1));
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) a[pl] = *reinterpret_cast<const bf8v*>(sa + pl * PL + o);
+    }
+    {
+      const int col = wn * 32 + (lane & 31);
+      const int o = col * BK + 8 * (ch ^ ((col >> 3) & 1));
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) bb[pl] = *reinterpret_cast<const bf8v*>(sb + pl * PL + o);
+      if (g.conjB) {
+        bb[2] = neg8(bb[2]);
+        bb[3] = neg8(bb[3]);
+      }
+    }
+    const bf8v nih = neg8(a[2]), nil = neg8(a[3]);
+    const bf8v rh = g.conjA ? a[2] : nih, rl = g.conjA ? a[3] : nil;
+    const bf8v ih = g.conjA ? nih : a[2], il = g.conjA ? nil : a[3];
+    accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], bb[0], accR, 0, 0, 0);
+    accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], bb[2], accI, 0, 0, 0);
+    accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], bb[1], accR, 0, 0, 0);
+    accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], bb[3], accI, 0, 0, 0);
+    accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rl, bb[2], accR, 0, 0, 0);
+    accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(il, bb[0], accI, 0, 0, 0);
+    accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rh, bb[3], accR, 0, 0, 0);
+    accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ih, bb[1], accI, 0, 0, 0);
+    accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], bb[0], accR, 0, 0, 0);
+    accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], bb[2], accI, 0, 0, 0);
+    accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rh, bb[2], accR, 0, 0, 0);
+    accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ih, bb[0], accI, 0, 0, 0);
+  }
+  // register r holds row 8 (r / 4) + 4 (lane / 32) + r % 4, column lane % 32 of the wave's tile
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = m0 + wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    const int col = n0 + wn * 32 + (lane & 31);
+    if (row >= g.M || col >= g.N) continue;
+    const long long ro = off_of(g.c_tab, g.c_tab_pb, g.c_sb, g.c_si, b, g.M, row);
+    TC* o = (TC*)g.C + 2 * (ro + (long long)col * g.c_sj);
+    double vr = g.alpha * (double)accR[r], vi = g.alpha * (double)accI[r];
+    if (g.beta) {
+      vr += (double)o[0];
+      vi += (double)o[1];
+    }
+    o[0] = (TC)vr;
+    o[1] = (TC)vi;
+  }
+}
+
 // ----------------------------------------------------------------------------
 // BF16X3, both operands pre-split and k-major:  C[b][m][n] = sum_k A[b][k][m] B[b][k][n]
 //
@@ -1083,6 +1190,15 @@ bse_status cgemm_split(const GemmArgs& g, bool a_split, bool b_split, bool c_spl
     return BSE_ESHAPE;
   }
   if (a_split && b_split && dma_ok(g)) {
+    if (!c_split && g.M <= 64 && g.N <= 64) {  // small per-pair products: quarter-size tiles
+      const long long tiles = (long long)g.batch;
+      if (out_f64)
+        hipLaunchKernelGGL(cgemm_b3_dma64<double>, dim3((unsigned)tiles), dim3(256), 0, st, g);
+      else
+        hipLaunchKernelGGL(cgemm_b3_dma64<float>, dim3((unsigned)tiles), dim3(256), 0, st, g);
+      BSE_CHECK_LAUNCH();
+      return BSE_OK;
+    }
     if (c_split) return launch_dma<true, float>(g, st);
     return out_f64 ? launch_dma<false, double>(g, st) : launch_dma<false, float>(g, st);
   }
