@@ -497,6 +497,8 @@ bse_status build_plan(Plan* p, const bse_dims* d, const double* eps_qp, const vo
       BSE_TRY(plan_alloc(p, (void**)&p->kqm, sizeof(int) * hm.size()));
       BSE_HIP(hipMemcpyAsync(p->kqp, hp.data(), sizeof(int) * hp.size(), hipMemcpyHostToDevice, st));
       BSE_HIP(hipMemcpyAsync(p->kqm, hm.data(), sizeof(int) * hm.size(), hipMemcpyHostToDevice, st));
+      BSE_TRY(plan_alloc(p, (void**)&p->qord, sizeof(int) * Nk));
+      BSE_HIP(hipMemcpyAsync(p->qord, order.data(), sizeof(int) * Nk, hipMemcpyHostToDevice, st));
       // the W step reads W(q) in this order: permute the plan's copy once
       int* dorder = nullptr;
       void* tmp = nullptr;

@@ -212,19 +212,23 @@ __global__ void adj_gm_kernel(int Nk, int nq, int q0, int nv, int nc, int nb, co
 }
 
 // GmT[qi][k][(c' c)][(v' v)] = sum_b Ybar[k][(c v)][b] conj(X[k'][(c' v')][b]) as four bf16 planes (plane
-// stride ps): the k-major operand of Z = Gm conj(Mc) on the BF16x3 path
+// stride ps): the k-major operand of Z = Gm conj(Mc) on the BF16x3 path, k' = k + q.  SWAP forms the
+// operand of the partner gradient g_W(-q) from the same pairs instead:
+//   G'T[qi][k][(c c')][(v v')] = sum_b Ybar[k'][(c v)][b] conj(X[k][(c' v')][b]).
+template <bool SWAP>
 __global__ void adj_gmT_split_kernel(int Nk, int nq, int q0, int nv, int nc, int nb, const int* __restrict__ kq,
                                      const double* __restrict__ Yb, const double* __restrict__ X,
                                      __bf16* __restrict__ G, long long ps) {
   const int k = blockIdx.x % Nk, qi = blockIdx.x / Nk;
   const int nt = nc * nv, nt2 = nt * nt, nv2 = nv * nv;
   const int kp = kq[(long long)k * Nk + q0 + qi];
-  const double* y = Yb + 2 * (long long)k * nt * nb;
-  const double* x = X + 2 * (long long)kp * nt * nb;
+  const double* y = Yb + 2 * (long long)(SWAP ? kp : k) * nt * nb;
+  const double* x = X + 2 * (long long)(SWAP ? k : kp) * nt * nb;
   __bf16* out = G + ((long long)qi * Nk + k) * nt2;
   for (int e = threadIdx.x; e < nt2; e += blockDim.x) {
-    const int col = e / nv2, row = e % nv2;  // col = (c' c), row = (v' v)
-    const int cp = col / nc, c = col % nc, vp = row / nv, v = row % nv;
+    const int col = e / nv2, row = e % nv2;  // col = (first c, second c), row = (first v, second v)
+    const int cp = SWAP ? col % nc : col / nc, c = SWAP ? col / nc : col % nc;
+    const int vp = SWAP ? row % nv : row / nv, v = SWAP ? row / nv : row % nv;
     const double* yr = y + 2 * (long long)(c * nv + v) * nb;
     const double* xr = x + 2 * (long long)(cp * nv + vp) * nb;
     double sr = 0, si = 0;
@@ -537,6 +541,75 @@ bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t
   return BSE_OK;
 }
 
+// One q batch of the k-major BF16x3 adjoint: Z = Gm conj(Mc) (or, for the partner, Z' = G' Mc) written
+// pre-split into P, then g_W of the batch's q = -(1/N_k) sum over pairs of Gv^T Z (conj(Gv)^T Z'), stored
+// at the W-gradient index given by dst (plan-order q -> dense-mesh q) or at q0 + i without a table
+bse_status adjoint_tn_pass(Plan* p, int q0, int i0, int nq, bool swap, const int* kq, const int* dst,
+                           const double* Ybar, const double* X, int nb, double* gWq, bool acc, hipStream_t st) {
+  const int Nk = p->Nk, nv = p->d.nv, nc = p->d.nc, na = p->d.n_aux;
+  const long long pair_v = (long long)nv * nv * na, pair_c = (long long)nc * nc * na;
+  const long long nt2 = (long long)nc * nc * nv * nv;
+  __bf16* G = (__bf16*)p->T + (long long)i0 * Nk * nt2;
+  if (swap)
+    hipLaunchKernelGGL(adj_gmT_split_kernel<true>, dim3(nq * Nk), dim3(256), 0, st, Nk, nq, q0 + i0, nv, nc, nb, kq,
+                       Ybar, X, G, p->ps_T);
+  else
+    hipLaunchKernelGGL(adj_gmT_split_kernel<false>, dim3(nq * Nk), dim3(256), 0, st, Nk, nq, q0 + i0, nv, nc, nb, kq,
+                       Ybar, X, G, p->ps_T);
+  BSE_CHECK_LAUNCH();
+  {  // Z[(v'v)][nu] = sum_{c'c} Gm[(v'v)][(c'c)] conj(Mc[(c'c)][nu]); the partner: Z' = sum G'[.][(c c')] Mc[(c c')]
+    GemmArgs g;
+    g.batch = nq * Nk;
+    g.M = nv * nv;
+    g.N = na;
+    g.K = nc * nc;
+    g.A = G;
+    g.a_sb = nt2;
+    g.a_si = 1;
+    g.a_sk = nv * nv;
+    g.a_ps = p->ps_T;
+    g.B = (const __bf16*)p->Mc + (long long)i0 * Nk * pair_c;
+    g.b_sb = pair_c;
+    g.b_sk = na;
+    g.b_sj = 1;
+    g.b_ps = p->ps_Mc;
+    g.conjB = swap ? 0 : 1;
+    g.C = (__bf16*)p->P + (long long)i0 * Nk * pair_v;
+    g.c_sb = pair_v;
+    g.c_si = na;
+    g.c_sj = 1;
+    g.c_ps = p->ps_Mv;
+    BSE_TRY(cgemm_split(g, true, true, true, false, st));
+  }
+  {  // gWq[q][mu][nu] = -(1/N_k) sum_{(k v' v)} Gv[(k v' v)][mu] Z[(k v' v)][nu]   (conj(Gv) for the partner)
+    GemmArgs g;
+    g.batch = nq;
+    g.M = na;
+    g.N = na;
+    g.K = Nk * nv * nv;
+    g.A = (const __bf16*)p->Mv + (long long)i0 * Nk * pair_v;
+    g.a_sb = (long long)Nk * pair_v;
+    g.a_si = 1;
+    g.a_sk = na;
+    g.a_ps = p->ps_Mv;
+    g.conjA = swap ? 1 : 0;
+    g.B = (const __bf16*)p->P + (long long)i0 * Nk * pair_v;
+    g.b_sb = (long long)Nk * pair_v;
+    g.b_sk = na;
+    g.b_sj = 1;
+    g.b_ps = p->ps_Mv;
+    g.C = dst ? gWq : gWq + 2 * (long long)(q0 + i0) * na * na;
+    g.c_bidx = dst ? dst + q0 + i0 : nullptr;
+    g.c_sb = (long long)na * na;
+    g.c_si = na;
+    g.c_sj = 1;
+    g.alpha = -1.0 / (double)Nk;
+    g.beta = acc ? 1 : 0;
+    BSE_TRY(cgemm_split(g, true, true, false, true, st));
+  }
+  return BSE_OK;
+}
+
 bse_status adjoint_direct(Plan* p, const double* Ybar, const double* X, int nb, double* gWq, bool acc,
                           hipStream_t st) {
   const bse_dims& d = p->d;
@@ -546,14 +619,33 @@ bse_status adjoint_direct(Plan* p, const double* Ybar, const double* X, int nb, 
   // BF16x3 with 8-aligned n_v^2 and N_aux: every operand pre-split, both reductions on the k-major kernel
   const bool tn = p->split && (nv * nv) % 8 == 0 && na % 8 == 0;
   if (!p->Mc) BSE_TRY(plan_alloc(p, &p->Mc, p->esz * (size_t)p->qb * Nk * nc * nc * na));
+  if (tn && p->herm_half) {
+    // pair symmetry of the gradient: with Hermitian C^mu the pairs (k, k - q) of g_W(-q) carry the pair
+    // densities of (k - q, k), M_vv'(k, k-q) = conj M_v'v(k-q, k) and M_c'c(k-q, k) = conj M_cc'(k, k-q),
+    // so the pair densities of one q of each pair {q, -q} serve both gradients:
+    //   g_W(-q) = -(1/N_k) sum_{k, k' = k + q} sum conj(Gv[(v v')]) Mc[(c c')] Ybar(k')[(c v)] conj X(k)[(c' v')]
+    for (int q0 = 0; q0 < p->nhalf; q0 += p->qb) {
+      const int nq = (p->nhalf - q0) < p->qb ? (p->nhalf - q0) : p->qb;
+      BSE_TRY(form_pair_densities(p, q0, nq, true, p->kqp, st, true));
+      StageMark sm_(p, BSE_STAGE_ADJOINT, st);
+      BSE_TRY(adjoint_tn_pass(p, q0, 0, nq, false, p->kqp, p->qord, Ybar, X, nb, gWq, acc, st));
+      // partners: plan-order q j >= nself, whose -q sits at j + (nhalf - nself) of the order
+      const int i0 = q0 < p->nself ? std::min(nq, p->nself - q0) : 0;
+      if (i0 < nq)
+        BSE_TRY(adjoint_tn_pass(p, q0, i0, nq - i0, true, p->kqp, p->qord + (p->nhalf - p->nself), Ybar, X, nb,
+                                gWq, acc, st));
+    }
+    return BSE_OK;
+  }
   for (int q0 = 0; q0 < Nk; q0 += p->qb) {
     const int nq = (Nk - q0) < p->qb ? (Nk - q0) : p->qb;
     BSE_TRY(form_pair_densities(p, q0, nq, true, p->kq, st, tn));
     StageMark sm_(p, BSE_STAGE_ADJOINT, st);
-    if (tn)
-      hipLaunchKernelGGL(adj_gmT_split_kernel, dim3(nq * Nk), dim3(256), 0, st, Nk, nq, q0, nv, nc, nb, p->kq, Ybar,
-                         X, (__bf16*)p->T, p->ps_T);
-    else if (f64)
+    if (tn) {
+      BSE_TRY(adjoint_tn_pass(p, q0, 0, nq, false, p->kq, nullptr, Ybar, X, nb, gWq, acc, st));
+      continue;
+    }
+    if (f64)
       hipLaunchKernelGGL(adj_gm_kernel<double>, dim3(nq * Nk), dim3(256), 0, st, Nk, nq, q0, nv, nc, nb, p->kq,
                          Ybar, X, (double*)p->T);
     else
@@ -567,6 +659,9 @@ bse_status adjoint_direct(Plan* p, const double* Ybar, const double* X, int nb, 
       g.N = na;
       g.K = nc * nc;
       g.A = p->T;
+      g.a_sb = (long long)nc * nc * nv * nv;
+      g.a_si = nc * nc;
+      g.a_sk = 1;
       g.B = p->Mc;
       g.b_sb = (long long)nc * nc * na;
       g.b_sk = na;
@@ -576,20 +671,7 @@ bse_status adjoint_direct(Plan* p, const double* Ybar, const double* X, int nb, 
       g.c_sb = (long long)nv * nv * na;
       g.c_si = na;
       g.c_sj = 1;
-      if (tn) {  // A = GmT [(c'c)][(v'v)], Z written pre-split
-        g.a_sb = (long long)nc * nc * nv * nv;
-        g.a_si = 1;
-        g.a_sk = nv * nv;
-        g.a_ps = p->ps_T;
-        g.b_ps = p->ps_Mc;
-        g.c_ps = p->ps_Mv;
-        BSE_TRY(cgemm_split(g, true, true, true, false, st));
-      } else {
-        g.a_sb = (long long)nc * nc * nv * nv;
-        g.a_si = nc * nc;
-        g.a_sk = 1;
-        BSE_TRY(cgemm(g, ar, f64, f64, st));
-      }
+      BSE_TRY(cgemm(g, ar, f64, f64, st));
     }
     {  // gWq[q][mu][nu] = -(1/N_k) sum_{(k v' v)} Gv[(k v' v)][mu] Z[(k v' v)][nu]
       GemmArgs g;
@@ -613,8 +695,7 @@ bse_status adjoint_direct(Plan* p, const double* Ybar, const double* X, int nb, 
       g.beta = acc ? 1 : 0;
       if (p->split) {
         g.a_ps = p->ps_Mv;
-        g.b_ps = p->ps_Mv;
-        BSE_TRY(cgemm_split(g, true, tn, false, true, st));
+        BSE_TRY(cgemm_split(g, true, false, false, true, st));
       } else {
         BSE_TRY(cgemm(g, ar, f64, true, st));
       }

@@ -77,6 +77,8 @@ struct GemmArgs {
   long long a_ps = 0, b_ps = 0, c_ps = 0;
   // set by the caller when every table offset (a_tab, b_tab) is a multiple of 8 elements
   int tab_aligned = 0;
+  // k-major kernel with a c128 result: batch entry b of the product is stored at C batch c_bidx[b]
+  const int* c_bidx = nullptr;
 };
 
 // in_f64: A and B are c128 (else c64); out_f64: C is c128 (else c64).
@@ -147,6 +149,7 @@ struct Plan {
   int mc_direct = 1;
   int* kqp = nullptr;
   int* kqm = nullptr;
+  int* qord = nullptr;              // [Nk] dense-mesh index of the j-th q of that order
 
   // exchange / misc workspaces (FP64)
   double* xt = nullptr;       // c128 split-K partials [nsplit][n_aux][max_nb]

@@ -1032,7 +1032,8 @@ __global__ __launch_bounds__(256) void cgemm_b3_tn(GemmArgs g, int nsplit, int k
   }
 }
 
-// C[b][m][n] = alpha * sum_s part[b][s][m][n] (+ C if beta), splits added in order; C is c128
+// C[b'][m][n] = alpha * sum_s part[b][s][m][n] (+ C if beta), splits added in order; C is c128 and
+// b' = c_bidx[b] when a batch index table is given
 __global__ void tn_reduce(GemmArgs g, int nsplit, const double* __restrict__ part) {
   const long long mn = (long long)g.M * g.N, n = mn * g.batch;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
@@ -1044,7 +1045,8 @@ __global__ void tn_reduce(GemmArgs g, int nsplit, const double* __restrict__ par
       sr += v.x;
       si += v.y;
     }
-    double* o = (double*)g.C + 2 * (b * g.c_sb + (long long)row * g.c_si + (long long)col * g.c_sj);
+    const long long bo = g.c_bidx ? (long long)g.c_bidx[b] : b;
+    double* o = (double*)g.C + 2 * (bo * g.c_sb + (long long)row * g.c_si + (long long)col * g.c_sj);
     double vr = g.alpha * sr, vi = g.alpha * si;
     if (g.beta) {
       vr += o[0];
@@ -1154,6 +1156,10 @@ bool tn_ok(const GemmArgs& g) {
 bse_status launch_tn(const GemmArgs& g, bool c_split, hipStream_t st) {
   const long long tiles = (long long)((g.N + 127) / 128) * ((g.M + 127) / 128) * g.batch;
   if (c_split) {
+    if (g.c_bidx) {
+      set_error("cgemm_b3_tn: a batch index table needs a c128 result");
+      return BSE_EINVAL;
+    }
     hipLaunchKernelGGL(cgemm_b3_tn<true>, dim3((unsigned)tiles), dim3(256), 0, st, g, 1, g.K, (double*)nullptr);
     BSE_CHECK_LAUNCH();
     return BSE_OK;
@@ -1189,6 +1195,11 @@ bse_status cgemm_split(const GemmArgs& g, bool a_split, bool b_split, bool c_spl
     set_error("cgemm_split: K must be positive");
     return BSE_ESHAPE;
   }
+  if (g.c_bidx) {  // only the k-major kernel scatters its batches
+    if (a_split && b_split && !c_split && out_f64 && !dma_ok(g) && tn_ok(g)) return launch_tn(g, false, st);
+    set_error("cgemm_split: a batch index table needs the k-major kernel");
+    return BSE_EINVAL;
+  }
   if (a_split && b_split && dma_ok(g)) {
     if (!c_split && g.M <= 64 && g.N <= 64) {  // small per-pair products: quarter-size tiles
       const long long tiles = (long long)g.batch;
@@ -1221,6 +1232,10 @@ bse_status cgemm_split(const GemmArgs& g, bool a_split, bool b_split, bool c_spl
 
 bse_status cgemm(const GemmArgs& g, Arith ar, bool in_f64, bool out_f64, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return BSE_OK;
+  if (g.c_bidx) {
+    set_error("cgemm: batch index tables are for the k-major split kernel only");
+    return BSE_EINVAL;
+  }
   if (g.K <= 0) {
     set_error("cgemm: K must be positive");
     return BSE_ESHAPE;

@@ -4,7 +4,7 @@ apply and adjoint.
 
 The explicit H (262144^2) is out of reach, so the oracle evaluates sampled outputs one at a time from
 their definition (its row-at-a-time forms, pinned against the block forms on small meshes): two k rows
-of H X and the W(q) gradient at one q; the energy gradient is checked everywhere.  Tolerance as for
+of H X and the W(q) gradient at one pair {q, -q}; the energy gradient is checked everywhere.  Tolerance as for
 every BF16x3 contraction: 5e-4 relative to the largest reference element of the sample.  The module
 takes a few minutes, most of it the oracle on the host cores."""
 import time
@@ -19,7 +19,8 @@ from synth import dense_kmesh, make_problem, random_block
 pytestmark = pytest.mark.gpu
 
 ROWS = [0, 2731]   # k = Gamma and a generic k
-Q = 1234           # a q with q != -q on the mesh
+QS = [1234, 3134]  # a q with q != -q on the mesh and its partner -q (the gradient of the pair comes from the
+                   # pair densities of one of them)
 
 
 def rel(a, b):
@@ -77,13 +78,13 @@ def test_largest_adjoint_sampled_q(big):
     # g_WR is the interpolation adjoint of g_Wq (FP64 on both sides)
     gr = B.interpolate_W_adjoint(g["W_q"], p.R, p.w_R, dense_kmesh(p.nk))
     assert (g["W_R"] - gr).abs().max().item() <= 1e-12 * gr.abs().max().item()
-    gq = g["W_q"][Q].cpu().numpy()
+    gq = g["W_q"][QS].cpu().numpy()
     ge = g["eps"].cpu().numpy()
     del g, gr
     torch.cuda.empty_cache()
     assert rel(ge, O.grad_eps(p, Yb, X)) < 1e-13
     t0 = time.time()
-    ref = O.grad_Wq_at(p, Yb, X, [Q])[0]
+    ref = O.grad_Wq_at(p, Yb, X, QS)
     err = rel(gq, ref)
     print("[largest] oracle g_W(q) %.1f s, rel err %.2e" % (time.time() - t0, err), flush=True)
     assert err < 5e-4

@@ -338,18 +338,22 @@ ADJ_TN = dict(cfg_id=80, coarse=(2, 2, 2), dense=(3, 2, 2), n_ao=16, nv=4, nc=3,
 ADJ_SPLIT = dict(cfg_id=81, coarse=(2, 2, 2), dense=(4, 4, 2), n_ao=16, nv=8, nc=2, n_aux=24)
 
 
+@pytest.mark.parametrize("all_pairs", [False, True])
 @pytest.mark.parametrize("cfg", ["ADJ_TN", "ADJ_SPLIT"])
-def test_apply_adjoint_kmajor(B, cfg):
+def test_apply_adjoint_kmajor(B, cfg, all_pairs):
+    # all_pairs=False: the gradient of each q pair {q, -q} from one set of pair densities
     conf = {"ADJ_TN": ADJ_TN, "ADJ_SPLIT": ADJ_SPLIT}[cfg]
     p = make_problem(conf, 6, "G2", coarse=(3, 3, 2))
-    plan, Wq = _plan(B, p, "bf16x3", nb=4)
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
+    plan = B.plan_from_problem(p, Wq, prec="bf16x3", max_nb=4, all_pairs=all_pairs)
+    assert (plan.pairs[0] < p.Nk) == (not all_pairs)
     plan.set_R(p.R, p.w_R)
     Yb, X = random_block(p.N, 4, seed=31), random_block(p.N, 4, seed=32)
     g = plan.apply_adjoint(T(Yb), T(X), want_WR=True, want_Wq=True, want_eps=True)
     ge, gq = O.grad_apply(p, H_(Wq), Yb, X)
     gr = O.grad_WR_from_Wq(gq, p.R, p.w_R, dense_kmesh(p.nk))
     eq, er = rel(H_(g["W_q"]), gq), rel(H_(g["W_R"]), gr)
-    print("[adjoint k-major %s] W_q %.2e W_R %.2e" % (cfg, eq, er), flush=True)
+    print("[adjoint k-major %s all_pairs=%s] W_q %.2e W_R %.2e" % (cfg, all_pairs, eq, er), flush=True)
     assert rel(H_(g["eps"]), ge) < 1e-13
     assert eq < 5e-4 and er < 5e-4
 
