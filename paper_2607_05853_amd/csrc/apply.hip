@@ -42,33 +42,67 @@ __global__ void tables_kernel(int Nk, int nq, int q0, int nv, int nc, int nbnd, 
 // k' = k + q_j with j = q0 + qi in the order of kqp (block (k, chunk), chunks of qlen consecutive q).
 // For j >= nself the partner block is added too: D(k, k - q) = D(k - q, k)^dagger, i.e.
 //   part += sum_{c'v'} conj(T[qi][k''][(c c')][(v v')]) X[k''][(c' v')][b],   k'' = kqm[k][j] = k - q_j.
+// The (q, pass) items of a chunk are staged in LDS `group` at a time (one T block and one X slice each,
+// 16-byte loads where the block size allows), so one pair of barriers serves several items; every
+// thread adds the items in the same order as one item at a time.
+constexpr size_t TX_STAGE_BYTES = 12 * 1024;  // LDS budget of the staged T.X items per block (occupancy first)
+
 template <typename TT, int SLOTS>
 __global__ __launch_bounds__(256) void direct_tx_kernel(int Nk, int nq, int q0, int nv, int nc, int nb, int qlen,
                                                         const int* __restrict__ kqp, const int* __restrict__ kqm,
-                                                        int nself, const TT* __restrict__ T,
+                                                        int nself, int group, int x16, const TT* __restrict__ T,
                                                         const double* __restrict__ X, double* __restrict__ part) {
-  extern __shared__ double smem[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char sbytes[];
   const int k = blockIdx.x, chunk = blockIdx.y;
   const int nt = nc * nv, nt2 = nt * nt;
-  TT* Ts = reinterpret_cast<TT*>(smem);                       // [nt2] complex
-  double* Xs = reinterpret_cast<double*>(Ts + 2 * (size_t)nt2);  // [nt*nb] complex
+  const int tbytes = nt2 * 2 * (int)sizeof(TT);
+  const int tstride = (tbytes + 15) & ~15;
+  const int item_bytes = tstride + nt * nb * 16;
+  const bool t16 = (tbytes & 15) == 0;  // T blocks are then 16-byte aligned in global memory as well
   const int nout = nt * nb;  // SLOTS outputs per thread: nt * nb <= SLOTS * 256
   double accr[SLOTS], acci[SLOTS];
 #pragma unroll
   for (int r = 0; r < SLOTS; ++r) accr[r] = acci[r] = 0.0;
   const int qa = chunk * qlen, qe = min(nq, qa + qlen);
-  for (int qi = qa; qi < qe; ++qi) {
-    const int j = q0 + qi;
-    const int npass = j >= nself ? 2 : 1;
-    for (int pass = 0; pass < npass; ++pass) {
-      const int kb = pass == 0 ? k : kqm[(long long)k * Nk + j];   // block row of the stored T
-      const int kx = pass == 0 ? kqp[(long long)k * Nk + j] : kb;  // k-point of the X slice
-      const TT* Tg = T + 2 * ((long long)qi * Nk + kb) * nt2;
+  // items in order: (qi, pass 0), then (qi, pass 1) when q0 + qi >= nself
+  int qi = qa, pass = 0;
+  while (qi < qe) {
+    // stage up to `group` items
+    int cnt = 0, sq = qi, sp = pass;
+    __syncthreads();
+    while (cnt < group && sq < qe) {
+      const int j = q0 + sq;
+      const int kb = sp == 0 ? k : kqm[(long long)k * Nk + j];  // block row of the stored T
+      const int kx = sp == 0 ? kqp[(long long)k * Nk + j] : kb;  // k-point of the X slice
+      const TT* Tg = T + 2 * ((long long)sq * Nk + kb) * nt2;
       const double* Xg = X + 2 * (long long)kx * nt * nb;
-      __syncthreads();
-      for (int i = threadIdx.x; i < 2 * nt2; i += blockDim.x) Ts[i] = Tg[i];
-      for (int i = threadIdx.x; i < 2 * nout; i += blockDim.x) Xs[i] = Xg[i];
-      __syncthreads();
+      unsigned char* slot = sbytes + (size_t)cnt * item_bytes;
+      if (t16) {
+        for (int i = threadIdx.x; i < tbytes / 16; i += blockDim.x)
+          reinterpret_cast<uint4*>(slot)[i] = reinterpret_cast<const uint4*>(Tg)[i];
+      } else {
+        for (int i = threadIdx.x; i < tbytes / 8; i += blockDim.x)
+          reinterpret_cast<uint2*>(slot)[i] = reinterpret_cast<const uint2*>(Tg)[i];
+      }
+      if (x16) {
+        for (int i = threadIdx.x; i < nout; i += blockDim.x)
+          reinterpret_cast<uint4*>(slot + tstride)[i] = reinterpret_cast<const uint4*>(Xg)[i];
+      } else {  // X given at 8-byte alignment only
+        for (int i = threadIdx.x; i < 2 * nout; i += blockDim.x)
+          reinterpret_cast<uint2*>(slot + tstride)[i] = reinterpret_cast<const uint2*>(Xg)[i];
+      }
+      ++cnt;
+      if (sp == 0 && j >= nself) {
+        sp = 1;
+      } else {
+        sp = 0;
+        ++sq;
+      }
+    }
+    __syncthreads();
+    for (int it = 0; it < cnt; ++it) {
+      const TT* Ts = reinterpret_cast<const TT*>(sbytes + (size_t)it * item_bytes);
+      const double* Xs = reinterpret_cast<const double*>(sbytes + (size_t)it * item_bytes + tstride);
 #pragma unroll
       for (int r = 0; r < SLOTS; ++r) {
         const int o = threadIdx.x + r * blockDim.x;
@@ -98,6 +132,13 @@ __global__ __launch_bounds__(256) void direct_tx_kernel(int Nk, int nq, int q0, 
         }
         accr[r] += sr;
         acci[r] += si;
+      }
+      // advance (qi, pass) in step with the staging order
+      if (pass == 0 && q0 + qi >= nself) {
+        pass = 1;
+      } else {
+        pass = 0;
+        ++qi;
       }
     }
   }
@@ -141,19 +182,21 @@ bse_status tx_set_attributes() {
 // outputs per thread: the smallest of 1, 2, 4, 8 that covers nt * nb over 256 threads
 template <typename TT>
 bse_status launch_tx(int slots, dim3 grid, size_t sh, hipStream_t st, int Nk, int nq, int q0, int nv, int nc, int nb,
-                     int qlen, const int* kqp, const int* kqm, int nself, const TT* T, const double* X, double* part) {
+                     int qlen, const int* kqp, const int* kqm, int nself, int group, const TT* T, const double* X,
+                     double* part) {
+  const int x16 = (reinterpret_cast<uintptr_t>(X) & 15) == 0 ? 1 : 0;
   if (slots <= 1)
     hipLaunchKernelGGL((direct_tx_kernel<TT, 1>), grid, dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, qlen, kqp, kqm,
-                       nself, T, X, part);
+                       nself, group, x16, T, X, part);
   else if (slots <= 2)
     hipLaunchKernelGGL((direct_tx_kernel<TT, 2>), grid, dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, qlen, kqp, kqm,
-                       nself, T, X, part);
+                       nself, group, x16, T, X, part);
   else if (slots <= 4)
     hipLaunchKernelGGL((direct_tx_kernel<TT, 4>), grid, dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, qlen, kqp, kqm,
-                       nself, T, X, part);
+                       nself, group, x16, T, X, part);
   else
     hipLaunchKernelGGL((direct_tx_kernel<TT, 8>), grid, dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, qlen, kqp, kqm,
-                       nself, T, X, part);
+                       nself, group, x16, T, X, part);
   BSE_CHECK_LAUNCH();
   return BSE_OK;
 }
@@ -512,7 +555,11 @@ bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t
     }
     {
       StageMark sm_(p, BSE_STAGE_TX, st);
-      const size_t sh = (size_t)nt * nt * p->esz + (size_t)nt * nb * 16;
+      // LDS per staged (q, pass) item: one T block (16-byte padded) and one X slice; up to 8 items in
+      // TX_STAGE_BYTES
+      const size_t item = (((size_t)nt * nt * p->esz + 15) & ~(size_t)15) + (size_t)nt * nb * 16;
+      const int group = (int)std::max<size_t>(1, std::min<size_t>(8, TX_STAGE_BYTES / item));
+      const size_t sh = item * group;
       const int nself = p->herm_half ? p->nself : nqt;  // q from index nself on also give partner blocks
       const double scale = -1.0 / (double)Nk;
       static bool attr_set = false;
@@ -527,10 +574,10 @@ bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t
       const dim3 grid((unsigned)Nk, (unsigned)nch);
       const int slots = (nt * nb + 255) / 256;
       if (f64)
-        BSE_TRY(launch_tx<double>(slots, grid, sh, st, Nk, nq, q0, nv, nc, nb, qlen, kq, p->kqm, nself,
+        BSE_TRY(launch_tx<double>(slots, grid, sh, st, Nk, nq, q0, nv, nc, nb, qlen, kq, p->kqm, nself, group,
                                   (const double*)p->T, X, p->txp));
       else
-        BSE_TRY(launch_tx<float>(slots, grid, sh, st, Nk, nq, q0, nv, nc, nb, qlen, kq, p->kqm, nself,
+        BSE_TRY(launch_tx<float>(slots, grid, sh, st, Nk, nq, q0, nv, nc, nb, qlen, kq, p->kqm, nself, group,
                                  (const float*)p->T, X, p->txp));
       const long long n = p->N * nb;
       hipLaunchKernelGGL(tx_reduce, dim3((unsigned)std::min<long long>((n + 255) / 256, 65536)), dim3(256), 0, st, n,
