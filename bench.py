@@ -466,6 +466,37 @@ def gradients_mode(config, m):
     res["dS_deps"] = {"adjoint": ane, "fd": fde}
     res["dS_dW_fd_rel_err"] = abs(fdW - anW) / abs(anW)
     res["dS_deps_fd_rel_err"] = abs(fde - ane) / abs(ane)
+
+    # the mixed-precision path: the same two gradients from a BF16x3 plan, against the FP64 adjoint ones
+    def relmax(a, b):
+        return float(np.abs(a - b).max() / np.abs(b).max())
+
+    Wq3 = B.interpolate_W(T(p.W_R), p.R, p.w_R, kq)
+    pl3 = B.Plan(p.nk, p.n_ao, p.nv, p.nc, p.n_aux, T(p.eps_qp, torch.float64), T(p.psi), T(p.C), T(p.Vbar), Wq3,
+                 alpha=p.alpha, prec="bf16x3", max_nb=max(nb, 64))
+    pl3.set_R(p.R, p.w_R)
+    t0 = time.time()
+    # Omega_1: Hellmann-Feynman through the BF16x3 adjoint with the FP64 eigenvector (block LOBPCG on the
+    # BF16x3 operator stalls above a 1e-7 residual)
+    _, Xl, _ = plan.lowest_excitons(n_block=nb, tol=1e-12, max_iter=500)
+    x1 = Xl[:, :1].contiguous()
+    g3 = pl3.apply_adjoint(x1, x1, want_WR=True, want_eps=True)
+    om3 = torch.real(torch.sum(torch.conj(x1) * pl3.apply(x1)))
+    W_R4 = T(p.W_R).requires_grad_(True)
+    eps4 = T(p.eps_qp, torch.float64).requires_grad_(True)
+    S3 = AG.haydock_spectrum(pl3, P, W_R4, eps4, m, omega, eta)
+    torch.sum(T(gamma, torch.float64) * S3).backward()
+    torch.cuda.synchronize()
+    res["bf16x3_vs_f64"] = {
+        "time_s": time.time() - t0,
+        "Omega1_rel_err": abs(om3.item() - res["Omega1_eV"]) / abs(res["Omega1_eV"]),
+        "dOmega1_dW_rel_err": relmax(g3["W_R"].cpu().numpy(), gW),
+        "dOmega1_deps_rel_err": relmax(g3["eps"].cpu().numpy(), ge),
+        "spectrum_rel_err": relmax(S3.detach().cpu().numpy(), S.detach().cpu().numpy()),
+        "dS_dW_rel_err": relmax(W_R4.grad.detach().cpu().numpy(), W_R2.grad.detach().cpu().numpy()),
+        "dS_deps_rel_err": relmax(eps4.grad.detach().cpu().numpy(), eps2.grad.detach().cpu().numpy())}
+    print("[gradients] bf16x3 %s" % json.dumps(res["bf16x3_vs_f64"]), file=sys.stderr, flush=True)
+    pl3.close()
     print(json.dumps({"mode": "gradients", "workload": "%s: dense %s, N_ao=%d, nv=%d, nc=%d, N_aux=%d, BSE dim %d, "
                                                       "LOBPCG block %d, spectrum at 64 frequencies, Haydock %d steps"
                       % (config, "x".join(map(str, p.nk)), p.n_ao, p.nv, p.nc, p.n_aux, p.N, nb, m),

@@ -25,6 +25,11 @@ def H_(t):
     return t.detach().cpu().numpy()
 
 
+def OW(p):
+    """The oracle's own W(q) on the dense mesh (oracle inputs never come from the GPU path)."""
+    return O.interpolate_W_matmul(p.W_R, p.R, p.w_R, dense_kmesh(p.nk))
+
+
 def rel(a, b):
     return np.abs(a - b).max() / np.abs(b).max()
 
@@ -65,7 +70,7 @@ def _admissible(p, seed, scale=1e-2):
 def test_lobpcg_lowest(B, cfg, wgen):
     p = make_problem(cfg, 0, wgen) if cfg == "mesh4_ao16" else make_problem(cfg, 0, wgen)
     plan, Wq = _plan(B, p, nb=4)
-    H = O.build_H(p, H_(Wq))
+    H = O.build_H(p, OW(p))
     ev, Z = np.linalg.eigh(H)
     om, x, it = plan.lowest_excitons(n_block=4, tol=1e-10, max_iter=500)
     print("[lobpcg] iterations %d, omega %s" % (it, om), flush=True)
@@ -82,7 +87,7 @@ def test_lowest_gradient_vs_oracle_and_fd(B):
     plan, Wq = _plan(B, p, W_R.detach(), eps.detach(), nb=4)
     om1 = AG.lowest_exciton_energy(plan, W_R, eps, n_block=4, tol=1e-12)
     om1.backward()
-    Om_ref, ge_ref, gq_ref = O.grad_lowest(p, H_(Wq))
+    Om_ref, ge_ref, gq_ref = O.grad_lowest(p, OW(p))
     gr_ref = O.grad_WR_from_Wq(gq_ref, p.R, p.w_R, dense_kmesh(p.nk))
     assert abs(om1.item() - Om_ref) < 1e-10
     assert rel(H_(eps.grad), ge_ref) < 1e-7
@@ -110,14 +115,15 @@ def test_apply_autograd_matches_explicit(B):
     eps = T(p.eps_qp, torch.float64).requires_grad_(True)
     plan, Wq = _plan(B, p, W_R.detach(), eps.detach(), nb=3)
     X = T(random_block(p.N, 3, seed=4)).requires_grad_(True)
-    Yb = T(random_block(p.N, 3, seed=6))
+    Yb_h = random_block(p.N, 3, seed=6)
+    Yb = T(Yb_h)
     Y = AG.apply(plan, X, W_R, eps)
     L = torch.real(torch.sum(torch.conj(Yb) * Y))
     L.backward()
-    H = O.build_H(p, H_(Wq))
-    ge, gq = O.grad_apply(p, H_(Wq), H_(Yb), H_(X))
+    H = O.build_H(p, OW(p))
+    ge, gq = O.grad_apply(p, OW(p), Yb_h, random_block(p.N, 3, seed=4))
     gr = O.grad_WR_from_Wq(gq, p.R, p.w_R, dense_kmesh(p.nk))
-    assert rel(H_(X.grad), H @ H_(Yb)) < 1e-12
+    assert rel(H_(X.grad), H @ Yb_h) < 1e-12
     assert rel(H_(eps.grad), ge) < 1e-12
     assert rel(H_(W_R.grad), gr) < 1e-11
 
@@ -136,7 +142,7 @@ def test_spectrum_vjp_full_krylov_vs_oracle(B):
     gamma = np.random.default_rng(3).standard_normal((2, len(w)))
     S = AG.haydock_spectrum(plan, T(P), W_R, eps, p.N, w, eta)
     torch.sum(T(gamma, torch.float64) * S).backward()
-    ge, gq = O.grad_spectrum(p, H_(Wq), P, w, eta, gamma)
+    ge, gq = O.grad_spectrum(p, OW(p), P, w, eta, gamma)
     gr = O.grad_WR_from_Wq(gq, p.R, p.w_R, dense_kmesh(p.nk))
     print("[spectrum vjp] eps %.2e W_R %.2e" % (rel(H_(eps.grad), ge), rel(H_(W_R.grad), gr)), flush=True)
     assert rel(H_(eps.grad), ge) < 1e-7
@@ -168,3 +174,49 @@ def test_spectrum_vjp_fd_converged_chain(B):
     fd = (f(p.eps_qp + h * de) - f(p.eps_qp - h * de)) / (2 * h)
     an = float(np.sum(H_(eps.grad) * de))
     assert abs(fd - an) < 1e-4 * max(abs(an), 1e-8)
+
+
+# BF16x3 gradients against the oracle's exact FP64 gradients, to the 1e-4 the mixed-precision path is held
+# to.  SMALL (N_aux = 20) runs the BF16x3 adjoint on the register-staged kernels, TN_GRAD (n_v^2 and N_aux
+# multiples of 8) on the k-major kernel with the pair-symmetric gradient
+TN_GRAD = dict(cfg_id=84, coarse=(3, 3, 2), dense=(3, 2, 2), n_ao=16, nv=4, nc=3, n_aux=40)
+TN_SPEC = dict(cfg_id=85, coarse=(3, 3, 2), dense=(2, 2, 2), n_ao=12, nv=4, nc=2, n_aux=24)
+
+
+@pytest.mark.parametrize("cfg", ["SMALL", "TN_GRAD"])
+def test_bf16x3_lowest_gradient_vs_oracle(B, cfg):
+    # Hellmann-Feynman gradient of Omega_1 through the BF16x3 adjoint, with the eigenvector of the FP64
+    # LOBPCG (block LOBPCG on the BF16x3 operator stalls above a 1e-7 residual; the gradient only needs x)
+    p = make_problem({"SMALL": SMALL, "TN_GRAD": TN_GRAD}[cfg], 1, "G2")
+    plan64, _ = _plan(B, p, prec="f64", nb=4)
+    om, X, _ = plan64.lowest_excitons(n_block=4, tol=1e-12, max_iter=500)
+    x = X[:, :1].contiguous()
+    plan, _ = _plan(B, p, prec="bf16x3", nb=4)
+    g = plan.apply_adjoint(x, x, want_WR=True, want_eps=True)
+    om16 = torch.real(torch.sum(torch.conj(x) * plan.apply(x))).item()
+    Om_ref, ge_ref, gq_ref = O.grad_lowest(p, OW(p))
+    gr_ref = O.grad_WR_from_Wq(gq_ref, p.R, p.w_R, dense_kmesh(p.nk))
+    e_om, e_e, e_w = abs(om16 - Om_ref) / abs(Om_ref), rel(H_(g["eps"]), ge_ref), rel(H_(g["W_R"]), gr_ref)
+    print("[bf16x3 grad Omega1 %s] Omega %.1e eps %.1e W_R %.1e" % (cfg, e_om, e_e, e_w), flush=True)
+    assert e_om < 1e-6 and e_e < 1e-4 and e_w < 1e-4
+
+
+@pytest.mark.parametrize("cfg", ["SPEC", "TN_SPEC"])
+def test_bf16x3_spectrum_vjp_vs_oracle(B, cfg):
+    from paper_2607_05853_amd import autograd as AG
+    conf = {"SPEC": dict(cfg_id=97, coarse=(3, 3, 2), dense=(2, 2, 2), n_ao=8, nv=2, nc=2, n_aux=12),
+            "TN_SPEC": TN_SPEC}[cfg]
+    p = make_problem(conf, 0, "G2")
+    W_R = T(p.W_R).requires_grad_(True)
+    eps = T(p.eps_qp, torch.float64).requires_grad_(True)
+    plan, _ = _plan(B, p, W_R.detach(), eps.detach(), prec="bf16x3", nb=2)
+    P = O.velocity_start(p, np.eye(3))[:, :2]
+    w = np.linspace(1.6, 3.2, 17)
+    gamma = np.random.default_rng(3).standard_normal((2, len(w)))
+    S = AG.haydock_spectrum(plan, T(P), W_R, eps, p.N, w, 0.1)  # full Krylov space: exact resolvent
+    torch.sum(T(gamma, torch.float64) * S).backward()
+    ge, gq = O.grad_spectrum(p, OW(p), P, w, 0.1, gamma)
+    gr = O.grad_WR_from_Wq(gq, p.R, p.w_R, dense_kmesh(p.nk))
+    e_e, e_w = rel(H_(eps.grad), ge), rel(H_(W_R.grad), gr)
+    print("[bf16x3 spectrum vjp %s] eps %.1e W_R %.1e" % (cfg, e_e, e_w), flush=True)
+    assert e_e < 1e-4 and e_w < 1e-4
