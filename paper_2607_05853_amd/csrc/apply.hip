@@ -265,8 +265,17 @@ __global__ void adj_gmT_split_kernel(int Nk, int nq, int q0, int nv, int nc, int
   const int k = blockIdx.x % Nk, qi = blockIdx.x / Nk;
   const int nt = nc * nv, nt2 = nt * nt, nv2 = nv * nv;
   const int kp = kq[(long long)k * Nk + q0 + qi];
-  const double* y = Yb + 2 * (long long)(SWAP ? kp : k) * nt * nb;
-  const double* x = X + 2 * (long long)(SWAP ? k : kp) * nt * nb;
+  const double* yg = Yb + 2 * (long long)(SWAP ? kp : k) * nt * nb;
+  const double* xg = X + 2 * (long long)(SWAP ? k : kp) * nt * nb;
+  // both slices in LDS (2 nt nb complex, at most 64 KiB): every output reads n_b values of each
+  extern __shared__ double gsm[];
+  double* y = gsm;
+  double* x = gsm + 2 * nt * nb;
+  for (int i = threadIdx.x; i < 2 * nt * nb; i += blockDim.x) {
+    y[i] = yg[i];
+    x[i] = xg[i];
+  }
+  __syncthreads();
   __bf16* out = G + ((long long)qi * Nk + k) * nt2;
   for (int e = threadIdx.x; e < nt2; e += blockDim.x) {
     const int col = e / nv2, row = e % nv2;  // col = (first c, second c), row = (first v, second v)
@@ -597,12 +606,13 @@ bse_status adjoint_tn_pass(Plan* p, int q0, int i0, int nq, bool swap, const int
   const long long pair_v = (long long)nv * nv * na, pair_c = (long long)nc * nc * na;
   const long long nt2 = (long long)nc * nc * nv * nv;
   __bf16* G = (__bf16*)p->T + (long long)i0 * Nk * nt2;
+  const size_t gsh = 2 * (size_t)nc * nv * nb * 16;  // <= 64 KiB since nv nc max_nb <= 2048
   if (swap)
-    hipLaunchKernelGGL(adj_gmT_split_kernel<true>, dim3(nq * Nk), dim3(256), 0, st, Nk, nq, q0 + i0, nv, nc, nb, kq,
+    hipLaunchKernelGGL(adj_gmT_split_kernel<true>, dim3(nq * Nk), dim3(256), gsh, st, Nk, nq, q0 + i0, nv, nc, nb, kq,
                        Ybar, X, G, p->ps_T);
   else
-    hipLaunchKernelGGL(adj_gmT_split_kernel<false>, dim3(nq * Nk), dim3(256), 0, st, Nk, nq, q0 + i0, nv, nc, nb, kq,
-                       Ybar, X, G, p->ps_T);
+    hipLaunchKernelGGL(adj_gmT_split_kernel<false>, dim3(nq * Nk), dim3(256), gsh, st, Nk, nq, q0 + i0, nv, nc, nb,
+                       kq, Ybar, X, G, p->ps_T);
   BSE_CHECK_LAUNCH();
   {  // Z[(v'v)][nu] = sum_{c'c} Gm[(v'v)][(c'c)] conj(Mc[(c'c)][nu]); the partner: Z' = sum G'[.][(c c')] Mc[(c c')]
     GemmArgs g;

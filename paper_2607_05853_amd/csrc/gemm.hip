@@ -905,11 +905,14 @@ __global__ __launch_bounds__(256) void cgemm_b3_dma64(GemmArgs g) {
 // ----------------------------------------------------------------------------
 __device__ __forceinline__ int tn_row(int m) { return (m & ~7) | ((m ^ (m >> 3)) & 7); }
 
-template <bool CS>
+// TM = 32-row tiles per wave in m: BM = 64 TM (TM = 1 for products of at most 64 rows, such as the n_v^2
+// rows of Z at n_v = 8, which would leave half of a 128-row tile empty)
+template <bool CS, int TM>
 __global__ __launch_bounds__(256) void cgemm_b3_tn(GemmArgs g, int nsplit, int kc, double* __restrict__ part) {
-  constexpr int BM = 128, BN = 128, BK = 16;
-  constexpr int PL = BM * BK;  // bf16 per plane per operand per stage
-  __shared__ __attribute__((aligned(16))) __bf16 smem[2 * 8 * PL];
+  constexpr int BM = 64 * TM, BN = 128, BK = 16;
+  constexpr int PLA = BM * BK, PLB = BN * BK;  // bf16 per plane per stage of A and of B
+  constexpr int SS = 4 * (PLA + PLB);
+  __shared__ __attribute__((aligned(16))) __bf16 smem[2 * SS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int gxn = (g.N + BN - 1) / BN, gyn = (g.M + BM - 1) / BM;
@@ -921,17 +924,21 @@ __global__ __launch_bounds__(256) void cgemm_b3_tn(GemmArgs g, int nsplit, int k
   const int k_lo = s * kc, k_hi = min(g.K, k_lo + kc);
   const int nK = (k_hi - k_lo + BK - 1) / BK;
 
-  // staging role (wave-uniform operand): threads 0..127 stage A, 128..255 B; plane pl, k half kh
-  // (rows 8 kh .. 8 kh + 7 of the step), columns 8 cb .. 8 cb + 7 of the tile
-  const int isB = tid >> 7, u = tid & 127;
-  const int pl = u >> 5, kh = (u >> 3) & 1, cb = (u & 7) | ((u >> 1) & 8);  // 16 lanes: 16 distinct bank slots
+  // staging role (wave-uniform operand): threads 0 .. BM-1 stage A, the next 128 B (the last wave idles
+  // when TM = 1); plane pl, k half kh (rows 8 kh .. 8 kh + 7 of the step), columns 8 cb .. 8 cb + 7
+  const int isB = tid >= BM ? 1 : 0;
+  const bool active = tid < BM + 128;
+  const int u = isB ? tid - BM : tid;
+  const int per_plane = isB ? 32 : 16 * TM;
+  const int pl = u / per_plane, w = u % per_plane;
+  const int kh = (w >> 3) & 1, cb = (w & 7) | ((w >> 4) << 3);  // 16 lanes: 16 distinct bank slots
   const int c0 = (isB ? n0 : m0) + 8 * cb;
-  const bool cok = c0 < (isB ? g.N : g.M);
+  const bool cok = active && c0 < (isB ? g.N : g.M);
   const long long ld = isB ? g.b_sk : g.a_sk;
   const __bf16* src = (const __bf16*)(isB ? g.B : g.A) + (isB ? g.b_ps : g.a_ps) * pl +
                       (long long)b * (isB ? g.b_sb : g.a_sb) + (cok ? c0 : 0);
   const unsigned flip = ((isB ? g.conjB : g.conjA) && pl >= 2) ? 0x80008000u : 0u;  // conj: -Im planes
-  __bf16* const dst0 = smem + (isB * 4 + pl) * PL + 8 * kh;
+  __bf16* const dst0 = smem + (isB ? 4 * PLA + pl * PLB : pl * PLA) + 8 * kh;
 
   u4v v[8];
   auto gload = [&](int kt) {
@@ -945,7 +952,8 @@ __global__ __launch_bounds__(256) void cgemm_b3_tn(GemmArgs g, int nsplit, int k
     }
   };
   auto lstore = [&](int st) {
-    __bf16* dst = dst0 + st * 8 * PL;
+    if (!active) return;
+    __bf16* dst = dst0 + st * SS;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       // column c of the 8 x 8 block: dword j holds rows 2j (low half) and 2j + 1 (high half)
@@ -960,9 +968,9 @@ __global__ __launch_bounds__(256) void cgemm_b3_tn(GemmArgs g, int nsplit, int k
     }
   };
 
-  f16v accR[2][2], accI[2][2];
+  f16v accR[TM][2], accI[TM][2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -979,23 +987,23 @@ __global__ __launch_bounds__(256) void cgemm_b3_tn(GemmArgs g, int nsplit, int k
   for (int kt = 0; kt < nK; ++kt) {
     const int st = kt & 1;
     if (kt + 1 < nK) gload(kt + 1);
-    const __bf16* sa = smem + st * 8 * PL;
-    const __bf16* sb = sa + 4 * PL;
-    bf8v a[2][4], bb[2][4];
+    const __bf16* sa = smem + st * SS;
+    const __bf16* sb = sa + 4 * PLA;
+    bf8v a[TM][4], bb[2][4];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int o = tn_row(wm * 64 + i * 32 + (lane & 31)) * BK + fo;
+    for (int i = 0; i < TM; ++i) {
+      const int o = tn_row(wm * 32 * TM + i * 32 + (lane & 31)) * BK + fo;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) a[i][q] = *reinterpret_cast<const bf8v*>(sa + q * PL + o);
+      for (int q = 0; q < 4; ++q) a[i][q] = *reinterpret_cast<const bf8v*>(sa + q * PLA + o);
     }
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int o = tn_row(wn * 64 + j * 32 + (lane & 31)) * BK + fo;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) bb[j][q] = *reinterpret_cast<const bf8v*>(sb + q * PL + o);
+      for (int q = 0; q < 4; ++q) bb[j][q] = *reinterpret_cast<const bf8v*>(sb + q * PLB + o);
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < TM; ++i) {
       const bf8v nih = neg8(a[i][2]), nil = neg8(a[i][3]);
 #pragma unroll
       for (int j = 0; j < 2; ++j) cmma_b3(a[i], nih, nil, bb[j], accR[i][j], accI[i][j]);
@@ -1005,10 +1013,10 @@ __global__ __launch_bounds__(256) void cgemm_b3_tn(GemmArgs g, int nsplit, int k
   }
   // register r of a lane holds row 8 (r / 4) + 4 (lane / 32) + r % 4, column lane % 32 of its 32 x 32 tile
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < TM; ++i) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int row = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      const int row = m0 + wm * 32 * TM + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
       if (row >= g.M) continue;
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
@@ -1154,13 +1162,17 @@ bool tn_ok(const GemmArgs& g) {
 
 // split K over enough blocks to fill the chip (about 2048 blocks, at least 1024 k per split)
 bse_status launch_tn(const GemmArgs& g, bool c_split, hipStream_t st) {
-  const long long tiles = (long long)((g.N + 127) / 128) * ((g.M + 127) / 128) * g.batch;
+  const bool small = g.M <= 64;  // 64-row tiles
+  const long long tiles = (long long)((g.N + 127) / 128) * ((g.M + (small ? 63 : 127)) / (small ? 64 : 128)) * g.batch;
   if (c_split) {
     if (g.c_bidx) {
       set_error("cgemm_b3_tn: a batch index table needs a c128 result");
       return BSE_EINVAL;
     }
-    hipLaunchKernelGGL(cgemm_b3_tn<true>, dim3((unsigned)tiles), dim3(256), 0, st, g, 1, g.K, (double*)nullptr);
+    if (small)
+      hipLaunchKernelGGL((cgemm_b3_tn<true, 1>), dim3((unsigned)tiles), dim3(256), 0, st, g, 1, g.K, (double*)nullptr);
+    else
+      hipLaunchKernelGGL((cgemm_b3_tn<true, 2>), dim3((unsigned)tiles), dim3(256), 0, st, g, 1, g.K, (double*)nullptr);
     BSE_CHECK_LAUNCH();
     return BSE_OK;
   }
@@ -1171,7 +1183,10 @@ bse_status launch_tn(const GemmArgs& g, bool c_split, hipStream_t st) {
   double* part = nullptr;
   const size_t bytes = 16 * (size_t)g.batch * nsplit * g.M * g.N;
   BSE_HIP(hipMallocAsync((void**)&part, bytes, st));
-  hipLaunchKernelGGL(cgemm_b3_tn<false>, dim3((unsigned)(tiles * nsplit)), dim3(256), 0, st, g, nsplit, kc, part);
+  if (small)
+    hipLaunchKernelGGL((cgemm_b3_tn<false, 1>), dim3((unsigned)(tiles * nsplit)), dim3(256), 0, st, g, nsplit, kc, part);
+  else
+    hipLaunchKernelGGL((cgemm_b3_tn<false, 2>), dim3((unsigned)(tiles * nsplit)), dim3(256), 0, st, g, nsplit, kc, part);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) {
     const long long n = (long long)g.batch * g.M * g.N;

@@ -342,13 +342,15 @@ def test_apply_adjoint(B, prec):
 # W-gradient reduction split over two k ranges
 ADJ_TN = dict(cfg_id=80, coarse=(2, 2, 2), dense=(3, 2, 2), n_ao=16, nv=4, nc=3, n_aux=40)
 ADJ_SPLIT = dict(cfg_id=81, coarse=(2, 2, 2), dense=(4, 4, 2), n_ao=16, nv=8, nc=2, n_aux=24)
+# N_aux = 72 > 64: the W-gradient product takes the 128-row tiles (Z keeps the 64-row ones)
+ADJ_WIDE = dict(cfg_id=82, coarse=(2, 2, 2), dense=(3, 2, 2), n_ao=16, nv=4, nc=3, n_aux=72)
 
 
 @pytest.mark.parametrize("all_pairs", [False, True])
-@pytest.mark.parametrize("cfg", ["ADJ_TN", "ADJ_SPLIT"])
+@pytest.mark.parametrize("cfg", ["ADJ_TN", "ADJ_SPLIT", "ADJ_WIDE"])
 def test_apply_adjoint_kmajor(B, cfg, all_pairs):
     # all_pairs=False: the gradient of each q pair {q, -q} from one set of pair densities
-    conf = {"ADJ_TN": ADJ_TN, "ADJ_SPLIT": ADJ_SPLIT}[cfg]
+    conf = {"ADJ_TN": ADJ_TN, "ADJ_SPLIT": ADJ_SPLIT, "ADJ_WIDE": ADJ_WIDE}[cfg]
     p = make_problem(conf, 6, "G2", coarse=(3, 3, 2))
     Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
     plan = B.plan_from_problem(p, Wq, prec="bf16x3", max_nb=4, all_pairs=all_pairs)
