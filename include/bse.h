@@ -220,6 +220,29 @@ bse_status bse_haydock_spectrum(bse_plan* plan, const void* P, int32_t nb, int32
                                 void* basis_out, void* hip_stream);
 
 /* ---------------------------------------------------------------------------
+ * k-offset averaging (Sec. IV.A, the k-point convergence study): the spectrum
+ * averaged over dense meshes shifted by offsets o_j (fractions of the mesh
+ * spacing, k_i + o_j / n) with weights w_j,
+ *     S(w) = sum_j w_j S_j(w),
+ * S_j the Haydock spectrum of plans[j], a plan built from the bands (psi, E)
+ * of the j-th shifted mesh and its start vectors P[j].  A common shift of k and
+ * k' leaves q = k' - k, and so W_q, unchanged: every plan takes the same W_q.
+ * plans[n_off] (same problem sizes), P[n_off] device c128 [N][nb] each,
+ * weights host [n_off]; S host [nb][n_w] (overwritten); steps_done host
+ * [n_off][nb] or NULL.  Each chain runs as in bse_haydock_spectrum;
+ * BSE_INFO_BREAKDOWN if any chain ended early (the result is still valid).
+ * ------------------------------------------------------------------------- */
+bse_status bse_offset_spectrum(bse_plan* const* plans, const void* const* P, const double* weights,
+                               int32_t n_off, int32_t nb, int32_t n_steps, const double* omega,
+                               int32_t n_w, double eta, double* S, int32_t* steps_done,
+                               void* hip_stream);
+
+/* The paper's offset set: the four classes of a 3x3x3 grid of offsets, (0,0,0)
+ * with weight 1/27, (1/3,0,0) 8/27, (1/3,1/3,0) 6/27, (2/3,1/3,0) 12/27.
+ * *n = 4; offsets host [4][3] and weights host [4] may each be NULL. */
+bse_status bse_offset_set(int32_t* n, double* offsets, double* weights);
+
+/* ---------------------------------------------------------------------------
  * Vector-Jacobian product of the Haydock spectrum: for L = sum_{b,w} gamma[b][w] S_b(w)
  * the gradients with respect to W(R) / W(q) and the energies, through
  *   dS(w) = -(1/(pi N_k)) Im( yt^H dA y ),  y = (z - A)^-1 p,  yt = (conj z - A)^-1 p,

@@ -22,6 +22,7 @@ __all__ = [
     "haydock", "continued_fraction", "haydock_spectrum", "lowest_exciton",
     "binding_energy", "grad_apply", "grad_WR_from_Wq", "grad_lowest", "grad_spectrum",
     "interpolate_W_matmul", "apply_H_rows_allpairs", "grad_Wq_at", "grad_eps",
+    "PAPER_OFFSETS", "PAPER_OFFSET_WEIGHTS", "offset_average",
 ]
 
 
@@ -231,6 +232,24 @@ def lowest_exciton(H):
 def binding_energy(prob, Omega1):
     """E_B = min_k [E_{c1 k} - E_{v_top k}] - Omega_1 (Sec. IV.C)."""
     return (prob.eps_qp[:, prob.nv] - prob.eps_qp[:, prob.nv - 1]).min() - Omega1
+
+
+# ----------------------------------------------------------------------------
+# k-offset averaging (Sec. IV.A, k-point convergence; the averaging scheme of Sander et al. 2015)
+# ----------------------------------------------------------------------------
+# The four classes of a 3x3x3 grid of mesh offsets that the paper uses, in units of the dense-mesh spacing,
+# with their weights (the class sizes over 27).
+PAPER_OFFSETS = ((0.0, 0.0, 0.0), (1.0 / 3, 0.0, 0.0), (1.0 / 3, 1.0 / 3, 0.0), (2.0 / 3, 1.0 / 3, 0.0))
+PAPER_OFFSET_WEIGHTS = (1.0 / 27, 8.0 / 27, 6.0 / 27, 12.0 / 27)
+
+
+def offset_average(spectra, weights):
+    """Offset-averaged spectrum sum_j w_j S_j, S_j computed independently on the dense mesh shifted by the
+    j-th offset (same W(q): q = k' - k does not move when k and k' shift together)."""
+    out = np.zeros_like(np.asarray(spectra[0], dtype=np.float64))
+    for S, w in zip(spectra, weights):
+        out = out + w * np.asarray(S, dtype=np.float64)
+    return out
 
 
 # ----------------------------------------------------------------------------

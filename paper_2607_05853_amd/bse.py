@@ -50,6 +50,8 @@ _SIGS = {
     "bse_plan_bytes": [_vp, ctypes.POINTER(ctypes.c_uint64)],
     "bse_plan_pairs": [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
     "bse_plan_conduction": [_vp, ctypes.POINTER(ctypes.c_int32)],
+    "bse_offset_spectrum": [_vp, _vp, _vp, _i32, _i32, _i32, _vp, _i32, ctypes.c_double, _vp, _vp, _vp],
+    "bse_offset_set": [ctypes.POINTER(ctypes.c_int32), _vp, _vp],
     "bse_apply": [_vp, _vp, _vp, _i32, _vp],
     "bse_apply_adjoint": [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp],
     "bse_velocity_start": [_vp, _vp, _vp, _i32, _vp, _vp, _vp],
@@ -332,6 +334,32 @@ class Plan:
                                   _stream(self.device))
         _check("bse_haydock_vjp", s)
         return {"W_R": gWR, "W_q": gWq, "eps": geps}
+
+
+def offset_set():
+    """The paper's k-offsets (units of the dense-mesh spacing) and weights: ([4][3], [4])."""
+    n = ctypes.c_int32()
+    off, w = np.zeros((4, 3)), np.zeros(4)
+    _check("bse_offset_set", lib().bse_offset_set(ctypes.byref(n), off.ctypes.data, w.ctypes.data))
+    return off[:n.value], w[:n.value]
+
+
+def offset_spectrum(plans, Ps, weights, n_steps, omega, eta):
+    """sum_j weights[j] * (Haydock spectrum of plans[j] from start block Ps[j]): k-offset averaging."""
+    n = len(plans)
+    if len(Ps) != n or len(weights) != n:
+        raise ValueError("offset_spectrum: one start block and one weight per plan")
+    nb = Ps[0].shape[1]
+    omega = _host(omega, np.float64).ravel()
+    weights = _host(weights, np.float64, (n,))
+    S = np.zeros((nb, len(omega)))
+    steps = np.zeros((n, nb), dtype=np.int32)
+    hp = (ctypes.c_void_p * n)(*[pl._ptr for pl in plans])
+    hP = (ctypes.c_void_p * n)(*[_dev(P, torch.complex128, (plans[j].N, nb), "P") for j, P in enumerate(Ps)])
+    s = lib().bse_offset_spectrum(hp, hP, weights.ctypes.data, n, nb, int(n_steps), omega.ctypes.data, len(omega),
+                                  float(eta), S.ctypes.data, steps.ctypes.data, _stream(plans[0].device))
+    _check("bse_offset_spectrum", s, allow_breakdown=True)
+    return {"S": S, "steps": steps, "breakdown": s == BSE_INFO_BREAKDOWN}
 
 
 def plan_from_problem(prob, W_q, prec="f64", max_nb=8, device="cuda:0", check_hermitian=False, all_pairs=False,

@@ -330,3 +330,62 @@ extern "C" bse_status bse_haydock_spectrum(bse_plan* plan, const void* P, int32_
     if (steps_done[i] < m) return BSE_INFO_BREAKDOWN;
   return BSE_OK;
 }
+
+// k-offset averaging (Sec. IV.A, k-point convergence): independent Haydock spectra on shifted dense meshes,
+// S = sum_j w_j S_j.  Every plan must describe the same problem sizes (they differ in their bands).
+extern "C" bse_status bse_offset_spectrum(bse_plan* const* plans, const void* const* P, const double* weights,
+                                          int32_t n_off, int32_t nb, int32_t n_steps, const double* omega,
+                                          int32_t n_w, double eta, double* S, int32_t* steps_done,
+                                          void* hip_stream) {
+  set_error("");
+  if (!plans || !P || !weights || !omega || !S || n_off <= 0 || nb <= 0 || n_steps <= 0 || n_w <= 0) {
+    set_error("bse_offset_spectrum: NULL argument or non-positive size");
+    return BSE_EINVAL;
+  }
+  for (int j = 0; j < n_off; ++j) {
+    if (!plans[j] || !P[j] || !std::isfinite(weights[j])) {
+      set_error("bse_offset_spectrum: NULL plan / start block or non-finite weight at offset " + std::to_string(j));
+      return BSE_EINVAL;
+    }
+    const bse_dims& a = plans[0]->impl.d;
+    const bse_dims& b = plans[j]->impl.d;
+    if (a.nk[0] != b.nk[0] || a.nk[1] != b.nk[1] || a.nk[2] != b.nk[2] || a.n_ao != b.n_ao || a.nv != b.nv ||
+        a.nc != b.nc || a.n_aux != b.n_aux) {
+      set_error("bse_offset_spectrum: the plans describe different problem sizes");
+      return BSE_ESHAPE;
+    }
+  }
+  const size_t ns = (size_t)nb * n_w;
+  std::vector<double> Sj(ns), a((size_t)nb * n_steps), b((size_t)nb * (n_steps + 1));
+  std::vector<int32_t> steps(nb);
+  for (size_t i = 0; i < ns; ++i) S[i] = 0.0;
+  bool breakdown = false;
+  for (int j = 0; j < n_off; ++j) {
+    const bse_status s = bse_haydock_spectrum(plans[j], P[j], nb, n_steps, omega, n_w, eta, Sj.data(), a.data(),
+                                              b.data(), steps.data(), nullptr, hip_stream);
+    if (s != BSE_OK && s != BSE_INFO_BREAKDOWN) return s;
+    breakdown = breakdown || s == BSE_INFO_BREAKDOWN;
+    for (size_t i = 0; i < ns; ++i) S[i] += weights[j] * Sj[i];
+    if (steps_done)
+      for (int i = 0; i < nb; ++i) steps_done[(size_t)j * nb + i] = steps[i];
+  }
+  return breakdown ? BSE_INFO_BREAKDOWN : BSE_OK;
+}
+
+// the paper's offset set: the four classes of a 3x3x3 grid of offsets (units of the mesh spacing)
+extern "C" bse_status bse_offset_set(int32_t* n, double* offsets, double* weights) {
+  set_error("");
+  if (!n) {
+    set_error("bse_offset_set: NULL argument");
+    return BSE_EINVAL;
+  }
+  static const double off[4][3] = {{0.0, 0.0, 0.0}, {1.0 / 3, 0.0, 0.0}, {1.0 / 3, 1.0 / 3, 0.0}, {2.0 / 3, 1.0 / 3, 0.0}};
+  static const double wts[4] = {1.0 / 27, 8.0 / 27, 6.0 / 27, 12.0 / 27};
+  *n = 4;
+  for (int j = 0; j < 4; ++j) {
+    if (offsets)
+      for (int i = 0; i < 3; ++i) offsets[3 * j + i] = off[j][i];
+    if (weights) weights[j] = wts[j];
+  }
+  return BSE_OK;
+}

@@ -62,11 +62,13 @@ CONFIGS = {
 }
 
 
-def dense_kmesh(nk):
-    """Gamma-centred mesh k = (i1/n1, i2/n2, i3/n3), index (i1*n2 + i2)*n3 + i3."""
+def dense_kmesh(nk, offset=(0.0, 0.0, 0.0)):
+    """Mesh k = ((i1 + o1)/n1, (i2 + o2)/n2, (i3 + o3)/n3), index (i1*n2 + i2)*n3 + i3: Gamma-centred for
+    a zero offset o, shifted by o mesh spacings otherwise."""
     n1, n2, n3 = nk
+    o1, o2, o3 = (float(x) for x in offset)
     i1, i2, i3 = np.meshgrid(np.arange(n1), np.arange(n2), np.arange(n3), indexing="ij")
-    k = np.stack([i1.ravel() / n1, i2.ravel() / n2, i3.ravel() / n3], axis=1)
+    k = np.stack([(i1.ravel() + o1) / n1, (i2.ravel() + o2) / n2, (i3.ravel() + o3) / n3], axis=1)
     return k.astype(np.float64)
 
 
@@ -133,6 +135,7 @@ class Problem:
     H_R: dict = field(default_factory=dict)   # tight-binding hoppings {R tuple: [n_ao][n_ao]}
     wgen: str = "G1"
     seed: int = 0
+    offset: tuple = (0.0, 0.0, 0.0)            # mesh offset in units of the dense-mesh spacing
 
     @property
     def Nk(self):
@@ -144,7 +147,7 @@ class Problem:
 
     @property
     def kfrac(self):
-        return dense_kmesh(self.nk)
+        return dense_kmesh(self.nk, self.offset)
 
 
 def _tb_hoppings(rng, n_ao):
@@ -197,7 +200,10 @@ def _bands(HR, kfrac, n_ao, nv, nc):
 def make_problem(cfg="mesh4_ao16", seed=0, wgen="G1", **over) -> Problem:
     """Draw the synthetic crystal of a named workload (or a dict), with overrides.
 
-    Overrides: dense, coarse, n_ao, nv, nc, n_aux, r_cut, alpha.
+    Overrides: dense, coarse, n_ao, nv, nc, n_aux, r_cut, alpha, offset (the dense mesh shifted by
+    offset mesh spacings: bands, start vectors and the velocity elements at the shifted k; C, Vbar, W and
+    the quasiparticle scissor are those of the unshifted mesh, so the problems of several offsets share
+    everything but the bands).
     Independent child streams (SeedSequence([SEED_BASE, cfg_id, seed]))
     feed the bands, C, Vbar and W so that changing one size leaves the
     other draws' structure intact.
@@ -220,9 +226,11 @@ def make_problem(cfg="mesh4_ao16", seed=0, wgen="G1", **over) -> Problem:
     r_tb, r_c, r_v, r_w = (np.random.default_rng(s) for s in ss.spawn(4))
 
     HR = _tb_hoppings(r_tb, n_ao)
-    kf = dense_kmesh(nk)
+    offset = tuple(float(x) for x in c.get("offset", (0.0, 0.0, 0.0)))
+    kf = dense_kmesh(nk, offset)
     eps_ks, psi, vel = _bands(HR, kf, n_ao, nv, nc)
-    gap = (eps_ks[:, nv] - eps_ks[:, nv - 1]).min()
+    e0 = eps_ks if offset == (0.0, 0.0, 0.0) else _bands(HR, dense_kmesh(nk), n_ao, nv, nc)[0]
+    gap = (e0[:, nv] - e0[:, nv - 1]).min()
     eps_qp = eps_ks.copy()
     eps_qp[:, nv:] += GAP_TARGET - gap
 
@@ -252,7 +260,7 @@ def make_problem(cfg="mesh4_ao16", seed=0, wgen="G1", **over) -> Problem:
         raise ValueError(wgen)
     return Problem(name=name, nk=nk, coarse=coarse, n_ao=n_ao, nv=nv, nc=nc, n_aux=n_aux,
                    alpha=alpha, eps_ks=eps_ks, eps_qp=eps_qp, psi=psi, vel=vel, C=C,
-                   Vbar=Vbar, R=R, w_R=w_R, W_R=W_R, H_R=HR, wgen=wgen, seed=seed)
+                   Vbar=Vbar, R=R, w_R=w_R, W_R=W_R, H_R=HR, wgen=wgen, seed=seed, offset=offset)
 
 
 def _w_g2(rng, R, coarse, n_aux, amp):

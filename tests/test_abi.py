@@ -92,6 +92,26 @@ def test_null_plan_calls(L):
     assert L.bse_plan_pairs(None, ctypes.byref(a), ctypes.byref(b)) == 1
     c = ctypes.c_int32()
     assert L.bse_plan_conduction(None, ctypes.byref(c)) == 1
+    # offset averaging: NULL arrays and empty offset lists are rejected before any HIP call
+    w = (ctypes.c_double * 1)(1.0)
+    om = (ctypes.c_double * 1)(2.0)
+    S = (ctypes.c_double * 1)()
+    assert L.bse_offset_spectrum(None, None, w, 1, 1, 1, om, 1, 0.1, S, None, None) == 1
+    plans = (ctypes.c_void_p * 1)(None)
+    Ps = (ctypes.c_void_p * 1)(dummy)
+    assert L.bse_offset_spectrum(plans, Ps, w, 1, 1, 1, om, 1, 0.1, S, None, None) == 1
+    assert L.bse_offset_spectrum(plans, Ps, w, 0, 1, 1, om, 1, 0.1, S, None, None) == 1
+    assert L.bse_offset_set(None, None, None) == 1
+
+
+def test_offset_set_is_the_papers(L):
+    n = ctypes.c_int32()
+    off = (ctypes.c_double * 12)()
+    w = (ctypes.c_double * 4)()
+    assert L.bse_offset_set(ctypes.byref(n), off, w) == 0
+    assert n.value == 4
+    assert [round(27 * w[j]) for j in range(4)] == [1, 8, 6, 12]
+    assert [round(3 * off[i]) for i in range(12)] == [0, 0, 0, 1, 0, 0, 1, 1, 0, 2, 1, 0]
 
 
 def test_binding_rejects_cpu_tensors():
