@@ -136,6 +136,7 @@ class Problem:
     wgen: str = "G1"
     seed: int = 0
     offset: tuple = (0.0, 0.0, 0.0)            # mesh offset in units of the dense-mesh spacing
+    momentum: tuple = (0.0, 0.0, 0.0)          # exciton momentum Q in units of the dense-mesh spacing
 
     @property
     def Nk(self):
@@ -200,7 +201,10 @@ def _bands(HR, kfrac, n_ao, nv, nc):
 def make_problem(cfg="mesh4_ao16", seed=0, wgen="G1", **over) -> Problem:
     """Draw the synthetic crystal of a named workload (or a dict), with overrides.
 
-    Overrides: dense, coarse, n_ao, nv, nc, n_aux, r_cut, alpha, offset (the dense mesh shifted by
+    Overrides: dense, coarse, n_ao, nv, nc, n_aux, r_cut, alpha, momentum (finite exciton momentum Q:
+    transitions (v k, c k+Q), i.e. the conduction bands of the band arrays taken at k + Q / n while the
+    valence bands stay at k; the velocity elements are then zero, the optical start vectors being a
+    Q = 0 notion), offset (the dense mesh shifted by
     offset mesh spacings: bands, start vectors and the velocity elements at the shifted k; C, Vbar, W and
     the quasiparticle scissor are those of the unshifted mesh, so the problems of several offsets share
     everything but the bands).
@@ -231,6 +235,12 @@ def make_problem(cfg="mesh4_ao16", seed=0, wgen="G1", **over) -> Problem:
     eps_ks, psi, vel = _bands(HR, kf, n_ao, nv, nc)
     e0 = eps_ks if offset == (0.0, 0.0, 0.0) else _bands(HR, dense_kmesh(nk), n_ao, nv, nc)[0]
     gap = (e0[:, nv] - e0[:, nv - 1]).min()
+    momentum = tuple(float(x) for x in c.get("momentum", (0.0, 0.0, 0.0)))
+    if momentum != (0.0, 0.0, 0.0):
+        shifted = tuple(o + m for o, m in zip(offset, momentum))
+        e_q, psi_q, _ = _bands(HR, dense_kmesh(nk, shifted), n_ao, nv, nc)
+        eps_ks[:, nv:], psi[:, nv:] = e_q[:, nv:], psi_q[:, nv:]
+        vel = np.zeros_like(vel)
     eps_qp = eps_ks.copy()
     eps_qp[:, nv:] += GAP_TARGET - gap
 
@@ -260,7 +270,8 @@ def make_problem(cfg="mesh4_ao16", seed=0, wgen="G1", **over) -> Problem:
         raise ValueError(wgen)
     return Problem(name=name, nk=nk, coarse=coarse, n_ao=n_ao, nv=nv, nc=nc, n_aux=n_aux,
                    alpha=alpha, eps_ks=eps_ks, eps_qp=eps_qp, psi=psi, vel=vel, C=C,
-                   Vbar=Vbar, R=R, w_R=w_R, W_R=W_R, H_R=HR, wgen=wgen, seed=seed, offset=offset)
+                   Vbar=Vbar, R=R, w_R=w_R, W_R=W_R, H_R=HR, wgen=wgen, seed=seed, offset=offset,
+                   momentum=momentum)
 
 
 def _w_g2(rng, R, coarse, n_aux, amp):
