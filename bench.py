@@ -113,7 +113,7 @@ def main():
     CONDUCTION = None if args.conduction == "auto" else args.conduction
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on exactly one GPU; --gpus %d is not supported" % args.gpus,
+        print("bench.py runs on exactly one GPU; --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:

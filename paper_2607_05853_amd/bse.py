@@ -72,7 +72,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError("libbse.so not built at %s: run __graft_entry__.build()" % LIB_PATH)
+            raise ImportError("libbse.so not built at %s: run python paper_2607_05853_amd/build_lib.py" % LIB_PATH)
         L = ctypes.CDLL(LIB_PATH)
         for name, args in _SIGS.items():
             f = getattr(L, name)
