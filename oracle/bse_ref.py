@@ -17,7 +17,7 @@ import numpy as np
 
 __all__ = [
     "kmesh", "q_index", "q_index_table", "interpolate_W", "coarse_to_R", "coarse_mesh",
-    "pair_density", "hamiltonian_block", "build_H", "apply_H", "apply_H_rows",
+    "pair_density", "lri_coeff_k", "pair_density_2c", "hamiltonian_block", "build_H", "apply_H", "apply_H_rows",
     "transition_energies", "velocity_start", "spectrum_exact", "eig_spectrum",
     "haydock", "continued_fraction", "haydock_spectrum", "lowest_exciton",
     "binding_energy", "grad_apply", "grad_WR_from_Wq", "grad_lowest", "grad_spectrum",
@@ -104,6 +104,36 @@ def pair_density(psi, C, ki, bi, kj, bj):
     return np.matmul(a.conj()[None], Cb)   # [mu][i][j]
 
 
+def lri_coeff_k(C_R, RC, k):
+    """C^mu_st(k) = sum_R C^mu_st(R) exp(+2 pi i k.R): Fourier transform of the two-centre LRI
+    coefficients over their single lattice vector (Sec. III.A).  Returns [n_aux][n_ao][n_ao]."""
+    ph = np.exp(2j * np.pi * (np.asarray(RC, dtype=np.float64) @ np.asarray(k, dtype=np.float64)))
+    return np.tensordot(ph, C_R, axes=(0, 0))
+
+
+def pair_density_2c(psi, C_R, RC, ka, k_a, bi, kb, k_b, bj):
+    """M^mu_{ij}(k_a, k_b) = C-tilde^mu_{i k_a, j k_b}
+         = sum_st conj(c^{k_a}_{s i}) c^{k_b}_{t j} [C^mu_st(k_b) + C^mu_ts(-k_a)]
+    with the k-dependent two-centre coefficients of Sec. III.A (the Bloch-summed AO product expanded
+    over the ABFs of both centres).  ka, kb are the psi indices, k_a, k_b the fractional k of those
+    bands.  Returns [n_aux][len(bi)][len(bj)]."""
+    Ceff = lri_coeff_k(C_R, RC, k_b) + np.transpose(lri_coeff_k(C_R, RC, -np.asarray(k_a)), (0, 2, 1))
+    a = psi[ka][list(bi)]
+    b = psi[kb][list(bj)]
+    return np.matmul(a.conj()[None], np.matmul(Ceff, b.T))
+
+
+def _pairs(prob, ka, bi, kb, bj):
+    """The pair densities M^mu_{ij}(k_a, k_b) of a problem: k-independent C (pair_density) or two-centre
+    C(R) (pair_density_2c, each band at the k of its band set)."""
+    if getattr(prob, "C_R", None) is None:
+        return pair_density(prob.psi, prob.C, ka, bi, kb, bj)
+    kv, kc = prob.band_k()
+    k_a = (kv if bi[0] < prob.nv else kc)[ka]
+    k_b = (kv if bj[0] < prob.nv else kc)[kb]
+    return pair_density_2c(prob.psi, prob.C_R, prob.RC, ka, k_a, bi, kb, k_b, bj)
+
+
 def _bands(prob):
     return list(range(prob.nv)), list(range(prob.nv, prob.nv + prob.nc))
 
@@ -123,10 +153,10 @@ def hamiltonian_block(prob, W_q, alpha, k, kp, cache=None):
     val, con = _bands(prob)
     Nk = prob.Nk
     nc, nv = prob.nc, prob.nv
-    Mcv = pair_density(prob.psi, prob.C, k, con, k, val)        # [mu][c][v]
-    Mvc = pair_density(prob.psi, prob.C, kp, val, kp, con)      # [nu][v'][c']
-    Mvv = pair_density(prob.psi, prob.C, kp, val, k, val)       # [mu][v'][v]
-    Mcc = pair_density(prob.psi, prob.C, k, con, kp, con)       # [nu][c][c']
+    Mcv = _pairs(prob, k, con, k, val)        # [mu][c][v]
+    Mvc = _pairs(prob, kp, val, kp, con)      # [nu][v'][c']
+    Mvv = _pairs(prob, kp, val, k, val)       # [mu][v'][v]
+    Mcc = _pairs(prob, k, con, kp, con)       # [nu][c][c']
     Wq = W_q[q_index(prob.nk, k, kp)]
     # exchange: sum_mu sum_nu Mcv[mu,c,v] Vbar[mu,nu] Mvc[nu,v',c']
     t1 = np.einsum("mcv,mn->ncv", Mcv, prob.Vbar)
@@ -342,8 +372,8 @@ def grad_apply(prob, W_q, Ybar, X, alpha=None):
     g_Wq = np.zeros((Nk, prob.n_aux, prob.n_aux), dtype=np.complex128)
     for k in range(Nk):
         for kp in range(Nk):
-            Mvv = pair_density(prob.psi, prob.C, kp, val, k, val)   # [mu][v'][v]
-            Mcc = pair_density(prob.psi, prob.C, k, con, kp, con)   # [nu][c][c']
+            Mvv = _pairs(prob, kp, val, k, val)   # [mu][v'][v]
+            Mcc = _pairs(prob, k, con, kp, con)   # [nu][c][c']
             G = Ybar[k * nt:(k + 1) * nt] @ X[kp * nt:(kp + 1) * nt].conj().T   # [(c v)][(c' v')]
             G = G.reshape(nc, nv, nc, nv)
             g_Wq[q_index(prob.nk, k, kp)] += -(1.0 / Nk) * np.einsum(
@@ -397,6 +427,8 @@ def apply_H_rows_allpairs(prob, W_q, X, rows, alpha=None, chunk=64):
     nt = nc * nv
     val, con = _bands(prob)
     pv, pc = _psi_sets(prob)
+    if getattr(prob, "C_R", None) is not None:
+        raise NotImplementedError("row-at-a-time forms take k-independent LRI coefficients")
     C = prob.C
     X = np.asarray(X).reshape(Nk, nt, -1)           # [k][(c v)][b]
     nb = X.shape[2]
@@ -445,6 +477,8 @@ def grad_Wq_at(prob, Ybar, X, qs, chunk=64):
     nv, nc, Nk, na = prob.nv, prob.nc, prob.Nk, prob.n_aux
     nt = nc * nv
     pv, pc = _psi_sets(prob)
+    if getattr(prob, "C_R", None) is not None:
+        raise NotImplementedError("row-at-a-time forms take k-independent LRI coefficients")
     C = prob.C
     Ybar = np.asarray(Ybar).reshape(Nk, nt, -1)
     X = np.asarray(X).reshape(Nk, nt, -1)

@@ -12,7 +12,10 @@ counts and structure:
   (a = 1, V = 1), hoppings to the 6 nearest cells, half filling, a
   scissor on the conduction bands standing in for E^GW vs E^KS;
 * C^mu: random complex Gaussian matrices, made Hermitian (the k-independent
-  form of the paper's two-centre relation for real ABFs);
+  form of the paper's two-centre relation for real ABFs), or (two_centre=True)
+  real two-centre coefficients C^mu_st(R) on R = 0 and the six nearest cells,
+  nonzero only when the auxiliary function mu sits on the atom of the first
+  AO s (the support of the paper's LRI coefficients, Sec. III.A);
 * Vbar: a real symmetric positive semi-definite matrix;
 * W(R): generator "G1" (real PSD L L^T times exp(-|R|/1.5), as quoted for
   the benchmark workloads) or "G2" (real, W(-R) = W(R)^T but not
@@ -42,6 +45,8 @@ GAP_TARGET = 2.0        # eV, min_k (e_c - e_v) after the scissor
 DECAY_LEN = 1.5         # lattice units, W(R) ~ exp(-|R| / DECAY_LEN)
 V_KERNEL = 0.3          # eV, target spectral norm of the exchange block (random-matrix estimate)
 W_KERNEL = 0.4          # eV, target spectral norm of the direct block (random-matrix estimate)
+TC_ATOMS = 2            # atoms per cell carrying the AOs and auxiliary functions of two-centre inputs
+TC_NEIGHBOUR = 0.5      # amplitude of the nearest-cell two-centre coefficients relative to R = 0
 
 CONFIGS = {
     # tiny: full diagonalisation + Haydock 200
@@ -137,6 +142,8 @@ class Problem:
     seed: int = 0
     offset: tuple = (0.0, 0.0, 0.0)            # mesh offset in units of the dense-mesh spacing
     momentum: tuple = (0.0, 0.0, 0.0)          # exciton momentum Q in units of the dense-mesh spacing
+    C_R: Optional[np.ndarray] = None           # f64 [NRC][n_aux][n_ao][n_ao] two-centre C^mu_st(R) (C is None then)
+    RC: Optional[np.ndarray] = None            # int32 [NRC][3] the R of C_R
 
     @property
     def Nk(self):
@@ -149,6 +156,12 @@ class Problem:
     @property
     def kfrac(self):
         return dense_kmesh(self.nk, self.offset)
+
+    def band_k(self):
+        """(k of the valence bands, k of the conduction bands) per mesh point, fractional [Nk][3] each:
+        the shifted mesh, and for the conduction bands that mesh moved by the exciton momentum."""
+        shifted = tuple(o + m for o, m in zip(self.offset, self.momentum))
+        return dense_kmesh(self.nk, self.offset), dense_kmesh(self.nk, shifted)
 
 
 def _tb_hoppings(rng, n_ao):
@@ -201,7 +214,9 @@ def _bands(HR, kfrac, n_ao, nv, nc):
 def make_problem(cfg="mesh4_ao16", seed=0, wgen="G1", **over) -> Problem:
     """Draw the synthetic crystal of a named workload (or a dict), with overrides.
 
-    Overrides: dense, coarse, n_ao, nv, nc, n_aux, r_cut, alpha, momentum (finite exciton momentum Q:
+    Overrides: dense, coarse, n_ao, nv, nc, n_aux, r_cut, alpha, two_centre (real two-centre LRI
+    coefficients C^mu_st(R) in C_R / RC instead of the k-independent Hermitian C, which is then None),
+    momentum (finite exciton momentum Q:
     transitions (v k, c k+Q), i.e. the conduction bands of the band arrays taken at k + Q / n while the
     valence bands stay at k; the velocity elements are then zero, the optical start vectors being a
     Q = 0 notion), offset (the dense mesh shifted by
@@ -227,7 +242,7 @@ def make_problem(cfg="mesh4_ao16", seed=0, wgen="G1", **over) -> Problem:
         raise ValueError("band window exceeds the tight-binding model")
     alpha = float(c.get("alpha", 2.0))
     ss = np.random.SeedSequence([SEED_BASE, cfg_id, int(seed)])
-    r_tb, r_c, r_v, r_w = (np.random.default_rng(s) for s in ss.spawn(4))
+    r_tb, r_c, r_v, r_w, r_2c = (np.random.default_rng(s) for s in ss.spawn(5))
 
     HR = _tb_hoppings(r_tb, n_ao)
     offset = tuple(float(x) for x in c.get("offset", (0.0, 0.0, 0.0)))
@@ -247,6 +262,10 @@ def make_problem(cfg="mesh4_ao16", seed=0, wgen="G1", **over) -> Problem:
     sigma_c = 1.0 / np.sqrt(n_ao)
     G = _cn(r_c, (n_aux, n_ao, n_ao))
     C = sigma_c * 0.5 * (G + np.conj(np.transpose(G, (0, 2, 1))))
+    C_R = RC = None
+    if c.get("two_centre", False):
+        C_R, RC = _two_centre(r_2c, n_ao, n_aux, sigma_c)
+        C = None
 
     # Scales chosen so that the exchange and direct blocks have roughly
     # config-independent spectral norms (random-matrix estimates with
@@ -271,7 +290,27 @@ def make_problem(cfg="mesh4_ao16", seed=0, wgen="G1", **over) -> Problem:
     return Problem(name=name, nk=nk, coarse=coarse, n_ao=n_ao, nv=nv, nc=nc, n_aux=n_aux,
                    alpha=alpha, eps_ks=eps_ks, eps_qp=eps_qp, psi=psi, vel=vel, C=C,
                    Vbar=Vbar, R=R, w_R=w_R, W_R=W_R, H_R=HR, wgen=wgen, seed=seed, offset=offset,
-                   momentum=momentum)
+                   momentum=momentum, C_R=C_R, RC=RC)
+
+
+def _two_centre(rng, n_ao, n_aux, sigma_c):
+    """Real C^mu_st(R) on R = 0 and the six nearest cells.
+
+    AO s sits on atom s * TC_ATOMS // n_ao and auxiliary function mu on atom mu * TC_ATOMS // n_aux; a
+    coefficient is nonzero only when mu sits on the atom of s.  Entries are N(0, a^2 d_R^2) with d_0 = 1,
+    d_R = TC_NEIGHBOUR for the neighbours, and a chosen so that the mean square of an entry of
+    C^mu_st(k1) + C^mu_ts(-k2) equals that of the k-independent draw (sigma_c^2 / 2).
+    """
+    RC = np.array([(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)],
+                  dtype=np.int32)
+    d = np.r_[1.0, TC_NEIGHBOUR * np.ones(len(RC) - 1)]
+    a = sigma_c * np.sqrt(TC_ATOMS / (4.0 * (d ** 2).sum()))
+    atom_s = np.arange(n_ao) * TC_ATOMS // n_ao
+    atom_mu = np.arange(n_aux) * TC_ATOMS // n_aux
+    mask = (atom_mu[:, None] == atom_s[None, :]).astype(np.float64)          # [mu][s]
+    C_R = rng.standard_normal((len(RC), n_aux, n_ao, n_ao)) * (a * d)[:, None, None, None]
+    C_R *= mask[None, :, :, None]
+    return np.ascontiguousarray(C_R), RC
 
 
 def _w_g2(rng, R, coarse, n_aux, amp):
