@@ -102,12 +102,14 @@ def main():
                     help="BF16x3 conduction side of the direct term: the plan's choice (auto), forming the "
                          "conduction pair densities (mc) or the B_c(k) contraction (u)")
     ap.add_argument("--mode", default="spectrum",
-                    choices=["spectrum", "precision", "gradients", "largest", "offsets"],
+                    choices=["spectrum", "precision", "gradients", "largest", "offsets", "two_centre"],
                     help="spectrum: the timed pipeline (default); precision: per-precision apply and "
                          "short-Haydock errors on a larger workload; gradients: LOBPCG and spectrum "
                          "gradients checked by central finite differences; largest: one BF16x3 apply and "
                          "adjoint on the 16x16x16 / N_ao = 128 workload; offsets: the spectrum averaged over "
-                         "the four shifted dense meshes of the k-offset scheme")
+                         "the four shifted dense meshes of the k-offset scheme; two_centre: the BF16x3 apply "
+                         "and Haydock run with k-dependent two-centre LRI coefficients beside the "
+                         "k-independent ones")
     args = ap.parse_args()
     global CONDUCTION
     CONDUCTION = None if args.conduction == "auto" else args.conduction
@@ -125,6 +127,10 @@ def main():
     if args.mode == "offsets":
         from synth import CONFIGS
         offsets_mode(args.config, args.haydock_steps or CONFIGS[args.config]["haydock_steps"])
+        return
+    if args.mode == "two_centre":
+        from synth import CONFIGS
+        two_centre_mode(args.config, args.haydock_steps or CONFIGS[args.config]["haydock_steps"])
         return
     if args.mode == "largest":
         largest_mode(args.config if args.config != "mesh8_ao64" else "mesh16_ao128")
@@ -377,6 +383,66 @@ def largest_mode(config):
         "apply_stage_ms": st_apply, "adjoint_s": tg, "F_adjoint_TFLOP": Fg / 1e12,
         "adjoint_GFLOP_s": Fg / tg / 1e9, "adjoint_stage_ms": st_adj}), flush=True)
     plan.close()
+
+
+def two_centre_mode(config, m):
+    """k-dependent two-centre LRI coefficients: one apply per precision (BF16x3 error against FP64) and the
+    BF16x3 Haydock spectrum, each beside the same run with the k-independent coefficients of the workload."""
+    from synth import CONFIGS, make_problem, polarisations, random_block
+    import torch
+    from paper_2607_05853_amd import bse as B
+    from synth import dense_kmesh
+    dev = torch.device("cuda:0")
+    T = lambda a, dt=torch.complex128: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)
+    nb = CONFIGS[config]["nb"]
+    res = {}
+    for kind in ["k_independent", "two_centre"]:
+        p = make_problem(config, 0, "G1", two_centre=(kind == "two_centre"))
+        Fa = f_apply(p.Nk, p.n_ao, p.nv, p.nc, p.n_aux, nb)
+        Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
+        X = T(random_block(p.N, nb, seed=1))
+        te = p.eps_qp[:, p.nv:][:, :, None] - p.eps_qp[:, :p.nv][:, None, :]
+        omega = np.linspace(te.min() - 1.0, te.max() + 1.0, 2001)
+        r = {}
+        Y64 = None
+        for prec in ["f64", "bf16x3"]:
+            torch.cuda.synchronize()
+            t0 = time.time()
+            plan = B.plan_from_problem(p, Wq, prec=prec, max_nb=nb)
+            torch.cuda.synchronize()
+            t_plan = time.time() - t0
+            plan.apply(X)
+            torch.cuda.synchronize()
+            plan.set_timing(True)
+            t0 = time.time()
+            Y = plan.apply(X)
+            torch.cuda.synchronize()
+            ta = time.time() - t0
+            st = {k: round(v[0], 2) for k, v in plan.stage_times().items() if v[1]}
+            plan.set_timing(False)
+            e = {"plan_s": t_plan, "apply_ms": ta * 1e3, "apply_stage_ms": st, "q_formed": plan.pairs[0],
+                 "conduction": plan.conduction}
+            if prec == "f64":
+                Y64 = Y
+            else:
+                e["apply_rel_err_vs_f64"] = float((Y - Y64).abs().max() / Y64.abs().max())
+                P = plan.velocity_start(T(p.vel), T(p.eps_ks, torch.float64), polarisations(nb))
+                torch.cuda.synchronize()
+                t0 = time.time()
+                out = plan.haydock(P, m, omega, 0.1)
+                torch.cuda.synchronize()
+                th = time.time() - t0
+                e.update({"haydock_steps": m, "haydock_s": th, "GFLOP_s": m * Fa / th / 1e9})
+            r[prec] = e
+            plan.close()
+            print("[two_centre mode] %s %s done" % (kind, prec), file=sys.stderr, flush=True)
+        res[kind] = r
+    print(json.dumps({"mode": "two_centre", "workload": "%s, %d Haydock steps, blocks of %d" % (config, m, nb),
+                      "coefficients": "real C^mu_st(R) on R = 0 and the 6 nearest cells, mu on the atom of s",
+                      "runs": res,
+                      "haydock_ratio_two_centre_over_k_independent":
+                          res["two_centre"]["bf16x3"]["haydock_s"] / res["k_independent"]["bf16x3"]["haydock_s"]}),
+          flush=True)
 
 
 def offsets_mode(config, m):

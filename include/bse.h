@@ -137,6 +137,35 @@ bse_status bse_plan_create(const bse_dims* d, const double* eps_qp, const void* 
                            const void* C, const void* Vbar, const void* W_q,
                            bse_prec prec, int32_t max_nb, uint32_t flags,
                            void* hip_stream, bse_plan** out);
+
+/* ---------------------------------------------------------------------------
+ * Plan with k-dependent two-centre LRI coefficients (Sec. III.A).  In place of
+ * the k-independent C^mu the plan takes the real coefficients C^mu_st(R) of the
+ * AO pair (s at cell 0, t at cell R) for the ABF mu on the atom of s, with
+ *     C^mu_st(k) = sum_R C^mu_st(R) exp(+2 pi i k.R)
+ * and forms the Kohn-Sham coefficients of the paper's C-tilde,
+ *     M^mu_ij(k_a, k_b) = sum_st conj(c^{k_a}_{s i}) c^{k_b}_{t j} [C^mu_st(k_b) + C^mu_ts(-k_a)],
+ * the first term for the ABFs on the centre of s, the second for those on the
+ * centre of t.  Every operation of bse_plan_create's plans (apply, adjoint,
+ * Haydock, LOBPCG, offsets) runs on such a plan unchanged.
+ * n_RC    number of lattice vectors of the coefficients (> 0)
+ * RC      host int32 [n_RC][3]
+ * C_R     device f64 [n_RC][n_aux][n_ao][n_ao], C_R[r][mu][s][t] = C^mu_st(R_r)
+ *         (real: the relation conj M_ij(k_a, k_b) = M_ji(k_b, k_a), on which the
+ *         pair symmetry and the Hermiticity of A rest, holds for real C only)
+ * k_frac  host f64 [2][Nk][3]: fractional k of the valence bands of each mesh
+ *         point, then of its conduction bands (the mesh itself, shifted by an
+ *         offset, and for the conduction bands moved by an exciton momentum)
+ * Other arguments as bse_plan_create.  Per pair the direct term forms the
+ * one-sided products for both orders of the pair (twice the pair-density GEMM
+ * work) and adds them; on BF16X3 the conduction side always forms M_cc'
+ * (BSE_CONDUCTION_U is BSE_EINVAL); BSE_CHECK_HERMITIAN checks Vbar only.
+ * ------------------------------------------------------------------------- */
+bse_status bse_plan_create_2c(const bse_dims* d, const double* eps_qp, const void* psi, int32_t n_RC,
+                              const int32_t* RC, const double* C_R, const double* k_frac,
+                              const void* Vbar, const void* W_q, bse_prec prec, int32_t max_nb,
+                              uint32_t flags, void* hip_stream, bse_plan** out);
+
 bse_status bse_plan_destroy(bse_plan* plan);
 
 /* Register the R set (host int32 [n_R][3], host f64 weights) used by

@@ -44,6 +44,8 @@ _SIGS = {
     "bse_interpolate_W_adjoint": [_i32, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _vp],
     "bse_plan_create": [ctypes.POINTER(_Dims), _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _i32, ctypes.c_uint32, _vp,
                         ctypes.POINTER(_vp)],
+    "bse_plan_create_2c": [ctypes.POINTER(_Dims), _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _i32,
+                           ctypes.c_uint32, _vp, ctypes.POINTER(_vp)],
     "bse_plan_destroy": [_vp],
     "bse_plan_set_R": [_vp, _i32, _vp, _vp],
     "bse_plan_set_eps": [_vp, _vp, _vp],
@@ -157,7 +159,11 @@ class Plan:
     """A TDA-BSE problem resident on one GPU (halves, rho, W_q and workspaces)."""
 
     def __init__(self, nk, n_ao, nv, nc, n_aux, eps_qp, psi, C, Vbar, W_q, alpha=2.0, prec="f64",
-                 max_nb=8, check_hermitian=False, all_pairs=False, conduction=None):
+                 max_nb=8, check_hermitian=False, all_pairs=False, conduction=None, two_centre=None):
+        """C: k-independent LRI coefficients (device c128 [n_aux][n_ao][n_ao]), or None with
+        two_centre = (C_R, RC, k_frac): real two-centre coefficients C^mu_st(R) (device f64
+        [n_RC][n_aux][n_ao][n_ao]), their lattice vectors (int [n_RC][3]) and the fractional k of the
+        valence and of the conduction bands ([2][Nk][3])."""
         self.nk = tuple(int(x) for x in nk)
         self.Nk = int(np.prod(self.nk))
         self.n_ao, self.nv, self.nc, self.n_aux = int(n_ao), int(nv), int(nc), int(n_aux)
@@ -168,17 +174,35 @@ class Plan:
         nb_ = self.nv + self.nc
         h = ctypes.c_void_p()
         self._ptr = None
-        s = lib().bse_plan_create(
-            ctypes.byref(d),
-            _dev(eps_qp, torch.float64, (self.Nk, nb_), "eps_qp"),
-            _dev(psi, torch.complex128, (self.Nk, nb_, self.n_ao), "psi"),
-            _dev(C, torch.complex128, (self.n_aux, self.n_ao, self.n_ao), "C"),
-            _dev(Vbar, torch.complex128, (self.n_aux, self.n_aux), "Vbar"),
-            _dev(W_q, torch.complex128, (self.Nk, self.n_aux, self.n_aux), "W_q"),
-            PREC[prec], self.max_nb,
-            (CHECK_HERMITIAN if check_hermitian else 0) | (ALL_PAIRS if all_pairs else 0) | CONDUCTION[conduction],
-            _stream(self.device), ctypes.byref(h))
-        _check("bse_plan_create", s)
+        flags = (CHECK_HERMITIAN if check_hermitian else 0) | (ALL_PAIRS if all_pairs else 0) | CONDUCTION[conduction]
+        self.two_centre = two_centre is not None
+        if two_centre is None:
+            s = lib().bse_plan_create(
+                ctypes.byref(d),
+                _dev(eps_qp, torch.float64, (self.Nk, nb_), "eps_qp"),
+                _dev(psi, torch.complex128, (self.Nk, nb_, self.n_ao), "psi"),
+                _dev(C, torch.complex128, (self.n_aux, self.n_ao, self.n_ao), "C"),
+                _dev(Vbar, torch.complex128, (self.n_aux, self.n_aux), "Vbar"),
+                _dev(W_q, torch.complex128, (self.Nk, self.n_aux, self.n_aux), "W_q"),
+                PREC[prec], self.max_nb, flags, _stream(self.device), ctypes.byref(h))
+            _check("bse_plan_create", s)
+        else:
+            if C is not None:
+                raise ValueError("give either C or two_centre")
+            C_R, RC, kf = two_centre
+            RC = _host(RC, np.int32).reshape(-1, 3)
+            kf = _host(kf, np.float64, (2, self.Nk, 3))
+            s = lib().bse_plan_create_2c(
+                ctypes.byref(d),
+                _dev(eps_qp, torch.float64, (self.Nk, nb_), "eps_qp"),
+                _dev(psi, torch.complex128, (self.Nk, nb_, self.n_ao), "psi"),
+                len(RC), RC.ctypes.data,
+                _dev(C_R, torch.float64, (len(RC), self.n_aux, self.n_ao, self.n_ao), "C_R"),
+                kf.ctypes.data,
+                _dev(Vbar, torch.complex128, (self.n_aux, self.n_aux), "Vbar"),
+                _dev(W_q, torch.complex128, (self.Nk, self.n_aux, self.n_aux), "W_q"),
+                PREC[prec], self.max_nb, flags, _stream(self.device), ctypes.byref(h))
+            _check("bse_plan_create_2c", s)
         self._ptr = h
 
     def close(self):
@@ -364,10 +388,15 @@ def offset_spectrum(plans, Ps, weights, n_steps, omega, eta):
 
 def plan_from_problem(prob, W_q, prec="f64", max_nb=8, device="cuda:0", check_hermitian=False, all_pairs=False,
                       conduction=None):
-    """Build a Plan from a synthetic crystal (inputs copied host -> device)."""
+    """Build a Plan from a synthetic crystal (inputs copied host -> device); a crystal with two-centre
+    coefficients (prob.C_R) gets a two-centre plan with the k of its valence and conduction bands."""
     dev = torch.device(device)
     t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)
+    if getattr(prob, "C_R", None) is not None:
+        C, tc = None, (t(prob.C_R, torch.float64), prob.RC, np.stack(prob.band_k()))
+    else:
+        C, tc = t(prob.C, torch.complex128), None
     return Plan(prob.nk, prob.n_ao, prob.nv, prob.nc, prob.n_aux, t(prob.eps_qp, torch.float64),
-                t(prob.psi, torch.complex128), t(prob.C, torch.complex128), t(prob.Vbar, torch.complex128),
+                t(prob.psi, torch.complex128), C, t(prob.Vbar, torch.complex128),
                 W_q, alpha=prob.alpha, prec=prec, max_nb=max_nb, check_hermitian=check_hermitian,
-                all_pairs=all_pairs, conduction=conduction)
+                all_pairs=all_pairs, conduction=conduction, two_centre=tc)

@@ -116,9 +116,11 @@ namespace {
 // plan-construction kernels
 // ---------------------------------------------------------------------------
 // rho[k][c][v][mu] = sum_t Bc[k][c][mu][t] psi[k][v][t]   (chunk of k, FP64)
+// two-centre coefficients (Bv not NULL): + conj(sum_t Bv[k][v][mu][t] psi[k][nv+c][t]), the pair
+// density of the reversed pair with its band indices exchanged
 __global__ void rho_kernel(int kcount, int k0, int nv, int nc, int nbnd, int n_ao, int n_aux,
                            const double* __restrict__ Bc, const double* __restrict__ psi,
-                           double* __restrict__ rho) {
+                           const double* __restrict__ Bv, double* __restrict__ rho) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long total = (long long)kcount * nc * n_aux;
   if (t >= total) return;
@@ -135,6 +137,18 @@ __global__ void rho_kernel(int kcount, int k0, int nv, int nc, int nbnd, int n_a
       const double ar = brow[2 * s], ai = brow[2 * s + 1], br = pv[2 * s], bi = pv[2 * s + 1];
       sr += ar * br - ai * bi;
       si += ar * bi + ai * br;
+    }
+    if (Bv) {
+      const double* vrow = Bv + 2 * (((long long)kl * nv + v) * n_aux + mu) * n_ao;
+      const double* pc = psi + 2 * ((long long)k * nbnd + nv + c) * n_ao;
+      double tr = 0, ti = 0;
+      for (int s = 0; s < n_ao; ++s) {
+        const double ar = vrow[2 * s], ai = vrow[2 * s + 1], br = pc[2 * s], bi = pc[2 * s + 1];
+        tr += ar * br - ai * bi;
+        ti += ar * bi + ai * br;
+      }
+      sr += tr;
+      si -= ti;
     }
     double* o = rho + 2 * ((((long long)k * nc + c) * nv + v) * n_aux + mu);
     o[0] = sr;
@@ -162,6 +176,37 @@ __global__ void velocity_kernel(long long N, int nv, int nc, int nb, long long N
   }
   P[2 * t] = sr / de;
   P[2 * t + 1] = si / de;
+}
+
+// two-centre halves as one FP64 GEMM of depth n_R * n_ao per k:
+//   B^mu_n(k)[t] = sum_{r, s} A[k][n][(r s)] Bst[(mu t)][(r s)]
+//   A[k][n][(r s)] = conj(psi_ns(k)) exp(-2 pi i k_n.R_r),   Bst[(mu t)][(r s)] = C^mu_ts(R_r)
+// so that B^mu_n(k) = psi_n(k)^H C^mu(-k_n)^T with C^mu(k) = sum_R C^mu(R) exp(+2 pi i k.R)
+__global__ void tc_stack_C(int nR, int na, int no, const double* __restrict__ C_R, double* __restrict__ Bst) {
+  const long long n = (long long)na * no * nR * no;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const int s = (int)(i % no);
+    const int r = (int)((i / no) % nR);
+    const long long row = i / ((long long)no * nR);  // mu * no + t
+    const int mu = (int)(row / no), t = (int)(row % no);
+    Bst[2 * i] = C_R[(((long long)r * na + mu) * no + t) * no + s];
+    Bst[2 * i + 1] = 0.0;
+  }
+}
+
+__global__ void tc_stack_psi(int kn, int k0, int Nk, int nv, int nbnd, int nR, int no, const double* __restrict__ psi,
+                             const double* __restrict__ ph, double* __restrict__ A) {
+  const long long n = (long long)kn * nbnd * nR * no;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const int s = (int)(i % no);
+    const int r = (int)((i / no) % nR);
+    const int b = (int)((i / ((long long)no * nR)) % nbnd);
+    const int k = k0 + (int)(i / ((long long)no * nR * nbnd));
+    const double* ps = psi + 2 * (((long long)k * nbnd + b) * no + s);
+    const double* pp = ph + 2 * (((long long)(b < nv ? 0 : 1) * Nk + k) * nR + r);
+    A[2 * i] = ps[0] * pp[0] + ps[1] * pp[1];
+    A[2 * i + 1] = ps[0] * pp[1] - ps[1] * pp[0];
+  }
 }
 
 bool bad_ptr(const void* p) { return p == nullptr; }
@@ -205,7 +250,10 @@ hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 // split (the BF16x3 apply never forms them; its adjoint allocates them on first use)
 size_t per_q_bytes(const Plan* p) {
   const long long Nk = p->Nk, nv = p->d.nv, nc = p->d.nc, na = p->d.n_aux;
-  return p->esz * (size_t)(Nk * nv * nv * na * 2 + (p->mc_direct ? Nk * nc * nc * na : 0) + Nk * nc * nc * nv * nv);
+  const size_t tc = p->two_centre ? (size_t)(p->prec == BSE_F64 ? 16 : 8) * 2 * (size_t)(Nk * (nv * nv + nc * nc) * na)
+                                  : 0;
+  return p->esz * (size_t)(Nk * nv * nv * na * 2 + (p->mc_direct ? Nk * nc * nc * na : 0) + Nk * nc * nc * nv * nv) +
+         tc;
 }
 
 // BF16X3 conduction side: estimated time per pair of forming M_cc' (pair-density GEMM, T = M_c P^T on
@@ -226,8 +274,8 @@ bool prefer_mc(const bse_dims& d) {
 
 bse_status check_hermitian(const void* C, const void* Vbar, const bse_dims* d, hipStream_t st) {
   const size_t na = d->n_aux, no = d->n_ao;
-  std::vector<double> hc(2 * na * no * no), hv(2 * na * na);
-  BSE_HIP(hipMemcpyAsync(hc.data(), C, hc.size() * 8, hipMemcpyDeviceToHost, st));
+  std::vector<double> hc(C ? 2 * na * no * no : 0), hv(2 * na * na);
+  if (C) BSE_HIP(hipMemcpyAsync(hc.data(), C, hc.size() * 8, hipMemcpyDeviceToHost, st));
   BSE_HIP(hipMemcpyAsync(hv.data(), Vbar, hv.size() * 8, hipMemcpyDeviceToHost, st));
   BSE_HIP(hipStreamSynchronize(st));
   auto herm = [](const double* m, size_t n) {
@@ -241,7 +289,7 @@ bse_status check_hermitian(const void* C, const void* Vbar, const bse_dims* d, h
       }
     return dev <= 1e-12 * std::fmax(mx, 1e-300);
   };
-  for (size_t m = 0; m < na; ++m)
+  for (size_t m = 0; C && m < na; ++m)
     if (!herm(hc.data() + 2 * m * no * no, no)) {
       set_error("C^mu is not Hermitian for mu = " + std::to_string(m));
       return BSE_ENOTHERM;
@@ -295,9 +343,19 @@ __global__ void permute_blocks(const unsigned short* __restrict__ in, unsigned s
   }
 }
 
+// two-centre LRI coefficients as given to plan creation
+struct TwoCentreIn {
+  int nR = 0;
+  const int32_t* R = nullptr;   // host [nR][3]
+  const double* C_R = nullptr;  // device f64 [nR][n_aux][n_ao][n_ao]
+  const double* kf = nullptr;   // host f64 [2][Nk][3]: k of the valence bands, then of the conduction bands
+};
+
 bse_status build_plan(Plan* p, const bse_dims* d, const double* eps_qp, const void* psi, const void* C,
-                      const void* Vbar, const void* W_q, bse_prec prec, int max_nb, uint32_t flags, hipStream_t st) {
+                      const TwoCentreIn* tc, const void* Vbar, const void* W_q, bse_prec prec, int max_nb,
+                      uint32_t flags, hipStream_t st) {
   p->d = *d;
+  p->two_centre = tc ? 1 : 0;
   p->Nk = d->nk[0] * d->nk[1] * d->nk[2];
   p->nbnd = d->nv + d->nc;
   p->nt = d->nv * d->nc;
@@ -370,36 +428,90 @@ bse_status build_plan(Plan* p, const bse_dims* d, const double* eps_qp, const vo
     kc = (int)std::max(1LL, std::min<long long>(Nk, budget / (16 * per_k)));
     s = dmalloc((void**)&tmp, 16 * (size_t)kc * per_k);
   }
+  // two-centre: the stacked coefficients and phases of the half GEMM (depth n_R * n_ao)
+  const int nR = tc ? tc->nR : 0;
+  double* bst = nullptr;
+  double* dph = nullptr;
+  double* astk = nullptr;
+  if (tc && s == BSE_OK) {
+    s = dmalloc((void**)&bst, 16 * (size_t)na * no * nR * no);
+    if (s == BSE_OK) s = dmalloc((void**)&dph, 16 * (size_t)2 * Nk * nR);
+    if (s == BSE_OK) s = dmalloc((void**)&astk, 16 * (size_t)kc * nbnd * nR * no);
+    if (s == BSE_OK) {
+      // exp(-2 pi i k.R) with k.R reduced to [0, 1) first
+      std::vector<double> hph((size_t)4 * Nk * nR);
+      for (int set = 0; set < 2; ++set)
+        for (int k = 0; k < Nk; ++k)
+          for (int r = 0; r < nR; ++r) {
+            const double* kk = tc->kf + 3 * ((size_t)set * Nk + k);
+            double x = kk[0] * tc->R[3 * r] + kk[1] * tc->R[3 * r + 1] + kk[2] * tc->R[3 * r + 2];
+            x -= std::floor(x);
+            const size_t o = 2 * (((size_t)set * Nk + k) * nR + r);
+            hph[o] = std::cos(2.0 * M_PI * x);
+            hph[o + 1] = -std::sin(2.0 * M_PI * x);
+          }
+      hipError_t e = hipMemcpyAsync(dph, hph.data(), 8 * hph.size(), hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL(tc_stack_C, dim3(4096), dim3(256), 0, st, nR, na, no, tc->C_R, bst);
+        e = hipGetLastError();
+      }
+      if (e == hipSuccess) e = hipStreamSynchronize(st);  // hph is released at the end of this block
+      if (e != hipSuccess) {
+        set_error(std::string("two-centre coefficients: ") + hipGetErrorString(e));
+        s = BSE_EDEVICE;
+      }
+    }
+  }
   for (int k0 = 0; s == BSE_OK && k0 < Nk; k0 += kc) {
     const int kn = std::min(kc, Nk - k0);
     double* dv = f64 ? (double*)p->Bv + 2LL * k0 * nv * na * no : tmp;
     double* dc = f64 ? (double*)p->Bc + 2LL * k0 * nc * na * no : tmp + 2LL * kn * nv * na * no;
+    if (tc) {
+      hipLaunchKernelGGL(tc_stack_psi, dim3(2048), dim3(256), 0, st, kn, k0, Nk,
+                         nv, nbnd, nR, no, p->psi64, dph, astk);
+      if (hipGetLastError() != hipSuccess) {
+        set_error("two-centre halves: launch failed");
+        s = BSE_EDEVICE;
+        break;
+      }
+    }
     for (int part = 0; part < 2 && s == BSE_OK; ++part) {
       const int nb_ = part == 0 ? nv : nc;
       GemmArgs g;
       g.batch = kn;
       g.M = nb_;
       g.N = na * no;
-      g.K = no;
-      g.A = (const double*)p->psi64 + 2 * ((long long)k0 * nbnd + (part == 0 ? 0 : nv)) * no;
-      g.a_sb = (long long)nbnd * no;
-      g.a_si = no;
-      g.a_sk = 1;
-      g.conjA = 1;
-      g.B = C;
-      g.b_tab = colt;
-      g.b_sk = no;
       g.C = part == 0 ? dv : dc;
       g.c_sb = (long long)nb_ * na * no;
       g.c_si = (long long)na * no;
       g.c_sj = 1;
+      if (tc) {
+        g.K = nR * no;
+        g.A = astk + 2LL * (part == 0 ? 0 : nv) * nR * no;
+        g.a_sb = (long long)nbnd * nR * no;
+        g.a_si = (long long)nR * no;
+        g.a_sk = 1;
+        g.B = bst;
+        g.b_sj = (long long)nR * no;
+        g.b_sk = 1;
+      } else {
+        g.K = no;
+        g.A = (const double*)p->psi64 + 2 * ((long long)k0 * nbnd + (part == 0 ? 0 : nv)) * no;
+        g.a_sb = (long long)nbnd * no;
+        g.a_si = no;
+        g.a_sk = 1;
+        g.conjA = 1;
+        g.B = C;
+        g.b_tab = colt;
+        g.b_sk = no;
+      }
       s = cgemm(g, AR_F64, true, true, st);
     }
     if (s != BSE_OK) break;
     {
       const long long tot = (long long)kn * nc * na;
       hipLaunchKernelGGL(rho_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, kn, k0, nv, nc, nbnd,
-                         no, na, dc, p->psi64, p->rho);
+                         no, na, dc, p->psi64, tc ? dv : nullptr, p->rho);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) {
         set_error(std::string("rho kernel: ") + hipGetErrorString(e));
@@ -436,6 +548,9 @@ bse_status build_plan(Plan* p, const bse_dims* d, const double* eps_qp, const vo
   }
   dfree(tmp);
   dfree(colt);
+  dfree(bst);
+  dfree(dph);
+  dfree(astk);
   if (s != BSE_OK) return s;
 
   // k + q table, and the q order of the pair symmetry
@@ -452,6 +567,14 @@ bse_status build_plan(Plan* p, const bse_dims* d, const double* eps_qp, const vo
     }
     BSE_TRY(plan_alloc(p, (void**)&p->kq, sizeof(int) * h.size()));
     BSE_HIP(hipMemcpyAsync(p->kq, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice, st));
+    if (p->two_centre) {
+      std::vector<int> hi((size_t)Nk * Nk);
+      for (int k = 0; k < Nk; ++k)
+        for (int q = 0; q < Nk; ++q) hi[(size_t)k * Nk + q] = h[(size_t)k * Nk + neg[q]];
+      BSE_TRY(plan_alloc(p, (void**)&p->kqinv, sizeof(int) * hi.size()));
+      BSE_HIP(hipMemcpyAsync(p->kqinv, hi.data(), sizeof(int) * hi.size(), hipMemcpyHostToDevice, st));
+      BSE_HIP(hipStreamSynchronize(st));  // hi is released at the end of this block
+    }
     // self-conjugate q (q = -q on the mesh) first, then the smaller index of each pair, then partners
     std::vector<int> order;
     order.reserve(Nk);
@@ -531,7 +654,9 @@ bse_status build_plan(Plan* p, const bse_dims* d, const double* eps_qp, const vo
   // conduction side of the direct term
   if (p->split) {
     const bool u_ok = (long long)nv * nv <= 128 && no <= 128;
-    if (flags & BSE_CONDUCTION_U) {
+    if (p->two_centre) {
+      p->mc_direct = 1;  // the second centre puts mu on the psi_c'(k') side: no B_c(k) contraction
+    } else if (flags & BSE_CONDUCTION_U) {
       p->mc_direct = 0;
     } else if (flags & BSE_CONDUCTION_MC) {
       p->mc_direct = 1;
@@ -563,6 +688,11 @@ bse_status build_plan(Plan* p, const bse_dims* d, const double* eps_qp, const vo
     BSE_TRY(plan_alloc(p, &p->P, p->esz * (size_t)(nq * Nk * nv * nv * na)));
     if (p->mc_direct) BSE_TRY(plan_alloc(p, &p->Mc, p->esz * (size_t)(nq * Nk * nc * nc * na)));
     BSE_TRY(plan_alloc(p, &p->T, p->esz * (size_t)(nq * Nk * nc * nc * nv * nv)));
+    if (p->two_centre) {
+      const size_t nn = (size_t)(f64 ? 16 : 8) * (size_t)(nq * Nk * (nv * nv + nc * nc) * na);
+      BSE_TRY(plan_alloc(p, &p->Nt, nn));
+      BSE_TRY(plan_alloc(p, &p->Nt2, nn));
+    }
     BSE_TRY(plan_alloc(p, (void**)&p->tab_psi_v, sizeof(long long) * (size_t)(nq * Nk * nv)));
     BSE_TRY(plan_alloc(p, (void**)&p->tab_mv, sizeof(long long) * (size_t)(nq * Nk * nv)));
     BSE_TRY(plan_alloc(p, (void**)&p->tab_psi_c, sizeof(long long) * (size_t)(nq * Nk * nc)));
@@ -645,65 +775,78 @@ bse_status bse_interpolate_W_adjoint(int32_t n_aux, int32_t n_R, const int32_t* 
   return interp_adjoint(n_aux, n_R, R, w_R, n_q, q_frac, (const double*)g_Wq, (double*)g_WR, S(hip_stream));
 }
 
-bse_status bse_plan_create(const bse_dims* d, const double* eps_qp, const void* psi, const void* C,
-                           const void* Vbar, const void* W_q, bse_prec prec, int32_t max_nb, uint32_t flags,
-                           void* hip_stream, bse_plan** out) {
+}  // extern "C"
+
+namespace bse {
+namespace {
+bse_status plan_create(const char* fn, const bse_dims* d, const double* eps_qp, const void* psi, const void* C,
+                       const TwoCentreIn* tc, const void* Vbar, const void* W_q, bse_prec prec, int32_t max_nb,
+                       uint32_t flags, void* hip_stream, bse_plan** out) {
+  const std::string f(fn);
   set_error("");
   if (!out) {
-    set_error("bse_plan_create: out is NULL");
+    set_error(f + ": out is NULL");
     return BSE_EINVAL;
   }
   *out = nullptr;
   BSE_TRY(validate_dims(d));
-  if (bad_ptr(eps_qp) || bad_ptr(psi) || bad_ptr(C) || bad_ptr(Vbar) || bad_ptr(W_q)) {
-    set_error("bse_plan_create: NULL input pointer");
+  if (bad_ptr(eps_qp) || bad_ptr(psi) || (!tc && bad_ptr(C)) || bad_ptr(Vbar) || bad_ptr(W_q)) {
+    set_error(f + ": NULL input pointer");
+    return BSE_EINVAL;
+  }
+  if (tc && (tc->nR <= 0 || bad_ptr(tc->R) || bad_ptr(tc->C_R) || bad_ptr(tc->kf))) {
+    set_error(f + ": two-centre coefficients need n_RC > 0 and non-NULL RC, C_R and k_frac");
     return BSE_EINVAL;
   }
   if (!valid_prec(prec)) {
-    set_error("bse_plan_create: unknown precision");
+    set_error(f + ": unknown precision");
     return BSE_EINVAL;
   }
   if (max_nb <= 0) {
-    set_error("bse_plan_create: max_nb must be positive");
+    set_error(f + ": max_nb must be positive");
     return BSE_EINVAL;
   }
   if ((long long)d->nv * d->nc * max_nb > 2048) {
-    set_error("bse_plan_create: nv*nc*max_nb must not exceed 2048");
+    set_error(f + ": nv*nc*max_nb must not exceed 2048");
     return BSE_ESHAPE;
   }
   {
     // the direct term stages one (nc nv)^2 block and one X slice per pair in LDS
     const long long nt = (long long)d->nv * d->nc;
     if (nt * nt * 16 + nt * max_nb * 16 > 150 * 1024) {
-      set_error("bse_plan_create: (nv*nc)^2 + nv*nc*max_nb too large for the LDS-staged pair block");
+      set_error(f + ": (nv*nc)^2 + nv*nc*max_nb too large for the LDS-staged pair block");
       return BSE_ESHAPE;
     }
   }
   if ((flags & BSE_CONDUCTION_MC) && (flags & BSE_CONDUCTION_U)) {
-    set_error("bse_plan_create: BSE_CONDUCTION_MC and BSE_CONDUCTION_U exclude each other");
+    set_error(f + ": BSE_CONDUCTION_MC and BSE_CONDUCTION_U exclude each other");
     return BSE_EINVAL;
   }
   if (flags & ~(BSE_CHECK_HERMITIAN | BSE_ALL_PAIRS | BSE_CONDUCTION_MC | BSE_CONDUCTION_U)) {
-    set_error("bse_plan_create: unknown flags");
+    set_error(f + ": unknown flags");
     return BSE_EINVAL;
   }
   if (flags & BSE_CONDUCTION_U) {
     if (prec != BSE_BF16X3) {
-      set_error("bse_plan_create: BSE_CONDUCTION_U applies to BSE_BF16X3 only");
+      set_error(f + ": BSE_CONDUCTION_U applies to BSE_BF16X3 only");
+      return BSE_EINVAL;
+    }
+    if (tc) {
+      set_error(f + ": BSE_CONDUCTION_U needs k-independent coefficients");
       return BSE_EINVAL;
     }
     if ((long long)d->nv * d->nv > 128 || d->n_ao > 128) {
-      set_error("bse_plan_create: BSE_CONDUCTION_U needs nv^2 <= 128 and n_ao <= 128");
+      set_error(f + ": BSE_CONDUCTION_U needs nv^2 <= 128 and n_ao <= 128");
       return BSE_ESHAPE;
     }
   }
-  if (flags & BSE_CHECK_HERMITIAN) BSE_TRY(check_hermitian(C, Vbar, d, S(hip_stream)));
+  if (flags & BSE_CHECK_HERMITIAN) BSE_TRY(check_hermitian(tc ? nullptr : C, Vbar, d, S(hip_stream)));
   bse_plan* h = new (std::nothrow) bse_plan();
   if (!h) {
-    set_error("bse_plan_create: host allocation failed");
+    set_error(f + ": host allocation failed");
     return BSE_ENOMEM;
   }
-  bse_status s = build_plan(&h->impl, d, eps_qp, psi, C, Vbar, W_q, prec, max_nb, flags, S(hip_stream));
+  bse_status s = build_plan(&h->impl, d, eps_qp, psi, C, tc, Vbar, W_q, prec, max_nb, flags, S(hip_stream));
   if (s != BSE_OK) {
     destroy_plan(&h->impl);
     delete h;
@@ -711,6 +854,30 @@ bse_status bse_plan_create(const bse_dims* d, const double* eps_qp, const void* 
   }
   *out = h;
   return BSE_OK;
+}
+}  // namespace
+}  // namespace bse
+
+extern "C" {
+
+bse_status bse_plan_create(const bse_dims* d, const double* eps_qp, const void* psi, const void* C,
+                           const void* Vbar, const void* W_q, bse_prec prec, int32_t max_nb, uint32_t flags,
+                           void* hip_stream, bse_plan** out) {
+  return bse::plan_create("bse_plan_create", d, eps_qp, psi, C, nullptr, Vbar, W_q, prec, max_nb, flags, hip_stream,
+                          out);
+}
+
+bse_status bse_plan_create_2c(const bse_dims* d, const double* eps_qp, const void* psi, int32_t n_RC,
+                              const int32_t* RC, const double* C_R, const double* k_frac, const void* Vbar,
+                              const void* W_q, bse_prec prec, int32_t max_nb, uint32_t flags, void* hip_stream,
+                              bse_plan** out) {
+  bse::TwoCentreIn tc;
+  tc.nR = n_RC;
+  tc.R = RC;
+  tc.C_R = C_R;
+  tc.kf = k_frac;
+  return bse::plan_create("bse_plan_create_2c", d, eps_qp, psi, nullptr, &tc, Vbar, W_q, prec, max_nb, flags,
+                          hip_stream, out);
 }
 
 bse_status bse_plan_pairs(const bse_plan* plan, int64_t* formed, int64_t* total) {

@@ -331,76 +331,152 @@ Arith arith_of(bse_prec p) { return p == BSE_F64 ? AR_F64 : (p == BSE_F32 ? AR_F
 
 char* off_bytes(void* base, long long elems, size_t esz) { return (char*)base + elems * (long long)esz; }
 
+// two-centre pair densities of one q batch, from the one-sided products N (pairs (k, k'), k' = kq[k][q0+qi])
+// and N2 (the reversed pairs, N(k', k) stored at slot (qi, k')):
+//   M[qi][k][b'][b][mu] = N[qi][k][b'][b][mu] + conj(N2[qi][k'][b][b'][mu])
+// written in the plan's storage: four bf16 planes at plane stride ps (SPLIT) or interleaved T
+template <typename T, bool SPLIT>
+__global__ void tc_combine_kernel(int nq, int Nk, int nb, int na, int q0, const int* __restrict__ kq,
+                                  const T* __restrict__ N, const T* __restrict__ N2, void* __restrict__ out,
+                                  long long ps) {
+  const long long n = (long long)nq * Nk * nb * nb * na;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+    const int mu = (int)(e % na);
+    long long r = e / na;
+    const int b = (int)(r % nb);
+    r /= nb;
+    const int bp = (int)(r % nb);
+    r /= nb;
+    const int k = (int)(r % Nk);
+    const int qi = (int)(r / Nk);
+    const int kp = kq[(long long)k * Nk + q0 + qi];
+    const long long e2 = ((((long long)qi * Nk + kp) * nb + b) * nb + bp) * na + mu;
+    const T re = N[2 * e] + N2[2 * e2];
+    const T im = N[2 * e + 1] - N2[2 * e2 + 1];
+    if constexpr (SPLIT) {
+      __bf16* o = (__bf16*)out;
+      __bf16 hi, lo;
+      split_bf16((float)re, hi, lo);
+      o[e] = hi;
+      o[ps + e] = lo;
+      split_bf16((float)im, hi, lo);
+      o[2 * ps + e] = hi;
+      o[3 * ps + e] = lo;
+    } else {
+      T* o = (T*)out;
+      o[2 * e] = re;
+      o[2 * e + 1] = im;
+    }
+  }
+}
+
 // S1: pair-density halves -> Gv and Mc for one q batch
+//   k-independent C: one GEMM per band set, the half at k times psi(k') from the table
+//   two-centre C(R): the same GEMM gives the one-sided product N(k, k') (half psi(k)^H C(-k)^T); it runs
+//   again with the reverse table for N(k', k), and the pair density is N(k, k') + conj N(k', k)^T
+//   (the second centre's term, C^mu(k') acting on psi(k'), is the first centre's term of the reversed
+//   pair because C(R) is real)
 bse_status form_pair_densities(Plan* p, int q0, int nq, bool need_c, const int* kq, hipStream_t st,
                                  bool c_split = false) {
   const bse_dims& d = p->d;
   const int Nk = p->Nk, nv = d.nv, nc = d.nc, na = d.n_aux, no = d.n_ao;
-  {
-    StageMark sm_(p, BSE_STAGE_TABLES, st);
-    hipLaunchKernelGGL(tables_kernel, dim3(Nk), dim3(256), 0, st, Nk, nq, q0, nv, nc, p->nbnd, no, na, kq,
-                     p->tab_psi_v, p->tab_psi_c, p->tab_mv, p->tab_mc);
-    BSE_CHECK_LAUNCH();
-  }
   const Arith ar = arith_of(p->prec);
   const bool f64 = p->prec == BSE_F64;
-  {
-    StageMark sm_(p, BSE_STAGE_PAIRDENS_V, st);
-    GemmArgs g;
-    g.batch = Nk;
-    g.M = nq * nv;
-    g.N = nv * na;
-    g.K = no;
-    g.A = p->psi;
-    g.a_tab = p->tab_psi_v;
-    g.a_tab_pb = 1;
-    g.a_sk = 1;
-    g.B = p->Bv;
-    g.b_sb = (long long)nv * na * no;
-    g.b_sj = no;
-    g.b_sk = 1;
-    g.C = p->Mv;
-    g.c_tab = p->tab_mv;
-    g.c_tab_pb = 1;
-    g.c_sj = 1;
-    g.tab_aligned = (no % 8 == 0);
-    if (p->split) {
-      g.a_ps = p->ps_psi;
-      g.b_ps = p->ps_Bv;
-      g.c_ps = p->ps_Mv;
-      BSE_TRY(cgemm_split(g, true, true, true, false, st));
-    } else {
-      BSE_TRY(cgemm(g, ar, f64, f64, st));
+  const bool tc = p->two_centre != 0;
+  const size_t gsz = f64 ? 16 : 8;  // bytes per element of a non-split GEMM result
+  const long long nt_c = (long long)p->qb * Nk * nv * nv * na;  // offset of the conduction part in Nt / Nt2
+  // out == nullptr: the plan's Mv / Mc; otherwise the non-split one-sided product buffer
+  auto gemms = [&](const int* ktab, void* out) -> bse_status {
+    {
+      StageMark sm_(p, BSE_STAGE_TABLES, st);
+      hipLaunchKernelGGL(tables_kernel, dim3(Nk), dim3(256), 0, st, Nk, nq, q0, nv, nc, p->nbnd, no, na, ktab,
+                         p->tab_psi_v, p->tab_psi_c, p->tab_mv, p->tab_mc);
+      BSE_CHECK_LAUNCH();
     }
-  }
-  if (need_c) {
-    StageMark sm_(p, BSE_STAGE_PAIRDENS_C, st);
-    GemmArgs g;
-    g.batch = Nk;
-    g.M = nq * nc;
-    g.N = nc * na;
-    g.K = no;
-    g.A = p->psi;
-    g.a_tab = p->tab_psi_c;
-    g.a_tab_pb = 1;
-    g.a_sk = 1;
-    g.B = p->Bc;
-    g.b_sb = (long long)nc * na * no;
-    g.b_sj = no;
-    g.b_sk = 1;
-    g.C = p->Mc;
-    g.c_tab = p->tab_mc;
-    g.c_tab_pb = 1;
-    g.c_sj = 1;
-    g.tab_aligned = (no % 8 == 0);
-    if (p->split) {
-      g.a_ps = p->ps_psi;
-      g.b_ps = p->ps_Bc;
-      g.c_ps = p->ps_Mc;
-      BSE_TRY(cgemm_split(g, true, true, c_split, false, st));
-    } else {
-      BSE_TRY(cgemm(g, ar, f64, f64, st));
+    {
+      StageMark sm_(p, BSE_STAGE_PAIRDENS_V, st);
+      GemmArgs g;
+      g.batch = Nk;
+      g.M = nq * nv;
+      g.N = nv * na;
+      g.K = no;
+      g.A = p->psi;
+      g.a_tab = p->tab_psi_v;
+      g.a_tab_pb = 1;
+      g.a_sk = 1;
+      g.B = p->Bv;
+      g.b_sb = (long long)nv * na * no;
+      g.b_sj = no;
+      g.b_sk = 1;
+      g.C = out ? out : p->Mv;
+      g.c_tab = p->tab_mv;
+      g.c_tab_pb = 1;
+      g.c_sj = 1;
+      g.tab_aligned = (no % 8 == 0);
+      if (p->split) {
+        g.a_ps = p->ps_psi;
+        g.b_ps = p->ps_Bv;
+        g.c_ps = p->ps_Mv;
+        BSE_TRY(cgemm_split(g, true, true, out == nullptr, false, st));
+      } else {
+        BSE_TRY(cgemm(g, ar, f64, f64, st));
+      }
     }
+    if (need_c) {
+      StageMark sm_(p, BSE_STAGE_PAIRDENS_C, st);
+      GemmArgs g;
+      g.batch = Nk;
+      g.M = nq * nc;
+      g.N = nc * na;
+      g.K = no;
+      g.A = p->psi;
+      g.a_tab = p->tab_psi_c;
+      g.a_tab_pb = 1;
+      g.a_sk = 1;
+      g.B = p->Bc;
+      g.b_sb = (long long)nc * na * no;
+      g.b_sj = no;
+      g.b_sk = 1;
+      g.C = out ? off_bytes(out, nt_c, gsz) : p->Mc;
+      g.c_tab = p->tab_mc;
+      g.c_tab_pb = 1;
+      g.c_sj = 1;
+      g.tab_aligned = (no % 8 == 0);
+      if (p->split) {
+        g.a_ps = p->ps_psi;
+        g.b_ps = p->ps_Bc;
+        g.c_ps = p->ps_Mc;
+        BSE_TRY(cgemm_split(g, true, true, out == nullptr && c_split, false, st));
+      } else {
+        BSE_TRY(cgemm(g, ar, f64, f64, st));
+      }
+    }
+    return BSE_OK;
+  };
+  if (!tc) return gemms(kq, nullptr);
+
+  const int* kinv = (kq == p->kqp) ? p->kqm : p->kqinv;
+  BSE_TRY(gemms(kq, p->Nt));
+  BSE_TRY(gemms(kinv, p->Nt2));
+  StageMark sm_(p, BSE_STAGE_PAIRDENS_V, st);
+  for (int part = 0; part < (need_c ? 2 : 1); ++part) {
+    const int nb = part == 0 ? nv : nc;
+    const long long off = part == 0 ? 0 : nt_c;
+    void* out = part == 0 ? p->Mv : p->Mc;
+    const bool split_out = p->split && (part == 0 || c_split);
+    const long long ps = part == 0 ? p->ps_Mv : p->ps_Mc;
+    const void* n1 = off_bytes(p->Nt, off, gsz);
+    const void* n2 = off_bytes(p->Nt2, off, gsz);
+    if (f64)
+      hipLaunchKernelGGL((tc_combine_kernel<double, false>), dim3(4096), dim3(256), 0, st, nq, Nk, nb, na, q0, kq,
+                         (const double*)n1, (const double*)n2, out, ps);
+    else if (split_out)
+      hipLaunchKernelGGL((tc_combine_kernel<float, true>), dim3(4096), dim3(256), 0, st, nq, Nk, nb, na, q0, kq,
+                         (const float*)n1, (const float*)n2, out, ps);
+    else
+      hipLaunchKernelGGL((tc_combine_kernel<float, false>), dim3(4096), dim3(256), 0, st, nq, Nk, nb, na, q0, kq,
+                         (const float*)n1, (const float*)n2, out, ps);
+    BSE_CHECK_LAUNCH();
   }
   return BSE_OK;
 }

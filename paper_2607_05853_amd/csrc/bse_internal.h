@@ -150,6 +150,13 @@ struct Plan {
   int* kqp = nullptr;
   int* kqm = nullptr;
   int* qord = nullptr;              // [Nk] dense-mesh index of the j-th q of that order
+  // two-centre LRI coefficients: the halves hold psi_n(k)^H C^mu(-k_n)^T, and every pair density is
+  // the one-sided product N(k, k') plus conj N(k', k) with the band indices exchanged; Nt / Nt2 hold
+  // N for the pairs of a q batch and for their reverses (GEMM output type: c128 on F64, else c64)
+  int two_centre = 0;
+  void* Nt = nullptr;               // [qb][Nk][nv][nv][n_aux] then [qb][Nk][nc][nc][n_aux]
+  void* Nt2 = nullptr;              // same layout, pair (k + q, k) stored at slot (q, k + q)
+  int* kqinv = nullptr;             // [Nk][Nk] (k, q) -> k - q, the reverse of kq
 
   // exchange / misc workspaces (FP64)
   double* xt = nullptr;       // c128 split-K partials [nsplit][n_aux][max_nb]

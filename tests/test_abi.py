@@ -79,6 +79,25 @@ def test_plan_create_validation_before_hip(L):
     assert out.value is None
 
 
+def test_plan_create_2c_validation_before_hip(L):
+    dummy = ctypes.c_void_p(16)
+    out = ctypes.c_void_p()
+    RC = np.zeros((1, 3), np.int32)
+    kf = np.zeros((2, 8, 3))
+    args = lambda d=None, nR=1, rc=RC.ctypes.data, cr=dummy, k=kf.ctypes.data, prec=0, flags=0: \
+        L.bse_plan_create_2c(ctypes.byref(d or _dims()), dummy, dummy, nR, rc, cr, k, dummy, dummy, prec, 4, flags,
+                             None, ctypes.byref(out))
+    assert args(nR=0) == 1
+    assert args(rc=None) == 1
+    assert args(cr=None) == 1
+    assert args(k=None) == 1
+    assert args(d=_dims(nv=0)) == 1
+    assert args(prec=2, flags=8) == 1                    # no B_c(k) contraction with two centres
+    assert b"k-independent" in L.bse_last_error()
+    assert args(flags=32) == 1
+    assert out.value is None
+
+
 def test_null_plan_calls(L):
     dummy = ctypes.c_void_p(16)
     assert L.bse_apply(None, dummy, dummy, 1, None) == 1

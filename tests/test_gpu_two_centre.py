@@ -1,0 +1,111 @@
+"""GPU parity of the two-centre LRI coefficients (Sec. III.A, C-tilde with C^mu(k_b) + C^mu(-k_a)^T):
+the plan forms both one-sided products of every pair and adds them; apply, adjoint and Haydock must
+reproduce the oracle's Hamiltonian built with the same coefficients, on the matrix-core shapes (N_ao a
+multiple of 8) and on ragged ones, with and without the pair symmetry, and on shifted meshes and at
+finite momentum (each band set at its own k)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from synth import dense_kmesh, make_problem, polarisations, random_block
+
+pytestmark = pytest.mark.gpu
+
+DMA = dict(cfg_id=84, coarse=(3, 3, 2), dense=(4, 4, 2), n_ao=16, nv=4, nc=4, n_aux=48)
+RAGGED = dict(cfg_id=85, coarse=(3, 3, 2), dense=(3, 2, 2), n_ao=10, nv=2, nc=3, n_aux=20)
+CONFS = {"DMA": DMA, "RAGGED": RAGGED}
+TOL = {"f64": 1e-12, "f32": 2e-5, "bf16x3": 5e-4}
+
+
+def T(a, dt=torch.complex128):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(torch.device("cuda:0"), dt)
+
+
+def H_(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def OW(p):
+    """The oracle's own W(q) on the dense mesh (oracle inputs never come from the GPU path)."""
+    return O.interpolate_W_matmul(p.W_R, p.R, p.w_R, dense_kmesh(p.nk))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2607_05853_amd import bse
+    return bse
+
+
+@pytest.mark.parametrize("all_pairs", [False, True])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
+@pytest.mark.parametrize("cfg", ["DMA", "RAGGED"])
+def test_two_centre_apply(B, cfg, prec, all_pairs):
+    p = make_problem(CONFS[cfg], 1, "G2", two_centre=True)
+    print("[two-centre apply %s %s all_pairs=%s]" % (cfg, prec, all_pairs), flush=True)
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
+    plan = B.plan_from_problem(p, Wq, prec=prec, max_nb=4, check_hermitian=True, all_pairs=all_pairs)
+    assert plan.two_centre and plan.conduction == "mc"
+    assert (plan.pairs[0] == p.Nk) == all_pairs
+    H = O.build_H(p, OW(p))
+    X = random_block(p.N, 3, seed=11)
+    err = rel(H_(plan.apply(T(X))), H @ X)
+    print("    rel err %.2e" % err, flush=True)
+    assert err < TOL[prec]
+    plan.close()
+
+
+@pytest.mark.parametrize("over", [dict(offset=(1.0 / 3, 1.0 / 3, 0.0)), dict(momentum=(0.5, 0.25, 0.0))])
+@pytest.mark.parametrize("prec", ["f64", "bf16x3"])
+def test_two_centre_band_k(B, prec, over):
+    # the phases of C^mu(k) follow the k of each band set: a shifted mesh, and conduction bands at k + Q
+    p = make_problem(DMA, 2, "G2", two_centre=True, **over)
+    print("[two-centre %s %s]" % (over, prec), flush=True)
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
+    plan = B.plan_from_problem(p, Wq, prec=prec, max_nb=4)
+    H = O.build_H(p, OW(p))
+    X = random_block(p.N, 2, seed=12)
+    err = rel(H_(plan.apply(T(X))), H @ X)
+    print("    rel err %.2e" % err, flush=True)
+    assert err < TOL[prec]
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
+def test_two_centre_adjoint(B, prec):
+    p = make_problem(DMA, 3, "G2", two_centre=True)
+    print("[two-centre adjoint %s]" % prec, flush=True)
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
+    plan = B.plan_from_problem(p, Wq, prec=prec, max_nb=4)
+    plan.set_R(p.R, p.w_R)
+    Yb, X = random_block(p.N, 3, seed=13), random_block(p.N, 3, seed=14)
+    g = plan.apply_adjoint(T(Yb), T(X), want_WR=True, want_Wq=True, want_eps=True)
+    ge, gq = O.grad_apply(p, OW(p), Yb, X)
+    gr = O.grad_WR_from_Wq(gq, p.R, p.w_R, dense_kmesh(p.nk))
+    eq, er = rel(H_(g["W_q"]), gq), rel(H_(g["W_R"]), gr)
+    print("    W_q %.2e W_R %.2e" % (eq, er), flush=True)
+    tol = {"f64": 1e-11, "f32": 5e-5, "bf16x3": 5e-4}[prec]
+    assert rel(H_(g["eps"]), ge) < 1e-13
+    assert eq < tol and er < tol
+    plan.close()
+
+
+def test_two_centre_haydock(B):
+    p = make_problem(DMA, 4, "G2", two_centre=True)
+    print("[two-centre haydock]", flush=True)
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
+    w = np.linspace(1.0, 5.0, 61)
+    H = O.build_H(p, OW(p))
+    Sref = O.haydock_spectrum(lambda x: H @ x, O.velocity_start(p, polarisations(2)), 40, w, 0.1, p.Nk)[0]
+    for prec, tol in [("f64", 1e-9), ("bf16x3", 1e-5)]:
+        plan = B.plan_from_problem(p, Wq, prec=prec, max_nb=2)
+        P = plan.velocity_start(T(p.vel), T(p.eps_ks, torch.float64), polarisations(2))
+        out = plan.haydock(P, 40, w, 0.1)
+        err = rel(out["S"], Sref)
+        print("    %s spectrum rel err %.2e" % (prec, err), flush=True)
+        assert err < tol
+        plan.close()
