@@ -23,6 +23,7 @@ __all__ = [
     "binding_energy", "grad_apply", "grad_WR_from_Wq", "grad_lowest", "grad_spectrum",
     "interpolate_W_matmul", "apply_H_rows_allpairs", "grad_Wq_at", "grad_eps",
     "PAPER_OFFSETS", "PAPER_OFFSET_WEIGHTS", "offset_average",
+    "lorentzian", "coupling_block", "build_B", "build_full", "full_bse_eig", "full_bse_amplitudes", "full_bse_spectrum",
 ]
 
 
@@ -191,6 +192,94 @@ def build_H(prob, W_q, alpha=None):
         for kp in range(Nk):
             H[k * nt:(k + 1) * nt, kp * nt:(kp + 1) * nt] = hamiltonian_block(prob, W_q, alpha, k, kp)
     return H
+
+
+def coupling_block(prob, W_q, alpha, k, kp):
+    """Block B[(k, c, v), (k', c', v')] of the coupling block of Eq. (Hamiltonian).
+
+    exchange : + alpha (c k*, v k | V | c' k'*, v' k')
+             = + (alpha/N_k) sum_munu M^mu_{cv}(k,k) Vbar_munu M^nu_{c'v'}(k',k')
+    direct   : - (c' k'*, v k | W | c k*, v' k')
+             = - (1/N_k) sum_munu M^mu_{c'v}(k',k) W_munu(k'-k) M^nu_{cv'}(k,k')
+    (a = c, i = v, k1 = k, b = c', j = v', k2 = k'; the first density of the direct integral
+    carries k' -> k as in the resonant block, hence the same W(k' - k)).
+    Returned as [nc*nv][nc*nv] with row (c, v) and column (c', v').
+    """
+    val, con = _bands(prob)
+    nc, nv = prob.nc, prob.nv
+    Mcv = _pairs(prob, k, con, k, val)        # [mu][c][v]
+    Mcv2 = _pairs(prob, kp, con, kp, val)     # [nu][c'][v']
+    Mcpv = _pairs(prob, kp, con, k, val)      # [mu][c'][v]
+    Mcvp = _pairs(prob, k, con, kp, val)      # [nu][c][v']
+    Wq = W_q[q_index(prob.nk, k, kp)]
+    Xb = (alpha / prob.Nk) * np.einsum("mcv,mn,ndp->cvdp", Mcv, prob.Vbar, Mcv2)
+    Db = -(1.0 / prob.Nk) * np.einsum("mdv,mn,ncp->cvdp", Mcpv, Wq, Mcvp)
+    return (Xb + Db).reshape(nc * nv, nc * nv)
+
+
+def build_B(prob, W_q, alpha=None):
+    """Explicit coupling block B [N][N] of Eq. (Hamiltonian)."""
+    alpha = prob.alpha if alpha is None else alpha
+    Nk, nt = prob.Nk, prob.nc * prob.nv
+    B = np.zeros((Nk * nt, Nk * nt), dtype=np.complex128)
+    for k in range(Nk):
+        for kp in range(Nk):
+            B[k * nt:(k + 1) * nt, kp * nt:(kp + 1) * nt] = coupling_block(prob, W_q, alpha, k, kp)
+    return B
+
+
+def build_full(prob, W_q, alpha=None):
+    """The full BSE Hamiltonian [[A, B], [-B*, -A*]] [2N][2N] (matrix form above Eq. (Hamiltonian))."""
+    A = build_H(prob, W_q, alpha)
+    B = build_B(prob, W_q, alpha)
+    return np.block([[A, B], [-B.conj(), -A.conj()]])
+
+
+def full_bse_eig(A, B):
+    """Positive eigenvalues Omega_S (ascending) of [[A, B], [-B*, -A*]] with right eigenvectors (X, Y)
+    normalised as X^H X - Y^H Y = 1 (the convention of Eqs. (right)/(left)).
+
+    Paired formulation: with J = diag(I, -I) the Hamiltonian is J M, M = [[A, B], [B*, A*]] Hermitian
+    and (for a stable ground state) positive definite, so H z = Omega z is the Hermitian-definite
+    problem J z = (1/Omega) M z; its M-orthonormal solutions with 1/Omega > 0 are the positive branch,
+    rescaled so that z^H J z = 1.  Returns Omega [N], X [N][N], Y [N][N] (column S)."""
+    import scipy.linalg
+    N = A.shape[0]
+    M = np.block([[A, B], [B.conj(), A.conj()]])
+    J = np.diag(np.r_[np.ones(N), -np.ones(N)]).astype(np.complex128)
+    lam, Z = scipy.linalg.eigh(J, M)          # J z = lam M z, z^H M z = 1
+    pos = lam > 0
+    Om = 1.0 / lam[pos]
+    Z = Z[:, pos] * np.sqrt(Om)[None, :]      # z^H J z = lam z^H M z = 1/Omega -> 1
+    order = np.argsort(Om)
+    Om, Z = Om[order], Z[:, order]
+    return Om, Z[:N], Z[N:]
+
+
+def full_bse_amplitudes(prob, pol, X, Y):
+    """Oscillator amplitudes of Eq. (full_BSE_epsilon2): for each exciton S and polarisation e
+    a_S = sum_{cvk} [e.<v k|v|c k> / (E_ck - E_vk)] X_{cvk} + [e.<c k|v|v k> / (E_vk - E_ck)] Y_{cvk}
+    with <v|v|c> = conj <c|v|v> and Kohn-Sham energies.  Returns [n_S][n_pol]."""
+    pol = np.atleast_2d(pol)
+    nv, nc = prob.nv, prob.nc
+    out = np.zeros((X.shape[1], len(pol)), dtype=np.complex128)
+    for b, e in enumerate(pol):
+        for k in range(prob.Nk):
+            for c in range(nc):
+                for v in range(nv):
+                    I = (k * nc + c) * nv + v
+                    d = prob.eps_ks[k, nv + c] - prob.eps_ks[k, v]
+                    m = sum(e[a] * prob.vel[a, k, c, v] for a in range(3))
+                    out[:, b] += np.conj(m) / d * X[I] + m / (-d) * Y[I]
+    return out
+
+
+def full_bse_spectrum(prob, pol, Omega, X, Y, omega, eta):
+    """S_e(omega) = (1/N_k) sum_S |a_S|^2 L_eta(omega - Omega_S) over the positive solutions
+    (Eq. (full_BSE_epsilon2) without 4 pi^2/(3V)).  Returns [n_pol][n_omega]."""
+    amp = np.abs(full_bse_amplitudes(prob, pol, X, Y)) ** 2
+    L = lorentzian(np.asarray(omega)[None, :] - np.asarray(Omega)[:, None], eta)
+    return (amp.T @ L) / prob.Nk
 
 
 def apply_H_rows(prob, W_q, X, rows, alpha=None):
