@@ -303,6 +303,40 @@ bse_status bse_lowest_excitons(bse_plan* plan, int32_t n_block, int32_t max_iter
                                void* hip_stream);
 
 /* ---------------------------------------------------------------------------
+ * Full BSE (Eq. (Hamiltonian) with its coupling block; the paired solutions of
+ * Eqs. (right)/(left); the spectrum of Eq. (full_BSE_epsilon2)).  Plans from
+ * bse_plan_create only (two-centre plans return BSE_EINVAL).
+ *
+ * bse_apply_coupling: Y = B X with
+ *   B_{cvk,c'v'k'} = (alpha/N_k) sum_munu M^mu_cv(k,k) Vbar_munu M^nu_c'v'(k',k')
+ *                  - (1/N_k) sum_munu M^mu_c'v(k',k) W_munu(k'-k) M^nu_cv'(k,k')
+ * (every pair formed; Vbar real symmetric and W(-R) = W(R)^T make B symmetric).
+ * X, Y device c128 [N][nb], 1 <= nb <= max_nb, not overlapping; Y overwritten.
+ *
+ * bse_apply_full: out = [[A, B], [-B*, -A*]] [X; Y].  XY and out device c128
+ * [2N][nb] (rows 0..N-1 the X block, N..2N-1 the Y block); needs 2 nb <= max_nb
+ * (A is applied to [X | conj Y] and B to [Y | conj X] as one block each).
+ *
+ * bse_full_spectrum: for each of the nb columns p of P (device c128 [N][nb],
+ * velocity start vectors as from bse_velocity_start)
+ *   S[b][w] = (1/N_k) sum_{Omega_S > 0} |p^H X^S - p^T Y^S|^2 L_eta(omega_w - Omega_S)
+ * with X^H X - Y^H Y = 1, by n_steps of Lanczos in the inner product
+ * <x, y> = x^H J H y (J = diag(I, -I); positive definite for a stable ground
+ * state) from [p; p*], full re-orthogonalisation, and Gauss quadrature on the
+ * leading even-sized tridiagonal (its Ritz values come in +- pairs).  Needs
+ * 2 nb <= max_nb and 2 <= n_steps <= 2N.  S host f64 [nb][n_w]; a host f64
+ * [nb][n_steps] (diagonal, zero up to rounding), b host f64 [nb][n_steps+1]
+ * (b[0] = |[p; p*]|, then the off-diagonal); steps_done host int32 [nb].
+ * Exact once the Krylov space is invariant; BSE_INFO_BREAKDOWN when a chain
+ * stopped early (its spectrum uses the steps done).
+ * ------------------------------------------------------------------------- */
+bse_status bse_apply_coupling(bse_plan* plan, const void* X, void* Y, int32_t nb, void* hip_stream);
+bse_status bse_apply_full(bse_plan* plan, const void* XY, void* out, int32_t nb, void* hip_stream);
+bse_status bse_full_spectrum(bse_plan* plan, const void* P, int32_t nb, int32_t n_steps, const double* omega,
+                             int32_t n_w, double eta, double* S, double* a, double* b, int32_t* steps_done,
+                             void* hip_stream);
+
+/* ---------------------------------------------------------------------------
  * Stage timing (tracing): when enabled, HIP events are recorded on the call's
  * stream around every stage launched by bse_apply / bse_apply_adjoint /
  * bse_haydock_spectrum, and bse_plan_stage_times() synchronises on them and
@@ -319,7 +353,8 @@ typedef enum {
     BSE_STAGE_ADJOINT = 7,    /* adjoint-only contractions                                 */
     BSE_STAGE_PAIRDENS_C = 8, /* conduction pair densities M_cc' from the halves (1 kernel) */
     BSE_STAGE_TABLES = 9,     /* gather tables of a q batch                                */
-    BSE_NSTAGES = 10
+    BSE_STAGE_COUPLING = 10,  /* direct term of the coupling block B (full BSE)            */
+    BSE_NSTAGES = 11
 } bse_stage;
 bse_status bse_plan_set_timing(bse_plan* plan, int enable);
 /* ms, launches: host arrays of BSE_NSTAGES entries; reset != 0 clears the totals */

@@ -59,6 +59,9 @@ _SIGS = {
     "bse_velocity_start": [_vp, _vp, _vp, _i32, _vp, _vp, _vp],
     "bse_haydock_spectrum": [_vp, _vp, _i32, _i32, _vp, _i32, ctypes.c_double, _vp, _vp, _vp, _vp, _vp, _vp],
     "bse_lowest_excitons": [_vp, _i32, _i32, ctypes.c_double, _vp, _vp, _vp, _vp, _vp],
+    "bse_apply_coupling": [_vp, _vp, _vp, _i32, _vp],
+    "bse_apply_full": [_vp, _vp, _vp, _i32, _vp],
+    "bse_full_spectrum": [_vp, _vp, _i32, _i32, _vp, _i32, ctypes.c_double, _vp, _vp, _vp, _vp, _vp],
     "bse_haydock_vjp": [_vp, _vp, _vp, _vp, _vp, _i32, _i32, _vp, _i32, ctypes.c_double, _vp, _vp, _vp, _vp, _vp],
     "bse_plan_set_timing": [_vp, ctypes.c_int],
     "bse_plan_stage_times": [_vp, _vp, _vp, ctypes.c_int],
@@ -261,6 +264,39 @@ class Plan:
         _check("bse_apply", s)
         return Y
 
+    def apply_coupling(self, X, out=None):
+        """Y = B X (coupling block of the full BSE) for X [N][nb] complex128 on the device."""
+        nb = X.shape[1]
+        Y = torch.empty_like(X) if out is None else out
+        s = lib().bse_apply_coupling(self._ptr, _dev(X, torch.complex128, (self.N, nb), "X"),
+                                     _dev(Y, torch.complex128, (self.N, nb), "Y"), nb, _stream(self.device))
+        _check("bse_apply_coupling", s)
+        return Y
+
+    def apply_full(self, XY, out=None):
+        """[[A, B], [-B*, -A*]] [X; Y] for XY [2N][nb] (X rows first); needs 2 nb <= max_nb."""
+        nb = XY.shape[1]
+        R = torch.empty_like(XY) if out is None else out
+        s = lib().bse_apply_full(self._ptr, _dev(XY, torch.complex128, (2 * self.N, nb), "XY"),
+                                 _dev(R, torch.complex128, (2 * self.N, nb), "out"), nb, _stream(self.device))
+        _check("bse_apply_full", s)
+        return R
+
+    def full_spectrum(self, P, n_steps, omega, eta):
+        """Full-BSE spectrum of the columns of P over the positive excitations (structure-preserving
+        Lanczos, n_steps steps); returns S [nb][n_w], a, b, steps, breakdown."""
+        nb = P.shape[1]
+        omega = _host(omega, np.float64).ravel()
+        S = np.zeros((nb, len(omega)))
+        a = np.zeros((nb, n_steps))
+        b = np.zeros((nb, n_steps + 1))
+        steps = np.zeros(nb, dtype=np.int32)
+        s = lib().bse_full_spectrum(self._ptr, _dev(P, torch.complex128, (self.N, nb), "P"), nb, int(n_steps),
+                                    omega.ctypes.data, len(omega), float(eta), S.ctypes.data, a.ctypes.data,
+                                    b.ctypes.data, steps.ctypes.data, _stream(self.device))
+        _check("bse_full_spectrum", s, allow_breakdown=True)
+        return {"S": S, "a": a, "b": b, "steps": steps, "breakdown": s == BSE_INFO_BREAKDOWN}
+
     def apply_adjoint(self, Ybar, X, want_WR=True, want_Wq=False, want_eps=True):
         """Gradients of Re <Ybar, A X> w.r.t. W(R) (or W(q)) and the energies."""
         nb = X.shape[1]
@@ -280,7 +316,7 @@ class Plan:
         return {"W_R": gWR, "W_q": gWq, "eps": geps}
 
     STAGES = ("pairdens_v", "wstep", "dblock", "tx", "exchange", "diag", "lanczos", "adjoint", "pairdens_c",
-              "tables")
+              "tables", "coupling")
 
     def set_timing(self, enable=True):
         _check("bse_plan_set_timing", lib().bse_plan_set_timing(self._ptr, 1 if enable else 0))

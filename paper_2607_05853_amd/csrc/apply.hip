@@ -481,7 +481,252 @@ bse_status form_pair_densities(Plan* p, int q0, int nq, bool need_c, const int* 
   return BSE_OK;
 }
 
+// tables of one q batch of the coupling block, per-batch layout [k][nq*nband]:
+//   rows (q, c') of psi_c(k') and their Gb slots, rows (q, v') of psi_v(k') and their M2 slots
+__global__ void tables_b_kernel(int Nk, int nq, int q0, int nv, int nc, int nbnd, int n_ao, int n_aux,
+                                const int* __restrict__ kq, long long* __restrict__ tpc, long long* __restrict__ tg,
+                                long long* __restrict__ tpv, long long* __restrict__ tm2) {
+  const int k = blockIdx.x;
+  for (int t = threadIdx.x; t < nq * (nv + nc); t += blockDim.x) {
+    if (t < nq * nc) {
+      const int qi = t / nc, c = t % nc;
+      const int kp = kq[(long long)k * Nk + q0 + qi];
+      tpc[(long long)k * nq * nc + t] = ((long long)kp * nbnd + nv + c) * n_ao;
+      tg[(long long)k * nq * nc + t] = (((long long)qi * Nk + k) * nc + c) * nv * n_aux;
+    } else {
+      const int u = t - nq * nc;
+      const int qi = u / nv, v = u % nv;
+      const int kp = kq[(long long)k * Nk + q0 + qi];
+      tpv[(long long)k * nq * nv + u] = ((long long)kp * nbnd + v) * n_ao;
+      tm2[(long long)k * nq * nv + u] = (((long long)qi * Nk + k) * nv + v) * nc * n_aux;
+    }
+  }
+}
+
+// part[chunk][k][(c v)][b] = sum_{qi in chunk} sum_{c'v'} Tb[qi][k][(v' c)][(c' v)] X[k'][(c' v')][b],
+// k' = kq[k][q0 + qi]; one Tb block and one X slice staged in LDS per q
+template <typename TT>
+__global__ __launch_bounds__(256) void coupling_tx_kernel(int Nk, int nq, int q0, int nv, int nc, int nb, int qlen,
+                                                          const int* __restrict__ kq, const TT* __restrict__ T,
+                                                          const double* __restrict__ X, double* __restrict__ part) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char sbytes[];
+  const int k = blockIdx.x, chunk = blockIdx.y;
+  const int nt = nc * nv, nt2 = nt * nt, ne = nt * nb;
+  TT* ts = reinterpret_cast<TT*>(sbytes);
+  double* xs = reinterpret_cast<double*>(sbytes + (((size_t)nt2 * 2 * sizeof(TT) + 15) & ~(size_t)15));
+  const int qa = chunk * qlen, qe = min(nq, qa + qlen);
+  double accr[8], acci[8];
+  for (int sl = 0; sl < 8; ++sl) accr[sl] = acci[sl] = 0.0;
+  for (int qi = qa; qi < qe; ++qi) {
+    const int kp = kq[(long long)k * Nk + q0 + qi];
+    const TT* tb = T + 2 * (((long long)qi * Nk + k) * nt2);
+    const double* xb = X + 2 * ((long long)kp * ne);
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2 * nt2; i += blockDim.x) ts[i] = tb[i];
+    for (int i = threadIdx.x; i < 2 * ne; i += blockDim.x) xs[i] = xb[i];
+    __syncthreads();
+    for (int sl = 0; sl < 8; ++sl) {
+      const int e = threadIdx.x + 256 * sl;
+      if (e >= ne) break;
+      const int b = e % nb, cv = e / nb, c = cv / nv, v = cv % nv;
+      double sr = 0.0, si = 0.0;
+      for (int c2 = 0; c2 < nc; ++c2)
+        for (int v2 = 0; v2 < nv; ++v2) {
+          const int ti = (v2 * nc + c) * nt + c2 * nv + v;
+          const double tr = (double)ts[2 * ti], tim = (double)ts[2 * ti + 1];
+          const double xr = xs[2 * ((c2 * nv + v2) * nb + b)], xi = xs[2 * ((c2 * nv + v2) * nb + b) + 1];
+          sr += tr * xr - tim * xi;
+          si += tr * xi + tim * xr;
+        }
+      accr[sl] += sr;
+      acci[sl] += si;
+    }
+  }
+  const long long n = (long long)Nk * ne;
+  for (int sl = 0; sl < 8; ++sl) {
+    const int e = threadIdx.x + 256 * sl;
+    if (e >= ne) break;
+    double* o = part + 2 * ((long long)chunk * n + (long long)k * ne + e);
+    o[0] = accr[sl];
+    o[1] = acci[sl];
+  }
+}
+
 }  // namespace
+
+// Direct term of the coupling block B of Eq. (Hamiltonian), added to Y:
+//   Y[(c v k)] -= (1/N_k) sum_{k'} sum_{c'v'} sum_munu M^mu_{c'v}(k',k) W_munu(k'-k) M^nu_{cv'}(k,k') X[(c'v'k')]
+// over every pair (no pair symmetry), in q batches: Gb = conj M_{c'v}(k',k) = M_{vc'}(k,k') and
+// M2 = M_{cv'}(k,k') from the halves (Hermitian C), Pb = conj(Gb) W(q), Tb = M2 Pb^T, then Tb X(k').
+bse_status apply_coupling_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t st) {
+  const bse_dims& d = p->d;
+  const int Nk = p->Nk, nv = d.nv, nc = d.nc, na = d.n_aux, no = d.n_ao, nt = nv * nc;
+  const Arith ar = arith_of(p->prec);
+  const bool f64 = p->prec == BSE_F64;
+  if (!p->Gb) {
+    // the same workspace budget as the resonant direct term
+    const long long per_q_a = (long long)Nk * (nv * nv * na * 2 + (p->mc_direct ? nc * nc * na : 0) + nt * nt);
+    const long long per_q_b = (long long)Nk * (3LL * nc * nv * na + (long long)nt * nt);
+    const long long qb = std::max(1LL, std::min<long long>(Nk, (long long)p->qb * per_q_a / per_q_b));
+    p->qbB = (int)qb;
+    p->ps_Gb = qb * Nk * nc * nv * na;
+    BSE_TRY(plan_alloc(p, &p->Gb, p->esz * (size_t)p->ps_Gb));
+    BSE_TRY(plan_alloc(p, &p->Pb, p->esz * (size_t)p->ps_Gb));
+    BSE_TRY(plan_alloc(p, &p->M2, p->esz * (size_t)p->ps_Gb));
+    BSE_TRY(plan_alloc(p, &p->Tb, p->esz * (size_t)(qb * Nk * nt * nt)));
+    BSE_TRY(plan_alloc(p, (void**)&p->tabB_psi_c, sizeof(long long) * (size_t)(qb * Nk * nc)));
+    BSE_TRY(plan_alloc(p, (void**)&p->tabB_g, sizeof(long long) * (size_t)(qb * Nk * nc)));
+    BSE_TRY(plan_alloc(p, (void**)&p->tabB_psi_v, sizeof(long long) * (size_t)(qb * Nk * nv)));
+    BSE_TRY(plan_alloc(p, (void**)&p->tabB_m2, sizeof(long long) * (size_t)(qb * Nk * nv)));
+    BSE_HIP(hipFuncSetAttribute((const void*)coupling_tx_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                160 * 1024));
+    BSE_HIP(hipFuncSetAttribute((const void*)coupling_tx_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                160 * 1024));
+  }
+  // every q in the plan's order (W(q) is stored in that order)
+  const int* kq = p->herm_half ? p->kqp : p->kq;
+  const long long slot = (long long)nc * nv * na;
+  for (int q0 = 0; q0 < Nk; q0 += p->qbB) {
+    const int nq = std::min(p->qbB, Nk - q0);
+    StageMark sm_(p, BSE_STAGE_COUPLING, st);
+    hipLaunchKernelGGL(tables_b_kernel, dim3(Nk), dim3(256), 0, st, Nk, nq, q0, nv, nc, p->nbnd, no, na, kq,
+                       p->tabB_psi_c, p->tabB_g, p->tabB_psi_v, p->tabB_m2);
+    BSE_CHECK_LAUNCH();
+    {  // Gb[(q c')][(v mu)] = sum_t psi_c'(k')_t B^mu_vt(k)
+      GemmArgs g;
+      g.batch = Nk;
+      g.M = nq * nc;
+      g.N = nv * na;
+      g.K = no;
+      g.A = p->psi;
+      g.a_tab = p->tabB_psi_c;
+      g.a_tab_pb = 1;
+      g.a_sk = 1;
+      g.B = p->Bv;
+      g.b_sb = (long long)nv * na * no;
+      g.b_sj = no;
+      g.b_sk = 1;
+      g.C = p->Gb;
+      g.c_tab = p->tabB_g;
+      g.c_tab_pb = 1;
+      g.c_sj = 1;
+      g.tab_aligned = (no % 8 == 0);
+      if (p->split) {
+        g.a_ps = p->ps_psi;
+        g.b_ps = p->ps_Bv;
+        g.c_ps = p->ps_Gb;
+        BSE_TRY(cgemm_split(g, true, true, true, false, st));
+      } else {
+        BSE_TRY(cgemm(g, ar, f64, f64, st));
+      }
+    }
+    {  // M2[(q v')][(c nu)] = sum_t psi_v'(k')_t B^nu_ct(k)
+      GemmArgs g;
+      g.batch = Nk;
+      g.M = nq * nv;
+      g.N = nc * na;
+      g.K = no;
+      g.A = p->psi;
+      g.a_tab = p->tabB_psi_v;
+      g.a_tab_pb = 1;
+      g.a_sk = 1;
+      g.B = p->Bc;
+      g.b_sb = (long long)nc * na * no;
+      g.b_sj = no;
+      g.b_sk = 1;
+      g.C = p->M2;
+      g.c_tab = p->tabB_m2;
+      g.c_tab_pb = 1;
+      g.c_sj = 1;
+      g.tab_aligned = (no % 8 == 0);
+      if (p->split) {
+        g.a_ps = p->ps_psi;
+        g.b_ps = p->ps_Bc;
+        g.c_ps = p->ps_Gb;
+        BSE_TRY(cgemm_split(g, true, true, true, false, st));
+      } else {
+        BSE_TRY(cgemm(g, ar, f64, f64, st));
+      }
+    }
+    {  // Pb = conj(Gb) W(q)
+      GemmArgs g;
+      g.batch = nq;
+      g.M = Nk * nc * nv;
+      g.N = na;
+      g.K = na;
+      g.A = p->Gb;
+      g.a_sb = (long long)Nk * slot;
+      g.a_si = na;
+      g.a_sk = 1;
+      g.conjA = 1;
+      g.C = p->Pb;
+      g.c_sb = (long long)Nk * slot;
+      g.c_si = na;
+      g.c_sj = 1;
+      if (p->split) {
+        g.B = (const __bf16*)p->Wq + (long long)q0 * na * na;
+        g.b_sb = (long long)na * na;
+        g.b_sk = 1;
+        g.b_sj = na;
+        g.a_ps = p->ps_Gb;
+        g.b_ps = p->ps_W;
+        g.c_ps = p->ps_Gb;
+        BSE_TRY(cgemm_split(g, true, true, true, false, st));
+      } else {
+        g.B = off_bytes(p->Wq, (long long)q0 * na * na, p->esz);
+        g.b_sb = (long long)na * na;
+        g.b_sk = na;
+        g.b_sj = 1;
+        BSE_TRY(cgemm(g, ar, f64, f64, st));
+      }
+    }
+    {  // Tb[(v' c)][(c' v)] = sum_nu M2[(v' c)][nu] Pb[(c' v)][nu]
+      GemmArgs g;
+      g.batch = nq * Nk;
+      g.M = nt;
+      g.N = nt;
+      g.K = na;
+      g.A = p->M2;
+      g.a_sb = slot;
+      g.a_si = na;
+      g.a_sk = 1;
+      g.B = p->Pb;
+      g.b_sb = slot;
+      g.b_sj = na;
+      g.b_sk = 1;
+      g.C = p->Tb;
+      g.c_sb = (long long)nt * nt;
+      g.c_si = nt;
+      g.c_sj = 1;
+      if (p->split) {
+        g.a_ps = p->ps_Gb;
+        g.b_ps = p->ps_Gb;
+        BSE_TRY(cgemm_split(g, true, true, false, false, st));
+      } else {
+        BSE_TRY(cgemm(g, ar, f64, f64, st));
+      }
+    }
+    {
+      const size_t tsz = f64 ? 8 : 4;
+      const size_t sh = ((((size_t)nt * nt * 2 * tsz) + 15) & ~(size_t)15) + (size_t)nt * nb * 16;
+      const int nch = std::min(TX_CHUNKS, nq);
+      const int qlen = (nq + nch - 1) / nch;
+      const dim3 grid((unsigned)Nk, (unsigned)nch);
+      if (f64)
+        hipLaunchKernelGGL(coupling_tx_kernel<double>, grid, dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, qlen, kq,
+                           (const double*)p->Tb, X, p->txp);
+      else
+        hipLaunchKernelGGL(coupling_tx_kernel<float>, grid, dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, qlen, kq,
+                           (const float*)p->Tb, X, p->txp);
+      BSE_CHECK_LAUNCH();
+      const long long n = p->N * nb;
+      hipLaunchKernelGGL(tx_reduce, dim3((unsigned)std::min<long long>((n + 255) / 256, 65536)), dim3(256), 0, st, n,
+                         nch, -1.0 / (double)Nk, p->txp, Y);
+      BSE_CHECK_LAUNCH();
+    }
+  }
+  return BSE_OK;
+}
 
 bse_status apply_diag(Plan* p, const double* X, double* Y, int nb, hipStream_t st) {
   StageMark sm_(p, BSE_STAGE_DIAG, st);
@@ -492,12 +737,14 @@ bse_status apply_diag(Plan* p, const double* X, double* Y, int nb, hipStream_t s
   return BSE_OK;
 }
 
-bse_status apply_exchange(Plan* p, const double* X, double* Y, int nb, hipStream_t st) {
+// resonant exchange (alpha/N_k) rho Vbar rho^H X, or with transpose the exchange part of the coupling
+// block, (alpha/N_k) rho Vbar rho^T X
+bse_status apply_exchange(Plan* p, const double* X, double* Y, int nb, hipStream_t st, bool transpose) {
   if (p->d.alpha == 0.0) return BSE_OK;
   StageMark sm_(p, BSE_STAGE_EXCHANGE, st);
   const int na = p->d.n_aux;
   const long long Ks = p->N / p->xsplit;
-  {  // partial t_s = rho_s^H X_s
+  {  // partial t_s = rho_s^H X_s (rho_s^T X_s)
     GemmArgs g;
     g.batch = p->xsplit;
     g.M = na;
@@ -507,7 +754,7 @@ bse_status apply_exchange(Plan* p, const double* X, double* Y, int nb, hipStream
     g.a_sb = Ks * na;
     g.a_si = 1;
     g.a_sk = na;
-    g.conjA = 1;
+    g.conjA = transpose ? 0 : 1;
     g.B = X;
     g.b_sb = Ks * nb;
     g.b_sk = nb;

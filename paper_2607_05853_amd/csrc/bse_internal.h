@@ -158,6 +158,24 @@ struct Plan {
   void* Nt2 = nullptr;              // same layout, pair (k + q, k) stored at slot (q, k + q)
   int* kqinv = nullptr;             // [Nk][Nk] (k, q) -> k - q, the reverse of kq
 
+  // coupling block B of the full BSE (allocated on the first coupling apply), per pair (k, k' = k + q):
+  //   Gb[c'][v][mu] = conj M^mu_{c'v}(k', k),  Pb = conj(Gb) W(q),  M2[v'][c][nu] = M^nu_{cv'}(k, k'),
+  //   Tb[(v' c)][(c' v)] = sum_nu M2 Pb,  B_d X = -(1/N_k) sum_q Tb X(k')
+  int qbB = 0;
+  void* Gb = nullptr;               // [qbB][Nk][nc][nv][n_aux]
+  void* Pb = nullptr;               // [qbB][Nk][nc][nv][n_aux]
+  void* M2 = nullptr;               // [qbB][Nk][nv][nc][n_aux]
+  void* Tb = nullptr;               // [qbB][Nk][nt][nt]
+  long long ps_Gb = 0;              // plane stride of Gb, Pb and M2
+  long long* tabB_psi_c = nullptr;  // [Nk][qbB*nc]
+  long long* tabB_psi_v = nullptr;  // [Nk][qbB*nv]
+  long long* tabB_g = nullptr;      // [Nk][qbB*nc]
+  long long* tabB_m2 = nullptr;     // [Nk][qbB*nv]
+  // full BSE apply: packed [N][2 nb] operands and results (allocated on first use)
+  double* fz = nullptr;
+  double* fra = nullptr;
+  double* frb = nullptr;
+
   // exchange / misc workspaces (FP64)
   double* xt = nullptr;       // c128 split-K partials [nsplit][n_aux][max_nb]
   double* xu = nullptr;       // c128 [n_aux][max_nb]
@@ -199,7 +217,8 @@ bse_status plan_alloc(Plan* p, void** ptr, size_t bytes);
 
 // stage launchers (apply.hip)
 bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t st);
-bse_status apply_exchange(Plan* p, const double* X, double* Y, int nb, hipStream_t st);
+bse_status apply_exchange(Plan* p, const double* X, double* Y, int nb, hipStream_t st, bool transpose = false);
+bse_status apply_coupling_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t st);
 bse_status apply_diag(Plan* p, const double* X, double* Y, int nb, hipStream_t st);
 bse_status adjoint_direct(Plan* p, const double* Ybar, const double* X, int nb, double* gWq, bool acc,
                           hipStream_t st);

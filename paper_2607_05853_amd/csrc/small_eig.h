@@ -4,8 +4,10 @@
 // CPU tests.
 #pragma once
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
+#include <limits>
 #include <vector>
 
 namespace bse {
@@ -216,6 +218,69 @@ inline void tridiag_resolvent(int m, const double* a, const double* b, double b0
   }
   s[m - 1] = dp[m - 1];
   for (int i = m - 2; i >= 0; --i) s[i] = dp[i] - cp[i] * s[i + 1];
+}
+
+// Eigenvalues of the real symmetric tridiagonal matrix with diagonal d[0..n-1] and off-diagonal
+// e[0..n-2] (e[i] couples i and i + 1), with the first component of each normalised eigenvector
+// (the Gauss-quadrature weights of a Lanczos tridiagonal): implicit QL iteration with a shift from the
+// leading 2 x 2 block (Bowdler, Martin, Reinsch & Wilkinson, Numer. Math. 11, 1968), the rotations
+// applied to the first row of the eigenvector matrix only.  On return w is ascending and z[i] belongs
+// to w[i].  Returns false if an eigenvalue needs more than 64 iterations.
+inline bool tridiag_eig_first(int n, const double* d_in, const double* e_in, std::vector<double>& w,
+                              std::vector<double>& z) {
+  std::vector<double> d(d_in, d_in + n), e((size_t)n + 1, 0.0), q(n, 0.0);
+  for (int i = 0; i + 1 < n; ++i) e[i] = e_in[i];
+  if (n > 0) q[0] = 1.0;
+  const double eps = std::numeric_limits<double>::epsilon();
+  for (int l = 0; l < n; ++l) {
+    for (int iter = 0;; ++iter) {
+      int m = l;
+      while (m + 1 < n && std::fabs(e[m]) > eps * (std::fabs(d[m]) + std::fabs(d[m + 1]))) ++m;
+      if (m == l) break;
+      if (iter >= 64) return false;
+      // shift: the eigenvalue of [[d_l, e_l], [e_l, d_l+1]] nearer to d_l
+      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+      double r = std::hypot(g, 1.0);
+      g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
+      double s = 1.0, c = 1.0, p = 0.0;
+      bool split = false;
+      for (int i = m - 1; i >= l; --i) {
+        const double f = s * e[i], b = c * e[i];
+        r = std::hypot(f, g);
+        e[i + 1] = r;
+        if (r == 0.0) {  // the rotation underflowed: the matrix splits at i + 1
+          d[i + 1] -= p;
+          e[m] = 0.0;
+          split = true;
+          break;
+        }
+        s = f / r;
+        c = g / r;
+        g = d[i + 1] - p;
+        r = (d[i] - g) * s + 2.0 * c * b;
+        p = s * r;
+        d[i + 1] = g + p;
+        g = c * r - b;
+        const double t = q[i + 1];
+        q[i + 1] = s * q[i] + c * t;
+        q[i] = c * q[i] - s * t;
+      }
+      if (split) continue;
+      d[l] -= p;
+      e[l] = g;
+      e[m] = 0.0;
+    }
+  }
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return d[a] < d[b]; });
+  w.resize(n);
+  z.resize(n);
+  for (int i = 0; i < n; ++i) {
+    w[i] = d[idx[i]];
+    z[i] = q[idx[i]];
+  }
+  return true;
 }
 
 }  // namespace small

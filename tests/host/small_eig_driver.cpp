@@ -3,6 +3,7 @@
 // mode 1: n, A, G            -> w, X        (generalised, Cholesky + Jacobi)
 // mode 2: m, a(m), b(m), b0, zr, zi -> s(m) (tridiagonal resolvent)
 // mode 3: n, A, G            -> r, w(r), X(n*r) (rank-revealing generalised)
+// mode 4: n, d(n), e(n-1)     -> w(n), z(n)   (symmetric tridiagonal, first eigenvector components)
 #include <cstdio>
 #include <vector>
 
@@ -23,6 +24,15 @@ static std::vector<cd> read_mat(int n) {
 int main() {
   int mode, n;
   if (scanf("%d %d", &mode, &n) != 2) return 1;
+  if (mode == 4) {
+    std::vector<double> d(n), e(n > 0 ? n - 1 : 0), w, z;
+    for (auto& x : d) scanf("%lf", &x);
+    for (auto& x : e) scanf("%lf", &x);
+    if (!bse::small::tridiag_eig_first(n, d.data(), e.data(), w, z)) return 3;
+    for (double x : w) printf("%.17g\n", x);
+    for (double x : z) printf("%.17g\n", x);
+    return 0;
+  }
   if (mode == 3) {
     std::vector<cd> A = read_mat(n), G = read_mat(n), X;
     std::vector<double> w;

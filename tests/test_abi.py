@@ -121,6 +121,10 @@ def test_null_plan_calls(L):
     assert L.bse_offset_spectrum(plans, Ps, w, 1, 1, 1, om, 1, 0.1, S, None, None) == 1
     assert L.bse_offset_spectrum(plans, Ps, w, 0, 1, 1, om, 1, 0.1, S, None, None) == 1
     assert L.bse_offset_set(None, None, None) == 1
+    # full BSE
+    assert L.bse_apply_coupling(None, dummy, dummy, 1, None) == 1
+    assert L.bse_apply_full(None, dummy, dummy, 1, None) == 1
+    assert L.bse_full_spectrum(None, dummy, 1, 2, om, 1, 0.1, S, S, S, None, None) == 1
 
 
 def test_offset_set_is_the_papers(L):

@@ -1,0 +1,109 @@
+"""GPU parity of the full BSE: the coupling block B of Eq. (Hamiltonian), the full Hamiltonian
+[[A, B], [-B*, -A*]] and the spectrum of Eq. (full_BSE_epsilon2) from the structure-preserving Lanczos
+recurrence, against the oracle's explicit matrices and its paired eigensolution."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from synth import dense_kmesh, make_problem, polarisations, random_block
+
+pytestmark = pytest.mark.gpu
+
+DMA = dict(cfg_id=79, coarse=(3, 3, 2), dense=(4, 4, 2), n_ao=16, nv=4, nc=4, n_aux=48)
+RAGGED = dict(cfg_id=78, coarse=(3, 3, 2), dense=(3, 2, 2), n_ao=10, nv=2, nc=3, n_aux=20)
+CONFS = {"DMA": DMA, "RAGGED": RAGGED}
+TOL = {"f64": 1e-12, "f32": 2e-5, "bf16x3": 5e-4}
+
+
+def T(a, dt=torch.complex128):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(torch.device("cuda:0"), dt)
+
+
+def H_(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def OW(p):
+    """The oracle's own W(q) on the dense mesh (oracle inputs never come from the GPU path)."""
+    return O.interpolate_W_matmul(p.W_R, p.R, p.w_R, dense_kmesh(p.nk))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2607_05853_amd import bse
+    return bse
+
+
+@pytest.mark.parametrize("all_pairs", [False, True])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
+@pytest.mark.parametrize("cfg", ["DMA", "RAGGED"])
+def test_coupling_apply(B, cfg, prec, all_pairs):
+    p = make_problem(CONFS[cfg], 1, "G2")
+    print("[coupling apply %s %s all_pairs=%s]" % (cfg, prec, all_pairs), flush=True)
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
+    plan = B.plan_from_problem(p, Wq, prec=prec, max_nb=6, all_pairs=all_pairs)
+    Bm = O.build_B(p, OW(p))
+    X = random_block(p.N, 3, seed=21)
+    err = rel(H_(plan.apply_coupling(T(X))), Bm @ X)
+    print("    rel err %.2e" % err, flush=True)
+    assert err < TOL[prec]
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "bf16x3"])
+def test_full_apply(B, prec):
+    p = make_problem(DMA, 2, "G2")
+    print("[full apply %s]" % prec, flush=True)
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
+    plan = B.plan_from_problem(p, Wq, prec=prec, max_nb=4)
+    H = O.build_full(p, OW(p))
+    XY = random_block(2 * p.N, 2, seed=22)
+    err = rel(H_(plan.apply_full(T(XY))), H @ XY)
+    print("    rel err %.2e" % err, flush=True)
+    assert err < TOL[prec]
+    plan.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-8), ("bf16x3", 1e-5)])
+@pytest.mark.parametrize("cfg", ["RAGGED", "DMA"])
+def test_full_spectrum_full_krylov(B, cfg, prec, tol):
+    # with n_steps = 2N the Krylov space is invariant and the quadrature is exact
+    p = make_problem(CONFS[cfg], 3, "G2")
+    print("[full spectrum %s %s]" % (cfg, prec), flush=True)
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
+    plan = B.plan_from_problem(p, Wq, prec=prec, max_nb=4)
+    A, Bm = O.build_H(p, OW(p)), O.build_B(p, OW(p))
+    Om, X, Y = O.full_bse_eig(A, Bm)
+    pol = polarisations(2)
+    te = p.eps_qp[:, p.nv:][:, :, None] - p.eps_qp[:, :p.nv][:, None, :]
+    w = np.linspace(te.min() - 1.0, te.max() + 1.0, 201)
+    Sref = O.full_bse_spectrum(p, pol, Om, X, Y, w, 0.1)
+    P = plan.velocity_start(T(p.vel), T(p.eps_ks, torch.float64), pol)
+    out = plan.full_spectrum(P, 2 * p.N, w, 0.1)
+    err = rel(out["S"], Sref)
+    print("    steps %s rel err %.2e, max |a| / max b %.1e" % (out["steps"], err,
+          np.abs(out["a"]).max() / out["b"].max()), flush=True)
+    assert err < tol
+    plan.close()
+
+
+def test_full_spectrum_without_coupling_is_tda(B):
+    # alpha = 0 and W = 0 leave B = 0: the full-BSE recurrence reproduces the TDA Haydock spectrum
+    # (both on invariant Krylov spaces)
+    p = make_problem(RAGGED, 4, "G1", alpha=0.0)
+    print("[full spectrum, no coupling]", flush=True)
+    Wq = torch.zeros((p.Nk, p.n_aux, p.n_aux), dtype=torch.complex128, device="cuda:0")
+    plan = B.plan_from_problem(p, Wq, prec="f64", max_nb=4)
+    P = plan.velocity_start(T(p.vel), T(p.eps_ks, torch.float64), polarisations(2))
+    w = np.linspace(1.0, 6.0, 101)
+    full = plan.full_spectrum(P, 2 * p.N, w, 0.1)["S"]
+    tda = plan.haydock(P, p.N, w, 0.1)["S"]
+    err = rel(full, tda)
+    print("    rel diff %.2e" % err, flush=True)
+    assert err < 1e-8
+    plan.close()

@@ -95,3 +95,34 @@ def test_generalised_rank_deficient(exe):
     ref = np.linalg.eigvalsh(Q.conj().T @ H @ Q)
     assert rank == r
     assert np.abs(w - ref).max() < 1e-9
+
+
+@pytest.mark.parametrize("n,kind", [(1, "rand"), (2, "rand"), (7, "rand"), (40, "rand"), (64, "zero_diag"),
+                                    (200, "zero_diag"), (30, "graded"), (12, "split")])
+def test_tridiagonal_eigen_first_components(exe, n, kind):
+    r = np.random.default_rng(n)
+    d = r.standard_normal(n)
+    e = r.random(max(n - 1, 0)) + 0.1
+    if kind == "zero_diag":          # the structure of the full-BSE Lanczos tridiagonal: +-theta pairs
+        d[:] = 0.0
+    if kind == "graded":
+        d = d * 10.0 ** np.linspace(0, 8, n)
+        e = e * 10.0 ** np.linspace(0, 7, n - 1)
+    if kind == "split":
+        e[5] = 0.0
+    lines = _run(exe, "4 %d %s %s" % (n, " ".join("%.17g" % x for x in d), " ".join("%.17g" % x for x in e)))
+    w = np.array([float(x) for x in lines[:n]])
+    z = np.array([float(x) for x in lines[n:2 * n]])
+    T = np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+    ref_w, ref_V = np.linalg.eigh(T)
+    scale = max(1.0, np.abs(ref_w).max())
+    assert np.abs(w - ref_w).max() < 1e-12 * scale
+    if kind == "zero_diag":
+        assert np.abs(w + w[::-1]).max() < 1e-12 * scale
+    # first components: z_i^2 are the quadrature weights (sum 1); compare where eigenvalues are simple
+    assert abs((z ** 2).sum() - 1.0) < 1e-12
+    gap = np.diff(ref_w)
+    simple = np.ones(n, bool)
+    simple[:-1] &= gap > 1e-8 * scale
+    simple[1:] &= gap > 1e-8 * scale
+    assert np.abs(z[simple] ** 2 - ref_V[0, simple] ** 2).max() < 1e-10
