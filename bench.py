@@ -102,14 +102,15 @@ def main():
                     help="BF16x3 conduction side of the direct term: the plan's choice (auto), forming the "
                          "conduction pair densities (mc) or the B_c(k) contraction (u)")
     ap.add_argument("--mode", default="spectrum",
-                    choices=["spectrum", "precision", "gradients", "largest", "offsets", "two_centre"],
+                    choices=["spectrum", "precision", "gradients", "largest", "offsets", "two_centre", "full_bse"],
                     help="spectrum: the timed pipeline (default); precision: per-precision apply and "
                          "short-Haydock errors on a larger workload; gradients: LOBPCG and spectrum "
                          "gradients checked by central finite differences; largest: one BF16x3 apply and "
                          "adjoint on the 16x16x16 / N_ao = 128 workload; offsets: the spectrum averaged over "
                          "the four shifted dense meshes of the k-offset scheme; two_centre: the BF16x3 apply "
                          "and Haydock run with k-dependent two-centre LRI coefficients beside the "
-                         "k-independent ones")
+                         "k-independent ones; full_bse: the spectrum of the full BSE (coupling block B) by the "
+                         "structure-preserving Lanczos recurrence beside the TDA Haydock spectrum")
     args = ap.parse_args()
     global CONDUCTION
     CONDUCTION = None if args.conduction == "auto" else args.conduction
@@ -127,6 +128,10 @@ def main():
     if args.mode == "offsets":
         from synth import CONFIGS
         offsets_mode(args.config, args.haydock_steps or CONFIGS[args.config]["haydock_steps"])
+        return
+    if args.mode == "full_bse":
+        from synth import CONFIGS
+        full_bse_mode(args.config, args.haydock_steps or CONFIGS[args.config]["haydock_steps"])
         return
     if args.mode == "two_centre":
         from synth import CONFIGS
@@ -383,6 +388,63 @@ def largest_mode(config):
         "apply_stage_ms": st_apply, "adjoint_s": tg, "F_adjoint_TFLOP": Fg / 1e12,
         "adjoint_GFLOP_s": Fg / tg / 1e9, "adjoint_stage_ms": st_adj}), flush=True)
     plan.close()
+
+
+def full_bse_mode(config, m):
+    """Full BSE: the BF16x3 spectrum of Eq. (full_BSE_epsilon2) from m steps of the structure-preserving
+    Lanczos recurrence (one full apply = A on [X | conj Y] and B on [Y | conj X] per step), timed, beside
+    the BF16x3 TDA Haydock spectrum of the same m; the BF16x3 error against FP64 on a shorter run of both."""
+    from synth import CONFIGS, polarisations, random_block
+    B, T, p, kq, torch = _setup(config)
+    nb = CONFIGS[config]["nb"]
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, kq)
+    te = p.eps_qp[:, p.nv:][:, :, None] - p.eps_qp[:, :p.nv][:, None, :]
+    omega = np.linspace(te.min() - 1.0, te.max() + 1.0, 2001)
+    res = {}
+    m_short = 40
+    spec = {}
+    for prec in ["bf16x3", "f64"]:
+        plan = B.plan_from_problem(p, Wq, prec=prec, max_nb=2 * nb)
+        P = plan.velocity_start(T(p.vel), T(p.eps_ks, torch.float64), polarisations(nb))
+        r = {"q_formed_A": plan.pairs[0], "conduction": plan.conduction}
+        X = T(random_block(p.N, nb, seed=1))
+        XY = T(random_block(2 * p.N, nb, seed=2))
+        plan.apply_full(XY)
+        torch.cuda.synchronize()
+        for name, fn in [("apply_A_ms", lambda: plan.apply(X)), ("apply_B_ms", lambda: plan.apply_coupling(X)),
+                         ("apply_full_ms", lambda: plan.apply_full(XY))]:
+            plan.set_timing(True)
+            torch.cuda.synchronize()
+            t0 = time.time()
+            fn()
+            torch.cuda.synchronize()
+            r[name] = (time.time() - t0) * 1e3
+            r[name.replace("_ms", "_stage_ms")] = {k: round(v[0], 2) for k, v in plan.stage_times().items() if v[1]}
+            plan.set_timing(False)
+        spec[prec] = plan.full_spectrum(P, m_short, omega, 0.1)["S"]
+        if prec == "bf16x3":
+            torch.cuda.synchronize()
+            t0 = time.time()
+            out = plan.full_spectrum(P, m, omega, 0.1)
+            torch.cuda.synchronize()
+            r["full_spectrum_s"] = time.time() - t0
+            r["full_steps"] = int(out["steps"].min())
+            r["max_abs_diagonal_over_max_offdiagonal"] = float(np.abs(out["a"]).max() / np.abs(out["b"][:, 1:]).max())
+            torch.cuda.synchronize()
+            t0 = time.time()
+            hay = plan.haydock(P, m, omega, 0.1)
+            torch.cuda.synchronize()
+            r["tda_haydock_s"] = time.time() - t0
+            r["max_rel_diff_full_vs_tda"] = float(np.abs(out["S"] - hay["S"]).max() / np.abs(hay["S"]).max())
+            r["peak_shift_eV (full - tda, first polarisation)"] = float(omega[np.argmax(out["S"][0])] -
+                                                                       omega[np.argmax(hay["S"][0])])
+        res[prec] = r
+        plan.close()
+        print("[full_bse mode] %s done" % prec, file=sys.stderr, flush=True)
+    err = float(np.abs(spec["bf16x3"] - spec["f64"]).max() / np.abs(spec["f64"]).max())
+    print(json.dumps({"mode": "full_bse", "workload": "%s, %d chains, %d Lanczos steps (error check %d steps)" %
+                      (config, nb, m, m_short), "runs": res,
+                      "spectrum_rel_err_bf16x3_vs_f64_%d_steps" % m_short: err}), flush=True)
 
 
 def two_centre_mode(config, m):
