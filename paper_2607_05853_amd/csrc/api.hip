@@ -309,26 +309,32 @@ void destroy_plan(Plan* p) {
   p->owned.clear();
 }
 
-// max |W[-q] - conj W[q]| and max |W| over all q and elements (non-negative doubles compared as
-// their bit patterns)
-__global__ void w_pair_check(long long per_q, int Nk, const int* __restrict__ neg, const double* __restrict__ W,
+// max |W[-q] - conj W[q]|, max |W|, and max |W[q] - W[q]^H| over all q and elements (non-negative
+// doubles compared as their bit patterns)
+__global__ void w_pair_check(int na, int Nk, const int* __restrict__ neg, const double* __restrict__ W,
                              unsigned long long* __restrict__ out) {
-  double dmax = 0.0, wmax = 0.0;
+  double dmax = 0.0, wmax = 0.0, hmax = 0.0;
+  const long long per_q = (long long)na * na;
   const long long n = per_q * Nk;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     const long long q = i / per_q, e = i % per_q;
+    const long long et = (e % na) * na + e / na;
     const double2 a = reinterpret_cast<const double2*>(W)[i];
     const double2 b = reinterpret_cast<const double2*>(W)[(long long)neg[q] * per_q + e];
+    const double2 t = reinterpret_cast<const double2*>(W)[q * per_q + et];
     dmax = fmax(dmax, fmax(fabs(b.x - a.x), fabs(b.y + a.y)));
     wmax = fmax(wmax, fmax(fabs(a.x), fabs(a.y)));
+    hmax = fmax(hmax, fmax(fabs(t.x - a.x), fabs(t.y + a.y)));
   }
   for (int o = 32; o > 0; o >>= 1) {
     dmax = fmax(dmax, __shfl_down(dmax, o));
     wmax = fmax(wmax, __shfl_down(wmax, o));
+    hmax = fmax(hmax, __shfl_down(hmax, o));
   }
   if ((threadIdx.x & 63) == 0) {
     atomicMax(&out[0], (unsigned long long)__double_as_longlong(dmax));
     atomicMax(&out[1], (unsigned long long)__double_as_longlong(wmax));
+    atomicMax(&out[2], (unsigned long long)__double_as_longlong(hmax));
   }
 }
 
@@ -591,23 +597,26 @@ bse_status build_plan(Plan* p, const bse_dims* d, const double* eps_qp, const vo
       int* dneg = nullptr;
       unsigned long long* dout = nullptr;
       BSE_TRY(dmalloc((void**)&dneg, sizeof(int) * Nk));
-      bse_status s = dmalloc((void**)&dout, 16);
-      unsigned long long hout[2] = {0, 0};
+      bse_status s = dmalloc((void**)&dout, 24);
+      unsigned long long hout[3] = {0, 0, 0};
       if (s == BSE_OK) {
         (void)hipMemcpyAsync(dneg, neg.data(), sizeof(int) * Nk, hipMemcpyHostToDevice, st);
-        (void)hipMemsetAsync(dout, 0, 16, st);
-        hipLaunchKernelGGL(w_pair_check, dim3(1024), dim3(256), 0, st, (long long)na * na, Nk, dneg,
-                           (const double*)W_q, dout);
-        (void)hipMemcpyAsync(hout, dout, 16, hipMemcpyDeviceToHost, st);
+        (void)hipMemsetAsync(dout, 0, 24, st);
+        hipLaunchKernelGGL(w_pair_check, dim3(1024), dim3(256), 0, st, na, Nk, dneg, (const double*)W_q, dout);
+        (void)hipMemcpyAsync(hout, dout, 24, hipMemcpyDeviceToHost, st);
         if (hipStreamSynchronize(st) != hipSuccess) s = BSE_EDEVICE;
       }
       dfree(dneg);
       dfree(dout);
       BSE_TRY(s);
-      double dmax, wmax;
+      double dmax, wmax, hmax;
       std::memcpy(&dmax, &hout[0], 8);
       std::memcpy(&wmax, &hout[1], 8);
+      std::memcpy(&hmax, &hout[2], 8);
       use = dmax <= 1e-12 * wmax;
+      // the coupling block's transpose relation D_B(k', k) = D_B(k, k')^T needs W(-q) = W(q)^T as well,
+      // i.e. (with the relation above) a Hermitian W(q)
+      p->b_pairs = use && hmax <= 1e-12 * wmax;
     }
     if (use) {
       std::vector<int> hp((size_t)Nk * Nk), hm((size_t)Nk * Nk);

@@ -504,10 +504,13 @@ __global__ void tables_b_kernel(int Nk, int nq, int q0, int nv, int nc, int nbnd
 }
 
 // part[chunk][k][(c v)][b] = sum_{qi in chunk} sum_{c'v'} Tb[qi][k][(v' c)][(c' v)] X[k'][(c' v')][b],
-// k' = kq[k][q0 + qi]; one Tb block and one X slice staged in LDS per q
+// k' = kq[k][q0 + qi]; for j = q0 + qi >= nself also the transposed partner block
+// D_B(k, k - q_j) = D_B(k - q_j, k)^T:  part += sum_{CV} Tb[qi][k''][(v C)][(c V)] X[k''][(C V)][b],
+// k'' = kqm[k][j].  One Tb block and one X slice staged in LDS per (q, pass).
 template <typename TT>
 __global__ __launch_bounds__(256) void coupling_tx_kernel(int Nk, int nq, int q0, int nv, int nc, int nb, int qlen,
-                                                          const int* __restrict__ kq, const TT* __restrict__ T,
+                                                          const int* __restrict__ kq, const int* __restrict__ kqm,
+                                                          int nself, const TT* __restrict__ T,
                                                           const double* __restrict__ X, double* __restrict__ part) {
   extern __shared__ __attribute__((aligned(16))) unsigned char sbytes[];
   const int k = blockIdx.x, chunk = blockIdx.y;
@@ -518,28 +521,31 @@ __global__ __launch_bounds__(256) void coupling_tx_kernel(int Nk, int nq, int q0
   double accr[8], acci[8];
   for (int sl = 0; sl < 8; ++sl) accr[sl] = acci[sl] = 0.0;
   for (int qi = qa; qi < qe; ++qi) {
-    const int kp = kq[(long long)k * Nk + q0 + qi];
-    const TT* tb = T + 2 * (((long long)qi * Nk + k) * nt2);
-    const double* xb = X + 2 * ((long long)kp * ne);
-    __syncthreads();
-    for (int i = threadIdx.x; i < 2 * nt2; i += blockDim.x) ts[i] = tb[i];
-    for (int i = threadIdx.x; i < 2 * ne; i += blockDim.x) xs[i] = xb[i];
-    __syncthreads();
-    for (int sl = 0; sl < 8; ++sl) {
-      const int e = threadIdx.x + 256 * sl;
-      if (e >= ne) break;
-      const int b = e % nb, cv = e / nb, c = cv / nv, v = cv % nv;
-      double sr = 0.0, si = 0.0;
-      for (int c2 = 0; c2 < nc; ++c2)
-        for (int v2 = 0; v2 < nv; ++v2) {
-          const int ti = (v2 * nc + c) * nt + c2 * nv + v;
-          const double tr = (double)ts[2 * ti], tim = (double)ts[2 * ti + 1];
-          const double xr = xs[2 * ((c2 * nv + v2) * nb + b)], xi = xs[2 * ((c2 * nv + v2) * nb + b) + 1];
-          sr += tr * xr - tim * xi;
-          si += tr * xi + tim * xr;
-        }
-      accr[sl] += sr;
-      acci[sl] += si;
+    const int npass = (q0 + qi >= nself) ? 2 : 1;
+    for (int pass = 0; pass < npass; ++pass) {
+      const int kk = pass == 0 ? kq[(long long)k * Nk + q0 + qi] : kqm[(long long)k * Nk + q0 + qi];
+      const TT* tb = T + 2 * (((long long)qi * Nk + (pass == 0 ? k : kk)) * nt2);
+      const double* xb = X + 2 * ((long long)kk * ne);
+      __syncthreads();
+      for (int i = threadIdx.x; i < 2 * nt2; i += blockDim.x) ts[i] = tb[i];
+      for (int i = threadIdx.x; i < 2 * ne; i += blockDim.x) xs[i] = xb[i];
+      __syncthreads();
+      for (int sl = 0; sl < 8; ++sl) {
+        const int e = threadIdx.x + 256 * sl;
+        if (e >= ne) break;
+        const int b = e % nb, cv = e / nb, c = cv / nv, v = cv % nv;
+        double sr = 0.0, si = 0.0;
+        for (int c2 = 0; c2 < nc; ++c2)
+          for (int v2 = 0; v2 < nv; ++v2) {
+            const int ti = pass == 0 ? (v2 * nc + c) * nt + c2 * nv + v : (v * nc + c2) * nt + c * nv + v2;
+            const double tr = (double)ts[2 * ti], tim = (double)ts[2 * ti + 1];
+            const double xr = xs[2 * ((c2 * nv + v2) * nb + b)], xi = xs[2 * ((c2 * nv + v2) * nb + b) + 1];
+            sr += tr * xr - tim * xi;
+            si += tr * xi + tim * xr;
+          }
+        accr[sl] += sr;
+        acci[sl] += si;
+      }
     }
   }
   const long long n = (long long)Nk * ne;
@@ -556,8 +562,9 @@ __global__ __launch_bounds__(256) void coupling_tx_kernel(int Nk, int nq, int q0
 
 // Direct term of the coupling block B of Eq. (Hamiltonian), added to Y:
 //   Y[(c v k)] -= (1/N_k) sum_{k'} sum_{c'v'} sum_munu M^mu_{c'v}(k',k) W_munu(k'-k) M^nu_{cv'}(k,k') X[(c'v'k')]
-// over every pair (no pair symmetry), in q batches: Gb = conj M_{c'v}(k',k) = M_{vc'}(k,k') and
-// M2 = M_{cv'}(k,k') from the halves (Hermitian C), Pb = conj(Gb) W(q), Tb = M2 Pb^T, then Tb X(k').
+// in q batches: Gb = conj M_{c'v}(k',k) = M_{vc'}(k,k') and M2 = M_{cv'}(k,k') from the halves (Hermitian
+// C), Pb = conj(Gb) W(q), Tb = M2 Pb^T, then Tb X(k').  When W(-q) = W(q)^T (checked at plan creation) the
+// blocks obey D_B(k', k) = D_B(k, k')^T and only the q of the pair-symmetric order's first half are formed.
 bse_status apply_coupling_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t st) {
   const bse_dims& d = p->d;
   const int Nk = p->Nk, nv = d.nv, nc = d.nc, na = d.n_aux, no = d.n_ao, nt = nv * nc;
@@ -583,11 +590,14 @@ bse_status apply_coupling_direct(Plan* p, const double* X, double* Y, int nb, hi
     BSE_HIP(hipFuncSetAttribute((const void*)coupling_tx_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 160 * 1024));
   }
-  // every q in the plan's order (W(q) is stored in that order)
+  // q in the plan's order (W(q) is stored in that order): the first half only with the transpose relation
+  const bool sym = p->herm_half && p->b_pairs;
+  const int nqt = sym ? p->nhalf : Nk;
+  const int nself = sym ? p->nself : nqt;
   const int* kq = p->herm_half ? p->kqp : p->kq;
   const long long slot = (long long)nc * nv * na;
-  for (int q0 = 0; q0 < Nk; q0 += p->qbB) {
-    const int nq = std::min(p->qbB, Nk - q0);
+  for (int q0 = 0; q0 < nqt; q0 += p->qbB) {
+    const int nq = std::min(p->qbB, nqt - q0);
     StageMark sm_(p, BSE_STAGE_COUPLING, st);
     hipLaunchKernelGGL(tables_b_kernel, dim3(Nk), dim3(256), 0, st, Nk, nq, q0, nv, nc, p->nbnd, no, na, kq,
                        p->tabB_psi_c, p->tabB_g, p->tabB_psi_v, p->tabB_m2);
@@ -714,10 +724,10 @@ bse_status apply_coupling_direct(Plan* p, const double* X, double* Y, int nb, hi
       const dim3 grid((unsigned)Nk, (unsigned)nch);
       if (f64)
         hipLaunchKernelGGL(coupling_tx_kernel<double>, grid, dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, qlen, kq,
-                           (const double*)p->Tb, X, p->txp);
+                           p->kqm, nself, (const double*)p->Tb, X, p->txp);
       else
         hipLaunchKernelGGL(coupling_tx_kernel<float>, grid, dim3(256), sh, st, Nk, nq, q0, nv, nc, nb, qlen, kq,
-                           (const float*)p->Tb, X, p->txp);
+                           p->kqm, nself, (const float*)p->Tb, X, p->txp);
       BSE_CHECK_LAUNCH();
       const long long n = p->N * nb;
       hipLaunchKernelGGL(tx_reduce, dim3((unsigned)std::min<long long>((n + 255) / 256, 65536)), dim3(256), 0, st, n,

@@ -161,6 +161,7 @@ struct Plan {
   // coupling block B of the full BSE (allocated on the first coupling apply), per pair (k, k' = k + q):
   //   Gb[c'][v][mu] = conj M^mu_{c'v}(k', k),  Pb = conj(Gb) W(q),  M2[v'][c][nu] = M^nu_{cv'}(k, k'),
   //   Tb[(v' c)][(c' v)] = sum_nu M2 Pb,  B_d X = -(1/N_k) sum_q Tb X(k')
+  int b_pairs = 0;                  // 1: the coupling block forms the q of the pair-symmetric order only
   int qbB = 0;
   void* Gb = nullptr;               // [qbB][Nk][nc][nv][n_aux]
   void* Pb = nullptr;               // [qbB][Nk][nc][nv][n_aux]

@@ -107,3 +107,23 @@ def test_full_spectrum_without_coupling_is_tda(B):
     print("    rel diff %.2e" % err, flush=True)
     assert err < 1e-8
     plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "bf16x3"])
+def test_coupling_apply_without_transpose_relation(B, prec):
+    # a real W(R) without W(-R) = W(R)^T keeps W(-q) = conj W(q) (the resonant pair symmetry) but W(q) is not
+    # Hermitian: B is then not symmetric and the coupling block must form every pair
+    p = make_problem(DMA, 5, "G2")
+    rng = np.random.default_rng(7)
+    p.W_R = p.W_R + 0.3 * np.abs(p.W_R).max() * rng.standard_normal(p.W_R.shape)
+    print("[coupling apply, W(q) not Hermitian, %s]" % prec, flush=True)
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
+    plan = B.plan_from_problem(p, Wq, prec=prec, max_nb=4)
+    assert plan.pairs[0] < p.Nk
+    Bm = O.build_B(p, OW(p))
+    assert np.abs(Bm - Bm.T).max() > 1e-3 * np.abs(Bm).max()
+    X = random_block(p.N, 3, seed=23)
+    err = rel(H_(plan.apply_coupling(T(X))), Bm @ X)
+    print("    rel err %.2e" % err, flush=True)
+    assert err < TOL[prec]
+    plan.close()
