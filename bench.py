@@ -438,6 +438,17 @@ def full_bse_mode(config, m):
             r["max_rel_diff_full_vs_tda"] = float(np.abs(out["S"] - hay["S"]).max() / np.abs(hay["S"]).max())
             r["peak_shift_eV (full - tda, first polarisation)"] = float(omega[np.argmax(out["S"][0])] -
                                                                        omega[np.argmax(hay["S"][0])])
+            torch.cuda.synchronize()
+            t0 = time.time()
+            omf, _, itf = plan.full_lowest(n_block=4, max_iter=200, tol=1e-6, want_vectors=False,
+                                           allow_unconverged=True)
+            torch.cuda.synchronize()
+            r["full_lowest"] = {"omega_eV": [float(x) for x in omf], "iterations": itf, "s": time.time() - t0,
+                                "tol": 1e-6}
+            omt, _, itt = plan.lowest_excitons(n_block=4, max_iter=200, tol=1e-6, want_vectors=False,
+                                               allow_unconverged=True)
+            r["tda_lowest"] = {"omega_eV": [float(x) for x in omt], "iterations": itt}
+            r["omega1_shift_meV (full - tda)"] = float(1e3 * (omf[0] - omt[0]))
         res[prec] = r
         plan.close()
         print("[full_bse mode] %s done" % prec, file=sys.stderr, flush=True)

@@ -330,6 +330,19 @@ bse_status bse_lowest_excitons(bse_plan* plan, int32_t n_block, int32_t max_iter
  * Exact once the Krylov space is invariant; BSE_INFO_BREAKDOWN when a chain
  * stopped early (its spectrum uses the steps done).
  * ------------------------------------------------------------------------- */
+/* bse_full_lowest: the n_block smallest positive Omega_S of the full BSE with
+ * right eigenvectors [X; Y] normalised X^H X - Y^H Y = 1 (Eqs. (right)/(left);
+ * the negative partners are -Omega_S with [Y*; X*]).  Block LOBPCG on the
+ * Hermitian-definite pencil J z = (1/Omega) (J H) z, whose largest eigenvalues
+ * are the smallest positive Omega; one bse_apply_full per iteration, Rayleigh-
+ * Ritz in FP64 on the host.  Needs 2 n_block <= max_nb.  X0 device c128
+ * [2N][n_block] start block (NULL: pseudo-random X part, zero Y part); omega
+ * host f64 [n_block] ascending; xy_out device c128 [2N][n_block] (NULL
+ * allowed); iters host int32 (NULL allowed).  Converged means
+ * |H z - Omega z| <= tol Omega |z| for every pair; otherwise the last iterate
+ * with BSE_INFO_NOT_CONVERGED.  Synchronises the stream every iteration. */
+bse_status bse_full_lowest(bse_plan* plan, int32_t n_block, int32_t max_iter, double tol, const void* X0,
+                           double* omega, void* xy_out, int32_t* iters, void* hip_stream);
 bse_status bse_apply_coupling(bse_plan* plan, const void* X, void* Y, int32_t nb, void* hip_stream);
 bse_status bse_apply_full(bse_plan* plan, const void* XY, void* out, int32_t nb, void* hip_stream);
 bse_status bse_full_spectrum(bse_plan* plan, const void* P, int32_t nb, int32_t n_steps, const double* omega,

@@ -62,6 +62,7 @@ _SIGS = {
     "bse_apply_coupling": [_vp, _vp, _vp, _i32, _vp],
     "bse_apply_full": [_vp, _vp, _vp, _i32, _vp],
     "bse_full_spectrum": [_vp, _vp, _i32, _i32, _vp, _i32, ctypes.c_double, _vp, _vp, _vp, _vp, _vp],
+    "bse_full_lowest": [_vp, _i32, _i32, ctypes.c_double, _vp, _vp, _vp, _vp, _vp],
     "bse_haydock_vjp": [_vp, _vp, _vp, _vp, _vp, _i32, _i32, _vp, _i32, ctypes.c_double, _vp, _vp, _vp, _vp, _vp],
     "bse_plan_set_timing": [_vp, ctypes.c_int],
     "bse_plan_stage_times": [_vp, _vp, _vp, ctypes.c_int],
@@ -296,6 +297,20 @@ class Plan:
                                     b.ctypes.data, steps.ctypes.data, _stream(self.device))
         _check("bse_full_spectrum", s, allow_breakdown=True)
         return {"S": S, "a": a, "b": b, "steps": steps, "breakdown": s == BSE_INFO_BREAKDOWN}
+
+    def full_lowest(self, n_block=2, max_iter=200, tol=1e-10, X0=None, want_vectors=True, allow_unconverged=False):
+        """Smallest positive full-BSE excitations: (omega ascending, [X; Y] [2N][n_block] with
+        X^H X - Y^H Y = 1, iterations)."""
+        omega = np.zeros(n_block)
+        iters = np.zeros(1, dtype=np.int32)
+        z = torch.empty((2 * self.N, n_block), dtype=torch.complex128, device=self.device) if want_vectors else None
+        s = lib().bse_full_lowest(self._ptr, n_block, max_iter, tol,
+                                  _dev(X0, torch.complex128, (2 * self.N, n_block), "X0") if X0 is not None else None,
+                                  omega.ctypes.data, _dev(z, torch.complex128, None, "xy") if want_vectors else None,
+                                  iters.ctypes.data, _stream(self.device))
+        if not (allow_unconverged and s == BSE_INFO_NOT_CONVERGED):
+            _check("bse_full_lowest", s)
+        return omega, z, int(iters[0])
 
     def apply_adjoint(self, Ybar, X, want_WR=True, want_Wq=False, want_eps=True):
         """Gradients of Re <Ybar, A X> w.r.t. W(R) (or W(q)) and the energies."""

@@ -125,6 +125,7 @@ def test_null_plan_calls(L):
     assert L.bse_apply_coupling(None, dummy, dummy, 1, None) == 1
     assert L.bse_apply_full(None, dummy, dummy, 1, None) == 1
     assert L.bse_full_spectrum(None, dummy, 1, 2, om, 1, 0.1, S, S, S, None, None) == 1
+    assert L.bse_full_lowest(None, 1, 10, 1e-8, None, om, None, None, None) == 1
 
 
 def test_offset_set_is_the_papers(L):

@@ -127,3 +127,29 @@ def test_coupling_apply_without_transpose_relation(B, prec):
     print("    rel err %.2e" % err, flush=True)
     assert err < TOL[prec]
     plan.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("bf16x3", 1e-6)])
+def test_full_lowest_paired(B, prec, tol):
+    # the smallest positive Omega of the paired problem and its (X, Y) with X^H X - Y^H Y = 1
+    p = make_problem(DMA, 6, "G2")
+    print("[full lowest %s]" % prec, flush=True)
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
+    plan = B.plan_from_problem(p, Wq, prec=prec, max_nb=6)
+    A, Bm = O.build_H(p, OW(p)), O.build_B(p, OW(p))
+    Om, X, Y = O.full_bse_eig(A, Bm)
+    H = O.build_full(p, OW(p))
+    om, z, it = plan.full_lowest(n_block=3, max_iter=300, tol=tol, allow_unconverged=(prec == "bf16x3"))
+    z = H_(z)
+    N = p.N
+    print("    iterations %d, Omega %s, ref %s" % (it, om, Om[:3]), flush=True)
+    assert np.abs(om - Om[:3]).max() < (1e-9 if prec == "f64" else 1e-6) * Om[0]
+    Xg, Yg = z[:N], z[N:]
+    norm = np.real(np.einsum("ij,ij->j", Xg.conj(), Xg) - np.einsum("ij,ij->j", Yg.conj(), Yg))
+    assert np.abs(norm - 1.0).max() < 1e-8
+    # eigenvectors of the oracle's explicit Hamiltonian; the lowest one equals the oracle's up to a phase
+    res = np.abs(H @ z - z * om[None, :]).max() / np.abs(z).max()
+    assert res < (1e-8 if prec == "f64" else 1e-5) * Om[0]
+    ov = abs(np.vdot(np.r_[X[:, 0], Y[:, 0]], np.r_[Xg[:, 0], -Yg[:, 0]]))
+    assert abs(ov - 1.0) < 1e-6
+    plan.close()
