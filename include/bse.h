@@ -147,7 +147,7 @@ bse_status bse_plan_create(const bse_dims* d, const double* eps_qp, const void* 
  *     M^mu_ij(k_a, k_b) = sum_st conj(c^{k_a}_{s i}) c^{k_b}_{t j} [C^mu_st(k_b) + C^mu_ts(-k_a)],
  * the first term for the ABFs on the centre of s, the second for those on the
  * centre of t.  Every operation of bse_plan_create's plans (apply, adjoint,
- * Haydock, LOBPCG, offsets) runs on such a plan unchanged.
+ * Haydock, LOBPCG, offsets, full BSE) runs on such a plan unchanged.
  * n_RC    number of lattice vectors of the coefficients (> 0)
  * RC      host int32 [n_RC][3]
  * C_R     device f64 [n_RC][n_aux][n_ao][n_ao], C_R[r][mu][s][t] = C^mu_st(R_r)
@@ -304,8 +304,10 @@ bse_status bse_lowest_excitons(bse_plan* plan, int32_t n_block, int32_t max_iter
 
 /* ---------------------------------------------------------------------------
  * Full BSE (Eq. (Hamiltonian) with its coupling block; the paired solutions of
- * Eqs. (right)/(left); the spectrum of Eq. (full_BSE_epsilon2)).  Plans from
- * bse_plan_create only (two-centre plans return BSE_EINVAL).
+ * Eqs. (right)/(left); the spectrum of Eq. (full_BSE_epsilon2)), for plans of
+ * either kind of LRI coefficients (on two-centre plans the cross pair densities
+ * are formed from both one-sided products, as the resonant ones) and zero
+ * exciton momentum.
  *
  * bse_apply_coupling: Y = B X with
  *   B_{cvk,c'v'k'} = (alpha/N_k) sum_munu M^mu_cv(k,k) Vbar_munu M^nu_c'v'(k',k')

@@ -333,24 +333,24 @@ char* off_bytes(void* base, long long elems, size_t esz) { return (char*)base + 
 
 // two-centre pair densities of one q batch, from the one-sided products N (pairs (k, k'), k' = kq[k][q0+qi])
 // and N2 (the reversed pairs, N(k', k) stored at slot (qi, k')):
-//   M[qi][k][b'][b][mu] = N[qi][k][b'][b][mu] + conj(N2[qi][k'][b][b'][mu])
+//   M[qi][k][a][b][mu] = N[qi][k][a][b][mu] + conj(N2[qi][k'][b][a][mu]),  a < na_, b < nb_
 // written in the plan's storage: four bf16 planes at plane stride ps (SPLIT) or interleaved T
 template <typename T, bool SPLIT>
-__global__ void tc_combine_kernel(int nq, int Nk, int nb, int na, int q0, const int* __restrict__ kq,
+__global__ void tc_combine_kernel(int nq, int Nk, int na_, int nb_, int na, int q0, const int* __restrict__ kq,
                                   const T* __restrict__ N, const T* __restrict__ N2, void* __restrict__ out,
                                   long long ps) {
-  const long long n = (long long)nq * Nk * nb * nb * na;
+  const long long n = (long long)nq * Nk * na_ * nb_ * na;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
     const int mu = (int)(e % na);
     long long r = e / na;
-    const int b = (int)(r % nb);
-    r /= nb;
-    const int bp = (int)(r % nb);
-    r /= nb;
+    const int b = (int)(r % nb_);
+    r /= nb_;
+    const int a = (int)(r % na_);
+    r /= na_;
     const int k = (int)(r % Nk);
     const int qi = (int)(r / Nk);
     const int kp = kq[(long long)k * Nk + q0 + qi];
-    const long long e2 = ((((long long)qi * Nk + kp) * nb + b) * nb + bp) * na + mu;
+    const long long e2 = ((((long long)qi * Nk + kp) * nb_ + b) * na_ + a) * na + mu;
     const T re = N[2 * e] + N2[2 * e2];
     const T im = N[2 * e + 1] - N2[2 * e2 + 1];
     if constexpr (SPLIT) {
@@ -368,6 +368,23 @@ __global__ void tc_combine_kernel(int nq, int Nk, int nb, int na, int q0, const 
       o[2 * e + 1] = im;
     }
   }
+}
+
+// launch of the combine in the plan's storage (f64: c128; split: bf16 planes; else c64)
+bse_status tc_combine(Plan* p, int nq, int na_, int nb_, int q0, const int* kq, const void* n1, const void* n2,
+                      void* out, bool split_out, long long ps, hipStream_t st) {
+  const int Nk = p->Nk, na = p->d.n_aux;
+  if (p->prec == BSE_F64)
+    hipLaunchKernelGGL((tc_combine_kernel<double, false>), dim3(4096), dim3(256), 0, st, nq, Nk, na_, nb_, na, q0, kq,
+                       (const double*)n1, (const double*)n2, out, ps);
+  else if (split_out)
+    hipLaunchKernelGGL((tc_combine_kernel<float, true>), dim3(4096), dim3(256), 0, st, nq, Nk, na_, nb_, na, q0, kq,
+                       (const float*)n1, (const float*)n2, out, ps);
+  else
+    hipLaunchKernelGGL((tc_combine_kernel<float, false>), dim3(4096), dim3(256), 0, st, nq, Nk, na_, nb_, na, q0, kq,
+                       (const float*)n1, (const float*)n2, out, ps);
+  BSE_CHECK_LAUNCH();
+  return BSE_OK;
 }
 
 // S1: pair-density halves -> Gv and Mc for one q batch
@@ -465,18 +482,8 @@ bse_status form_pair_densities(Plan* p, int q0, int nq, bool need_c, const int* 
     void* out = part == 0 ? p->Mv : p->Mc;
     const bool split_out = p->split && (part == 0 || c_split);
     const long long ps = part == 0 ? p->ps_Mv : p->ps_Mc;
-    const void* n1 = off_bytes(p->Nt, off, gsz);
-    const void* n2 = off_bytes(p->Nt2, off, gsz);
-    if (f64)
-      hipLaunchKernelGGL((tc_combine_kernel<double, false>), dim3(4096), dim3(256), 0, st, nq, Nk, nb, na, q0, kq,
-                         (const double*)n1, (const double*)n2, out, ps);
-    else if (split_out)
-      hipLaunchKernelGGL((tc_combine_kernel<float, true>), dim3(4096), dim3(256), 0, st, nq, Nk, nb, na, q0, kq,
-                         (const float*)n1, (const float*)n2, out, ps);
-    else
-      hipLaunchKernelGGL((tc_combine_kernel<float, false>), dim3(4096), dim3(256), 0, st, nq, Nk, nb, na, q0, kq,
-                         (const float*)n1, (const float*)n2, out, ps);
-    BSE_CHECK_LAUNCH();
+    BSE_TRY(tc_combine(p, nq, nb, nb, q0, kq, off_bytes(p->Nt, off, gsz), off_bytes(p->Nt2, off, gsz), out, split_out,
+                       ps, st));
   }
   return BSE_OK;
 }
@@ -570,16 +577,23 @@ bse_status apply_coupling_direct(Plan* p, const double* X, double* Y, int nb, hi
   const int Nk = p->Nk, nv = d.nv, nc = d.nc, na = d.n_aux, no = d.n_ao, nt = nv * nc;
   const Arith ar = arith_of(p->prec);
   const bool f64 = p->prec == BSE_F64;
+  const bool tc = p->two_centre != 0;
+  const size_t gsz = f64 ? 16 : 8;  // bytes per element of a non-split GEMM result
   if (!p->Gb) {
     // the same workspace budget as the resonant direct term
-    const long long per_q_a = (long long)Nk * (nv * nv * na * 2 + (p->mc_direct ? nc * nc * na : 0) + nt * nt);
-    const long long per_q_b = (long long)Nk * (3LL * nc * nv * na + (long long)nt * nt);
-    const long long qb = std::max(1LL, std::min<long long>(Nk, (long long)p->qb * per_q_a / per_q_b));
+    const double per_q_a =
+        (double)p->esz * Nk * (nv * nv * na * 2 + (p->mc_direct ? nc * nc * na : 0) + nt * nt) +
+        (tc ? 2.0 * gsz * Nk * (nv * nv + nc * nc) * na : 0.0);
+    const double per_q_b =
+        (double)p->esz * Nk * (3.0 * nc * nv * na + (double)nt * nt) + (tc ? 4.0 * gsz * Nk * nc * nv * na : 0.0);
+    const long long qb = std::max(1LL, std::min<long long>(Nk, (long long)((double)p->qb * per_q_a / per_q_b)));
     p->qbB = (int)qb;
     p->ps_Gb = qb * Nk * nc * nv * na;
     BSE_TRY(plan_alloc(p, &p->Gb, p->esz * (size_t)p->ps_Gb));
     BSE_TRY(plan_alloc(p, &p->Pb, p->esz * (size_t)p->ps_Gb));
     BSE_TRY(plan_alloc(p, &p->M2, p->esz * (size_t)p->ps_Gb));
+    if (tc)
+      for (int i = 0; i < 4; ++i) BSE_TRY(plan_alloc(p, &p->Btc[i], gsz * (size_t)p->ps_Gb));
     BSE_TRY(plan_alloc(p, &p->Tb, p->esz * (size_t)(qb * Nk * nt * nt)));
     BSE_TRY(plan_alloc(p, (void**)&p->tabB_psi_c, sizeof(long long) * (size_t)(qb * Nk * nc)));
     BSE_TRY(plan_alloc(p, (void**)&p->tabB_g, sizeof(long long) * (size_t)(qb * Nk * nc)));
@@ -599,64 +613,81 @@ bse_status apply_coupling_direct(Plan* p, const double* X, double* Y, int nb, hi
   for (int q0 = 0; q0 < nqt; q0 += p->qbB) {
     const int nq = std::min(p->qbB, nqt - q0);
     StageMark sm_(p, BSE_STAGE_COUPLING, st);
-    hipLaunchKernelGGL(tables_b_kernel, dim3(Nk), dim3(256), 0, st, Nk, nq, q0, nv, nc, p->nbnd, no, na, kq,
-                       p->tabB_psi_c, p->tabB_g, p->tabB_psi_v, p->tabB_m2);
-    BSE_CHECK_LAUNCH();
-    {  // Gb[(q c')][(v mu)] = sum_t psi_c'(k')_t B^mu_vt(k)
-      GemmArgs g;
-      g.batch = Nk;
-      g.M = nq * nc;
-      g.N = nv * na;
-      g.K = no;
-      g.A = p->psi;
-      g.a_tab = p->tabB_psi_c;
-      g.a_tab_pb = 1;
-      g.a_sk = 1;
-      g.B = p->Bv;
-      g.b_sb = (long long)nv * na * no;
-      g.b_sj = no;
-      g.b_sk = 1;
-      g.C = p->Gb;
-      g.c_tab = p->tabB_g;
-      g.c_tab_pb = 1;
-      g.c_sj = 1;
-      g.tab_aligned = (no % 8 == 0);
-      if (p->split) {
-        g.a_ps = p->ps_psi;
-        g.b_ps = p->ps_Bv;
-        g.c_ps = p->ps_Gb;
-        BSE_TRY(cgemm_split(g, true, true, true, false, st));
-      } else {
-        BSE_TRY(cgemm(g, ar, f64, f64, st));
+    // the pair densities Gb and M2 of the batch (into the plan's storage), or with two-centre coefficients
+    // the one-sided products (non-split) of the pairs or, with the reverse table, of their reverses
+    auto gemms = [&](const int* ktab, void* outG, void* outM2) -> bse_status {
+      hipLaunchKernelGGL(tables_b_kernel, dim3(Nk), dim3(256), 0, st, Nk, nq, q0, nv, nc, p->nbnd, no, na, ktab,
+                         p->tabB_psi_c, p->tabB_g, p->tabB_psi_v, p->tabB_m2);
+      BSE_CHECK_LAUNCH();
+      const bool split_out = p->split && !tc;
+      {  // Gb[(q c')][(v mu)] = sum_t psi_c'(k')_t B^mu_vt(k)
+        GemmArgs g;
+        g.batch = Nk;
+        g.M = nq * nc;
+        g.N = nv * na;
+        g.K = no;
+        g.A = p->psi;
+        g.a_tab = p->tabB_psi_c;
+        g.a_tab_pb = 1;
+        g.a_sk = 1;
+        g.B = p->Bv;
+        g.b_sb = (long long)nv * na * no;
+        g.b_sj = no;
+        g.b_sk = 1;
+        g.C = outG;
+        g.c_tab = p->tabB_g;
+        g.c_tab_pb = 1;
+        g.c_sj = 1;
+        g.tab_aligned = (no % 8 == 0);
+        if (p->split) {
+          g.a_ps = p->ps_psi;
+          g.b_ps = p->ps_Bv;
+          g.c_ps = p->ps_Gb;
+          BSE_TRY(cgemm_split(g, true, true, split_out, false, st));
+        } else {
+          BSE_TRY(cgemm(g, ar, f64, f64, st));
+        }
       }
-    }
-    {  // M2[(q v')][(c nu)] = sum_t psi_v'(k')_t B^nu_ct(k)
-      GemmArgs g;
-      g.batch = Nk;
-      g.M = nq * nv;
-      g.N = nc * na;
-      g.K = no;
-      g.A = p->psi;
-      g.a_tab = p->tabB_psi_v;
-      g.a_tab_pb = 1;
-      g.a_sk = 1;
-      g.B = p->Bc;
-      g.b_sb = (long long)nc * na * no;
-      g.b_sj = no;
-      g.b_sk = 1;
-      g.C = p->M2;
-      g.c_tab = p->tabB_m2;
-      g.c_tab_pb = 1;
-      g.c_sj = 1;
-      g.tab_aligned = (no % 8 == 0);
-      if (p->split) {
-        g.a_ps = p->ps_psi;
-        g.b_ps = p->ps_Bc;
-        g.c_ps = p->ps_Gb;
-        BSE_TRY(cgemm_split(g, true, true, true, false, st));
-      } else {
-        BSE_TRY(cgemm(g, ar, f64, f64, st));
+      {  // M2[(q v')][(c nu)] = sum_t psi_v'(k')_t B^nu_ct(k)
+        GemmArgs g;
+        g.batch = Nk;
+        g.M = nq * nv;
+        g.N = nc * na;
+        g.K = no;
+        g.A = p->psi;
+        g.a_tab = p->tabB_psi_v;
+        g.a_tab_pb = 1;
+        g.a_sk = 1;
+        g.B = p->Bc;
+        g.b_sb = (long long)nc * na * no;
+        g.b_sj = no;
+        g.b_sk = 1;
+        g.C = outM2;
+        g.c_tab = p->tabB_m2;
+        g.c_tab_pb = 1;
+        g.c_sj = 1;
+        g.tab_aligned = (no % 8 == 0);
+        if (p->split) {
+          g.a_ps = p->ps_psi;
+          g.b_ps = p->ps_Bc;
+          g.c_ps = p->ps_Gb;
+          BSE_TRY(cgemm_split(g, true, true, split_out, false, st));
+        } else {
+          BSE_TRY(cgemm(g, ar, f64, f64, st));
+        }
       }
+      return BSE_OK;
+    };
+    if (!tc) {
+      BSE_TRY(gemms(kq, p->Gb, p->M2));
+    } else {
+      // Gb = N_vc'(k, k') + conj N_c'v(k', k),  M2 = N_cv'(k, k') + conj N_v'c(k', k): the reversed pairs'
+      // products come from the other GEMM of the pair with the reverse table
+      const int* kinv = (kq == p->kqp) ? p->kqm : p->kqinv;
+      BSE_TRY(gemms(kq, p->Btc[0], p->Btc[1]));
+      BSE_TRY(gemms(kinv, p->Btc[2], p->Btc[3]));
+      BSE_TRY(tc_combine(p, nq, nc, nv, q0, kq, p->Btc[0], p->Btc[3], p->Gb, p->split, p->ps_Gb, st));
+      BSE_TRY(tc_combine(p, nq, nv, nc, q0, kq, p->Btc[1], p->Btc[2], p->M2, p->split, p->ps_Gb, st));
     }
     {  // Pb = conj(Gb) W(q)
       GemmArgs g;

@@ -168,6 +168,7 @@ struct Plan {
   void* M2 = nullptr;               // [qbB][Nk][nv][nc][n_aux]
   void* Tb = nullptr;               // [qbB][Nk][nt][nt]
   long long ps_Gb = 0;              // plane stride of Gb, Pb and M2
+  void* Btc[4] = {};                // two-centre: one-sided Gb and M2 products of the pairs and of their reverses
   long long* tabB_psi_c = nullptr;  // [Nk][qbB*nc]
   long long* tabB_psi_v = nullptr;  // [Nk][qbB*nv]
   long long* tabB_g = nullptr;      // [Nk][qbB*nc]

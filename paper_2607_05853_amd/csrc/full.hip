@@ -260,10 +260,6 @@ bse_status bse_apply_coupling(bse_plan* plan, const void* X, void* Y, int32_t nb
     set_error("bse_apply_coupling: X and Y must not alias");
     return BSE_EINVAL;
   }
-  if (p->two_centre) {
-    set_error("bse_apply_coupling: the coupling block takes k-independent LRI coefficients");
-    return BSE_EINVAL;
-  }
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   BSE_TRY(zero_fill(Y, 16 * (size_t)p->N * nb, st));
   BSE_TRY(apply_exchange(p, (const double*)X, (double*)Y, nb, st, true));
@@ -284,10 +280,6 @@ bse_status bse_apply_full(bse_plan* plan, const void* XY, void* out, int32_t nb,
   }
   if (XY == out) {
     set_error("bse_apply_full: input and output must not alias");
-    return BSE_EINVAL;
-  }
-  if (p->two_centre) {
-    set_error("bse_apply_full: the coupling block takes k-independent LRI coefficients");
     return BSE_EINVAL;
   }
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
@@ -323,10 +315,6 @@ bse_status bse_full_spectrum(bse_plan* plan, const void* P, int32_t nb, int32_t 
   if ((long long)n_steps > 2 * p->N) {
     set_error("bse_full_spectrum: n_steps exceeds the dimension 2N");
     return BSE_ESHAPE;
-  }
-  if (p->two_centre) {
-    set_error("bse_full_spectrum: the coupling block takes k-independent LRI coefficients");
-    return BSE_EINVAL;
   }
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   const long long N = p->N, L = 2 * N;

@@ -524,10 +524,6 @@ extern "C" bse_status bse_full_lowest(bse_plan* plan, int32_t n_block, int32_t m
     set_error("bse_full_lowest: need 2 n_block <= max_nb and 3 n_block <= 2N");
     return BSE_EINVAL;
   }
-  if (p->two_centre) {
-    set_error("bse_full_lowest: the coupling block takes k-independent LRI coefficients");
-    return BSE_EINVAL;
-  }
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   const long long N = p->N, L = 2 * N;
   const size_t blk = 16 * (size_t)L * nb;

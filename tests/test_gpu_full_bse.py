@@ -153,3 +153,39 @@ def test_full_lowest_paired(B, prec, tol):
     ov = abs(np.vdot(np.r_[X[:, 0], Y[:, 0]], np.r_[Xg[:, 0], -Yg[:, 0]]))
     assert abs(ov - 1.0) < 1e-6
     plan.close()
+
+
+@pytest.mark.parametrize("all_pairs", [False, True])
+@pytest.mark.parametrize("prec", ["f64", "bf16x3"])
+@pytest.mark.parametrize("cfg", ["DMA", "RAGGED"])
+def test_coupling_apply_two_centre(B, cfg, prec, all_pairs):
+    # two-centre coefficients: the cross pair densities of B from both one-sided products
+    p = make_problem(CONFS[cfg], 8, "G2", two_centre=True)
+    print("[coupling apply two-centre %s %s all_pairs=%s]" % (cfg, prec, all_pairs), flush=True)
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
+    plan = B.plan_from_problem(p, Wq, prec=prec, max_nb=6, all_pairs=all_pairs)
+    Bm = O.build_B(p, OW(p))
+    X = random_block(p.N, 3, seed=24)
+    err = rel(H_(plan.apply_coupling(T(X))), Bm @ X)
+    print("    rel err %.2e" % err, flush=True)
+    assert err < TOL[prec]
+    plan.close()
+
+
+def test_full_spectrum_two_centre(B):
+    p = make_problem(RAGGED, 9, "G2", two_centre=True)
+    print("[full spectrum two-centre]", flush=True)
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
+    plan = B.plan_from_problem(p, Wq, prec="f64", max_nb=4)
+    Om, X, Y = O.full_bse_eig(O.build_H(p, OW(p)), O.build_B(p, OW(p)))
+    pol = polarisations(2)
+    w = np.linspace(1.0, 6.0, 201)
+    Sref = O.full_bse_spectrum(p, pol, Om, X, Y, w, 0.1)
+    P = plan.velocity_start(T(p.vel), T(p.eps_ks, torch.float64), pol)
+    out = plan.full_spectrum(P, 2 * p.N, w, 0.1)
+    err = rel(out["S"], Sref)
+    om, _, _ = plan.full_lowest(n_block=2, max_iter=300, tol=1e-10, want_vectors=False)
+    print("    spectrum rel err %.2e, lowest %s ref %s" % (err, om, Om[:2]), flush=True)
+    assert err < 1e-8
+    assert np.abs(om - Om[:2]).max() < 1e-9 * Om[0]
+    plan.close()
