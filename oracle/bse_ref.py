@@ -23,7 +23,7 @@ __all__ = [
     "binding_energy", "grad_apply", "grad_WR_from_Wq", "grad_lowest", "grad_spectrum",
     "interpolate_W_matmul", "apply_H_rows_allpairs", "grad_Wq_at", "grad_eps",
     "PAPER_OFFSETS", "PAPER_OFFSET_WEIGHTS", "offset_average",
-    "lorentzian", "coupling_block", "build_B", "build_full", "full_bse_eig", "full_bse_amplitudes", "full_bse_spectrum",
+    "lorentzian", "coupling_block", "apply_B_rows", "apply_rows_twosided", "build_B", "build_full", "full_bse_eig", "full_bse_amplitudes", "full_bse_spectrum",
 ]
 
 
@@ -215,6 +215,98 @@ def coupling_block(prob, W_q, alpha, k, kp):
     Xb = (alpha / prob.Nk) * np.einsum("mcv,mn,ndp->cvdp", Mcv, prob.Vbar, Mcv2)
     Db = -(1.0 / prob.Nk) * np.einsum("mdv,mn,ncp->cvdp", Mcpv, Wq, Mcvp)
     return (Xb + Db).reshape(nc * nv, nc * nv)
+
+
+def apply_B_rows(prob, W_q, X, rows, alpha=None):
+    """Rows k in `rows` of B X, each row block of the coupling block built by coupling_block and
+    multiplied by X.  Returns [len(rows)*nc*nv][nb]."""
+    alpha = prob.alpha if alpha is None else alpha
+    nt = prob.nc * prob.nv
+    X = np.asarray(X).reshape(prob.Nk * nt, -1)
+    out = np.zeros((len(rows) * nt, X.shape[1]), dtype=np.complex128)
+    for i, k in enumerate(rows):
+        for kp in range(prob.Nk):
+            out[i * nt:(i + 1) * nt] += coupling_block(prob, W_q, alpha, k, kp) @ X[kp * nt:(kp + 1) * nt]
+    return out
+
+
+def _F_sets(prob):
+    """F[k][mu][s][n] = sum_t C^mu_st(k_n) c^k_{tn} for the valence and the conduction bands, with which
+    every pair density is M^mu_ij(k_a, k_b) = sum_s conj(c^{k_a}_{si}) F[k_b][mu][s][j]
+                                           + sum_t conj(F[k_a][mu][t][i]) c^{k_b}_{tj}   (two-centre C(R))
+    or the first term alone (k-independent C).  The second term is sum_st conj(c_si) c_tj C^mu_ts(-k_a) for
+    real C(R) (C^mu(-k) = conj C^mu(k)).  Returns (Fv, Fc, two_sided)."""
+    pv, pc = _psi_sets(prob)
+    if getattr(prob, "C_R", None) is None:
+        Fv = np.transpose(np.tensordot(prob.C, pv, axes=([2], [2])), (2, 0, 1, 3))        # [k][mu][s][v]
+        Fc = np.transpose(np.tensordot(prob.C, pc, axes=([2], [2])), (2, 0, 1, 3))
+        return Fv, Fc, False
+    if np.iscomplexobj(prob.C_R):
+        raise ValueError("the row-at-a-time two-centre form takes real C(R)")
+    kv, kc = prob.band_k()
+    RC = np.asarray(prob.RC, dtype=np.float64)
+    out = []
+    for psi_n, kn in ((pv, kv), (pc, kc)):
+        F = np.zeros((prob.Nk, prob.n_aux, prob.n_ao, psi_n.shape[1]), dtype=np.complex128)
+        for r in range(len(RC)):
+            ph = np.exp(2j * np.pi * (kn @ RC[r]))                                          # [k]
+            G = np.tensordot(prob.C_R[r], psi_n, axes=([2], [2]))                           # [mu][s][k][n]
+            F += ph[:, None, None, None] * np.transpose(G, (2, 0, 1, 3))
+        out.append(F)
+    return out[0], out[1], True
+
+
+def _pairs_rows(pa, Fa, ka, pb, Fb, kb, two):
+    """M^mu_ij(k_a, k_b) for the pairs (ka[x], kb[x]) at once from psi sets and F sets: [x][mu][i][j]."""
+    M = np.einsum("xis,xmsj->xmij", pa[ka].conj(), Fb[kb], optimize=True)
+    if two:
+        M = M + np.einsum("xmti,xjt->xmij", Fa[ka].conj(), pb[kb], optimize=True)
+    return M
+
+
+def apply_rows_twosided(prob, W_q, X, rows, block="A", alpha=None, chunk=64):
+    """Rows k in `rows` of A X (block "A", Eq. (Hamiltonian)) or of B X (block "B", coupling block), every
+    k' of a row at once, for k-independent or real two-centre coefficients (pair densities from _F_sets).
+    The same sums as hamiltonian_block / coupling_block in another evaluation order.  [len(rows)*nt][nb]."""
+    alpha = prob.alpha if alpha is None else alpha
+    nv, nc, Nk, na = prob.nv, prob.nc, prob.Nk, prob.n_aux
+    nt = nc * nv
+    pv, pc = _psi_sets(prob)
+    Fv, Fc, two = _F_sets(prob)
+    X = np.asarray(X).reshape(Nk, nt, -1)
+    nb = X.shape[2]
+    allk = np.arange(Nk)
+    rho = _pairs_rows(pc, Fc, allk, pv, Fv, allk, two)                     # [k][mu][c][v] = M^mu_cv(k,k)
+    Xr = X.reshape(Nk, nc, nv, nb)
+    # exchange: t[nu][b] = sum_k' sum_{c'v'} M^nu_{v'c'}(k',k') X  (A) or M^nu_{c'v'}(k',k') X  (B)
+    if block == "A":
+        Mvc = _pairs_rows(pv, Fv, allk, pc, Fc, allk, two)                 # [k][nu][v'][c'] = M^nu_v'c'(k,k)
+        t = np.einsum("knvc,kcvb->nb", Mvc, Xr, optimize=True)
+    else:
+        t = np.einsum("kncv,kcvb->nb", rho, Xr, optimize=True)
+    u = prob.Vbar @ t
+    qtab = np.array([[q_index(prob.nk, k, kp) for kp in range(Nk)] for k in rows])
+    eps_t = transition_energies(prob)
+    out = np.zeros((len(rows), nt, nb), dtype=np.complex128)
+    for i, k in enumerate(rows):
+        out[i] += (alpha / Nk) * np.einsum("mcv,mb->cvb", rho[k], u).reshape(nt, nb)
+        if block == "A":
+            out[i] += eps_t[k][:, None] * X[k]
+        for k0 in range(0, Nk, chunk):
+            ks = np.arange(k0, min(Nk, k0 + chunk))
+            K = len(ks)
+            kk = np.full(K, k)
+            W = W_q[qtab[i, ks]]                                              # [K][mu][nu]
+            if block == "A":
+                L = _pairs_rows(pv, Fv, ks, pv, Fv, kk, two)                  # [K][mu][v'][v] = M_v'v(k',k)
+                Rt = _pairs_rows(pc, Fc, kk, pc, Fc, ks, two)                 # [K][nu][c][c'] = M_cc'(k,k')
+                D = -(1.0 / Nk) * np.einsum("xmpv,xmn,xncd->xcvdp", L, W, Rt, optimize=True)   # [(c v)][(c' v')]
+            else:
+                L = _pairs_rows(pc, Fc, ks, pv, Fv, kk, two)                  # [K][mu][c'][v] = M_c'v(k',k)
+                Rt = _pairs_rows(pc, Fc, kk, pv, Fv, ks, two)                 # [K][nu][c][v'] = M_cv'(k,k')
+                D = -(1.0 / Nk) * np.einsum("xmdv,xmn,xncp->xcvdp", L, W, Rt, optimize=True)
+            out[i] += np.einsum("xcvdp,xdpb->cvb", D, Xr[ks], optimize=True).reshape(nt, nb)
+    return out.reshape(len(rows) * nt, nb)
 
 
 def build_B(prob, W_q, alpha=None):

@@ -89,3 +89,32 @@ def test_grad_eps_matches_grad_apply():
     Yb, X = random_block(p.N, 3, seed=18), random_block(p.N, 3, seed=19)
     ge, _ = O.grad_apply(p, Wq, Yb, X)
     assert np.abs(O.grad_eps(p, Yb, X) - ge).max() < 1e-13 * np.abs(ge).max()
+
+
+def _general_2c(p, seed):
+    """Two-centre coefficients kept real (the form assumes it), a non-symmetric complex Vbar and a random
+    W(q) per q."""
+    rng = np.random.default_rng(seed)
+    q = dataclasses.replace(p, Vbar=_cn(rng, p.Vbar.shape) / p.n_aux)
+    Wq = _cn(rng, (p.Nk, p.n_aux, p.n_aux)) / p.n_aux
+    return q, Wq
+
+
+@pytest.mark.parametrize("over", [{}, dict(offset=(1.0 / 3, 1.0 / 3, 0.0)), dict(momentum=(0.5, 0.25, 0.0))])
+@pytest.mark.parametrize("two_centre", [False, True])
+@pytest.mark.parametrize("block", ["A", "B"])
+def test_twosided_rows_match_blocks(block, two_centre, over):
+    base = make_problem(RAGGED, 8, "G1", two_centre=two_centre, **over)
+    p, Wq = (_general_2c if two_centre else _general)(base, 21)
+    X = random_block(p.N, 3, seed=22)
+    rows = [0, 1, p.Nk // 2, p.Nk - 1]
+    ref = O.apply_H_rows(p, Wq, X, rows) if block == "A" else O.apply_B_rows(p, Wq, X, rows)
+    got = O.apply_rows_twosided(p, Wq, X, rows, block=block, chunk=7)
+    assert rel(got, ref) < 1e-13
+
+
+def test_twosided_rows_refuse_complex_two_centre_coefficients():
+    p = make_problem(RAGGED, 8, "G1", two_centre=True)
+    p = dataclasses.replace(p, C_R=p.C_R + 0j)
+    with pytest.raises(ValueError):
+        O.apply_rows_twosided(p, np.zeros((p.Nk, p.n_aux, p.n_aux), complex), np.zeros((p.N, 1)), [0])
