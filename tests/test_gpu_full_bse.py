@@ -189,3 +189,27 @@ def test_full_spectrum_two_centre(B):
     assert err < 1e-8
     assert np.abs(om - Om[:2]).max() < 1e-9 * Om[0]
     plan.close()
+
+
+def test_full_spectrum_edge_cases(B):
+    # a zero start column stops its chain at once (breakdown, zero spectrum) without touching the other;
+    # an odd step count uses the even-sized leading tridiagonal; 2 nb > max_nb is rejected
+    p = make_problem(RAGGED, 10, "G2")
+    print("[full spectrum edge cases]", flush=True)
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
+    plan = B.plan_from_problem(p, Wq, prec="f64", max_nb=4)
+    P = plan.velocity_start(T(p.vel), T(p.eps_ks, torch.float64), polarisations(2))
+    w = np.linspace(1.0, 6.0, 51)
+    ref = plan.full_spectrum(P, 20, w, 0.1)
+    P0 = P.clone()
+    P0[:, 1] = 0
+    out = plan.full_spectrum(P0, 20, w, 0.1)
+    assert out["breakdown"] and out["steps"][1] == 0 and np.abs(out["S"][1]).max() == 0.0
+    assert np.abs(out["S"][0] - ref["S"][0]).max() <= 1e-12 * np.abs(ref["S"][0]).max()
+    odd = plan.full_spectrum(P, 21, w, 0.1)
+    assert np.abs(odd["S"] - ref["S"]).max() <= 1e-12 * np.abs(ref["S"]).max()
+    with pytest.raises(B.BSEError):
+        plan.full_spectrum(T(random_block(p.N, 3, seed=1)), 10, w, 0.1)
+    with pytest.raises(B.BSEError):
+        plan.apply_full(T(random_block(2 * p.N, 3, seed=2)))
+    plan.close()
