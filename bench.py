@@ -453,8 +453,33 @@ def full_bse_mode(config, m):
         plan.close()
         print("[full_bse mode] %s done" % prec, file=sys.stderr, flush=True)
     err = float(np.abs(spec["bf16x3"] - spec["f64"]).max() / np.abs(spec["f64"]).max())
+    # the coupling block's direct term on BF16x3 (one B apply of the 2 n_b packed columns is what the full
+    # apply runs; here the stage of a B apply on n_b columns): algorithmic bytes of its per-pair
+    # intermediates G_B, M2, P_B (each written once and read once, G_B read by both W-step column tiles
+    # counted once) and its MFMA flops, against the stage time
+    rb = res["bf16x3"]
+    pairs = p.Nk * rb["q_formed_A"]  # the coupling block forms the same q (W(q) Hermitian here)
+    ntv = p.nc * p.nv
+    by = 6 * 8.0 * ntv * p.n_aux * pairs
+    fl = 8.0 * pairs * (2 * p.n_aux * p.n_ao * ntv + p.n_aux ** 2 * ntv + p.n_aux * ntv ** 2)
+    tst = rb["apply_B_stage_ms"].get("coupling", float("nan")) / 1e3
+    stage_roof = {"stage": "coupling (B direct term)", "bound": "hbm", "achieved": by / tst / 1e9, "peak": 8000.0,
+                  "unit": "GB/s", "frac": by / tst / 8e12, "mfma_TFLOP_s": fl / tst / 1e12,
+                  "mfma_frac": fl / tst / 1e12 / PEAK_TFLOPS["bf16x3"]}
+    cpu = None
+    if not os.environ.get("BENCH_NO_CPU"):
+        import oracle as O
+        Wq_o = O.interpolate_W_matmul(p.W_R, p.R, p.w_R, kq)
+        sel = [0, p.Nk // 2]
+        t0 = time.time()
+        O.apply_rows_twosided(p, Wq_o, random_block(p.N, nb, seed=3), sel, "B")
+        tc_ = time.time() - t0
+        cpu = {"value": tc_ * p.Nk / len(sel), "unit": "s per B apply", "kind": "oracle",
+               "sample": "%d of %d k rows of one FP64 coupling apply (row-at-a-time form), %.1f s, extrapolated x%d"
+                         % (len(sel), p.Nk, tc_, p.Nk // len(sel)),
+               "gpu_bf16x3_B_apply_s": rb["apply_B_ms"] / 1e3}
     print(json.dumps({"mode": "full_bse", "workload": "%s, %d chains, %d Lanczos steps (error check %d steps)" %
-                      (config, nb, m, m_short), "runs": res,
+                      (config, nb, m, m_short), "stage_roofline": stage_roof, "cpu_baseline": cpu, "runs": res,
                       "spectrum_rel_err_bf16x3_vs_f64_%d_steps" % m_short: err}), flush=True)
 
 
@@ -510,8 +535,35 @@ def two_centre_mode(config, m):
             plan.close()
             print("[two_centre mode] %s %s done" % (kind, prec), file=sys.stderr, flush=True)
         res[kind] = r
+    # the conduction pair densities of the two-centre BF16x3 apply (two one-sided GEMMs per q batch): their
+    # algorithmic flops and the bytes of their two c64 results, against the stage time
+    p2 = make_problem(config, 0, "G1", two_centre=True)
+    r2 = res["two_centre"]["bf16x3"]
+    qf = r2["q_formed"]
+    pairs = p2.Nk * qf
+    fl = 2 * 8.0 * p2.n_aux * p2.n_ao * p2.nc ** 2 * pairs
+    by = 2 * 8.0 * p2.nc ** 2 * p2.n_aux * pairs
+    tst = r2["apply_stage_ms"].get("pairdens_c", float("nan")) / 1e3
+    stage_roof = {"stage": "pairdens_c (two one-sided GEMMs per batch)", "bound": "hbm",
+                  "achieved": by / tst / 1e9, "peak": 8000.0, "unit": "GB/s", "frac": by / tst / 8e12,
+                  "mfma_TFLOP_s": fl / tst / 1e12, "mfma_frac": fl / tst / 1e12 / PEAK_TFLOPS["bf16x3"]}
+    cpu = None
+    if not os.environ.get("BENCH_NO_CPU"):
+        import oracle as O
+        Wq_o = O.interpolate_W_matmul(p2.W_R, p2.R, p2.w_R, dense_kmesh(p2.nk))
+        sel = [0, p2.Nk // 2]
+        t0 = time.time()
+        O.apply_rows_twosided(p2, Wq_o, random_block(p2.N, nb, seed=3), sel, "A")
+        tc_ = time.time() - t0
+        t_apply = tc_ * p2.Nk / len(sel)
+        cpu = {"value": f_apply(p2.Nk, p2.n_ao, p2.nv, p2.nc, p2.n_aux, nb) / t_apply / 1e9, "unit": "GFLOP/s",
+               "kind": "oracle", "sample": "%d of %d k rows of one FP64 two-centre apply (row-at-a-time form), "
+               "%.1f s, extrapolated x%d" % (len(sel), p2.Nk, tc_, p2.Nk // len(sel)),
+               "gpu_bf16x3_apply_GFLOP_s": f_apply(p2.Nk, p2.n_ao, p2.nv, p2.nc, p2.n_aux, nb) /
+               (r2["apply_ms"] / 1e3) / 1e9}
     print(json.dumps({"mode": "two_centre", "workload": "%s, %d Haydock steps, blocks of %d" % (config, m, nb),
                       "coefficients": "real C^mu_st(R) on R = 0 and the 6 nearest cells, mu on the atom of s",
+                      "stage_roofline": stage_roof, "cpu_baseline": cpu,
                       "runs": res,
                       "haydock_ratio_two_centre_over_k_independent":
                           res["two_centre"]["bf16x3"]["haydock_s"] / res["k_independent"]["bf16x3"]["haydock_s"]}),

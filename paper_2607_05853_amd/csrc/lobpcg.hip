@@ -72,6 +72,12 @@ __global__ void reduce_parts(int nsplit, int n, const double* __restrict__ part,
   out[2 * i + 1] = si;
 }
 
+// Rayleigh-Ritz drops basis directions whose Gram eigenvalue is below thr times the largest: the
+// whitening multiplies the error of the projected operator by 1 / g, so the threshold follows the
+// rounding of the apply (FP64 ~1e-15; FP32 and BF16x3 ~1e-8 relative, where 1e-12 would let that error
+// grow to spurious Ritz values of 1e4 |A| and beyond)
+double rr_threshold(const Plan* p) { return p->prec == BSE_F64 ? 1e-12 : 1e-6; }
+
 struct Work {
   std::vector<double*> bufs;
   ~Work() {
@@ -221,7 +227,7 @@ extern "C" bse_status bse_lowest_excitons(bse_plan* plan, int32_t n_block, int32
       GA[(size_t)j * nb + i] = std::conj(GA[(size_t)i * nb + j]);
       GB[(size_t)j * nb + i] = std::conj(GB[(size_t)i * nb + j]);
     }
-  if (small::gen_eig_robust(nb, GA, GB, w, C) < nb) {
+  if (small::gen_eig_robust(nb, GA, GB, w, C, rr_threshold(p)) < nb) {
     set_error("bse_lowest_excitons: start block is rank deficient");
     return BSE_ESHAPE;
   }
@@ -293,7 +299,7 @@ extern "C" bse_status bse_lowest_excitons(bse_plan* plan, int32_t n_block, int32
           GA[(size_t)i * n + j] *= sc[i] * sc[j];
           GB[(size_t)i * n + j] *= sc[i] * sc[j];
         }
-      rank = small::gen_eig_robust(n, GA, GB, w, C);
+      rank = small::gen_eig_robust(n, GA, GB, w, C, rr_threshold(p));
       if (rank < nb) return false;
       for (int i = 0; i < n; ++i)
         for (int j = 0; j < rank; ++j) C[(size_t)i * rank + j] *= sc[i];
@@ -586,7 +592,7 @@ extern "C" bse_status bse_full_lowest(bse_plan* plan, int32_t n_block, int32_t m
       GA[(size_t)i * nb + j] = 0.5 * (h[(size_t)i * nb + j] + std::conj(h[(size_t)j * nb + i]));
       GB[(size_t)i * nb + j] = 0.5 * (h[nn + (size_t)i * nb + j] + std::conj(h[nn + (size_t)j * nb + i]));
     }
-  int rank0 = small::gen_eig_robust(nb, GA, GB, w, C);
+  int rank0 = small::gen_eig_robust(nb, GA, GB, w, C, rr_threshold(p));
   if (rank0 < nb || !(w[0] > 0.0)) {
     set_error("bse_full_lowest: start block is rank deficient or not in the positive branch");
     return BSE_ESHAPE;
@@ -672,7 +678,7 @@ extern "C" bse_status bse_full_lowest(bse_plan* plan, int32_t n_block, int32_t m
           GA[(size_t)i * n + j] *= sc[i] * sc[j];
           GB[(size_t)i * n + j] *= sc[i] * sc[j];
         }
-      rank = small::gen_eig_robust(n, GA, GB, w, C);
+      rank = small::gen_eig_robust(n, GA, GB, w, C, rr_threshold(p));
       if (rank < nb || !(w[rank - nb] > 0.0)) return false;
       for (int i = 0; i < n; ++i)
         for (int j = 0; j < rank; ++j) C[(size_t)i * rank + j] *= sc[i];

@@ -11,6 +11,7 @@ from synth import dense_kmesh, make_problem, random_block
 pytestmark = pytest.mark.gpu
 
 SMALL = dict(cfg_id=96, coarse=(3, 3, 2), dense=(3, 2, 2), n_ao=10, nv=2, nc=3, n_aux=20)
+DMA_LOB = dict(cfg_id=77, coarse=(3, 3, 2), dense=(4, 4, 2), n_ao=16, nv=4, nc=4, n_aux=48)
 
 
 def dev():
@@ -220,3 +221,17 @@ def test_bf16x3_spectrum_vjp_vs_oracle(B, cfg):
     e_e, e_w = rel(H_(eps.grad), ge), rel(H_(W_R.grad), gr)
     print("[bf16x3 spectrum vjp %s] eps %.1e W_R %.1e" % (cfg, e_e, e_w), flush=True)
     assert e_e < 1e-4 and e_w < 1e-4
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "f32"])
+def test_lobpcg_lowest_reduced_precision(B, prec):
+    # Rayleigh-Ritz on a reduced-precision operator must drop nearly dependent directions at a threshold
+    # above the apply's rounding; otherwise the rounding turns into spurious Ritz values
+    p = make_problem(DMA_LOB, 0, "G2")
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
+    plan = B.plan_from_problem(p, Wq, prec=prec, max_nb=16)
+    ev = np.linalg.eigvalsh(O.build_H(p, OW(p)))
+    om, _, it = plan.lowest_excitons(n_block=4, tol=1e-6, max_iter=300, want_vectors=False)
+    print("[lobpcg %s] iterations %d, omega %s, ref %s" % (prec, it, om, ev[:4]), flush=True)
+    assert np.abs(om - ev[:4]).max() < 1e-6 * abs(ev[0])
+    plan.close()
