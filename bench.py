@@ -718,8 +718,8 @@ def gradients_mode(config, m):
                  alpha=p.alpha, prec="bf16x3", max_nb=max(nb, 64))
     pl3.set_R(p.R, p.w_R)
     t0 = time.time()
-    # Omega_1: Hellmann-Feynman through the BF16x3 adjoint with the FP64 eigenvector (block LOBPCG on the
-    # BF16x3 operator stalls above a 1e-7 residual)
+    # Omega_1: Hellmann-Feynman through the BF16x3 adjoint with the FP64 eigenvector (the residual of LOBPCG
+    # on the BF16x3 operator cannot fall below that operator's rounding, ~4e-8 of |A|)
     _, Xl, _ = plan.lowest_excitons(n_block=nb, tol=1e-12, max_iter=500)
     x1 = Xl[:, :1].contiguous()
     g3 = pl3.apply_adjoint(x1, x1, want_WR=True, want_eps=True)

@@ -187,7 +187,8 @@ TN_SPEC = dict(cfg_id=85, coarse=(3, 3, 2), dense=(2, 2, 2), n_ao=12, nv=4, nc=2
 @pytest.mark.parametrize("cfg", ["SMALL", "TN_GRAD"])
 def test_bf16x3_lowest_gradient_vs_oracle(B, cfg):
     # Hellmann-Feynman gradient of Omega_1 through the BF16x3 adjoint, with the eigenvector of the FP64
-    # LOBPCG (block LOBPCG on the BF16x3 operator stalls above a 1e-7 residual; the gradient only needs x)
+    # LOBPCG (on the BF16x3 operator the residual cannot fall below its rounding, ~4e-8 of |A|; the gradient
+    # only needs x)
     p = make_problem({"SMALL": SMALL, "TN_GRAD": TN_GRAD}[cfg], 1, "G2")
     plan64, _ = _plan(B, p, prec="f64", nb=4)
     om, X, _ = plan64.lowest_excitons(n_block=4, tol=1e-12, max_iter=500)
