@@ -144,3 +144,17 @@ def test_binding_rejects_cpu_tensors():
     with pytest.raises(TypeError):
         bse.interpolate_W(torch.zeros((1, 2, 2), dtype=torch.complex128), np.zeros((1, 3)), np.ones(1),
                           np.zeros((1, 3)))
+
+
+def test_header_is_plain_c(tmp_path):
+    # the boundary is a C ABI: the header compiles as strict C99 with no C++ or torch types
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "h.c"
+    src.write_text('#include "bse.h"\nint main(void) { return 0; }\n')
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only",
+                        "-I", os.path.join(ROOT, "include"), str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
