@@ -236,3 +236,17 @@ def test_lobpcg_lowest_reduced_precision(B, prec):
     print("[lobpcg %s] iterations %d, omega %s, ref %s" % (prec, it, om, ev[:4]), flush=True)
     assert np.abs(om - ev[:4]).max() < 1e-6 * abs(ev[0])
     plan.close()
+
+
+def test_lobpcg_mesh8_bf16x3_matches_f64(B):
+    # at the timed 8^3 workload the BF16x3 iteration once produced Ritz values near -1e24 (directions
+    # kept down to 1e-12 of the Gram spectrum); it must converge to the FP64 plan's lowest excitons
+    p = make_problem("mesh8_ao64", 0, "G1")
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
+    om = {}
+    for prec, tol in [("f64", 1e-9), ("bf16x3", 1e-6)]:
+        plan = B.plan_from_problem(p, Wq, prec=prec, max_nb=8)
+        om[prec], _, it = plan.lowest_excitons(n_block=4, tol=tol, max_iter=300, want_vectors=False)
+        print("[lobpcg mesh8 %s] iterations %d, omega %s" % (prec, it, om[prec]), flush=True)
+        plan.close()
+    assert np.abs(om["bf16x3"] - om["f64"]).max() < 1e-6 * om["f64"][0]
