@@ -13,6 +13,7 @@ namespace bse {
 namespace {
 thread_local std::string g_err;
 int g_alloc_count = 0;
+std::string g_fail_spec;  // the value of BSE_TEST_FAIL_ALLOC the count started from
 }  // namespace
 
 void set_error(const std::string& msg) { g_err = msg; }
@@ -20,7 +21,13 @@ const char* last_error() { return g_err.c_str(); }
 
 bse_status dmalloc(void** p, size_t bytes) {
   *p = nullptr;
+  // fault injection for tests: BSE_TEST_FAIL_ALLOC=n fails the n-th device allocation counted from the
+  // first one made under that value (a new value starts the count again)
   const char* f = std::getenv("BSE_TEST_FAIL_ALLOC");
+  if (g_fail_spec != (f ? f : "")) {
+    g_fail_spec = f ? f : "";
+    g_alloc_count = 0;
+  }
   ++g_alloc_count;
   if (f && std::atoi(f) == g_alloc_count) {
     set_error("device allocation failed (BSE_TEST_FAIL_ALLOC)");

@@ -579,7 +579,7 @@ bse_status apply_coupling_direct(Plan* p, const double* X, double* Y, int nb, hi
   const bool f64 = p->prec == BSE_F64;
   const bool tc = p->two_centre != 0;
   const size_t gsz = f64 ? 16 : 8;  // bytes per element of a non-split GEMM result
-  if (!p->Gb) {
+  if (!p->qbB) {
     // the same workspace budget as the resonant direct term
     const double per_q_a =
         (double)p->esz * Nk * (nv * nv * na * 2 + (p->mc_direct ? nc * nc * na : 0) + nt * nt) +
@@ -587,22 +587,27 @@ bse_status apply_coupling_direct(Plan* p, const double* X, double* Y, int nb, hi
     const double per_q_b =
         (double)p->esz * Nk * (3.0 * nc * nv * na + (double)nt * nt) + (tc ? 4.0 * gsz * Nk * nc * nv * na : 0.0);
     const long long qb = std::max(1LL, std::min<long long>(Nk, (long long)((double)p->qb * per_q_a / per_q_b)));
-    p->qbB = (int)qb;
-    p->ps_Gb = qb * Nk * nc * nv * na;
-    BSE_TRY(plan_alloc(p, &p->Gb, p->esz * (size_t)p->ps_Gb));
-    BSE_TRY(plan_alloc(p, &p->Pb, p->esz * (size_t)p->ps_Gb));
-    BSE_TRY(plan_alloc(p, &p->M2, p->esz * (size_t)p->ps_Gb));
-    if (tc)
-      for (int i = 0; i < 4; ++i) BSE_TRY(plan_alloc(p, &p->Btc[i], gsz * (size_t)p->ps_Gb));
-    BSE_TRY(plan_alloc(p, &p->Tb, p->esz * (size_t)(qb * Nk * nt * nt)));
-    BSE_TRY(plan_alloc(p, (void**)&p->tabB_psi_c, sizeof(long long) * (size_t)(qb * Nk * nc)));
-    BSE_TRY(plan_alloc(p, (void**)&p->tabB_g, sizeof(long long) * (size_t)(qb * Nk * nc)));
-    BSE_TRY(plan_alloc(p, (void**)&p->tabB_psi_v, sizeof(long long) * (size_t)(qb * Nk * nv)));
-    BSE_TRY(plan_alloc(p, (void**)&p->tabB_m2, sizeof(long long) * (size_t)(qb * Nk * nv)));
     BSE_HIP(hipFuncSetAttribute((const void*)coupling_tx_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 160 * 1024));
     BSE_HIP(hipFuncSetAttribute((const void*)coupling_tx_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 160 * 1024));
+    p->ps_Gb = qb * Nk * nc * nv * na;
+    p->qbB = (int)qb;
+  }
+  {
+    // each buffer on its own, so that a call after a failed allocation completes the set
+    const long long qb = p->qbB;
+    if (!p->Gb) BSE_TRY(plan_alloc(p, &p->Gb, p->esz * (size_t)p->ps_Gb));
+    if (!p->Pb) BSE_TRY(plan_alloc(p, &p->Pb, p->esz * (size_t)p->ps_Gb));
+    if (!p->M2) BSE_TRY(plan_alloc(p, &p->M2, p->esz * (size_t)p->ps_Gb));
+    if (tc)
+      for (int i = 0; i < 4; ++i)
+        if (!p->Btc[i]) BSE_TRY(plan_alloc(p, &p->Btc[i], gsz * (size_t)p->ps_Gb));
+    if (!p->Tb) BSE_TRY(plan_alloc(p, &p->Tb, p->esz * (size_t)(qb * Nk * nt * nt)));
+    if (!p->tabB_psi_c) BSE_TRY(plan_alloc(p, (void**)&p->tabB_psi_c, sizeof(long long) * (size_t)(qb * Nk * nc)));
+    if (!p->tabB_g) BSE_TRY(plan_alloc(p, (void**)&p->tabB_g, sizeof(long long) * (size_t)(qb * Nk * nc)));
+    if (!p->tabB_psi_v) BSE_TRY(plan_alloc(p, (void**)&p->tabB_psi_v, sizeof(long long) * (size_t)(qb * Nk * nv)));
+    if (!p->tabB_m2) BSE_TRY(plan_alloc(p, (void**)&p->tabB_m2, sizeof(long long) * (size_t)(qb * Nk * nv)));
   }
   // q in the plan's order (W(q) is stored in that order): the first half only with the transpose relation
   const bool sym = p->herm_half && p->b_pairs;

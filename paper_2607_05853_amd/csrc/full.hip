@@ -229,12 +229,11 @@ __global__ void fb_mark(int nb, int m, int j, int sidx, double tol, const double
 unsigned grid_of(long long n) { return (unsigned)std::max<long long>(1, std::min<long long>((n + 255) / 256, 65536)); }
 
 bse_status full_buffers(Plan* p) {
-  if (!p->fz) {
-    const size_t bytes = 16 * (size_t)p->N * p->max_nb;
-    BSE_TRY(plan_alloc(p, (void**)&p->fz, bytes));
-    BSE_TRY(plan_alloc(p, (void**)&p->fra, bytes));
-    BSE_TRY(plan_alloc(p, (void**)&p->frb, bytes));
-  }
+  // each buffer on its own, so that a call after a failed allocation completes the set
+  const size_t bytes = 16 * (size_t)p->N * p->max_nb;
+  if (!p->fz) BSE_TRY(plan_alloc(p, (void**)&p->fz, bytes));
+  if (!p->fra) BSE_TRY(plan_alloc(p, (void**)&p->fra, bytes));
+  if (!p->frb) BSE_TRY(plan_alloc(p, (void**)&p->frb, bytes));
   return BSE_OK;
 }
 

@@ -1,0 +1,150 @@
+"""Device-allocation failures, injected from the host (BSE_TEST_FAIL_ALLOC=n fails the n-th device
+allocation counted from the first one under that value): every call must return BSE_ENOMEM before it
+launches anything on a missing buffer, a failed plan creation must free what it took, and the lazily
+allocated workspaces (coupling block, full-BSE buffers) must be completed by the next call, which then
+gives the oracle's result.  No kernel ever sees a NULL buffer: the failure paths return on the host."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from synth import dense_kmesh, make_problem, polarisations, random_block
+
+pytestmark = pytest.mark.gpu
+
+RAGGED = dict(cfg_id=78, coarse=(3, 3, 2), dense=(3, 2, 2), n_ao=10, nv=2, nc=3, n_aux=20)
+ENV = "BSE_TEST_FAIL_ALLOC"
+ENOMEM = 3
+
+
+def T(a, dt=torch.complex128):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(torch.device("cuda:0"), dt)
+
+
+def H_(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def OW(p):
+    return O.interpolate_W_matmul(p.W_R, p.R, p.w_R, dense_kmesh(p.nk))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2607_05853_amd import bse
+    return bse
+
+
+def walk(B, monkeypatch, call, limit=120):
+    """Fail the 1st, 2nd, ... allocation of call() until it succeeds; returns (failures, result)."""
+    try:
+        for n in range(1, limit):
+            monkeypatch.setenv(ENV, str(n))
+            try:
+                out = call()
+            except B.BSEError as e:
+                assert e.status == ENOMEM and ENV in str(e), str(e)
+                continue
+            return n - 1, out
+        raise AssertionError("still failing after %d allocations" % limit)
+    finally:
+        monkeypatch.delenv(ENV, raising=False)
+
+
+def lazy_walk(B, monkeypatch, make_plan, call, check, limit=40):
+    """For n = 1, 2, ...: a fresh plan whose first call() fails at its n-th allocation; the next call on
+    that plan must complete the workspace and pass check().  Returns the number of failing n."""
+    for n in range(1, limit):
+        plan = make_plan()
+        monkeypatch.setenv(ENV, str(n))
+        try:
+            out, failed = call(plan), False
+        except B.BSEError as e:
+            assert e.status == ENOMEM and ENV in str(e), str(e)
+            failed = True
+        finally:
+            monkeypatch.delenv(ENV)
+        if failed:
+            out = call(plan)
+        check(out)
+        plan.close()
+        if not failed:
+            return n - 1
+    raise AssertionError("still failing after %d allocations" % limit)
+
+
+@pytest.mark.parametrize("two_centre", [False, True])
+def test_plan_creation_and_coupling_workspace(B, monkeypatch, two_centre):
+    p = make_problem(RAGGED, 7, "G2", two_centre=two_centre)
+    print("[allocation failures: plan + coupling, two_centre=%s]" % two_centre, flush=True)
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
+    torch.cuda.synchronize()
+    make = lambda: B.plan_from_problem(p, Wq, prec="bf16x3", max_nb=4)
+    nfail, plan = walk(B, monkeypatch, make)
+    print("    plan creation failed cleanly at each of %d allocations" % nfail, flush=True)
+    assert nfail >= 10
+    plan.close()
+    X = random_block(p.N, 2, seed=31)
+    ref = O.build_B(p, OW(p)) @ X
+    errs = []
+
+    def check(Y):
+        errs.append(rel(H_(Y), ref))
+        assert errs[-1] < 5e-4
+
+    # the coupling workspace: 8 buffers, 12 with the one-sided two-centre products
+    nfail = lazy_walk(B, monkeypatch, make, lambda pl: pl.apply_coupling(T(X)), check)
+    print("    coupling apply failed cleanly at each of %d allocations; max rel err of the retries %.2e"
+          % (nfail, max(errs)), flush=True)
+    assert nfail == (12 if two_centre else 8)
+    # a plan with its workspace in place allocates nothing more
+    plan = make()
+    Y = plan.apply_coupling(T(X))
+    monkeypatch.setenv(ENV, "1")
+    try:
+        Y2 = plan.apply_coupling(T(X))
+    finally:
+        monkeypatch.delenv(ENV)
+    assert rel(H_(Y2), H_(Y)) < 1e-14
+    plan.close()
+
+
+def test_full_bse_buffers_and_drivers(B, monkeypatch):
+    p = make_problem(RAGGED, 8, "G2")
+    print("[allocation failures: full BSE]", flush=True)
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
+    make = lambda: B.plan_from_problem(p, Wq, prec="f64", max_nb=4)
+    H = O.build_full(p, OW(p))
+    XY = random_block(2 * p.N, 2, seed=32)
+
+    def check(Z):
+        assert rel(H_(Z), H @ XY) < 1e-12
+
+    # three full-BSE buffers, then the eight of the coupling workspace
+    nfail = lazy_walk(B, monkeypatch, make, lambda pl: pl.apply_full(T(XY)), check)
+    print("    full apply failed cleanly at each of %d allocations" % nfail, flush=True)
+    assert nfail == 11
+    # the drivers hold their work buffers for one call only: every failure frees them
+    plan = make()
+    P = plan.velocity_start(T(p.vel), T(p.eps_ks, torch.float64), polarisations(2))
+    w = np.linspace(1.0, 5.0, 41)
+    nfail, out = walk(B, monkeypatch, lambda: plan.full_spectrum(P, 2 * p.N, w, 0.1))
+    print("    full spectrum failed cleanly at each of %d allocations" % nfail, flush=True)
+    assert nfail >= 5
+    A, Bm = O.build_H(p, OW(p)), O.build_B(p, OW(p))
+    Om, Xo, Yo = O.full_bse_eig(A, Bm)
+    ref = O.full_bse_spectrum(p, polarisations(2), Om, Xo, Yo, w, 0.1)
+    assert rel(out["S"], ref) < 1e-8
+    nfail, out = walk(B, monkeypatch, lambda: plan.haydock(P, 20, w, 0.1))
+    print("    haydock failed cleanly at each of %d allocations" % nfail, flush=True)
+    assert nfail >= 5
+    nfail, (om, _, _) = walk(B, monkeypatch, lambda: plan.full_lowest(n_block=2, max_iter=300, tol=1e-10,
+                                                                        want_vectors=False))
+    print("    full lowest failed cleanly at each of %d allocations" % nfail, flush=True)
+    assert nfail >= 5
+    assert np.abs(om - Om[:2]).max() < 1e-9 * Om[0]
+    plan.close()
