@@ -192,8 +192,11 @@ __global__ __launch_bounds__(256) void u_direct_b3(UArgs u) {
 
 // Same computation with direct-to-LDS staging of both operands (global_load_lds_dwordx4,
 // two stages, XOR-swizzled 16-byte k chunks as in the split GEMM); needs N_aux % 16 == 0.
-template <int TMW>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMW == 1 ? 2 : 1, TMW == 1 ? 2 : 1))) void u_direct_b3_dma(UArgs u) {
+// MEPI picks the epilogue at compile time: with both in one kernel the accumulators stay live across
+// the matrix-core epilogue and spill.  The 64-row tile (N_ao <= 64) fits 168 VGPRs and 48 KiB of LDS,
+// so three blocks share a CU (three waves per SIMD) to cover the per-stage barrier.
+template <int TMW, bool MEPI>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMW == 1 ? 3 : 1, TMW == 1 ? 3 : 1))) void u_direct_b3_dma(UArgs u) {
   constexpr int BM = 2 * TMW * 32, BN = 128, BK = 16, HN = 64;
   constexpr int PA = BM * BK, PB = BN * BK;  // bf16 per plane per stage
   constexpr int STAGE = 4 * (PA + PB);
@@ -298,7 +301,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMW == 1 ? 
   vm_wait_barrier0();
 
   const int nc = u.nc;
-  if (u.mfma_epi) {
+  if constexpr (MEPI) {
     // T_q = Psi_q U_q for every q of the group, on 16x16x32 MFMA: U is split into bf16 planes in LDS,
     // [plane][column][t] with row stride TPAD (zero for t >= n_ao), one pass per PW columns holding whole q
     constexpr int PW = 64, TPAD = BM + 8, UPL = PW * TPAD;
@@ -377,8 +380,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMW == 1 ? 
       }
       lds_wait_barrier();
     }
-    return;
-  }
+  } else {
   for (int h = 0; h < 2; ++h) {
     if (wn == h) {
 #pragma unroll
@@ -413,6 +415,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMW == 1 ? 
       out[1] = si_;
     }
     lds_wait_barrier();
+  }
   }
 }
 
@@ -450,10 +453,17 @@ bse_status direct_u_b3(Plan* p, int q0, int nq, const int* kq, hipStream_t st) {
   const bool dma = d.n_aux % 16 == 0 && u.ps_BcT % 8 == 0 && u.ps_P % 8 == 0 &&
                    (reinterpret_cast<uintptr_t>(u.BcT) & 15) == 0 && (reinterpret_cast<uintptr_t>(u.P) & 15) == 0;
   if (dma) {
-    if (d.n_ao <= 64)
-      hipLaunchKernelGGL(u_direct_b3_dma<1>, grid, dim3(256), 0, st, u);
-    else
-      hipLaunchKernelGGL(u_direct_b3_dma<2>, grid, dim3(256), 0, st, u);
+    if (d.n_ao <= 64) {
+      if (u.mfma_epi)
+        hipLaunchKernelGGL((u_direct_b3_dma<1, true>), grid, dim3(256), 0, st, u);
+      else
+        hipLaunchKernelGGL((u_direct_b3_dma<1, false>), grid, dim3(256), 0, st, u);
+    } else {
+      if (u.mfma_epi)
+        hipLaunchKernelGGL((u_direct_b3_dma<2, true>), grid, dim3(256), 0, st, u);
+      else
+        hipLaunchKernelGGL((u_direct_b3_dma<2, false>), grid, dim3(256), 0, st, u);
+    }
     BSE_CHECK_LAUNCH();
     return BSE_OK;
   }
