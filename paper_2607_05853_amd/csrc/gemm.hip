@@ -784,7 +784,9 @@ __global__ __launch_bounds__(256) void cgemm_b3_dma(GemmArgs g) {
 // n_c^2 x n_v^2 entries, 64 x 64 at n_c = n_v = 8, where a 128 x 128 tile would be three quarters
 // empty): four waves of one 32 x 32 tile each, waves 0 and 1 stage the A rows, 2 and 3 the B columns.
 // Each accumulator receives the same MFMA sequence as in cgemm_b3_dma, so the results are identical.
-template <typename TC>
+// CS writes C pre-split, as cgemm_b3_dma<.., true, ..> does; at 85 registers five blocks share a CU,
+// which hides the staging and the epilogue of products with a short K (the pair densities, K = N_ao).
+template <typename TC, bool CS = false>
 __global__ __launch_bounds__(256) void cgemm_b3_dma64(GemmArgs g) {
   constexpr int BM = 64, BN = 64, BK = 16, NS = 2;
   constexpr int PL = BM * BK;
@@ -870,6 +872,42 @@ __global__ __launch_bounds__(256) void cgemm_b3_dma64(GemmArgs g) {
     accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ih, bb[0], accI, 0, 0, 0);
   }
   // register r holds row 8 (r / 4) + 4 (lane / 32) + r % 4, column lane % 32 of the wave's tile
+  if constexpr (CS) {
+    // planes [4][64][64] through LDS (free once every wave is past its last stage read), then 16-byte stores
+    vm_lds_barrier<0>();
+    __bf16* sC = smem;
+    const float al = (float)g.alpha;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      const int col = wn * 32 + (lane & 31);
+      __bf16 hh, ll;
+      split_bf16(al * accR[r], hh, ll);
+      sC[(0 * 64 + row) * 64 + col] = hh;
+      sC[(1 * 64 + row) * 64 + col] = ll;
+      split_bf16(al * accI[r], hh, ll);
+      sC[(2 * 64 + row) * 64 + col] = hh;
+      sC[(3 * 64 + row) * 64 + col] = ll;
+    }
+    vm_lds_barrier<63>();
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const int id = tid + 256 * it;
+      const int c8 = id & 7, row = (id >> 3) & 63, pl = id >> 9;
+      const int grow = m0 + row, gcol = n0 + c8 * 8;
+      if (grow < g.M && gcol < g.N) {
+        const long long ro = off_of(g.c_tab, g.c_tab_pb, g.c_sb, g.c_si, b, g.M, grow);
+        __bf16* o = (__bf16*)g.C + pl * g.c_ps + ro + gcol;
+        const bf8v v = *reinterpret_cast<const bf8v*>(&sC[(pl * 64 + row) * 64 + c8 * 8]);
+        if (gcol + 8 <= g.N && ((ro + gcol) & 7) == 0) {
+          *reinterpret_cast<bf8v*>(o) = v;
+        } else {
+          for (int e = 0; e < 8 && gcol + e < g.N; ++e) o[e] = v[e];
+        }
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int row = m0 + wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
@@ -1224,6 +1262,14 @@ bse_status cgemm_split(const GemmArgs& g, bool a_split, bool b_split, bool c_spl
         hipLaunchKernelGGL(cgemm_b3_dma64<float>, dim3((unsigned)tiles), dim3(256), 0, st, g);
       BSE_CHECK_LAUNCH();
       return BSE_OK;
+    }
+    if (c_split && g.K <= 64) {  // short K: 64 x 64 tiles, five blocks per CU
+      const long long tiles = (long long)((g.N + 63) / 64) * ((g.M + 63) / 64) * g.batch;
+      if (tiles < (1LL << 31)) {
+        hipLaunchKernelGGL((cgemm_b3_dma64<float, true>), dim3((unsigned)tiles), dim3(256), 0, st, g);
+        BSE_CHECK_LAUNCH();
+        return BSE_OK;
+      }
     }
     if (c_split) return launch_dma<true, float>(g, st);
     return out_f64 ? launch_dma<false, double>(g, st) : launch_dma<false, float>(g, st);
