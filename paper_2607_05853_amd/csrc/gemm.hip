@@ -780,6 +780,164 @@ __global__ __launch_bounds__(256) void cgemm_b3_dma(GemmArgs g) {
   }
 }
 
+// 64 x 128 tiles of the same product with the result written pre-split (CS), for the long-K products
+// (the W step, K = N_aux): four waves of 32 x 64 hold 64 accumulator registers, so three blocks of
+// 48 KiB LDS share a CU (three waves per SIMD) where the 128 x 128 tile runs one.  A's two and B's four
+// 32-row DMA blocks go to waves 0..3 and 0..1.  Each accumulator receives the same MFMA sequence as in
+// cgemm_b3_dma, so the results are identical.
+template <int CJA, int CJB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void cgemm_b3_dma_m64(GemmArgs g) {
+  constexpr int BM = 64, BN = 128, BK = 16;
+  constexpr int PA = BM * BK, PB = BN * BK;  // bf16 per plane per stage
+  constexpr int STAGE = 4 * (PA + PB);
+  constexpr int RBA = BM / 32, RB = (BM + BN) / 32;
+  __shared__ __attribute__((aligned(1024))) __bf16 smem[2 * STAGE];
+  static_assert(4 * 32 * BN <= 2 * STAGE, "epilogue staging must fit in the stages");
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int nK = g.K / BK;
+  const int gxn = (g.N + BN - 1) / BN, gyn = (g.M + BM - 1) / BM;
+  const long long per_batch = (long long)gxn * gyn;
+  long long bl, t;
+  xcd_map(blockIdx.x, per_batch, g.batch, bl, t);
+  const int b = (int)bl;
+  const int m0 = (int)(t / gxn) * BM, n0 = (int)(t % gxn) * BN;
+  // DMA slot of 32-row block rb: lane -> row 32 rb' + lane / 2, 16-byte chunk (lane % 2) ^ bit 3 of the
+  // row; rows past the matrix edge re-load a valid row (their products are never stored)
+  auto slot = [&](int rb, const __bf16*& src, int& lo, long long& ps, int& pstride) {
+    const bool isA = rb < RBA;
+    const int r = 32 * (isA ? rb : rb - RBA) + (lane >> 1);
+    const int chunk = (lane & 1) ^ ((r >> 3) & 1);
+    if (isA) {
+      const int arow = (m0 + r < g.M) ? m0 + r : m0;
+      src = (const __bf16*)g.A + off_of(g.a_tab, g.a_tab_pb, g.a_sb, g.a_si, b, g.M, arow) + 8 * chunk;
+      lo = 32 * rb * BK;
+      ps = g.a_ps;
+      pstride = PA;
+    } else {
+      const int bcol = (n0 + r < g.N) ? n0 + r : n0;
+      src = (const __bf16*)g.B + off_of(g.b_tab, g.b_tab_pb, g.b_sb, g.b_sj, b, g.N, bcol) + 8 * chunk;
+      lo = 4 * PA + 32 * (rb - RBA) * BK;
+      ps = g.b_ps;
+      pstride = PB;
+    }
+  };
+  const __bf16 *src0 = nullptr, *src1 = nullptr;
+  int lo0 = 0, lo1 = 0, pst0 = 0, pst1 = 0;
+  long long ps0 = 0, ps1 = 0;
+  slot(wave, src0, lo0, ps0, pst0);
+  const bool two = wave + 4 < RB;
+  if (two) slot(wave + 4, src1, lo1, ps1, pst1);
+  auto issue = [&](int kt) {
+    __bf16* st = smem + (kt & 1) * STAGE;
+    const int kb = kt * BK;
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl)
+      __builtin_amdgcn_global_load_lds((const void*)(src0 + pl * ps0 + kb),
+                                       (__attribute__((address_space(3))) void*)(st + lo0 + pl * pst0), 16, 0, 0);
+    if (two) {
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl)
+        __builtin_amdgcn_global_load_lds((const void*)(src1 + pl * ps1 + kb),
+                                         (__attribute__((address_space(3))) void*)(st + lo1 + pl * pst1), 16, 0, 0);
+    }
+  };
+  f16v accR[2], accI[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      accR[j][r] = 0.f;
+      accI[j][r] = 0.f;
+    }
+  issue(0);
+  const int ch = lane >> 5;
+  for (int kt = 0; kt < nK; ++kt) {
+    vm_lds_barrier<0>();
+    if (kt + 1 < nK) issue(kt + 1);
+    const __bf16* sa = smem + (kt & 1) * STAGE;
+    const __bf16* sb = sa + 4 * PA;
+    bf8v a[4], bb[2][4];
+    {
+      const int row = wm * 32 + (lane & 31);
+      const int o = row * BK + 8 * (ch ^ ((row >> 3) & 1));
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) a[pl] = *reinterpret_cast<const bf8v*>(sa + pl * PA + o);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = wn * 64 + j * 32 + (lane & 31);
+      const int o = col * BK + 8 * (ch ^ ((col >> 3) & 1));
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) bb[j][pl] = *reinterpret_cast<const bf8v*>(sb + pl * PB + o);
+      if (CJB) {
+        bb[j][2] = neg8(bb[j][2]);
+        bb[j][3] = neg8(bb[j][3]);
+      }
+    }
+    const bf8v nih = neg8(a[2]), nil = neg8(a[3]);
+    const bf8v rh = CJA ? a[2] : nih, rl = CJA ? a[3] : nil;
+    const bf8v ih = CJA ? nih : a[2], il = CJA ? nil : a[3];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      f16v& cr = accR[j];
+      f16v& ci = accI[j];
+      cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], bb[j][0], cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], bb[j][2], ci, 0, 0, 0);
+      cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], bb[j][1], cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], bb[j][3], ci, 0, 0, 0);
+      cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rl, bb[j][2], cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(il, bb[j][0], ci, 0, 0, 0);
+      cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rh, bb[j][3], cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ih, bb[j][1], ci, 0, 0, 0);
+      cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], bb[j][0], cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], bb[j][2], ci, 0, 0, 0);
+      cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rh, bb[j][2], cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ih, bb[j][0], ci, 0, 0, 0);
+    }
+  }
+  vm_lds_barrier<0>();  // every wave is done with the stages before the epilogue reuses LDS
+  // one row half (32 rows) at a time through LDS as planes [4][32][128], then 16-byte stores
+  __bf16* sC = smem;
+  const float al = (float)g.alpha;
+  for (int h = 0; h < 2; ++h) {
+    if (wm == h) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          const int col = wn * 64 + j * 32 + (lane & 31);
+          __bf16 hh, ll;
+          split_bf16(al * accR[j][r], hh, ll);
+          sC[(0 * 32 + row) * BN + col] = hh;
+          sC[(1 * 32 + row) * BN + col] = ll;
+          split_bf16(al * accI[j][r], hh, ll);
+          sC[(2 * 32 + row) * BN + col] = hh;
+          sC[(3 * 32 + row) * BN + col] = ll;
+        }
+    }
+    vm_lds_barrier<63>();
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const int id = tid + 256 * it;
+      const int c8 = id & 15, row = (id >> 4) & 31, pl = id >> 9;
+      const int grow = m0 + h * 32 + row, gcol = n0 + c8 * 8;
+      if (grow < g.M && gcol < g.N) {
+        const long long ro = off_of(g.c_tab, g.c_tab_pb, g.c_sb, g.c_si, b, g.M, grow);
+        __bf16* o = (__bf16*)g.C + pl * g.c_ps + ro + gcol;
+        const bf8v v = *reinterpret_cast<const bf8v*>(&sC[(pl * 32 + row) * BN + c8 * 8]);
+        if (gcol + 8 <= g.N && ((ro + gcol) & 7) == 0) {
+          *reinterpret_cast<bf8v*>(o) = v;
+        } else {
+          for (int e = 0; e < 8 && gcol + e < g.N; ++e) o[e] = v[e];
+        }
+      }
+    }
+    vm_lds_barrier<63>();
+  }
+}
+
 // 64 x 64 tiles of the same product for small per-pair matrices (the direct block T = M_c P^T has
 // n_c^2 x n_v^2 entries, 64 x 64 at n_c = n_v = 8, where a 128 x 128 tile would be three quarters
 // empty): four waves of one 32 x 32 tile each, waves 0 and 1 stage the A rows, 2 and 3 the B columns.
@@ -1271,7 +1429,23 @@ bse_status cgemm_split(const GemmArgs& g, bool a_split, bool b_split, bool c_spl
         return BSE_OK;
       }
     }
-    if (c_split) return launch_dma<true, float>(g, st);
+    if (c_split) {  // longer K: 64 x 128 tiles, three blocks per CU
+      const long long tiles = (long long)((g.N + 127) / 128) * ((g.M + 63) / 64) * g.batch;
+      if (tiles < (1LL << 31)) {
+        const dim3 grid((unsigned)tiles), block(256);
+        if (g.conjA && g.conjB)
+          hipLaunchKernelGGL((cgemm_b3_dma_m64<1, 1>), grid, block, 0, st, g);
+        else if (g.conjA)
+          hipLaunchKernelGGL((cgemm_b3_dma_m64<1, 0>), grid, block, 0, st, g);
+        else if (g.conjB)
+          hipLaunchKernelGGL((cgemm_b3_dma_m64<0, 1>), grid, block, 0, st, g);
+        else
+          hipLaunchKernelGGL((cgemm_b3_dma_m64<0, 0>), grid, block, 0, st, g);
+        BSE_CHECK_LAUNCH();
+        return BSE_OK;
+      }
+      return launch_dma<true, float>(g, st);
+    }
     return out_f64 ? launch_dma<false, double>(g, st) : launch_dma<false, float>(g, st);
   }
   if (a_split && b_split && (c_split || out_f64) && tn_ok(g)) return launch_tn(g, c_split, st);
