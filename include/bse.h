@@ -44,7 +44,11 @@ typedef enum {
     BSE_OK = 0,
     BSE_EINVAL = 1,      /* null pointer, non-positive size, unknown enum        */
     BSE_ESHAPE = 2,      /* sizes inconsistent with each other or with the plan   */
-    BSE_ENOMEM = 3,      /* device allocation failed                              */
+    BSE_ENOMEM = 3,      /* device allocation failed; nothing was launched on the
+                            missing buffer and the plan stays usable: workspaces a
+                            plan allocates on first use are completed by the next
+                            call (tests force it with BSE_TEST_FAIL_ALLOC=n, which
+                            fails the n-th device allocation made under that value) */
     BSE_EDEVICE = 4,     /* a HIP call failed                                     */
     BSE_ENOTHERM = 5,    /* BSE_CHECK_HERMITIAN found a non-Hermitian input       */
     BSE_INFO_BREAKDOWN = 100, /* a Haydock chain stopped early (not an error)      */
