@@ -18,10 +18,10 @@ import numpy as np
 __all__ = [
     "kmesh", "q_index", "q_index_table", "interpolate_W", "coarse_to_R", "coarse_mesh",
     "pair_density", "lri_coeff_k", "pair_density_2c", "hamiltonian_block", "build_H", "apply_H", "apply_H_rows",
-    "transition_energies", "velocity_start", "spectrum_exact", "eig_spectrum",
+    "transition_energies", "velocity_start", "density_start", "spectrum_exact", "eig_spectrum",
     "haydock", "continued_fraction", "haydock_spectrum", "lowest_exciton",
     "binding_energy", "grad_apply", "grad_WR_from_Wq", "grad_lowest", "grad_spectrum",
-    "interpolate_W_matmul", "apply_H_rows_allpairs", "grad_Wq_at", "grad_eps",
+    "interpolate_W_matmul", "apply_H_rows_allpairs", "hamiltonian_rows", "grad_Wq_at", "grad_eps",
     "PAPER_OFFSETS", "PAPER_OFFSET_WEIGHTS", "offset_average",
     "lorentzian", "coupling_block", "apply_B_rows", "apply_rows_twosided", "build_B", "build_full", "full_bse_eig", "full_bse_amplitudes", "full_bse_spectrum",
 ]
@@ -394,7 +394,7 @@ def apply_H(prob, W_q, X, alpha=None):
 
 
 # ----------------------------------------------------------------------------
-# spectrum (Eq. (abs_vel)) and lowest exciton (E_B, Sec. IV.C)
+# spectrum (Eq. (abs_vel)) and lowest exciton (E_B, Sec. IV.B.3)
 # ----------------------------------------------------------------------------
 def velocity_start(prob, pol):
     """p_{cvk} = e.<c k| v |v k> / (E^KS_{ck} - E^KS_{vk})  for each polarisation e (rows of pol).
@@ -412,6 +412,23 @@ def velocity_start(prob, pol):
                     d = prob.eps_ks[k, nv + c] - prob.eps_ks[k, v]
                     amp = sum(e[a] * prob.vel[a, k, c, v] for a in range(3))
                     out[(k * nc + c) * nv + v, b] = amp / d
+    return out
+
+
+def density_start(prob):
+    """p_{cvk}(Q) = <c k+Q| e^{iQ.r} |v k> = <u_c^{k+Q}|u_v^k>: the transition density of a finite exciton
+    momentum Q, the matrix element the long-wavelength appendix writes as <u_i^k|u_a^{k+q}> (here
+    conjugated, so that the amplitude of an exciton X^S is |sum_I conj(p_I) X^S_I|^2 as for the velocity
+    form).  With the NAO Bloch sums orthonormal and each orbital's factor e^{iQ.(r - R)} taken at its centre,
+    <u_c^{k+Q}|u_v^k> = sum_s conj(c^{k+Q}_{s c}) c^k_{s v}; the conduction bands of a finite-momentum
+    problem are those at k + Q.  Its Q -> 0 limit is Q . <c|v|v>/(E_c - E_v), the velocity form of
+    Eq. (abs_vel) along Q (the perturbation expansion of the same appendix).  Returns [N][1]."""
+    nv, nc = prob.nv, prob.nc
+    out = np.zeros((prob.N, 1), dtype=np.complex128)
+    for k in range(prob.Nk):
+        for c in range(nc):
+            for v in range(nv):
+                out[(k * nc + c) * nv + v, 0] = np.vdot(prob.psi[k, nv + c], prob.psi[k, v])
     return out
 
 
@@ -441,7 +458,7 @@ def lowest_exciton(H):
 
 
 def binding_energy(prob, Omega1):
-    """E_B = min_k [E_{c1 k} - E_{v_top k}] - Omega_1 (Sec. IV.C)."""
+    """E_B = min_k [E_{c1 k} - E_{v_top k}] - Omega_1 (Sec. IV.B.3: the smallest direct quasiparticle gap over the mesh minus the lowest excitation)."""
     return (prob.eps_qp[:, prob.nv] - prob.eps_qp[:, prob.nv - 1]).min() - Omega1
 
 
@@ -649,6 +666,57 @@ def apply_H_rows_allpairs(prob, W_q, X, rows, alpha=None, chunk=64):
             D = np.transpose(D.reshape(K, nc, nc, nv, nv), (0, 1, 4, 2, 3)).reshape(K, nt, nt)  # [(c v)][(c' v')]
             out[i] += np.transpose(D, (1, 0, 2)).reshape(nt, K * nt) @ X[ks].reshape(K * nt, nb)   # sum_k' D X(k')
     return out.reshape(len(rows) * nt, nb)
+
+
+def hamiltonian_rows(prob, W_q, rows, alpha=None, chunk=64):
+    """Rows k in `rows` of the explicit TDA Hamiltonian A (Eq. (Hamiltonian), kernels of Eq. (W_LRI)),
+    every column block k' of a row at once: the same blocks hamiltonian_block gives one (k, k') at a time.
+
+      exchange  (alpha/N_k) sum_munu M^mu_{cv}(k,k) Vbar_munu M^nu_{v'c'}(k',k')
+      direct   -(1/N_k)     sum_munu M^mu_{v'v}(k',k) W_munu(k'-k) M^nu_{cc'}(k,k')
+      diagonal  (E_ck - E_vk) on the block k' = k.
+    Returns [len(rows)*nc*nv][N] with row (k, c, v) and column (k', c', v')."""
+    alpha = prob.alpha if alpha is None else alpha
+    nv, nc, Nk, na = prob.nv, prob.nc, prob.Nk, prob.n_aux
+    nt = nc * nv
+    val, con = _bands(prob)
+    pv, pc = _psi_sets(prob)
+    if getattr(prob, "C_R", None) is not None:
+        raise NotImplementedError("row-at-a-time forms take k-independent LRI coefficients")
+    C = prob.C
+    # M^nu_{v'c'}(k',k') for every k': [Nk][nu][v'][c']
+    Mvc = np.empty((Nk, na, nv, nc), dtype=np.complex128)
+    for k0 in range(0, Nk, chunk):
+        ks = slice(k0, min(Nk, k0 + chunk))
+        K = ks.stop - ks.start
+        Cpc = np.tensordot(C, pc[ks], axes=([2], [2]))                            # [nu][s][K][c']
+        Cpc = np.transpose(Cpc, (2, 1, 0, 3)).reshape(K, prob.n_ao, -1)           # [K][s][(nu c')]
+        M = np.matmul(pv[ks].conj(), Cpc).reshape(K, nv, na, nc)                  # [K][v'][nu][c']
+        Mvc[ks] = np.transpose(M, (0, 2, 1, 3))
+    qtab = np.array([[q_index(prob.nk, k, kp) for kp in range(Nk)] for k in rows])
+    eps_t = transition_energies(prob)
+    out = np.zeros((len(rows), nt, Nk, nt), dtype=np.complex128)
+    for i, k in enumerate(rows):
+        Mcv = pair_density(prob.psi, C, k, con, k, val)                           # [mu][c][v]
+        t1 = np.einsum("mcv,mn->ncv", Mcv, prob.Vbar)                             # [nu][c][v]
+        Xb = (alpha / Nk) * np.einsum("ncv,knpd->cvkdp", t1, Mvc)                 # [c][v][k'][c'][v']
+        out[i] += Xb.reshape(nt, Nk, nt)
+        out[i, :, k, :] += np.diag(eps_t[k])
+        Cv = np.matmul(C, pv[k].T)                                                # [mu][s][v]
+        Bc = np.matmul(pc[k].conj()[None], C)                                     # [nu][c][t]
+        for k0 in range(0, Nk, chunk):
+            ks = slice(k0, min(Nk, k0 + chunk))
+            K = ks.stop - ks.start
+            Mvv = np.tensordot(pv[ks].conj(), Cv, axes=([2], [1]))                # [K][v'][mu][v]
+            Mvv = np.transpose(Mvv, (0, 2, 1, 3)).reshape(K, na, nv * nv)         # [K][mu][(v' v)]
+            Mcc = np.tensordot(Bc, pc[ks], axes=([2], [2]))                       # [nu][c][K][c']
+            Mcc = np.transpose(Mcc, (2, 1, 3, 0)).reshape(K, nc * nc, na)         # [K][(c c')][nu]
+            W = W_q[qtab[i, ks]]                                                  # [K][mu][nu]
+            t2 = np.matmul(np.transpose(W, (0, 2, 1)), Mvv)                       # [K][nu][(v' v)]
+            D = -(1.0 / Nk) * np.matmul(Mcc, t2)                                  # [K][(c c')][(v' v)]
+            D = np.transpose(D.reshape(K, nc, nc, nv, nv), (1, 4, 0, 2, 3))       # [c][v][K][c'][v']
+            out[i, :, ks, :] += D.reshape(nt, K, nt)
+    return out.reshape(len(rows) * nt, Nk * nt)
 
 
 def grad_Wq_at(prob, Ybar, X, qs, chunk=64):

@@ -118,3 +118,27 @@ def test_twosided_rows_refuse_complex_two_centre_coefficients():
     p = dataclasses.replace(p, C_R=p.C_R + 0j)
     with pytest.raises(ValueError):
         O.apply_rows_twosided(p, np.zeros((p.Nk, p.n_aux, p.n_aux), complex), np.zeros((p.N, 1)), [0])
+
+
+@pytest.mark.parametrize("cfg,chunk", [("RAGGED", 7), ("WIDE_V", 5)])
+@pytest.mark.parametrize("alpha", [2.0, 0.0])
+def test_hamiltonian_rows_match_blocks(cfg, chunk, alpha):
+    # the explicit rows of A, every column block at once, against hamiltonian_block one (k, k') at a time,
+    # with general complex inputs so that a transposed block or a swapped (c', v') order cannot cancel
+    conf = {"RAGGED": RAGGED, "WIDE_V": WIDE_V}[cfg]
+    p, Wq = _general(make_problem(conf, 9, "G1"), 23)
+    rows = [0, 2, p.Nk - 1]
+    nt = p.nc * p.nv
+    got = O.hamiltonian_rows(p, Wq, rows, alpha=alpha, chunk=chunk)
+    ref = np.vstack([np.hstack([O.hamiltonian_block(p, Wq, alpha, k, kp) for kp in range(p.Nk)]) for k in rows])
+    assert got.shape == (len(rows) * nt, p.N)
+    assert rel(got, ref) < 1e-13
+
+
+def test_hamiltonian_rows_give_build_H():
+    p = make_problem(RAGGED, 5, "G2", coarse=(3, 3, 2))
+    Wq = O.interpolate_W(p.W_R, p.R, p.w_R, dense_kmesh(p.nk))
+    H = O.build_H(p, Wq)
+    got = O.hamiltonian_rows(p, Wq, list(range(p.Nk)), chunk=8)
+    assert rel(got, H) < 1e-13
+    assert np.abs(got - got.conj().T).max() < 1e-14 * np.abs(got).max()
