@@ -31,6 +31,11 @@ sys.path.insert(0, ROOT)
 
 CONDUCTION = None  # BF16x3 conduction route ("mc", "u" or the plan's choice)
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2516.6 / 3.0}
+METRIC = "BSE H\u00b7X GFLOP/s & %MFMA peak, mixed vs FP64 at \u22641e-5 rel. spectrum error"
+# default workload of each mode
+MODE_CONFIG = {"apply": "mesh16_ao128", "spectrum": "mesh8_ao64", "precision": "mesh12_ao96",
+               "gradients": "mesh8_ao64_grad", "largest": "mesh16_ao128", "offsets": "mesh8_ao64",
+               "two_centre": "mesh8_ao64", "full_bse": "mesh8_ao64"}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -89,29 +94,44 @@ def copy_calibration(nbytes=1 << 30):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--prec", default="auto", choices=["auto", "f64", "f32", "bf16x3"])
-    ap.add_argument("--config", default="mesh8_ao64")
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (apply mode: block applies; default 5)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps before the timed ones (default 1)")
+    ap.add_argument("--prec", default=None, choices=["auto", "f64", "f32", "bf16x3"],
+                    help="apply mode: arithmetic of the timed apply (default bf16x3); spectrum mode: auto picks "
+                         "the fastest precision within 1e-5 of the FP64 spectrum")
+    ap.add_argument("--config", default=None, help="workload (synth.CONFIGS); each mode has its own default")
     ap.add_argument("--haydock-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f64", action="store_true", help="apply mode: skip the FP64 reference apply")
+    ap.add_argument("--no-gate", action="store_true", help="apply mode: skip the 8x8x8 spectrum gate")
+    ap.add_argument("--no-adjoint", action="store_true", help="apply mode: skip the adjoint apply")
     ap.add_argument("--cpu-rows", type=int, default=2)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--conduction", default="auto", choices=["auto", "mc", "u"],
                     help="BF16x3 conduction side of the direct term: the plan's choice (auto), forming the "
                          "conduction pair densities (mc) or the B_c(k) contraction (u)")
-    ap.add_argument("--mode", default="spectrum",
-                    choices=["spectrum", "precision", "gradients", "largest", "offsets", "two_centre", "full_bse"],
-                    help="spectrum: the timed pipeline (default); precision: per-precision apply and "
-                         "short-Haydock errors on a larger workload; gradients: LOBPCG and spectrum "
-                         "gradients checked by central finite differences; largest: one BF16x3 apply and "
-                         "adjoint on the 16x16x16 / N_ao = 128 workload; offsets: the spectrum averaged over "
+    ap.add_argument("--mode", default="apply",
+                    choices=["apply", "spectrum", "precision", "gradients", "largest", "offsets", "two_centre",
+                             "full_bse"],
+                    help="apply (default): block applies of A on the largest workload, with the FP64 apply, "
+                         "the oracle's sampled rows and the adjoint beside them and the 8x8x8 spectrum gate; "
+                         "spectrum: the 8x8x8 Haydock pipeline timed per precision; precision: per-precision "
+                         "apply and short-Haydock errors on the 12x12x12 workload; gradients: LOBPCG and "
+                         "spectrum gradients checked by central finite differences; largest: one BF16x3 apply "
+                         "and adjoint on the 16x16x16 / N_ao = 128 workload; offsets: the spectrum averaged over "
                          "the four shifted dense meshes of the k-offset scheme; two_centre: the BF16x3 apply "
                          "and Haydock run with k-dependent two-centre LRI coefficients beside the "
                          "k-independent ones; full_bse: the spectrum of the full BSE (coupling block B) by the "
                          "structure-preserving Lanczos recurrence beside the TDA Haydock spectrum")
     args = ap.parse_args()
+    args.config = args.config or MODE_CONFIG[args.mode]
+    if args.steps is None:
+        args.steps = 5 if args.mode == "apply" else 1
+    if args.warmup is None:
+        args.warmup = 1
+    if args.prec is None:
+        args.prec = "bf16x3" if args.mode == "apply" else "auto"
     global CONDUCTION
     CONDUCTION = None if args.conduction == "auto" else args.conduction
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -123,7 +143,7 @@ def main():
         copy_calibration()
         return
     if args.mode == "precision":
-        precision_mode(args.config if args.config != "mesh8_ao64" else "mesh12_ao96", args.haydock_steps or 10)
+        precision_mode(args.config, args.haydock_steps or 10)
         return
     if args.mode == "offsets":
         from synth import CONFIGS
@@ -138,14 +158,22 @@ def main():
         two_centre_mode(args.config, args.haydock_steps or CONFIGS[args.config]["haydock_steps"])
         return
     if args.mode == "largest":
-        largest_mode(args.config if args.config != "mesh8_ao64" else "mesh16_ao128")
+        largest_mode(args.config)
         return
     if args.mode == "gradients":
         from synth import CONFIGS
-        gcfg = args.config if args.config != "mesh8_ao64" else "mesh8_ao64_grad"
-        gradients_mode(gcfg, args.haydock_steps or CONFIGS[gcfg]["haydock_steps"])
+        gradients_mode(args.config, args.haydock_steps or CONFIGS[args.config]["haydock_steps"])
         return
 
+    if args.mode == "spectrum":
+        spectrum_mode(args)
+        return
+    apply_mode(args)
+
+
+def spectrum_mode(args):
+    """The 8x8x8 pipeline: interpolation, plan, start vectors, a Haydock run and one adjoint per step, each
+    precision timed, the fastest one within 1e-5 of the FP64 spectrum timed over the steps."""
     import torch
     from paper_2607_05853_amd import bse as B
     from synth import CONFIGS, dense_kmesh, make_problem, polarisations
@@ -277,6 +305,234 @@ def main():
         "conduction": routes[prec],
     }
     print(json.dumps(rec), flush=True)
+
+
+def log(msg):
+    print("[bench %s] %s" % (time.strftime("%H:%M:%S"), msg), file=sys.stderr, flush=True)
+
+
+def workload_text(p, config, nb, r_cut=None):
+    cut = ", W(R) within |R|<=%g (%d R)" % (r_cut, len(p.R)) if r_cut else ", %d R" % len(p.R)
+    return ("%s: dense %s k-mesh from coarse %s%s, N_ao=%d, nv=%d, nc=%d, N_aux=%d, BSE dim %d, blocks of %d" %
+            (config, "x".join(map(str, p.nk)), "x".join(map(str, p.coarse)), cut, p.n_ao, p.nv, p.nc, p.n_aux,
+             p.N, nb))
+
+
+def dominant_roofline(p, prec, route, stages, pairs_run, config):
+    """Roofline of the single-kernel stage that takes the most time: its algorithmic flops per launch
+    (per-pair figure of kernel_flops_per_pair x the pairs one launch covers) over its average launch time
+    (HIP events on the library's stream over the timed steps)."""
+    fpp = kernel_flops_per_pair(p, prec, route)
+    cand = {k: v for k, v in stages.items() if k in fpp and v[1] > 0}
+    dom = max(cand, key=lambda k: cand[k][0])
+    ms, n = cand[dom]
+    pairs_per_launch = pairs_run / n
+    achieved = fpp[dom] * pairs_per_launch / (ms / n * 1e-3) / 1e12
+    traffic = measured_traffic(dom, config, prec)
+    roof = {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+            "frac": achieved / PEAK_TFLOPS[prec],
+            "traffic": traffic["bytes_per_launch"] if traffic else None,
+            "algorithmic_flops_per_pair": fpp[dom],
+            "algorithmic_bytes_per_launch": kernel_bytes_per_pair(p, prec, route)[dom] * pairs_per_launch,
+            "avg_launch_ms": ms / n, "launches": n, "pairs_per_launch": pairs_per_launch}
+    if traffic and traffic.get("mfma_issue_frac") is not None:
+        roof["mfma_issue_frac"] = traffic["mfma_issue_frac"]
+    return roof
+
+
+def apply_mode(args):
+    """Block applies of A (Eq. (Hamiltonian), pair densities formed on the fly) on one workload.
+
+    One step is one apply of A to a block of nb vectors resident in HBM.  Around the timed steps: the FP64
+    apply of the same block on the GPU (speedup and error of the timed precision against it), the oracle's
+    FP64 apply on sampled k rows (the CPU baseline, and the error of both GPU results against it), one
+    adjoint apply, and the 8x8x8 spectrum gate (the timed precision's 300-step Haydock spectrum against the
+    oracle's, stored by tests/golden/make_mesh8_golden.py)."""
+    import torch
+    from paper_2607_05853_amd import bse as B
+    from synth import CONFIGS, dense_kmesh, make_problem, random_block
+
+    config, prec = args.config, args.prec
+    if prec == "auto":
+        prec = "bf16x3"
+    cfg = CONFIGS[config]
+    nb = cfg["nb"]
+    dev = torch.device("cuda:0")
+    T = lambda a, dt=torch.complex128: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)
+    sync = torch.cuda.synchronize
+    t0 = time.time()
+    p = make_problem(config, 0, "G1")
+    kq = dense_kmesh(p.nk)
+    Fa = f_apply(p.Nk, p.n_ao, p.nv, p.nc, p.n_aux, nb)
+    log("workload %s: N=%d, nb=%d, F_apply=%.1f TFLOP, inputs drawn in %.1f s" %
+        (config, p.N, nb, Fa / 1e12, time.time() - t0))
+    # inputs resident in HBM before any timed region
+    d_WR, d_psi, d_C, d_V = T(p.W_R), T(p.psi), T(p.C), T(p.Vbar)
+    d_eps = T(p.eps_qp, torch.float64)
+    Xh = random_block(p.N, nb, seed=1)
+    X = T(Xh)
+    Y = torch.empty_like(X)
+
+    def make_plan(pr):
+        t = time.time()
+        Wq = B.interpolate_W(d_WR, p.R, p.w_R, kq)
+        plan = B.Plan(p.nk, p.n_ao, p.nv, p.nc, p.n_aux, d_eps, d_psi, d_C, d_V, Wq, alpha=p.alpha, prec=pr,
+                      max_nb=nb, conduction=CONDUCTION if pr == "bf16x3" else None)
+        plan.set_R(p.R, p.w_R)
+        del Wq
+        sync()
+        torch.cuda.empty_cache()
+        log("%s plan %.2f s (%.1f GB), pairs %s, conduction %s" %
+            (pr, time.time() - t, plan.bytes / 2**30, plan.pairs, plan.conduction))
+        return plan
+
+    plan = make_plan(prec)
+    for _ in range(args.warmup):
+        plan.apply(X, out=Y)
+    sync()
+    log("%d warmup applies done" % args.warmup)
+    plan.set_timing(True)
+    plan.stage_times()
+    sync()
+    t0 = time.time()
+    for i in range(args.steps):
+        plan.apply(X, out=Y)
+    sync()
+    dt = (time.time() - t0) / args.steps
+    stages = plan.stage_times()
+    plan.set_timing(False)
+    value = Fa / dt / 1e9
+    log("timed: %d %s applies, %.3f s per apply -> %.1f GFLOP/s" % (args.steps, prec, dt, value))
+    q_formed, q_total = plan.pairs
+    route = plan.conduction
+    roof = dominant_roofline(p, prec, route, stages, args.steps * p.Nk * q_formed, config)
+    Fx = f_apply(p.Nk, p.n_ao, p.nv, p.nc, p.n_aux, nb, q_formed=q_formed)
+    stage_ms = {k: round(v[0] / args.steps, 2) for k, v in stages.items() if v[1] > 0}
+
+    adj = None
+    if not args.no_adjoint:
+        Yb = T(random_block(p.N, nb, seed=2))
+        plan.set_timing(True)
+        plan.stage_times()
+        sync()
+        t0 = time.time()
+        g = plan.apply_adjoint(Yb, X, want_WR=True, want_eps=True)
+        sync()
+        ta = time.time() - t0
+        st = {k: round(v[0], 1) for k, v in plan.stage_times().items() if v[1] > 0}
+        plan.set_timing(False)
+        na, no, nv, nc = p.n_aux, p.n_ao, p.nv, p.nc
+        Fg = 8 * p.Nk ** 2 * (na * no * (nv ** 2 + nc ** 2) + nv ** 2 * nc ** 2 * na + na ** 2 * nv ** 2
+                              + nv ** 2 * nc ** 2 * nb)
+        adj = {"s": ta, "F_TFLOP": Fg / 1e12, "GFLOP_s": Fg / ta / 1e9, "stage_ms": st}
+        log("adjoint %.2f s" % ta)
+        del g, Yb
+    plan.close()
+    del plan
+    torch.cuda.empty_cache()
+
+    rows = list(np.linspace(0, p.Nk - 1, args.cpu_rows).astype(int)) if args.cpu_rows > 0 else []
+    cpu = orc = None
+    if not args.no_cpu_baseline and rows:
+        cpu, orc = cpu_baseline_rows(p, kq, Xh, rows, Fa)
+        log("oracle rows %s: %.1f s (%.2f GFLOP/s on %d threads)" % (rows, cpu["_t"], cpu["value"], cpu["cores"]))
+        del cpu["_t"]
+
+    # kernel part of the result: Y - D X with D the FP64 diagonal of transition energies
+    te = (d_eps[:, p.nv:][:, :, None] - d_eps[:, :p.nv][:, None, :]).reshape(-1, 1)
+    DX = te * X
+    nt = p.nc * p.nv
+
+    def rows_of(Z):
+        return np.vstack([Z[k * nt:(k + 1) * nt].cpu().numpy() for k in rows])
+
+    acc = {}
+    if orc is not None:
+        ref, DXr = orc
+        acc["kernel_rel_err_vs_oracle_rows"] = float(np.abs(rows_of(Y) - ref).max() / np.abs(ref - DXr).max())
+        acc["oracle_rows"] = [int(k) for k in rows]
+    prec_rec = {prec: {"apply_s": dt, "GFLOP_s": value}}
+    speedup = None
+    if not args.no_f64 and prec != "f64":
+        plan = make_plan("f64")
+        Y64 = torch.empty_like(X)
+        sync()
+        t0 = time.time()
+        plan.apply(X, out=Y64)
+        sync()
+        t64 = time.time() - t0
+        plan.close()
+        del plan
+        torch.cuda.empty_cache()
+        log("f64 apply %.2f s" % t64)
+        prec_rec["f64"] = {"apply_s": t64, "GFLOP_s": Fa / t64 / 1e9}
+        speedup = t64 / dt
+        acc["kernel_rel_err_vs_f64_gpu"] = ((Y - Y64).abs().max() / (Y64 - DX).abs().max()).item()
+        if orc is not None:
+            acc["f64_gpu_kernel_rel_err_vs_oracle_rows"] = float(np.abs(rows_of(Y64) - orc[0]).max() /
+                                                                 np.abs(orc[0] - orc[1]).max())
+        del Y64
+    gate = None
+    if not args.no_gate:
+        gate = spectrum_gate(prec)
+
+    rec = {
+        "metric": METRIC,
+        "value": value, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": prec, "data": "synthetic",
+        "config": {"workload": workload_text(p, config, nb, cfg.get("r_cut")) +
+                   "; one step = one apply of A to the block", "F_apply_TFLOP": Fa / 1e12,
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "accuracy": acc,
+        "precision": prec_rec,
+        "speedup_vs_f64_gpu": speedup,
+        # D(k, k-q) = D(k-q, k)^dagger: the apply forms the direct blocks of q_formed of the q_total
+        # differences; F_apply counts all of them, the executed count scales its pair terms
+        "direct_pairs": {"q_formed": q_formed, "q_total": q_total, "F_apply_executed_TFLOP": Fx / 1e12},
+        "pct_mfma_peak_apply": Fx / dt / 1e12 / PEAK_TFLOPS[prec],
+        "pct_mfma_peak_apply_F_apply": Fa / dt / 1e12 / PEAK_TFLOPS[prec],
+        "stage_ms_per_apply": stage_ms,
+        "conduction": route,
+        "adjoint": adj,
+        "spectrum_gate": gate,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+def spectrum_gate(prec):
+    """The timed precision's 300-step Haydock spectrum at the 8x8x8 workload (generator G1, seed 0, 8
+    polarisations, 2001 frequencies) against the oracle's Haydock spectrum of the explicit A stored by
+    tests/golden/make_mesh8_golden.py."""
+    import torch
+    from paper_2607_05853_amd import bse as B
+    from synth import dense_kmesh, make_problem
+    path = os.path.join(ROOT, "tests", "golden", "mesh8_ao64_spectrum.json")
+    if not os.path.exists(path):
+        return None
+    g = json.load(open(path))
+    p = make_problem(g["config"], g["seed"], g["wgen"])
+    dev = torch.device("cuda:0")
+    T = lambda a, dt=torch.complex128: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)
+    w = np.linspace(g["omega"]["lo"], g["omega"]["hi"], g["omega"]["n"])
+    t0 = time.time()
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
+    plan = B.plan_from_problem(p, Wq, prec=prec, max_nb=g["nb"])
+    del Wq
+    P = plan.velocity_start(T(p.vel), T(p.eps_ks, torch.float64), np.array(g["polarisations"]))
+    out = plan.haydock(P, g["n_steps"], w, g["eta"])
+    torch.cuda.synchronize()
+    t = time.time() - t0
+    plan.close()
+    S_or = np.array(g["S"])
+    err = float(np.abs(out["S"] - S_or).max() / np.abs(S_or).max())
+    log("spectrum gate: %s 300-step Haydock at %s in %.1f s, error vs oracle %.2e" % (prec, g["config"], t, err))
+    return {"workload": "%s (generator %s, seed %d): %d polarisations, %d Haydock steps, %d frequencies, eta=%g eV"
+                        % (g["config"], g["wgen"], g["seed"], g["nb"], g["n_steps"], g["omega"]["n"], g["eta"]),
+            "prec": prec, "s": t, "spectrum_rel_err_vs_oracle": err, "target": 1e-5, "pass": err <= 1e-5,
+            "oracle_haydock_vs_eigh": g["haydock_vs_eigh_max_rel"]}
 
 
 def _setup(config, wgen="G1"):
@@ -769,9 +1025,14 @@ def measured_traffic(kernel, config, prec):
     if vals.get("source_digest") != source_digest():
         return None
     try:
-        return {"bytes_per_launch": float(vals["hbm_bytes_per_launch"])}
+        out = {"bytes_per_launch": float(vals["hbm_bytes_per_launch"])}
     except (KeyError, ValueError):
         return None
+    try:
+        out["mfma_issue_frac"] = float(vals["mfma_issue_frac"])
+    except (KeyError, ValueError):
+        pass
+    return out
 
 
 def cpu_baseline(p, kq, nb, Fa, rows):
@@ -793,6 +1054,31 @@ def cpu_baseline(p, kq, nb, Fa, rows):
     return {"value": Fa / t_apply / 1e9, "unit": "GFLOP/s", "cores": int(cores), "kind": "oracle",
             "sample": "%d of %d k rows of one FP64 matrix-free apply (nb=%d), %.1f s, extrapolated x%d"
                       % (rows, p.Nk, nb, t, p.Nk // rows)}
+
+
+def cpu_baseline_rows(p, kq, Xh, rows, Fa):
+    """The FP64 oracle's row-at-a-time apply (every k' of a row at once, the form used for sampled rows on
+    the large meshes) on a few k rows of the same block, extrapolated to one apply; returns the baseline
+    record and (the oracle's rows, their D X) for the accuracy figures."""
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    W = O.interpolate_W_matmul(p.W_R, p.R, p.w_R, kq)
+    t0 = time.time()
+    ref = O.apply_H_rows_allpairs(p, W, Xh, rows)
+    t = time.time() - t0
+    del W
+    nt = p.nc * p.nv
+    te = O.transition_energies(p)
+    DXr = np.vstack([te[k][:, None] * Xh[k * nt:(k + 1) * nt] for k in rows])
+    t_apply = t * p.Nk / len(rows)
+    rec = {"value": Fa / t_apply / 1e9, "unit": "GFLOP/s", "cores": int(cores), "kind": "oracle",
+           "sample": "%d of %d k rows of one FP64 apply (row-at-a-time oracle form, nb=%d), %.1f s, extrapolated x%d"
+                     % (len(rows), p.Nk, Xh.shape[1], t, p.Nk // len(rows)), "_t": t}
+    return rec, (ref, DXr)
 
 
 if __name__ == "__main__":

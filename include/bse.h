@@ -8,7 +8,7 @@
  *             W_munu(R) on a small Born-von-Karman R set (Sec. III.B, workflow);
  *   outputs : the action of the TDA Hamiltonian A (Eq. (Hamiltonian) with the
  *             LRI kernel of Eq. (W_LRI)), the absorption spectrum (Eq. (abs_vel))
- *             and the lowest exciton (binding energy, Sec. IV.C).
+ *             and the lowest exciton (binding energy, Sec. IV.B.3).
  *
  * Conventions shared by every call
  *   - all arrays row-major; complex = interleaved {re, im} doubles ("c128") or
@@ -50,7 +50,7 @@ typedef enum {
                             call (tests force it with BSE_TEST_FAIL_ALLOC=n, which
                             fails the n-th device allocation made under that value) */
     BSE_EDEVICE = 4,     /* a HIP call failed                                     */
-    BSE_ENOTHERM = 5,    /* BSE_CHECK_HERMITIAN found a non-Hermitian input       */
+    BSE_ENOTHERM = 5,    /* plan creation found a non-Hermitian C^mu or Vbar      */
     BSE_INFO_BREAKDOWN = 100, /* a Haydock chain stopped early (not an error)      */
     BSE_INFO_NOT_CONVERGED = 101 /* an iterative driver hit its iteration limit    */
 } bse_status;
@@ -65,7 +65,7 @@ typedef enum {
  * and the Lanczos recurrence run in FP64. */
 typedef enum { BSE_F64 = 0, BSE_F32 = 1, BSE_BF16X3 = 2 } bse_prec;
 
-#define BSE_CHECK_HERMITIAN 1u   /* plan_create: verify C^mu and Vbar Hermitian */
+#define BSE_CHECK_HERMITIAN 1u   /* accepted; plan creation always verifies C^mu and Vbar */
 #define BSE_ALL_PAIRS 2u         /* plan_create: form every (k, k') block of the direct term */
 #define BSE_CONDUCTION_MC 4u     /* plan_create, BF16X3: form the conduction pair densities M_cc' */
 #define BSE_CONDUCTION_U 8u      /* plan_create, BF16X3: contract B_c(k) with the W step instead  */
@@ -114,11 +114,17 @@ bse_status bse_interpolate_W_adjoint(int32_t n_aux, int32_t n_R, const int32_t* 
  * psi     device c128 [Nk][nv+nc][n_ao]   row n = c^k_{s n}
  * C       device c128 [n_aux][n_ao][n_ao], each C^mu Hermitian (the k-independent
  *         form of the two-centre relation of Sec. III.A); the direct term uses
- *         conj M^mu_ij(k,k') = M^mu_ji(k',k), which holds only then
- * Vbar    device c128 [n_aux][n_aux]  (V_munu(0) of Sec. III.A)
+ *         conj M^mu_ij(k,k') = M^mu_ji(k',k) and the exchange term
+ *         M^nu_v'c'(k',k') = conj rho^nu_c'v'k', which hold only then
+ * Vbar    device c128 [n_aux][n_aux], Hermitian (V_munu(0) of Sec. III.A)
+ * Plan creation checks on the device, before anything else is allocated, that
+ * max |C^mu - C^mu^H| <= 1e-12 max |C| over all mu and max |Vbar - Vbar^H| <=
+ * 1e-12 max |Vbar|, and returns BSE_ENOTHERM (nothing created) otherwise: for
+ * other inputs the plan would apply an operator different from Eq.
+ * (Hamiltonian).  This synchronises the stream once.
  * W_q     device c128 [Nk][n_aux][n_aux], q = dense-mesh index
  * prec    arithmetic of the direct term; max_nb the largest block size later used
- * flags   BSE_CHECK_HERMITIAN (synchronises the stream), BSE_ALL_PAIRS
+ * flags   BSE_ALL_PAIRS (BSE_CHECK_HERMITIAN is accepted and changes nothing)
  * Pair symmetry: with Hermitian C^mu the direct block of Eq. (Hamiltonian)
  * obeys D(k, k-q) = D(k-q, k)^dagger as soon as W_q(-q) = conj W_q(q)
  * elementwise (true for any real W(R) interpolated with Sec. III.B).  Plan
@@ -163,7 +169,8 @@ bse_status bse_plan_create(const bse_dims* d, const double* eps_qp, const void* 
  * Other arguments as bse_plan_create.  Per pair the direct term forms the
  * one-sided products for both orders of the pair (twice the pair-density GEMM
  * work) and adds them; on BF16X3 the conduction side always forms M_cc'
- * (BSE_CONDUCTION_U is BSE_EINVAL); BSE_CHECK_HERMITIAN checks Vbar only.
+ * (BSE_CONDUCTION_U is BSE_EINVAL); the Hermiticity check covers Vbar only
+ * (real C_R guarantees the relation).
  * ------------------------------------------------------------------------- */
 bse_status bse_plan_create_2c(const bse_dims* d, const double* eps_qp, const void* psi, int32_t n_RC,
                               const int32_t* RC, const double* C_R, const double* k_frac,
@@ -230,6 +237,20 @@ bse_status bse_velocity_start(const bse_plan* plan, const void* vel, const doubl
                               int32_t nb, const double* pol, void* P, void* hip_stream);
 
 /* ---------------------------------------------------------------------------
+ * Start vector of a momentum-resolved spectrum (finite exciton momentum Q, the
+ * extension of the conclusion; matrix element of the long-wavelength appendix
+ * at finite q):
+ *   P[I] = <c k+Q| e^{iQ.r} |v k> = <u_c^{k+Q}|u_v^k> = sum_s conj(psi[k][nv+c][s]) psi[k][v][s]
+ * for orthonormal NAO Bloch sums with each orbital's e^{iQ.(r-R)} taken at its
+ * centre.  psi is the band array of the plan (device c128 [Nk][nv+nc][n_ao],
+ * valence rows at k, conduction rows at k + Q); P device c128 [N] (one column).
+ * Haydock on a plan built at momentum Q from this vector gives
+ * S(Q, w) = -(1/(pi N_k)) Im <P|(w + i eta - A_Q)^-1|P>; as Q -> 0, P / |Q|
+ * tends to the velocity-form vector along Q.
+ * ------------------------------------------------------------------------- */
+bse_status bse_density_start(const bse_plan* plan, const void* psi, void* P, void* hip_stream);
+
+/* ---------------------------------------------------------------------------
  * nb independent Haydock chains (Lanczos with full re-orthogonalisation by
  * classical Gram-Schmidt done twice) from the start vectors P, in FP64:
  *   b_0 = |p|, q_1 = p / b_0;  w = A q_j;  a_j = Re q_j^H w;
@@ -293,7 +314,7 @@ bse_status bse_haydock_vjp(bse_plan* plan, const void* basis, const double* a, c
 
 /* ---------------------------------------------------------------------------
  * Lowest exciton by block LOBPCG (Knyazev 2001) on the FP64 apply, with
- * Rayleigh-Ritz in FP64 on the host:  Omega_1 and its eigenvector (Sec. IV.C:
+ * Rayleigh-Ritz in FP64 on the host:  Omega_1 and its eigenvector (Sec. IV.B.3:
  * E_B = min_k (E_c1k - E_vtop k) - Omega_1).
  * n_block >= 1 (block size), max_iter, tol (relative residual |r| <= tol |Omega|).
  * X0 device c128 [N][n_block] start block (NULL: deterministic pseudo-random);

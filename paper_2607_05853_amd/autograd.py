@@ -62,8 +62,16 @@ class _Lowest(torch.autograd.Function):
         return gW, ge, None, None, None, None
 
 
-def lowest_exciton_energy(plan, W_R, eps, n_block=4, tol=1e-10, max_iter=300):
-    """Omega_1 (the lowest TDA eigenvalue) with its Hellmann-Feynman gradient."""
+# LOBPCG residual tolerance per plan precision: the residual of an FP32 or BF16x3 operator cannot fall
+# below its rounding (about 4e-8 of |A| for BF16x3), so those plans converge to 1e-6
+LOBPCG_TOL = {"f64": 1e-10, "f32": 1e-6, "bf16x3": 1e-6}
+
+
+def lowest_exciton_energy(plan, W_R, eps, n_block=4, tol=None, max_iter=300):
+    """Omega_1 (the lowest TDA eigenvalue) with its Hellmann-Feynman gradient; tol defaults to the
+    residual the plan's precision can reach."""
+    if tol is None:
+        tol = LOBPCG_TOL[plan.prec]
     return _Lowest.apply(W_R, eps, plan, n_block, tol, max_iter)
 
 

@@ -57,6 +57,7 @@ _SIGS = {
     "bse_apply": [_vp, _vp, _vp, _i32, _vp],
     "bse_apply_adjoint": [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp],
     "bse_velocity_start": [_vp, _vp, _vp, _i32, _vp, _vp, _vp],
+    "bse_density_start": [_vp, _vp, _vp, _vp],
     "bse_haydock_spectrum": [_vp, _vp, _i32, _i32, _vp, _i32, ctypes.c_double, _vp, _vp, _vp, _vp, _vp, _vp],
     "bse_lowest_excitons": [_vp, _i32, _i32, ctypes.c_double, _vp, _vp, _vp, _vp, _vp],
     "bse_apply_coupling": [_vp, _vp, _vp, _i32, _vp],
@@ -352,6 +353,15 @@ class Plan:
                                      _dev(eps_ks, torch.float64, (self.Nk, self.nv + self.nc), "eps_ks"), nb,
                                      pol.ctypes.data, _dev(P, torch.complex128, None, "P"), _stream(self.device))
         _check("bse_velocity_start", s)
+        return P
+
+    def density_start(self, psi):
+        """<c k+Q| e^{iQ.r} |v k> for the plan's band arrays (conduction bands at k + Q): [N][1]."""
+        P = torch.empty((self.N, 1), dtype=torch.complex128, device=self.device)
+        s = lib().bse_density_start(self._ptr, _dev(psi, torch.complex128, (self.Nk, self.nv + self.nc, self.n_ao),
+                                                    "psi"), _dev(P, torch.complex128, None, "P"),
+                                    _stream(self.device))
+        _check("bse_density_start", s)
         return P
 
     def haydock(self, P, n_steps, omega, eta, keep_basis=False):

@@ -163,6 +163,28 @@ __global__ void rho_kernel(int kcount, int k0, int nv, int nc, int nbnd, int n_a
   }
 }
 
+// P[(k c v)] = sum_s conj(psi[k][nv+c][s]) psi[k][v][s]: <u_c^{k+Q}|u_v^k> with the conduction rows of psi
+// at k + Q, one thread per transition
+__global__ void density_kernel(long long N, int nv, int nc, int n_ao, const double* __restrict__ psi,
+                               double* __restrict__ P) {
+  const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= N) return;
+  const int v = (int)(I % nv);
+  const long long kc = I / nv;
+  const int c = (int)(kc % nc);
+  const long long k = kc / nc;
+  const double* pc = psi + 2 * ((k * (nv + nc) + nv + c) * n_ao);
+  const double* pv = psi + 2 * ((k * (nv + nc) + v) * n_ao);
+  double sr = 0, si = 0;
+  for (int s = 0; s < n_ao; ++s) {
+    const double ar = pc[2 * s], ai = pc[2 * s + 1], br = pv[2 * s], bi = pv[2 * s + 1];
+    sr += ar * br + ai * bi;
+    si += ar * bi - ai * br;
+  }
+  P[2 * I] = sr;
+  P[2 * I + 1] = si;
+}
+
 __global__ void velocity_kernel(long long N, int nv, int nc, int nb, long long Nk, const double* __restrict__ vel,
                                 const double* __restrict__ eks, const double* __restrict__ pol,
                                 double* __restrict__ P) {
@@ -279,30 +301,64 @@ bool prefer_mc(const bse_dims& d) {
   return t_mc < t_u;
 }
 
+// max |A_ij - conj A_ji| and max |A_ij| (per component) over nmat complex n x n matrices, as the bit
+// patterns of the non-negative doubles
+__global__ void herm_check(const double* __restrict__ A, long long nmat, int n, unsigned long long* __restrict__ out) {
+  double dmax = 0.0, amax = 0.0;
+  const long long per = (long long)n * n;
+  const long long tot = per * nmat;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (long long)gridDim.x * blockDim.x) {
+    const long long m = i / per, e = i % per;
+    const long long et = (e % n) * n + e / n;
+    const double2 a = reinterpret_cast<const double2*>(A)[i];
+    const double2 t = reinterpret_cast<const double2*>(A)[m * per + et];
+    dmax = fmax(dmax, fmax(fabs(t.x - a.x), fabs(t.y + a.y)));
+    amax = fmax(amax, fmax(fabs(a.x), fabs(a.y)));
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    dmax = fmax(dmax, __shfl_down(dmax, o));
+    amax = fmax(amax, __shfl_down(amax, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(&out[0], (unsigned long long)__double_as_longlong(dmax));
+    atomicMax(&out[1], (unsigned long long)__double_as_longlong(amax));
+  }
+}
+
+// Every C^mu (k-independent coefficients; C == nullptr skips them) and Vbar Hermitian to 1e-12 of their
+// largest element, checked on the device; BSE_ENOTHERM otherwise.  The direct term reads
+// M^mu_v'v(k',k) as conj M^mu_vv'(k,k') and the exchange term M^nu_v'c'(k',k') as conj rho, both of which
+// hold only for Hermitian C^mu, so a plan on other coefficients would apply a different operator.
 bse_status check_hermitian(const void* C, const void* Vbar, const bse_dims* d, hipStream_t st) {
-  const size_t na = d->n_aux, no = d->n_ao;
-  std::vector<double> hc(C ? 2 * na * no * no : 0), hv(2 * na * na);
-  if (C) BSE_HIP(hipMemcpyAsync(hc.data(), C, hc.size() * 8, hipMemcpyDeviceToHost, st));
-  BSE_HIP(hipMemcpyAsync(hv.data(), Vbar, hv.size() * 8, hipMemcpyDeviceToHost, st));
-  BSE_HIP(hipStreamSynchronize(st));
-  auto herm = [](const double* m, size_t n) {
-    double mx = 0, dev = 0;
-    for (size_t i = 0; i < n; ++i)
-      for (size_t j = 0; j < n; ++j) {
-        const double ar = m[2 * (i * n + j)], ai = m[2 * (i * n + j) + 1];
-        const double br = m[2 * (j * n + i)], bi = -m[2 * (j * n + i) + 1];
-        mx = std::fmax(mx, std::hypot(ar, ai));
-        dev = std::fmax(dev, std::hypot(ar - br, ai - bi));
-      }
-    return dev <= 1e-12 * std::fmax(mx, 1e-300);
-  };
-  for (size_t m = 0; C && m < na; ++m)
-    if (!herm(hc.data() + 2 * m * no * no, no)) {
-      set_error("C^mu is not Hermitian for mu = " + std::to_string(m));
-      return BSE_ENOTHERM;
-    }
-  if (!herm(hv.data(), na)) {
-    set_error("Vbar is not Hermitian");
+  unsigned long long* dout = nullptr;
+  BSE_TRY(dmalloc((void**)&dout, 32));
+  unsigned long long hout[4] = {0, 0, 0, 0};
+  bse_status s = BSE_OK;
+  if (hipMemsetAsync(dout, 0, 32, st) != hipSuccess) s = BSE_EDEVICE;
+  if (s == BSE_OK && C)
+    hipLaunchKernelGGL(herm_check, dim3(1024), dim3(256), 0, st, (const double*)C, (long long)d->n_aux, d->n_ao,
+                       dout);
+  if (s == BSE_OK)
+    hipLaunchKernelGGL(herm_check, dim3(256), dim3(256), 0, st, (const double*)Vbar, 1LL, d->n_aux, dout + 2);
+  if (s == BSE_OK && (hipGetLastError() != hipSuccess ||
+                      hipMemcpyAsync(hout, dout, 32, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                      hipStreamSynchronize(st) != hipSuccess))
+    s = BSE_EDEVICE;
+  dfree(dout);
+  if (s != BSE_OK) {
+    set_error("Hermiticity check of C and Vbar failed on the device");
+    return s;
+  }
+  double v[4];
+  std::memcpy(v, hout, sizeof(v));
+  if (C && !(v[0] <= 1e-12 * v[1])) {
+    set_error("C^mu is not Hermitian: max |C - C^H| = " + std::to_string(v[0]) + " against max |C| = " +
+              std::to_string(v[1]));
+    return BSE_ENOTHERM;
+  }
+  if (!(v[2] <= 1e-12 * v[3])) {
+    set_error("Vbar is not Hermitian: max |V - V^H| = " + std::to_string(v[2]) + " against max |V| = " +
+              std::to_string(v[3]));
     return BSE_ENOTHERM;
   }
   return BSE_OK;
@@ -856,7 +912,7 @@ bse_status plan_create(const char* fn, const bse_dims* d, const double* eps_qp, 
       return BSE_ESHAPE;
     }
   }
-  if (flags & BSE_CHECK_HERMITIAN) BSE_TRY(check_hermitian(tc ? nullptr : C, Vbar, d, S(hip_stream)));
+  BSE_TRY(check_hermitian(tc ? nullptr : C, Vbar, d, S(hip_stream)));
   bse_plan* h = new (std::nothrow) bse_plan();
   if (!h) {
     set_error(f + ": host allocation failed");
@@ -1036,6 +1092,24 @@ bse_status bse_apply_adjoint(bse_plan* plan, const void* Ybar, const void* X, in
     const int nR = (int)p->wR.size();
     const std::vector<double> q = plan_kfrac(p);
     BSE_TRY(interp_adjoint(na, nR, p->R.data(), p->wR.data(), p->Nk, q.data(), gq, (double*)g_WR, st));
+  }
+  return BSE_OK;
+}
+
+bse_status bse_density_start(const bse_plan* plan, const void* psi, void* P, void* hip_stream) {
+  set_error("");
+  if (!plan || bad_ptr(psi) || bad_ptr(P)) {
+    set_error("bse_density_start: invalid argument");
+    return BSE_EINVAL;
+  }
+  const Plan* p = &plan->impl;
+  hipStream_t st = S(hip_stream);
+  hipLaunchKernelGGL(density_kernel, dim3((unsigned)((p->N + 255) / 256)), dim3(256), 0, st, p->N, p->d.nv,
+                     p->d.nc, p->d.n_ao, (const double*)psi, (double*)P);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error(std::string("bse_density_start: ") + hipGetErrorString(e));
+    return BSE_EDEVICE;
   }
   return BSE_OK;
 }

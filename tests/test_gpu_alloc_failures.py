@@ -9,6 +9,7 @@ import torch
 
 import oracle as O
 from synth import dense_kmesh, make_problem, polarisations, random_block
+from tolerances import KERNEL_TOL
 
 pytestmark = pytest.mark.gpu
 
@@ -94,7 +95,7 @@ def test_plan_creation_and_coupling_workspace(B, monkeypatch, two_centre):
 
     def check(Y):
         errs.append(rel(H_(Y), ref))
-        assert errs[-1] < 5e-4
+        assert errs[-1] < KERNEL_TOL["bf16x3"]   # B has no diagonal
 
     # the coupling workspace: 8 buffers, 12 with the one-sided two-centre products
     nfail = lazy_walk(B, monkeypatch, make, lambda pl: pl.apply_coupling(T(X)), check)

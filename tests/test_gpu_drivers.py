@@ -250,3 +250,20 @@ def test_lobpcg_mesh8_bf16x3_matches_f64(B):
         print("[lobpcg mesh8 %s] iterations %d, omega %s" % (prec, it, om[prec]), flush=True)
         plan.close()
     assert np.abs(om["bf16x3"] - om["f64"]).max() < 1e-6 * om["f64"][0]
+
+
+def test_bf16x3_autograd_lowest_energy_vs_oracle(B):
+    # the differentiable lowest exciton energy on a BF16x3 plan end to end: LOBPCG to the tolerance the plan's
+    # precision can reach (its default), Hellmann-Feynman backward through the BF16x3 adjoint
+    from paper_2607_05853_amd import autograd as AG
+    p = make_problem(DMA_LOB, 1, "G2")
+    W_R = T(p.W_R).requires_grad_(True)
+    eps = T(p.eps_qp, torch.float64).requires_grad_(True)
+    plan, _ = _plan(B, p, W_R.detach(), eps.detach(), prec="bf16x3", nb=4)
+    om1 = AG.lowest_exciton_energy(plan, W_R, eps, n_block=4)
+    om1.backward()
+    Om_ref, ge_ref, gq_ref = O.grad_lowest(p, OW(p))
+    gr_ref = O.grad_WR_from_Wq(gq_ref, p.R, p.w_R, dense_kmesh(p.nk))
+    e_om, e_e, e_w = abs(om1.item() - Om_ref) / abs(Om_ref), rel(H_(eps.grad), ge_ref), rel(H_(W_R.grad), gr_ref)
+    print("[bf16x3 autograd Omega1] Omega %.1e eps %.1e W_R %.1e" % (e_om, e_e, e_w), flush=True)
+    assert e_om < 1e-6 and e_e < 1e-4 and e_w < 1e-4

@@ -4,9 +4,9 @@ apply and adjoint.
 
 The explicit H (262144^2) is out of reach, so the oracle evaluates sampled outputs one at a time from
 their definition (its row-at-a-time forms, pinned against the block forms on small meshes): two k rows
-of H X and the W(q) gradient at one pair {q, -q}; the energy gradient is checked everywhere.  Tolerance as for
-every BF16x3 contraction: 5e-4 relative to the largest reference element of the sample.  The module
-takes a few minutes, most of it the oracle on the host cores."""
+of H X and the W(q) gradient at one pair {q, -q}; the energy gradient is checked everywhere.  Bounds as for
+every BF16x3 result (tests/tolerances.py): the apply on its kernel part, the gradient relative to its
+largest element.  The module takes a few minutes, most of it the oracle on the host cores."""
 import time
 
 import numpy as np
@@ -15,6 +15,7 @@ import torch
 
 import oracle as O
 from synth import dense_kmesh, make_problem, random_block
+from tolerances import GRAD_TOL, KERNEL_TOL, diag_times, kernel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -63,9 +64,10 @@ def test_largest_apply_sampled_rows(big):
     del Y
     t0 = time.time()
     ref = O.apply_H_rows_allpairs(p, big["W"], X, ROWS)
-    err = rel(got, ref)
-    print("[largest] oracle rows %.1f s, rel err %.2e" % (time.time() - t0, err), flush=True)
-    assert err < 5e-4
+    err = kernel_err(got, ref, diag_times(p, X, ROWS))
+    print("[largest] oracle rows %.1f s, kernel-part err %.2e (of max |Y|: %.2e)" %
+          (time.time() - t0, err, rel(got, ref)), flush=True)
+    assert err < KERNEL_TOL["bf16x3"]
 
 
 def test_largest_adjoint_sampled_q(big):
@@ -87,4 +89,4 @@ def test_largest_adjoint_sampled_q(big):
     ref = O.grad_Wq_at(p, Yb, X, QS)
     err = rel(gq, ref)
     print("[largest] oracle g_W(q) %.1f s, rel err %.2e" % (time.time() - t0, err), flush=True)
-    assert err < 5e-4
+    assert err < GRAD_TOL["bf16x3"]
