@@ -96,6 +96,22 @@ bse_status bse_interpolate_W(int32_t n_aux, int32_t n_R, const void* W_R,
                              int32_t n_q, const double* q_frac,
                              void* W_q, bse_prec out_prec, void* hip_stream);
 
+/* The same interpolation for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): arguments, results and errors as bse_interpolate_W, but the
+ * workspace (the q, R and weight tables and the [n_q][n_R] phase table) lives
+ * in a static device array of 16 MiB per GPU, held until the process ends,
+ * and no device memory is allocated or freed.  Sizes whose workspace exceeds
+ * it (about n_q * n_R > 10^6: 16 bytes per phase plus 36 per q and R) return
+ * BSE_ESHAPE before any HIP call.  Every call on a GPU shares that GPU's array:
+ * calls that overlap on one GPU (other streams or host threads) race; calls
+ * on one stream are ordered.  The host tables are copied with
+ * hipMemcpyAsync from the caller's host memory. */
+bse_status bse_interpolate_W_noalloc(int32_t n_aux, int32_t n_R, const void* W_R,
+                                     const int32_t* R, const double* w_R,
+                                     int32_t n_q, const double* q_frac,
+                                     void* W_q, bse_prec out_prec, void* hip_stream);
+
 /* Conjugate transpose of the map above (the adjoint used for gradients):
  *     g_WR[R] = w_R sum_q exp(-2 pi i q.R) g_Wq[q]
  * With q the coarse mesh and w_R = 1/N_coarse this is also the coarse -> R

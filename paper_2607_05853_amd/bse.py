@@ -42,6 +42,7 @@ _vp, _i32, _f64p, _i32p = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes
 _SIGS = {
     "bse_interpolate_W": [_i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, ctypes.c_int, _vp],
     "bse_interpolate_W_adjoint": [_i32, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _vp],
+    "bse_interpolate_W_noalloc": [_i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, ctypes.c_int, _vp],
     "bse_plan_create": [ctypes.POINTER(_Dims), _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _i32, ctypes.c_uint32, _vp,
                         ctypes.POINTER(_vp)],
     "bse_plan_create_2c": [ctypes.POINTER(_Dims), _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _i32,
@@ -142,6 +143,22 @@ def interpolate_W(W_R, R, w_R, q_frac, out_prec="f64"):
                                 R.ctypes.data, w_R.ctypes.data, len(q), q.ctypes.data,
                                 _dev(out, out.dtype, None, "W_q"), PREC[out_prec], _stream(W_R.device))
     _check("bse_interpolate_W", s)
+    return out
+
+
+def interpolate_W_noalloc(W_R, R, w_R, q_frac, out, out_prec="f64"):
+    """interpolate_W into a caller-provided W_q, with the library's static device workspace (no device
+    allocation by the library)."""
+    n_R, na, _ = W_R.shape
+    R = _host(R, np.int32, (n_R, 3))
+    w_R = _host(w_R, np.float64, (n_R,))
+    q = _host(q_frac, np.float64).reshape(-1, 3)
+    dt = torch.complex128 if out_prec == "f64" else torch.complex64
+    s = lib().bse_interpolate_W_noalloc(na, n_R, _dev(W_R, torch.complex128, (n_R, na, na), "W_R"),
+                                        R.ctypes.data, w_R.ctypes.data, len(q), q.ctypes.data,
+                                        _dev(out, dt, (len(q), na, na), "W_q"), PREC[out_prec],
+                                        _stream(W_R.device))
+    _check("bse_interpolate_W_noalloc", s)
     return out
 
 

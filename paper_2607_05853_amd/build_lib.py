@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libbse.so")
 SOURCES = ["api.hip", "gemm.hip", "interp.hip", "apply.hip", "direct_b3.hip", "lanczos.hip", "lobpcg.hip",
-           "util.hip", "full.hip"]
+           "util.hip", "full.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

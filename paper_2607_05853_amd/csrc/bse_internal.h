@@ -230,9 +230,13 @@ bse_status adjoint_eps(Plan* p, const double* Ybar, const double* X, int nb, dou
 // the dense-mesh k list of a plan (fractional coordinates, host)
 std::vector<double> plan_kfrac(const Plan* p);
 
-// interpolation (interp.hip)
+// interpolation (interp.hip); interp_forward allocates its workspace on the stream, interp_forward_ws takes
+// one of at least interp_scratch_bytes(n_q, n_R) bytes (256-byte aligned)
+size_t interp_scratch_bytes(int n_q, int n_R);
 bse_status interp_forward(int n_aux, int n_R, const double* W_R, const int32_t* R, const double* w_R,
                           int n_q, const double* q, void* W_q, bool out_f64, hipStream_t st);
+bse_status interp_forward_ws(int n_aux, int n_R, const double* W_R, const int32_t* R, const double* w_R,
+                             int n_q, const double* q, void* W_q, bool out_f64, void* ws, hipStream_t st);
 bse_status interp_adjoint(int n_aux, int n_R, const int32_t* R, const double* w_R, int n_q,
                           const double* q, const double* g_Wq, double* g_WR, hipStream_t st);
 

@@ -22,27 +22,33 @@ __global__ void phase_kernel(int n_q, int n_R, const double* __restrict__ q, con
   ph[2 * t + 1] = w[ir] * s;
 }
 
-struct Tmp {
-  double* q = nullptr;
-  int* R = nullptr;
-  double* w = nullptr;
-  double* ph = nullptr;
-  hipStream_t st = nullptr;
-  ~Tmp() {
-    if (q) (void)hipFreeAsync(q, st);
-    if (R) (void)hipFreeAsync(R, st);
-    if (w) (void)hipFreeAsync(w, st);
-    if (ph) (void)hipFreeAsync(ph, st);
-  }
+// Workspace of one interpolation: q [3 n_q] f64, R [3 n_R] int32, w [n_R] f64 and the phase table
+// [n_q][n_R] c128, each at a 256-byte aligned offset.
+struct Ws {
+  double* q;
+  int* R;
+  double* w;
+  double* ph;
 };
 
-bse_status make_phases(Tmp& t, int n_R, const int32_t* R, const double* w_R, int n_q, const double* q,
+size_t up256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+Ws carve(void* base, int n_q, int n_R) {
+  char* b = static_cast<char*>(base);
+  Ws ws;
+  ws.q = reinterpret_cast<double*>(b);
+  b += up256(sizeof(double) * 3 * (size_t)n_q);
+  ws.R = reinterpret_cast<int*>(b);
+  b += up256(sizeof(int) * 3 * (size_t)n_R);
+  ws.w = reinterpret_cast<double*>(b);
+  b += up256(sizeof(double) * (size_t)n_R);
+  ws.ph = reinterpret_cast<double*>(b);
+  return ws;
+}
+
+// the host tables go to the workspace (stream-ordered copies) and the phase kernel fills the table
+bse_status make_phases(const Ws& t, int n_R, const int32_t* R, const double* w_R, int n_q, const double* q,
                        hipStream_t st) {
-  t.st = st;
-  BSE_HIP(hipMallocAsync((void**)&t.q, sizeof(double) * 3 * n_q, st));
-  BSE_HIP(hipMallocAsync((void**)&t.R, sizeof(int) * 3 * n_R, st));
-  BSE_HIP(hipMallocAsync((void**)&t.w, sizeof(double) * n_R, st));
-  BSE_HIP(hipMallocAsync((void**)&t.ph, sizeof(double) * 2 * (size_t)n_q * n_R, st));
   BSE_HIP(hipMemcpyAsync(t.q, q, sizeof(double) * 3 * n_q, hipMemcpyHostToDevice, st));
   BSE_HIP(hipMemcpyAsync(t.R, R, sizeof(int) * 3 * n_R, hipMemcpyHostToDevice, st));
   BSE_HIP(hipMemcpyAsync(t.w, w_R, sizeof(double) * n_R, hipMemcpyHostToDevice, st));
@@ -53,11 +59,25 @@ bse_status make_phases(Tmp& t, int n_R, const int32_t* R, const double* w_R, int
   return BSE_OK;
 }
 
+// a workspace allocated on the stream and freed stream-ordered after the work that uses it
+struct StreamBuf {
+  void* p = nullptr;
+  hipStream_t st = nullptr;
+  ~StreamBuf() {
+    if (p) (void)hipFreeAsync(p, st);
+  }
+};
+
 }  // namespace
 
-bse_status interp_forward(int n_aux, int n_R, const double* W_R, const int32_t* R, const double* w_R,
-                          int n_q, const double* q, void* W_q, bool out_f64, hipStream_t st) {
-  Tmp t;
+size_t interp_scratch_bytes(int n_q, int n_R) {
+  return up256(sizeof(double) * 3 * (size_t)n_q) + up256(sizeof(int) * 3 * (size_t)n_R) +
+         up256(sizeof(double) * (size_t)n_R) + up256(sizeof(double) * 2 * (size_t)n_q * n_R);
+}
+
+bse_status interp_forward_ws(int n_aux, int n_R, const double* W_R, const int32_t* R, const double* w_R,
+                             int n_q, const double* q, void* W_q, bool out_f64, void* ws, hipStream_t st) {
+  const Ws t = carve(ws, n_q, n_R);
   BSE_TRY(make_phases(t, n_R, R, w_R, n_q, q, st));
   const long long a2 = (long long)n_aux * n_aux;
   GemmArgs g;
@@ -73,16 +93,23 @@ bse_status interp_forward(int n_aux, int n_R, const double* W_R, const int32_t* 
   g.C = W_q;
   g.c_si = a2;
   g.c_sj = 1;
-  bse_status s = cgemm(g, AR_F64, true, out_f64, st);
-  if (s == BSE_OK) {
-    // keep the temporaries alive until the GEMM has consumed them: freeing is stream-ordered
-  }
-  return s;
+  return cgemm(g, AR_F64, true, out_f64, st);
+}
+
+bse_status interp_forward(int n_aux, int n_R, const double* W_R, const int32_t* R, const double* w_R,
+                          int n_q, const double* q, void* W_q, bool out_f64, hipStream_t st) {
+  StreamBuf buf;
+  buf.st = st;
+  BSE_HIP(hipMallocAsync(&buf.p, interp_scratch_bytes(n_q, n_R), st));
+  return interp_forward_ws(n_aux, n_R, W_R, R, w_R, n_q, q, W_q, out_f64, buf.p, st);
 }
 
 bse_status interp_adjoint(int n_aux, int n_R, const int32_t* R, const double* w_R, int n_q,
                           const double* q, const double* g_Wq, double* g_WR, hipStream_t st) {
-  Tmp t;
+  StreamBuf buf;
+  buf.st = st;
+  BSE_HIP(hipMallocAsync(&buf.p, interp_scratch_bytes(n_q, n_R), st));
+  const Ws t = carve(buf.p, n_q, n_R);
   BSE_TRY(make_phases(t, n_R, R, w_R, n_q, q, st));
   const long long a2 = (long long)n_aux * n_aux;
   GemmArgs g;

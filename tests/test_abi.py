@@ -48,6 +48,16 @@ def test_interpolate_validation_before_hip(L):
     assert L.bse_interpolate_W(4, 1, dummy, R.ctypes.data, w.ctypes.data, 1, q.ctypes.data, dummy, 7, None) == 1
     assert b"precision" in L.bse_last_error()
     assert L.bse_interpolate_W_adjoint(4, 1, None, w.ctypes.data, 1, q.ctypes.data, dummy, dummy, None) == 1
+    # the allocation-free variant: same validation, and sizes beyond its static workspace are refused
+    # (BSE_ESHAPE) before any HIP call
+    assert L.bse_interpolate_W_noalloc(0, 1, dummy, R.ctypes.data, w.ctypes.data, 1, q.ctypes.data, dummy, 0,
+                                       None) == 1
+    assert L.bse_interpolate_W_noalloc(4, 1, None, R.ctypes.data, w.ctypes.data, 1, q.ctypes.data, dummy, 0,
+                                       None) == 1
+    Rb, wb, qb = np.zeros((1000, 3), np.int32), np.ones(1000), np.zeros((2000, 3))
+    assert L.bse_interpolate_W_noalloc(4, 1000, dummy, Rb.ctypes.data, wb.ctypes.data, 2000, qb.ctypes.data,
+                                       dummy, 0, None) == 2
+    assert b"static scratch" in L.bse_last_error()
 
 
 def _dims(**kw):
