@@ -152,6 +152,125 @@ __global__ __launch_bounds__(256) void direct_tx_kernel(int Nk, int nq, int q0, 
   }
 }
 
+// The same sums on the matrix cores for c64 T (FP32 and BF16x3 plans).  Per staged (q, pass) item the block
+// forms the complex product Y_k[(c v)][b] = sum_(c'v') T'[(c v)][(c' v')] X[(c' v')][b] as one real product
+// of the interleaved T' ([nt][2 nt]) and X expanded to [2 nt][2 nb] (row 2j: [Re, Im], row 2j + 1: [-Im, Re]
+// per column pair) on FP32 16x16x4 MFMA, the X slice rounded to FP32 as it is staged.  Each item's product
+// is added to FP64 accumulators, so the sum over the items of a chunk stays FP64.  T' is T[(c' c)][(v' v)]
+// on the first pass and conj T[(c c')][(v v')] of the partner block on the second.  The block's output
+// tiles (16 rows x 16 real columns) go round-robin to the four waves, at most TX_MAXT each.  FP64 plans
+// keep the vector-unit kernel above.
+constexpr int TX_MAXT = 8;
+
+__global__ __launch_bounds__(256) void direct_tx_mfma(int Nk, int nq, int q0, int nv, int nc, int nb, int qlen,
+                                                      const int* __restrict__ kqp, const int* __restrict__ kqm,
+                                                      int nself, int x16, const float* __restrict__ T,
+                                                      const double* __restrict__ X, double* __restrict__ part) {
+  using TT = float;
+  extern __shared__ __attribute__((aligned(16))) unsigned char sbytes[];
+  const int k = blockIdx.x, chunk = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nt = nc * nv, nt2 = nt * nt, nv2 = nv * nv;
+  const int tbytes = nt2 * 2 * (int)sizeof(TT);
+  const int tstride = (tbytes + 15) & ~15;
+  const bool t16 = (tbytes & 15) == 0;
+  TT* Ts = reinterpret_cast<TT*>(sbytes);
+  TT* Xs = reinterpret_cast<TT*>(sbytes + tstride);  // [nt][nb] complex
+  const int CT = (2 * nb + 15) / 16, ntile = ((nt + 15) / 16) * CT;
+  const int ksteps = (2 * nt + 3) / 4;
+  const int l4 = lane >> 4, l16 = lane & 15;
+  double acc[TX_MAXT][4];
+#pragma unroll
+  for (int s = 0; s < TX_MAXT; ++s)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[s][q] = 0.0;
+  const int qa = chunk * qlen, qe = min(nq, qa + qlen);
+  for (int qi = qa; qi < qe; ++qi) {
+    const int j = q0 + qi;
+    for (int pass = 0; pass < (j >= nself ? 2 : 1); ++pass) {
+      const int kb = pass == 0 ? k : kqm[(long long)k * Nk + j];  // block row of the stored T
+      const int kx = pass == 0 ? kqp[(long long)k * Nk + j] : kb;  // k-point of the X slice
+      const TT* Tg = T + 2 * ((long long)qi * Nk + kb) * nt2;
+      const double* Xg = X + 2 * (long long)kx * nt * nb;
+      __syncthreads();  // the previous item's reads are done
+      if (t16) {
+        for (int i = threadIdx.x; i < tbytes / 16; i += blockDim.x)
+          reinterpret_cast<uint4*>(Ts)[i] = reinterpret_cast<const uint4*>(Tg)[i];
+      } else {
+        for (int i = threadIdx.x; i < tbytes / 8; i += blockDim.x)
+          reinterpret_cast<uint2*>(Ts)[i] = reinterpret_cast<const uint2*>(Tg)[i];
+      }
+      if (x16) {
+        for (int i = threadIdx.x; i < nt * nb; i += blockDim.x) {
+          const double2 v = reinterpret_cast<const double2*>(Xg)[i];
+          Xs[2 * i] = (TT)v.x;
+          Xs[2 * i + 1] = (TT)v.y;
+        }
+      } else {
+        for (int i = threadIdx.x; i < 2 * nt * nb; i += blockDim.x) Xs[i] = (TT)Xg[i];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < TX_MAXT; ++s) {
+        const int t = wave + 4 * s;
+        if (t >= ntile) break;
+        const int rt = t / CT, ct = t % CT;
+        // A row of this lane: i = (c v); its part of the T' index
+        const int i = rt * 16 + l16;
+        const bool row_ok = i < nt;
+        const int c = row_ok ? i / nv : 0, v = row_ok ? i % nv : 0;
+        const int arow = pass == 0 ? c * nv2 + v : c * nc * nv2 + v * nv;
+        // B column of this lane: real column cc = 2 b + sb; the lane's K parity r = l4 & 1 is fixed
+        const int cc = ct * 16 + l16;
+        const bool col_ok = cc < 2 * nb;
+        const int b = cc >> 1, sb = cc & 1, r = l4 & 1;
+        const int comp = (r != sb) ? 1 : 0;
+        const TT bsg = (r == 1 && sb == 0) ? TT(-1) : TT(1);
+        const TT asg = (pass == 1 && r == 1) ? TT(-1) : TT(1);  // conj of the partner block
+        // complex column j = 2 ks + (l4 >> 1) of T' as (c', v'), advanced by 2 per step
+        int jc = l4 >> 1;
+        int cp = jc / nv, vp = jc % nv;
+        f4v a4 = {0, 0, 0, 0};
+        for (int ks = 0; ks < ksteps; ++ks) {
+          TT av = TT(0), bv = TT(0);
+          if (jc < nt) {
+            if (row_ok) {
+              const int idx = arow + (pass == 0 ? cp * nc * nv2 + vp * nv : cp * nv2 + vp);
+              av = asg * Ts[2 * idx + r];
+            }
+            if (col_ok) bv = bsg * Xs[2 * (jc * nb + b) + comp];
+          }
+          a4 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, a4, 0, 0, 0);
+          jc += 2;
+          vp += 2;
+          while (vp >= nv) {
+            vp -= nv;
+            ++cp;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[s][q] += (double)a4[q];
+      }
+    }
+  }
+  // register q of a lane holds real column l16 of row 4 l4 + q
+  const int nout = nt * nb;
+#pragma unroll
+  for (int s = 0; s < TX_MAXT; ++s) {
+    const int t = wave + 4 * s;
+    if (t >= ntile) break;
+    const int rt = t / CT, ct = t % CT;
+    const int cc = ct * 16 + l16;
+    if (cc >= 2 * nb) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = rt * 16 + 4 * l4 + q;
+      if (i >= nt) continue;
+      part[2 * (((long long)chunk * Nk + k) * nout + (long long)i * nb + (cc >> 1)) + (cc & 1)] = acc[s][q];
+    }
+  }
+}
+
 // Y[i] += scale * sum_chunk part[chunk][i] (complex, n = N * nb), chunks added in order
 __global__ void tx_reduce(long long n, int nchunks, double scale, const double* __restrict__ part,
                           double* __restrict__ Y) {
@@ -168,6 +287,9 @@ __global__ void tx_reduce(long long n, int nchunks, double scale, const double* 
 
 template <typename TT>
 bse_status tx_set_attributes() {
+  if (sizeof(TT) == 4)
+    BSE_HIP(hipFuncSetAttribute((const void*)direct_tx_mfma, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                160 * 1024));
   BSE_HIP(hipFuncSetAttribute((const void*)direct_tx_kernel<TT, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               160 * 1024));
   BSE_HIP(hipFuncSetAttribute((const void*)direct_tx_kernel<TT, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -946,17 +1068,27 @@ bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t
         BSE_TRY(tx_set_attributes<float>());
         attr_set = true;
       }
-      // q chunks spread the pairs of one k over several blocks; partial sums are added in chunk order
-      const int nch = std::min(TX_CHUNKS, nq);
+      // q chunks spread the pairs of one k over several blocks (enough for about 16k blocks); partial sums
+      // are added in chunk order
+      const int nch = std::max(1, std::min(std::min(TX_CHUNKS, nq), (16384 + Nk - 1) / Nk));
       const int qlen = (nq + nch - 1) / nch;
       const dim3 grid((unsigned)Nk, (unsigned)nch);
       const int slots = (nt * nb + 255) / 256;
-      if (f64)
+      const int ntile = ((nt + 15) / 16) * ((2 * nb + 15) / 16);
+      if (!f64 && ntile <= 4 * TX_MAXT) {  // FP32 matrix cores for c64 T: one item staged at a time
+        const size_t tb = ((size_t)nt * nt * p->esz + 15) & ~(size_t)15;
+        const size_t shm = tb + (size_t)nt * nb * p->esz;
+        const int x16 = (reinterpret_cast<uintptr_t>(X) & 15) == 0 ? 1 : 0;
+        hipLaunchKernelGGL(direct_tx_mfma, grid, dim3(256), shm, st, Nk, nq, q0, nv, nc, nb, qlen, kq, p->kqm,
+                           nself, x16, (const float*)p->T, X, p->txp);
+        BSE_CHECK_LAUNCH();
+      } else if (f64) {
         BSE_TRY(launch_tx<double>(slots, grid, sh, st, Nk, nq, q0, nv, nc, nb, qlen, kq, p->kqm, nself, group,
                                   (const double*)p->T, X, p->txp));
-      else
+      } else {
         BSE_TRY(launch_tx<float>(slots, grid, sh, st, Nk, nq, q0, nv, nc, nb, qlen, kq, p->kqm, nself, group,
                                  (const float*)p->T, X, p->txp));
+      }
       const long long n = p->N * nb;
       hipLaunchKernelGGL(tx_reduce, dim3((unsigned)std::min<long long>((n + 255) / 256, 65536)), dim3(256), 0, st, n,
                          nch, scale, p->txp, Y);
