@@ -62,8 +62,10 @@ __device__ __forceinline__ C2<T> ldc(const T* p, long long off) {
 // ----------------------------------------------------------------------------
 // FP64 / FP32 kernel
 // ----------------------------------------------------------------------------
+// at least two waves per SIMD: the 64 x 64 tile otherwise takes 244 VGPRs + 64 AGPRs (one wave), which
+// leaves the load and LDS latencies of its single-stage loop exposed; at 247 VGPRs it keeps no spills
 template <typename T, typename TC, int WM, int WN, int TM, int TN, int BK>
-__global__ __launch_bounds__(256) void cgemm_real(GemmArgs g) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void cgemm_real(GemmArgs g) {
   static_assert(WM * WN == 4, "4 waves");
   constexpr int BM = WM * TM * 16;   // complex rows per block
   constexpr int BNR = WN * TN * 16;  // real output columns per block
@@ -443,7 +445,8 @@ __global__ __launch_bounds__(256) void cgemm_b3_big(GemmArgs g) {
     long long bl, t;
     xcd_map(L, per_batch, g.batch, bl, t);
     const int b = (int)bl;
-    const int m0 = (int)(t / gxn) * BM, n0 = (int)(t % gxn) * BN;
+    int m0, n0;
+    tile_of(t, gxn, gyn, BM, BN, m0, n0);
     const bool aok = (m0 + sr) < g.M;
     const bool bok = (n0 + sr) < g.N;
     const long long aoff = aok ? off_of(g.a_tab, g.a_tab_pb, g.a_sb, g.a_si, b, g.M, m0 + sr) : 0;
@@ -626,7 +629,8 @@ __global__ __launch_bounds__(256) void cgemm_b3_dma(GemmArgs g) {
   long long bl, t;
   xcd_map(blockIdx.x, per_batch, g.batch, bl, t);
   const int b = (int)bl;
-  const int m0 = (int)(t / gxn) * BM, n0 = (int)(t % gxn) * BN;
+  int m0, n0;
+  tile_of(t, gxn, gyn, BM, BN, m0, n0);
   // this lane's DMA slot: row 32*wave + lane/2, stored chunk position lane%2 holds k chunk
   // (lane%2) ^ ((row >> 3) & 1).  Rows past the matrix edge re-load a valid row: those
   // products only reach output rows / columns that are never stored.
@@ -801,7 +805,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
   long long bl, t;
   xcd_map(blockIdx.x, per_batch, g.batch, bl, t);
   const int b = (int)bl;
-  const int m0 = (int)(t / gxn) * BM, n0 = (int)(t % gxn) * BN;
+  int m0, n0;
+  tile_of(t, gxn, gyn, BM, BN, m0, n0);
   // DMA slot of 32-row block rb: lane -> row 32 rb' + lane / 2, 16-byte chunk (lane % 2) ^ bit 3 of the
   // row; rows past the matrix edge re-load a valid row (their products are never stored)
   auto slot = [&](int rb, const __bf16*& src, int& lo, long long& ps, int& pstride) {
@@ -958,7 +963,8 @@ __global__ __launch_bounds__(256) void cgemm_b3_dma64(GemmArgs g) {
   long long bl, t;
   xcd_map(blockIdx.x, per_batch, g.batch, bl, t);
   const int b = (int)bl;
-  const int m0 = (int)(t / gxn) * BM, n0 = (int)(t % gxn) * BN;
+  int m0, n0;
+  tile_of(t, gxn, gyn, BM, BN, m0, n0);
   // DMA slot: row 32 (wave % 2) + lane / 2 of A (waves 0, 1) or of B (waves 2, 3), 16-byte chunk as above
   const bool isB = wave >= 2;
   const int drow = 32 * (wave & 1) + (lane >> 1);
@@ -1295,7 +1301,7 @@ Shape pick(const GemmArgs& g) {
 
 template <typename T, typename TC>
 bse_status run_real(const GemmArgs& g, hipStream_t st) {
-  constexpr int BK = (sizeof(T) == 8) ? 16 : 32;
+  constexpr int BK = 16;  // 16 complex k per stage: the FP32 tile spills at two waves per SIMD with 32
   switch (pick(g)) {
     case SH_NARROW_N:
       return launch(cgemm_real<T, TC, 4, 1, 1, 2, BK>, g, 64, 16, st);

@@ -51,6 +51,19 @@ __device__ __forceinline__ void xcd_map(long long L, long long per_batch, long l
   }
 }
 
+// output tile (m0, n0) of the t-th block of one batch entry: the dimension with fewer tiles runs fastest, so
+// the blocks that share a panel of the other operand (a B column panel when there are few row tiles, an A row
+// panel otherwise) run back to back on the same XCD and fetch it from HBM about once
+__device__ __forceinline__ void tile_of(long long t, int gxn, int gyn, int BM, int BN, int& m0, int& n0) {
+  if (gyn <= gxn) {
+    m0 = (int)(t % gyn) * BM;
+    n0 = (int)(t / gyn) * BN;
+  } else {
+    m0 = (int)(t / gxn) * BM;
+    n0 = (int)(t % gxn) * BN;
+  }
+}
+
 // one complex tile step of the BF16x3 product on 32x32x16 MFMA:
 //   cr += ar br - ai bi,  ci += ar bi + ai br   (each as hi*hi + hi*lo + lo*hi)
 // a[0..3] = (Re hi, Re lo, Im hi, Im lo) of A, b[0..3] likewise; nih / nil = -Im parts of A
