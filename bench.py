@@ -456,16 +456,19 @@ def apply_mode(args):
     if not args.no_f64 and prec != "f64":
         plan = make_plan("f64")
         Y64 = torch.empty_like(X)
+        plan.set_timing(True)
+        plan.stage_times()
         sync()
         t0 = time.time()
         plan.apply(X, out=Y64)
         sync()
         t64 = time.time() - t0
+        st64 = {k: round(v[0], 1) for k, v in plan.stage_times().items() if v[1] > 0}
         plan.close()
         del plan
         torch.cuda.empty_cache()
         log("f64 apply %.2f s" % t64)
-        prec_rec["f64"] = {"apply_s": t64, "GFLOP_s": Fa / t64 / 1e9}
+        prec_rec["f64"] = {"apply_s": t64, "GFLOP_s": Fa / t64 / 1e9, "stage_ms": st64}
         speedup = t64 / dt
         acc["kernel_rel_err_vs_f64_gpu"] = ((Y - Y64).abs().max() / (Y64 - DX).abs().max()).item()
         if orc is not None:
