@@ -1004,12 +1004,17 @@ def gradients_mode(config, m):
                       "fd_step": h, "results": res}), flush=True)
 
 
+# the sources of everything a timed apply runs (plan dispatch, the pair-density, W-step, T and T.X kernels);
+# the Lanczos, LOBPCG, full-BSE and interpolation sources do not change a counter taken on an apply
+APPLY_SOURCES = ("api.hip", "apply.hip", "direct_b3.hip", "gemm.hip", "util.hip", "bse_internal.h", "mfma_common.h")
+
+
 def source_digest():
-    """Digest of the HIP sources: counter summaries taken on other sources are stale."""
+    """Digest of the HIP sources of the apply: counter summaries taken on other sources are stale."""
     import hashlib
     h = hashlib.sha256()
     cdir = os.path.join(ROOT, "paper_2607_05853_amd", "csrc")
-    for f in sorted(os.listdir(cdir)):
+    for f in APPLY_SOURCES:
         with open(os.path.join(cdir, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]

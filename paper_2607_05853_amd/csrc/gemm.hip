@@ -1099,7 +1099,9 @@ __global__ __launch_bounds__(256) void cgemm_b3_dma64(GemmArgs g) {
 // registers and writes eight 16-byte column vectors to LDS.  LDS rows are the
 // tile's columns (16 k each, two 8-k halves); within each group of 8 rows the
 // row is XOR-permuted by the group index so that the eight rows a thread writes
-// per instruction, and the rows of different threads, spread over the banks.
+// per instruction, and the rows of different threads, spread over the banks, and
+// the two halves swap places in every other group (bit 3 of the row) so that the
+// fragment reads of rows r and r + 8 do not share banks.
 // Same tile and MFMA order as the other BF16x3 kernels.  The K range can be
 // split over blocks (split s covers [s kc, (s+1) kc)): partial sums go to a
 // FP64 buffer part[b][s][m][n] and are added in split order by tn_reduce.
@@ -1140,7 +1142,9 @@ __global__ __launch_bounds__(256) void cgemm_b3_tn(GemmArgs g, int nsplit, int k
   const __bf16* src = (const __bf16*)(isB ? g.B : g.A) + (isB ? g.b_ps : g.a_ps) * pl +
                       (long long)b * (isB ? g.b_sb : g.a_sb) + (cok ? c0 : 0);
   const unsigned flip = ((isB ? g.conjB : g.conjA) && pl >= 2) ? 0x80008000u : 0u;  // conj: -Im planes
-  __bf16* const dst0 = smem + (isB ? 4 * PLA + pl * PLB : pl * PLA) + 8 * kh;
+  // the two 8-k halves of a row are swapped in every other group of 8 rows (bit 3 of the row), as in the
+  // direct-to-LDS kernels: the fragment reads of rows r and r + 8 then fall on different banks
+  __bf16* const dst0 = smem + (isB ? 4 * PLA + pl * PLB : pl * PLA) + 8 * (kh ^ (cb & 1));
 
   u4v v[8];
   auto gload = [&](int kt) {
@@ -1185,7 +1189,6 @@ __global__ __launch_bounds__(256) void cgemm_b3_tn(GemmArgs g, int nsplit, int k
     lstore(0);
   }
   __syncthreads();
-  const int fo = 8 * (lane >> 5);
   for (int kt = 0; kt < nK; ++kt) {
     const int st = kt & 1;
     if (kt + 1 < nK) gload(kt + 1);
@@ -1194,13 +1197,15 @@ __global__ __launch_bounds__(256) void cgemm_b3_tn(GemmArgs g, int nsplit, int k
     bf8v a[TM][4], bb[2][4];
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
-      const int o = tn_row(wm * 32 * TM + i * 32 + (lane & 31)) * BK + fo;
+      const int r = tn_row(wm * 32 * TM + i * 32 + (lane & 31));
+      const int o = r * BK + 8 * ((lane >> 5) ^ ((r >> 3) & 1));
 #pragma unroll
       for (int q = 0; q < 4; ++q) a[i][q] = *reinterpret_cast<const bf8v*>(sa + q * PLA + o);
     }
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const int o = tn_row(wn * 64 + j * 32 + (lane & 31)) * BK + fo;
+      const int r = tn_row(wn * 64 + j * 32 + (lane & 31));
+      const int o = r * BK + 8 * ((lane >> 5) ^ ((r >> 3) & 1));
 #pragma unroll
       for (int q = 0; q < 4; ++q) bb[j][q] = *reinterpret_cast<const bf8v*>(sb + q * PLB + o);
     }

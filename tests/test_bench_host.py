@@ -31,10 +31,10 @@ def test_f_apply_formula():
 
 
 def test_source_digest_matches_committed_profiles():
-    # the traffic figure is reported only when the committed counter summary was taken on these sources
+    # the traffic figure is reported only when the committed counter summary was taken on the apply's sources
     dig = bench.source_digest()
     assert len(dig) == 16
-    txt = open(os.path.join(ROOT, "profiles", "pmc_dblock_mesh8_ao64_bf16x3.txt")).read()
+    txt = open(os.path.join(ROOT, "profiles", "pmc_wstep_mesh16_ao128_bf16x3.txt")).read()
     assert "source_digest=" in txt
     stored = txt.split("source_digest=")[1].split()[0]
     if stored != dig:
