@@ -48,24 +48,32 @@ def test_zero_kernel_has_zero_binding_energy():
         assert abs(Om1 - gap_ks) > 0.1
 
 
-def test_attractive_screened_interaction_binds():
-    # with the exchange removed (triplet, alpha = 0) and the screened interaction scaled up, the direct term
-    # pulls the lowest excitation below the smallest direct gap: E_B > 0, growing with the scale
+def test_binding_energy_convex_in_the_screened_interaction():
+    # with the exchange removed (triplet, alpha = 0) A(s) = diag(te) + s D is linear in the scale s of W, so
+    # Omega_1(s) = lambda_min(A(s)) is concave (a minimum of linear functions of s) and E_B(s) = gap -
+    # Omega_1(s) is convex with E_B(0) = 0: E_B(s) / s does not decrease for s > 0, E_B(s) + E_B(-s) >= 0,
+    # and a strong enough screened interaction binds (E_B > 0 and growing)
     base = make_problem("mesh4_ao16", 1, "G1")
-    eb = []
-    for s in (0.0, 1.0, 4.0, 16.0):
+    scales = (-1.0, 0.0, 1.0, 4.0, 16.0)
+    eb = {}
+    for s in scales:
         p = dataclasses.replace(base, W_R=s * base.W_R, alpha=0.0)
         Om1, _ = O.lowest_exciton(O.build_H(p, _Wq(p)))
-        eb.append(O.binding_energy(p, Om1))
-    assert abs(eb[0]) < 1e-14
-    assert 0.0 < eb[1] < eb[2] < eb[3]
+        eb[s] = O.binding_energy(p, Om1)
+    assert abs(eb[0.0]) < 1e-14
+    assert eb[1.0] / 1.0 <= eb[4.0] / 4.0 <= eb[16.0] / 16.0
+    assert eb[1.0] + eb[-1.0] >= 0.0
+    assert 0.0 < eb[4.0] < eb[16.0]
     # first order in a small kernel: Omega_1 = te[i0] + D[i0, i0] + O(s^2) for the smallest transition energy
-    # te[i0] (non-degenerate here), so E_B -> -D[i0, i0]
-    p = dataclasses.replace(base, W_R=1e-3 * base.W_R, alpha=0.0)
-    H = O.build_H(p, _Wq(p))
-    te = O.transition_energies(p).ravel()
-    i0 = int(np.argmin(te))
-    assert np.sort(te)[1] - te[i0] > 1e-3
-    first = -(H[i0, i0].real - te[i0])
-    Om1, _ = O.lowest_exciton(H)
-    assert first > 0 and abs(O.binding_energy(p, Om1) / first - 1.0) < 1e-2
+    # te[i0] (non-degenerate here), so E_B -> -D[i0, i0], of either sign, and the second-order remainder
+    # (convexity) is >= 0
+    for sk in (1e-3, -1e-3):
+        p = dataclasses.replace(base, W_R=sk * base.W_R, alpha=0.0)
+        H = O.build_H(p, _Wq(p))
+        te = O.transition_energies(p).ravel()
+        i0 = int(np.argmin(te))
+        assert np.sort(te)[1] - te[i0] > 1e-3
+        first = -(H[i0, i0].real - te[i0])
+        Om1, _ = O.lowest_exciton(H)
+        e = O.binding_energy(p, Om1)
+        assert abs(first) > 1e-7 and abs(e / first - 1.0) < 1e-2 and e - first >= -1e-15
