@@ -55,8 +55,10 @@ def kernel_flops_per_pair(p, prec, route="mc"):
     """Algorithmic flops per (k, k') pair of each single-kernel stage of the direct term.
 
     wstep      P = conj(M_v) W(q)              8 n_aux^2 nv^2
+               route "fused" (BF16x3): P and T = M_c P^T in one kernel, P kept on chip
+                                                8 n_aux^2 nv^2 + 8 n_aux nc^2 nv^2
     pairdens_v M_vv' from the halves            8 n_aux n_ao nv^2
-    pairdens_c M_cc' from the halves            8 n_aux n_ao nc^2      (route "mc")
+    pairdens_c M_cc' from the halves            8 n_aux n_ao nc^2      (routes "mc", "fused")
     dblock     route "mc": T = M_c P^T          8 n_aux nc^2 nv^2
                route "u" (BF16x3): U = B_c^T P^T and T = psi U (conduction pair densities never formed)
                                                 8 nc n_ao n_aux nv^2 + 8 nc^2 n_ao nv^2
@@ -66,6 +68,8 @@ def kernel_flops_per_pair(p, prec, route="mc"):
          "pairdens_v": 8 * na * no * nv * nv, "dblock": 8 * na * nc * nc * nv * nv}
     if route == "u":
         d["dblock"] = 8 * nc * no * na * nv * nv + 8 * nc * nc * no * nv * nv
+    if route == "fused":
+        d["wstep"] += d.pop("dblock")
     return d
 
 
@@ -73,11 +77,15 @@ def kernel_bytes_per_pair(p, prec, route="mc"):
     """Algorithmic HBM bytes per (k, k') pair of the single-kernel stages (each operand once)."""
     na, no, nv, nc, Nk = p.n_aux, p.n_ao, p.nv, p.nc, p.Nk
     e = 16 if prec == "f64" else 8
-    return {"wstep": e * (2 * nv * nv * na) + e * na * na / Nk,
-            "pairdens_v": e * nv * nv * na + e * (nv * na * no) / Nk,
-            "pairdens_c": e * nc * nc * na + e * (nc * na * no) / Nk,
-            "dblock": (e * nv * nv * na + 8 * nc * nc * nv * nv + e * nc * no * na / Nk) if route == "u"
-            else e * (nc * nc * na + nv * nv * na) + e * nc * nc * nv * nv}
+    d = {"wstep": e * (2 * nv * nv * na) + e * na * na / Nk,
+         "pairdens_v": e * nv * nv * na + e * (nv * na * no) / Nk,
+         "pairdens_c": e * nc * nc * na + e * (nc * na * no) / Nk,
+         "dblock": (e * nv * nv * na + 8 * nc * nc * nv * nv + e * nc * no * na / Nk) if route == "u"
+         else e * (nc * nc * na + nv * nv * na) + e * nc * nc * nv * nv}
+    if route == "fused":  # reads M_v, M_c and W(q), writes T (c64); P stays on chip
+        del d["dblock"]
+        d["wstep"] = e * (nv * nv * na + nc * nc * na) + e * na * na / Nk + 8 * nc * nc * nv * nv
+    return d
 
 
 def copy_calibration(nbytes=1 << 30):
@@ -404,7 +412,7 @@ def apply_mode(args):
     value = Fa / dt / 1e9
     log("timed: %d %s applies, %.3f s per apply -> %.1f GFLOP/s" % (args.steps, prec, dt, value))
     q_formed, q_total = plan.pairs
-    route = plan.conduction
+    route = "fused" if plan.fused else plan.conduction
     roof = dominant_roofline(p, prec, route, stages, args.steps * p.Nk * q_formed, config)
     Fx = f_apply(p.Nk, p.n_ao, p.nv, p.nc, p.n_aux, nb, q_formed=q_formed)
     stage_ms = {k: round(v[0] / args.steps, 2) for k, v in stages.items() if v[1] > 0}

@@ -212,6 +212,14 @@ bse_status bse_plan_pairs(const bse_plan* plan, int64_t* formed, int64_t* total)
  * Host pointer. */
 bse_status bse_plan_conduction(const bse_plan* plan, int32_t* forms_mc);
 
+/* *fused = 1 when bse_apply forms the W step P = conj(M_v) W(q) and the direct
+ * block T = M_c P^T in one kernel, so that P never leaves the chip (BF16X3 plans
+ * on the M_cc' route with n_v = n_c = 8, N_aux a multiple of 256 and an even
+ * N_k; the same sums as the two GEMMs, summed in another order), 0 otherwise.
+ * The environment variable BSE_FUSED_WSTEP=0, read at every apply, selects the
+ * two GEMMs instead.  Host pointer. */
+bse_status bse_plan_fused(const bse_plan* plan, int32_t* fused);
+
 /* Device bytes held by the plan (copies, halves and workspaces). */
 bse_status bse_plan_bytes(const bse_plan* plan, uint64_t* bytes);
 

@@ -53,6 +53,7 @@ _SIGS = {
     "bse_plan_bytes": [_vp, ctypes.POINTER(ctypes.c_uint64)],
     "bse_plan_pairs": [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
     "bse_plan_conduction": [_vp, ctypes.POINTER(ctypes.c_int32)],
+    "bse_plan_fused": [_vp, ctypes.POINTER(ctypes.c_int32)],
     "bse_offset_spectrum": [_vp, _vp, _vp, _i32, _i32, _i32, _vp, _i32, ctypes.c_double, _vp, _vp, _vp],
     "bse_offset_set": [ctypes.POINTER(ctypes.c_int32), _vp, _vp],
     "bse_apply": [_vp, _vp, _vp, _i32, _vp],
@@ -257,6 +258,13 @@ class Plan:
         v = ctypes.c_int32()
         _check("bse_plan_conduction", lib().bse_plan_conduction(self._ptr, ctypes.byref(v)))
         return "mc" if v.value else "u"
+
+    @property
+    def fused(self):
+        """True when an apply forms the W step and the direct block in one kernel (P kept on chip)."""
+        v = ctypes.c_int32()
+        _check("bse_plan_fused", lib().bse_plan_fused(self._ptr, ctypes.byref(v)))
+        return bool(v.value)
 
     @property
     def bytes(self):

@@ -737,6 +737,8 @@ bse_status build_plan(Plan* p, const bse_dims* d, const double* eps_qp, const vo
     }
   }
 
+  p->fused_wt = (p->split && p->mc_direct && nv == 8 && nc == 8 && na % 256 == 0 && Nk % 2 == 0) ? 1 : 0;
+
   // direct-term workspaces: at least 12 GiB, more where 16 q per batch need it and 40 % of the free
   // device memory allows (short q batches leave the pair-density tiles mostly empty)
   {
@@ -969,6 +971,15 @@ bse_status bse_plan_conduction(const bse_plan* plan, int32_t* forms_mc) {
     return BSE_EINVAL;
   }
   *forms_mc = plan->impl.mc_direct;
+  return BSE_OK;
+}
+
+bse_status bse_plan_fused(const bse_plan* plan, int32_t* fused) {
+  if (!plan || bad_ptr(fused)) {
+    set_error("bse_plan_fused: NULL argument");
+    return BSE_EINVAL;
+  }
+  *fused = (plan->impl.fused_wt && fused_wstep_enabled()) ? 1 : 0;
   return BSE_OK;
 }
 

@@ -13,6 +13,8 @@
 #include "bse_internal.h"
 #include "mfma_common.h"
 
+#include <cstdlib>
+
 namespace bse {
 namespace {
 
@@ -976,6 +978,13 @@ bse_status apply_exchange(Plan* p, const double* X, double* Y, int nb, hipStream
   return BSE_OK;
 }
 
+// BSE_FUSED_WSTEP=0 keeps the W step and the direct block as two GEMMs (identical results; read at every
+// apply so that one process can time and compare both)
+bool fused_wstep_enabled() {
+  const char* e = std::getenv("BSE_FUSED_WSTEP");
+  return !(e && e[0] == '0');
+}
+
 bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t st) {
   const bse_dims& d = p->d;
   const int Nk = p->Nk, nv = d.nv, nc = d.nc, na = d.n_aux;
@@ -986,10 +995,34 @@ bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t
   // that order); T.X adds the partner blocks D(k, k-q) = D(k-q, k)^dagger
   const int nqt = p->herm_half ? p->nhalf : Nk;
   const int* kq = p->herm_half ? p->kqp : p->kq;
+  // n_v = n_c = 8 with N_aux a multiple of 256 on the M_cc' route: the W step and the direct block run as one
+  // kernel and P stays on chip (same result as the two GEMMs below)
+  const bool fused = p->fused_wt && fused_wstep_enabled();
   for (int q0 = 0; q0 < nqt; q0 += p->qb) {
     const int nq = (nqt - q0) < p->qb ? (nqt - q0) : p->qb;
     BSE_TRY(form_pair_densities(p, q0, nq, p->mc_direct, kq, st, p->split));
-    {  // P = conj(Gv) W(q)
+    if (fused) {
+      StageMark sm_(p, BSE_STAGE_WSTEP, st);
+      GemmArgs g;
+      g.batch = nq;
+      g.M = Nk * nv * nv;
+      g.N = na;
+      g.K = na;
+      g.A = p->Mv;
+      g.a_sb = (long long)Nk * nv * nv * na;
+      g.a_si = na;
+      g.a_sk = 1;
+      g.conjA = 1;
+      g.B = (const __bf16*)p->Wq + (long long)q0 * na * na;
+      g.b_sb = (long long)na * na;
+      g.b_sk = 1;
+      g.b_sj = na;
+      g.a_ps = p->ps_Mv;
+      g.b_ps = p->ps_W;
+      BSE_TRY(wstep_dblock(g, (const __bf16*)p->Mc, (long long)Nk * nc * nc * na, p->ps_Mc, (float*)p->T,
+                           (long long)Nk * nc * nc * nv * nv, st));
+    }
+    if (!fused) {  // P = conj(Gv) W(q)
     StageMark sm_(p, BSE_STAGE_WSTEP, st);
       GemmArgs g;
       g.batch = nq;
@@ -1023,7 +1056,9 @@ bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t
         BSE_TRY(cgemm(g, ar, f64, f64, st));
       }
     }
-    if (!p->mc_direct) {  // T from B_c(k) and P without the conduction pair densities (BF16X3)
+    if (fused) {
+      // T formed with the W step
+    } else if (!p->mc_direct) {  // T from B_c(k) and P without the conduction pair densities (BF16X3)
       StageMark sm_(p, BSE_STAGE_DBLOCK, st);
       BSE_TRY(direct_u_b3(p, q0, nq, kq, st));
     } else {  // T = Mc P^T over nu

@@ -88,6 +88,14 @@ bse_status cgemm(const GemmArgs& g, Arith ar, bool in_f64, bool out_f64, hipStre
 // (Re hi, Re lo, Im hi, Im lo at plane strides a_ps / b_ps / c_ps); non-split
 // operands are c64 (A, B) and c64 / c128 (C, per out_f64).
 bse_status cgemm_split(const GemmArgs& g, bool a_split, bool b_split, bool c_split, bool out_f64, hipStream_t st);
+// BF16x3 W step and direct block in one kernel (64 rows per pair on both band sides, N_aux a multiple of
+// 256): P = conj(Gv) W(q) as g describes it (A = Gv planes with conjA, B = W(q) planes, M = 64 N_k per q,
+// N = K = N_aux), stays on chip, and T[b][k] = Mc[b][k] P[b][k]^T is written as c64 [b][k][64][64] (stride
+// t_sb per batch entry); Mc planes at mc (stride mc_sb per batch entry, plane stride mc_ps, rows of N_aux)
+bse_status wstep_dblock(const GemmArgs& g, const __bf16* mc, long long mc_sb, long long mc_ps, float* t, long long t_sb,
+                        hipStream_t st);
+// BSE_FUSED_WSTEP=0 in the environment selects the two GEMMs (read at every call)
+bool fused_wstep_enabled();
 // split c64 / c128 arrays into four bf16 planes (util.hip); n complex elements,
 // optionally transposing each of `batch` rows x cols matrices
 bse_status split_planes(const void* in, bool in_f64, __bf16* out, long long n, long long plane_stride,
@@ -147,6 +155,7 @@ struct Plan {
   int herm_half = 0, nself = 0, nhalf = 0;
   // conduction side: 1 = form M_cc' and T = M_c P^T (FP64 / FP32 always), 0 = B_c(k) contraction (BF16X3)
   int mc_direct = 1;
+  int fused_wt = 0;  // the shape admits the fused W step + direct block (BF16X3, M_cc' route, n_v = n_c = 8)
   int* kqp = nullptr;
   int* kqm = nullptr;
   int* qord = nullptr;              // [Nk] dense-mesh index of the j-th q of that order

@@ -17,6 +17,8 @@
 #include "bse_internal.h"
 #include "mfma_common.h"
 
+#include <cstdlib>
+
 namespace bse {
 namespace {
 
@@ -943,6 +945,345 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
   }
 }
 
+// 128 x 256 tiles of the same product with the result written pre-split, for long-K products with a wide
+// B (the W step: K = N = N_aux).  Eight waves of 64 x 64 (two per SIMD, one block per CU) and three LDS
+// stages of 48 KiB: the loads of stage kt + 2 are issued while stage kt is multiplied, so two k steps of
+// matrix work cover the latency of each operand fetch, where the 64 x 128 tile's two stages cover one.
+// The A panel of 128 rows is shared by both column tiles of N = 512 and W(q) by every row tile of its
+// batch entry.  A's four and B's eight 32-row DMA blocks go to waves 0..7 and 0..3.  Each accumulator
+// receives the same MFMA sequence as in cgemm_b3_dma, so the results are identical.
+constexpr int WB_BM = 128, WB_BN = 256, WB_NS = 3, WB_BK = 16;
+#ifndef WT_AH
+#define WT_AH 1  // Mc k steps requested ahead in the fused direct block
+#endif
+constexpr int WB_STAGE = 4 * (WB_BM + WB_BN) * WB_BK;  // bf16 per stage
+constexpr size_t WB_LDS = (size_t)WB_NS * WB_STAGE * sizeof(__bf16);  // 144 KiB
+
+// The main loop of the wide tile: rows m0 .. m0 + 127, columns n0 .. n0 + 255 of batch entry b, all of K.
+// Wave (wm, wn) = (wave / 4, wave % 4) ends with the 64 x 64 block at rows 64 wm, columns 64 wn of the
+// tile in accR / accI ([i][j]: 32 x 32 sub-tiles); every wave has finished with LDS on return.
+template <int CJA, int CJB>
+__device__ __forceinline__ void wide_tile_kloop(const GemmArgs& g, __bf16* smem, int b, int m0, int n0,
+                                                f16v (&accR)[2][2], f16v (&accI)[2][2]) {
+  constexpr int BM = WB_BM, BN = WB_BN, BK = WB_BK, NS = WB_NS;
+  constexpr int PA = BM * BK, PB = BN * BK;  // bf16 per plane per stage
+  constexpr int STAGE = WB_STAGE;
+  constexpr int RBA = BM / 32, RB = (BM + BN) / 32;
+  static_assert(RB <= 16 && RB > 8, "two DMA blocks at most per wave");
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 2, wn = wave & 3;
+  const int nK = g.K / BK;
+  // DMA slot of 32-row block rb: lane -> row 32 rb' + lane / 2, 16-byte chunk (lane % 2) ^ bit 3 of the
+  // row; rows past the matrix edge re-load a valid row (their products are never stored)
+  auto slot = [&](int rb, const __bf16*& src, int& lo, long long& ps, int& pstride) {
+    const bool isA = rb < RBA;
+    const int r = 32 * (isA ? rb : rb - RBA) + (lane >> 1);
+    const int chunk = (lane & 1) ^ ((r >> 3) & 1);
+    if (isA) {
+      const int arow = (m0 + r < g.M) ? m0 + r : m0;
+      src = (const __bf16*)g.A + off_of(g.a_tab, g.a_tab_pb, g.a_sb, g.a_si, b, g.M, arow) + 8 * chunk;
+      lo = 32 * rb * BK;
+      ps = g.a_ps;
+      pstride = PA;
+    } else {
+      const int bcol = (n0 + r < g.N) ? n0 + r : n0;
+      src = (const __bf16*)g.B + off_of(g.b_tab, g.b_tab_pb, g.b_sb, g.b_sj, b, g.N, bcol) + 8 * chunk;
+      lo = 4 * PA + 32 * (rb - RBA) * BK;
+      ps = g.b_ps;
+      pstride = PB;
+    }
+  };
+  const __bf16 *src0 = nullptr, *src1 = nullptr;
+  int lo0 = 0, lo1 = 0, pst0 = 0, pst1 = 0;
+  long long ps0 = 0, ps1 = 0;
+  slot(wave, src0, lo0, ps0, pst0);
+  const bool two = wave + 8 < RB;
+  if (two) slot(wave + 8, src1, lo1, ps1, pst1);
+  auto issue = [&](int kt) {
+    __bf16* st = smem + (kt % NS) * STAGE;
+    const int kb = kt * BK;
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl)
+      __builtin_amdgcn_global_load_lds((const void*)(src0 + pl * ps0 + kb),
+                                       (__attribute__((address_space(3))) void*)(st + lo0 + pl * pst0), 16, 0, 0);
+    if (two) {
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl)
+        __builtin_amdgcn_global_load_lds((const void*)(src1 + pl * ps1 + kb),
+                                         (__attribute__((address_space(3))) void*)(st + lo1 + pl * pst1), 16, 0, 0);
+    }
+  };
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        accR[i][j][r] = 0.f;
+        accI[i][j][r] = 0.f;
+      }
+  issue(0);
+  if (nK > 1) issue(1);
+  const int ch = lane >> 5;
+  for (int kt = 0; kt < nK; ++kt) {
+    // stage kt has landed once only the loads of stage kt + 1 (if issued) may be outstanding; the barrier
+    // also guarantees that every wave has finished reading stage kt - 1, whose buffer is refilled next
+    if (kt + 1 < nK) {
+      if (two)
+        vm_lds_barrier<8>();
+      else
+        vm_lds_barrier<4>();
+    } else {
+      vm_lds_barrier<0>();
+    }
+    if (kt + 2 < nK) issue(kt + 2);
+    const __bf16* sa = smem + (kt % NS) * STAGE;
+    const __bf16* sb = sa + 4 * PA;
+    bf8v a[2][4], bb[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int row = wm * 64 + i * 32 + (lane & 31);
+      const int o = row * BK + 8 * (ch ^ ((row >> 3) & 1));
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) a[i][pl] = *reinterpret_cast<const bf8v*>(sa + pl * PA + o);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = wn * 64 + j * 32 + (lane & 31);
+      const int o = col * BK + 8 * (ch ^ ((col >> 3) & 1));
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) bb[j][pl] = *reinterpret_cast<const bf8v*>(sb + pl * PB + o);
+      if (CJB) {
+        bb[j][2] = neg8(bb[j][2]);
+        bb[j][3] = neg8(bb[j][3]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const bf8v nih = neg8(a[i][2]), nil = neg8(a[i][3]);
+      const bf8v rh = CJA ? a[i][2] : nih, rl = CJA ? a[i][3] : nil;
+      const bf8v ih = CJA ? nih : a[i][2], il = CJA ? nil : a[i][3];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        f16v& cr = accR[i][j];
+        f16v& ci = accI[i][j];
+        cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], bb[j][0], cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], bb[j][2], ci, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], bb[j][1], cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], bb[j][3], ci, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rl, bb[j][2], cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(il, bb[j][0], ci, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rh, bb[j][3], cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ih, bb[j][1], ci, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], bb[j][0], cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], bb[j][2], ci, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rh, bb[j][2], cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ih, bb[j][0], ci, 0, 0, 0);
+      }
+    }
+  }
+  vm_lds_barrier<0>();  // every wave is done with the stages before the caller reuses LDS
+}
+
+template <int CJA, int CJB>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void cgemm_b3_dma_w(GemmArgs g) {
+  constexpr int BM = WB_BM, BN = WB_BN;
+  extern __shared__ __attribute__((aligned(1024))) __bf16 smem_w[];
+  __bf16* smem = smem_w;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 2, wn = wave & 3;
+  const int gxn = (g.N + BN - 1) / BN, gyn = (g.M + BM - 1) / BM;
+  const long long per_batch = (long long)gxn * gyn;
+  long long bl, t;
+  xcd_map(blockIdx.x, per_batch, g.batch, bl, t);
+  const int b = (int)bl;
+  int m0, n0;
+  tile_of(t, gxn, gyn, BM, BN, m0, n0);
+  f16v accR[2][2], accI[2][2];
+  wide_tile_kloop<CJA, CJB>(g, smem, b, m0, n0, accR, accI);
+  // the real parts, then the imaginary parts, of the whole tile through LDS as two planes (hi, lo) of
+  // [128][256], then 16-byte stores; the real accumulators are dead before the imaginary ones are staged
+  static_assert(2 * BM * BN <= WB_NS * WB_STAGE, "epilogue staging must fit in the stages");
+  __bf16* sC = smem;
+  const float al = (float)g.alpha;
+#pragma unroll
+  for (int part = 0; part < 2; ++part) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          const int col = wn * 64 + j * 32 + (lane & 31);
+          __bf16 hh, ll;
+          split_bf16(al * (part ? accI[i][j][r] : accR[i][j][r]), hh, ll);
+          sC[row * BN + col] = hh;
+          sC[(BM + row) * BN + col] = ll;
+        }
+    vm_lds_barrier<63>();
+#pragma unroll 2
+    for (int it = 0; it < 16; ++it) {
+      const int id = tid + 512 * it;
+      const int c8 = id & 31, row = (id >> 5) & 127, pl = id >> 12;
+      const int grow = m0 + row, gcol = n0 + c8 * 8;
+      if (grow < g.M && gcol < g.N) {
+        const long long ro = off_of(g.c_tab, g.c_tab_pb, g.c_sb, g.c_si, b, g.M, grow);
+        __bf16* o = (__bf16*)g.C + (2 * part + pl) * g.c_ps + ro + gcol;
+        const bf8v v = *reinterpret_cast<const bf8v*>(&sC[(pl * BM + row) * BN + c8 * 8]);
+        if (gcol + 8 <= g.N && ((ro + gcol) & 7) == 0) {
+          *reinterpret_cast<bf8v*>(o) = v;
+        } else {
+          for (int e = 0; e < 8 && gcol + e < g.N; ++e) o[e] = v[e];
+        }
+      }
+    }
+    vm_lds_barrier<63>();
+  }
+}
+
+// The W step and the direct block of the BF16x3 apply in one kernel, for 64 rows per pair on both band
+// sides (n_v = n_c = 8) and N_aux a multiple of 256.  A workgroup takes the pairs (k0, k0 + 1) of one q
+// (batch entry b, rows m0 = 64 k0 .. m0 + 127 of Gv) and, for each 256-column tile n0 of P,
+//   P[(v'v)][nu] = sum_mu conj(Gv[(v'v)][mu]) W(q)[mu][nu]      (the wide-tile main loop)
+//   T[(c'c)][(v'v)] += sum_{nu in the tile} Mc[(c'c)][nu] P[(v'v)][nu]
+// P never reaches HBM.  After the main loop it is split into bf16 planes in LDS in two rounds: round s
+// stages rows (v'v) = 32 s .. 32 s + 31 of both pairs (every wave's sub-tile i = s, so the accumulators of
+// round 0 are dead before round 1), and the round's T columns are formed on 16x16x32 MFMA: wave w takes
+// pair w / 4, rows (c'c) 16 (w % 4) .. + 15, both 16-column blocks, with its Mc rows read from global
+// memory (the A operand, one k step ahead).  Partial T tiles are kept in the output between rounds and
+// column tiles (16 + 16 registers would not fit beside the main loop).  LDS slab [plane][64 rows][256 nu],
+// 16-byte chunk c of row r stored at position c ^ (r % 16).
+struct WTArgs {
+  GemmArgs g;              // the W step: A = Gv planes (conj), B = W(q) planes; M = 64 N_k, N = K = N_aux
+  const __bf16* mc;        // Mc planes: element (b, k, r, nu) at b mc_sb + (64 k + r) N_aux + nu
+  long long mc_sb, mc_ps;  // per batch entry stride, plane stride (elements)
+  float* t;                // T c64: element (b, k, r, c) at b t_sb + 4096 k + 64 r + c
+  long long t_sb;
+};
+
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void wstep_dblock_fused(WTArgs w) {
+  const GemmArgs& g = w.g;
+  constexpr int BM = WB_BM, BN = WB_BN;
+  constexpr int SR = 64;          // slab rows: 32 (v'v) of each pair
+  constexpr int SPL = SR * BN;    // bf16 per plane of the slab
+  extern __shared__ __attribute__((aligned(1024))) __bf16 smem_w[];
+  __bf16* smem = smem_w;
+  static_assert(4 * SPL <= WB_NS * WB_STAGE, "slab staging must fit in the stages");
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 2, wn = wave & 3;
+  const int gyn = g.M / BM;
+  long long bl, t;
+  xcd_map(blockIdx.x, gyn, g.batch, bl, t);
+  const int b = (int)bl;
+  const int m0 = (int)t * BM, k0 = m0 / 64;
+  const int na = g.N;
+  const int nN = g.N / BN;
+#pragma unroll 1
+  for (int nt = 0; nt < nN; ++nt) {
+    const int n0 = nt * BN;
+    f16v accR[2][2], accI[2][2];
+    wide_tile_kloop<1, 0>(g, smem, b, m0, n0, accR, accI);
+    // the index math of the T phase is derived from an opaque copy of the lane id, so that none of it is
+    // hoisted above the main loop (it would be live there and spilled)
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+    // this wave's T rows and the lane's place in the 16x16x32 operands / results
+    const int wp = wave >> 2, mb = wave & 3;
+    const int l16 = ln & 15, q4 = ln >> 4;
+    // Mc row 16 mb + l16 of pair wp, nu chunk 8 q4 of each k step (plane 0; planes at mc_ps)
+    const __bf16* mcl =
+        w.mc + (long long)b * w.mc_sb + (long long)(m0 + 64 * wp + 16 * mb + l16) * na + 8 * q4 + n0;
+    // T element (row 16 mb + 4 q4 + e, column 32 s + 16 jb + l16) of pair wp
+    float* tl = w.t + 2 * ((long long)b * w.t_sb + (long long)(k0 + wp) * 4096 + (16 * mb + 4 * q4) * 64 + l16);
+    // slab writes: element (j, r) of this wave's sub-tile goes to row 32 wm + 8 (r / 4) + 4 h + r % 4,
+    // column 64 wn + 32 j + lane % 32 (chunk 8 wn + 4 j + x, x = (lane % 32) / 8, stored at chunk ^ (row % 16))
+    const int h = ln >> 5, x = (ln & 31) >> 3;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      // stage rows 32 s .. 32 s + 31 of each pair (sub-tile i = s of every wave)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = 32 * wm + 8 * (r >> 2) + 4 * h + (r & 3);
+          const int chunk = (8 * wn + 4 * j + x) ^ (row & 15);
+          const int o = row * BN + 8 * chunk + (ln & 7);
+          __bf16 hh, ll;
+          split_bf16(accR[s][j][r], hh, ll);
+          smem[o] = hh;
+          smem[SPL + o] = ll;
+          split_bf16(accI[s][j][r], hh, ll);
+          smem[2 * SPL + o] = hh;
+          smem[3 * SPL + o] = ll;
+        }
+      // the round's first Mc k steps and the parked T tiles are requested once the slab is written (the
+      // staged accumulators are dead by then), before the barrier; later k steps are requested four ahead
+      constexpr int NKS = BN / 32, AH = WT_AH;
+      bf8v mf[AH][4];
+#pragma unroll
+      for (int ks = 0; ks < AH; ++ks)
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl)
+          mf[ks][pl] = *reinterpret_cast<const bf8v*>(mcl + pl * w.mc_ps + 32 * ks);
+      f4v tR[2], tI[2];
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          float2 v = make_float2(0.f, 0.f);
+          if (nt > 0) v = *reinterpret_cast<const float2*>(tl + 2 * (e * 64 + 32 * s + 16 * jb));
+          tR[jb][e] = v.x;
+          tI[jb][e] = v.y;
+        }
+      vm_lds_barrier<0>();  // the slab is staged (and the requested Mc and T have landed)
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) {
+        bf8v a[4];
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl) a[pl] = mf[ks % AH][pl];
+        if (ks + AH < NKS) {
+#pragma unroll
+          for (int pl = 0; pl < 4; ++pl)
+            mf[ks % AH][pl] = *reinterpret_cast<const bf8v*>(mcl + pl * w.mc_ps + 32 * (ks + AH));
+        }
+        const bf8v nih = neg8(a[2]), nil = neg8(a[3]);
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb) {
+          const int row = 32 * wp + 16 * jb + l16;
+          const int o = row * BN + 8 * ((4 * ks + q4) ^ (row & 15));
+          bf8v bb[4];
+#pragma unroll
+          for (int pl = 0; pl < 4; ++pl) bb[pl] = *reinterpret_cast<const bf8v*>(smem + pl * SPL + o);
+          f4v& cr = tR[jb];
+          f4v& ci = tI[jb];
+          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], bb[0], cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], bb[2], ci, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], bb[1], cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], bb[3], ci, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nil, bb[2], cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[3], bb[0], ci, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nih, bb[3], cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], bb[1], ci, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], bb[0], cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], bb[2], ci, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nih, bb[2], cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], bb[0], ci, 0, 0, 0);
+        }
+        // keep each k step's LDS reads with its products (hoisting them all would spill)
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      // park the round's T tiles (the final values after the last column tile)
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          *reinterpret_cast<float2*>(tl + 2 * (e * 64 + 32 * s + 16 * jb)) = make_float2(tR[jb][e], tI[jb][e]);
+      vm_lds_barrier<0>();  // every wave is done with the slab before it is restaged
+    }
+  }
+}
+
 // 64 x 64 tiles of the same product for small per-pair matrices (the direct block T = M_c P^T has
 // n_c^2 x n_v^2 entries, 64 x 64 at n_c = n_v = 8, where a 128 x 128 tile would be three quarters
 // empty): four waves of one 32 x 32 tile each, waves 0 and 1 stage the A rows, 2 and 3 the B columns.
@@ -1330,6 +1671,13 @@ bse_status run_bf16(const GemmArgs& g, hipStream_t st) {
   }
 }
 
+// BSE_WIDE_TILES=0 keeps long-K split-output products on the 64 x 128 tiles (identical results; read at
+// every launch so that one process can time and compare both)
+bool wide_tiles_enabled() {
+  const char* e = std::getenv("BSE_WIDE_TILES");
+  return !(e && e[0] == '0');
+}
+
 // the direct-to-LDS kernel needs unit k stride, whole K steps and 16-byte aligned operand rows
 bool dma_ok(const GemmArgs& g) {
   auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
@@ -1411,6 +1759,35 @@ bse_status launch_tn(const GemmArgs& g, bool c_split, hipStream_t st) {
 
 }  // namespace
 
+bse_status wstep_dblock(const GemmArgs& g, const __bf16* mc, long long mc_sb, long long mc_ps, float* t, long long t_sb,
+                        hipStream_t st) {
+  auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  if (g.M <= 0 || g.batch <= 0) return BSE_OK;
+  if (g.M % WB_BM || g.N % WB_BN || g.K % WB_BK || g.N != g.K || !g.conjA || g.conjB || g.a_tab || g.b_tab ||
+      g.a_sk != 1 || g.b_sk != 1 || !al(g.A) || !al(g.B) || !al(mc) || (g.a_sb & 7) || (g.a_si & 7) ||
+      (g.b_sb & 7) || (g.b_sj & 7) || (g.a_ps & 7) || (g.b_ps & 7) || (mc_sb & 7) || (mc_ps & 7)) {
+    set_error("wstep_dblock: unsupported operand shape or alignment");
+    return BSE_ESHAPE;
+  }
+  const long long tiles = (long long)(g.M / WB_BM) * g.batch;
+  if (tiles >= (1LL << 31)) {
+    set_error("wstep_dblock: too many tiles");
+    return BSE_ESHAPE;
+  }
+  WTArgs w;
+  w.g = g;
+  w.mc = mc;
+  w.mc_sb = mc_sb;
+  w.mc_ps = mc_ps;
+  w.t = t;
+  w.t_sb = t_sb;
+  BSE_HIP(hipFuncSetAttribute((const void*)wstep_dblock_fused, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)WB_LDS));
+  hipLaunchKernelGGL(wstep_dblock_fused, dim3((unsigned)tiles), dim3(512), WB_LDS, st, w);
+  BSE_CHECK_LAUNCH();
+  return BSE_OK;
+}
+
 bse_status cgemm_split(const GemmArgs& g, bool a_split, bool b_split, bool c_split, bool out_f64, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return BSE_OK;
   if (g.K <= 0) {
@@ -1438,6 +1815,23 @@ bse_status cgemm_split(const GemmArgs& g, bool a_split, bool b_split, bool c_spl
         hipLaunchKernelGGL((cgemm_b3_dma64<float, true>), dim3((unsigned)tiles), dim3(256), 0, st, g);
         BSE_CHECK_LAUNCH();
         return BSE_OK;
+      }
+    }
+    if (c_split && g.K >= 256 && g.N >= 256 && g.M >= 128 && wide_tiles_enabled()) {
+      // long K and a wide B (the W step): 128 x 256 tiles, three LDS stages
+      const long long tiles = (long long)((g.N + WB_BN - 1) / WB_BN) * ((g.M + WB_BM - 1) / WB_BM) * g.batch;
+      if (tiles < (1LL << 31)) {
+        const dim3 grid((unsigned)tiles), block(512);
+        auto go = [&](auto kern) -> bse_status {
+          BSE_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)WB_LDS));
+          hipLaunchKernelGGL(kern, grid, block, WB_LDS, st, g);
+          BSE_CHECK_LAUNCH();
+          return BSE_OK;
+        };
+        if (g.conjA && g.conjB) return go(cgemm_b3_dma_w<1, 1>);
+        if (g.conjA) return go(cgemm_b3_dma_w<1, 0>);
+        if (g.conjB) return go(cgemm_b3_dma_w<0, 1>);
+        return go(cgemm_b3_dma_w<0, 0>);
       }
     }
     if (c_split) {  // longer K: 64 x 128 tiles, three blocks per CU

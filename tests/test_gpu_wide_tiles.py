@@ -1,0 +1,99 @@
+"""GPU parity of the long-K BF16x3 kernels: the 128 x 256 three-stage W-step tile and the fused W step +
+direct block (P kept on chip), against the oracle's explicit A and against the two-kernel path.
+
+The wide tile gives results identical to the 64 x 128 tile (same MFMA sequence per accumulator); the fused
+kernel forms T = M_c P^T on 16x16x32 MFMA in another summation order, so it is held to the BF16x3 bound of
+the kernel part.  BSE_WIDE_TILES=0 / BSE_FUSED_WSTEP=0 select the previous kernels at the next apply.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from synth import dense_kmesh, make_problem, random_block
+from tolerances import KERNEL_TOL, diag_times, kernel_err
+
+pytestmark = pytest.mark.gpu
+
+# n_v = n_c = 8: the fused kernel; N_aux 256 (one 256-column tile of P) and 512 (two, T parked between them)
+FUSED_256 = dict(cfg_id=70, coarse=(2, 2, 2), dense=(2, 2, 2), n_ao=16, nv=8, nc=8, n_aux=256)
+FUSED_512 = dict(cfg_id=71, coarse=(2, 2, 2), dense=(2, 2, 2), n_ao=16, nv=8, nc=8, n_aux=512)
+# ragged wide tile: 18 k x 9 rows = 162 rows (128 + 34), N_aux = 272 (256 + 16)
+WIDE_RAGGED = dict(cfg_id=72, coarse=(2, 2, 2), dense=(3, 3, 2), n_ao=16, nv=3, nc=4, n_aux=272)
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def T(a, dt=torch.complex128):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(dev(), dt)
+
+
+def H_(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2607_05853_amd import bse
+    return bse
+
+
+def _apply_with(plan, X, var, value):
+    old = os.environ.get(var)
+    os.environ[var] = value
+    try:
+        return H_(plan.apply(T(X)))
+    finally:
+        if old is None:
+            del os.environ[var]
+        else:
+            os.environ[var] = old
+
+
+@pytest.mark.parametrize("wgen", ["G1", "G2"])
+@pytest.mark.parametrize("cfg", ["FUSED_256", "FUSED_512"])
+def test_fused_direct_block(B, cfg, wgen):
+    conf = {"FUSED_256": FUSED_256, "FUSED_512": FUSED_512}[cfg]
+    p = make_problem(conf, 1, wgen)
+    kq = dense_kmesh(p.nk)
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, kq)
+    plan = B.plan_from_problem(p, Wq, prec="bf16x3", max_nb=6, check_hermitian=True, conduction="mc")
+    assert plan.conduction == "mc"
+    X = random_block(p.N, 6, seed=4)
+    H = O.build_H(p, O.interpolate_W_matmul(p.W_R, p.R, p.w_R, kq))
+    DX = diag_times(p, X)
+    ref = H @ X
+    Yf = _apply_with(plan, X, "BSE_FUSED_WSTEP", "1")
+    Yu = _apply_with(plan, X, "BSE_FUSED_WSTEP", "0")
+    ef, eu = kernel_err(Yf, ref, DX), kernel_err(Yu, ref, DX)
+    d = kernel_err(Yf, Yu, DX)
+    # a second call reuses the workspaces and the parked T tiles: it must repeat the first bit for bit
+    Yf2 = _apply_with(plan, X, "BSE_FUSED_WSTEP", "1")
+    print("[fused %s %s] kernel-part err fused %.2e, two-kernel %.2e, between them %.2e" % (cfg, wgen, ef, eu, d),
+          flush=True)
+    assert np.array_equal(Yf, Yf2)
+    assert max(ef, eu) < KERNEL_TOL["bf16x3"]
+    assert d < KERNEL_TOL["bf16x3"]
+    plan.close()
+
+
+@pytest.mark.parametrize("all_pairs", [False, True])
+def test_wide_tile_ragged_identical(B, all_pairs):
+    p = make_problem(WIDE_RAGGED, 2, "G2")
+    kq = dense_kmesh(p.nk)
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, kq)
+    plan = B.plan_from_problem(p, Wq, prec="bf16x3", max_nb=5, conduction="mc", all_pairs=all_pairs)
+    X = random_block(p.N, 5, seed=6)
+    Yw = _apply_with(plan, X, "BSE_WIDE_TILES", "1")
+    Yn = _apply_with(plan, X, "BSE_WIDE_TILES", "0")
+    H = O.build_H(p, O.interpolate_W_matmul(p.W_R, p.R, p.w_R, kq))
+    err = kernel_err(Yw, H @ X, diag_times(p, X))
+    print("[wide tile ragged, all pairs %s] kernel-part err %.2e, identical to the 64 x 128 tile: %s" %
+          (all_pairs, err, np.array_equal(Yw, Yn)), flush=True)
+    assert np.array_equal(Yw, Yn)
+    assert err < KERNEL_TOL["bf16x3"]
+    plan.close()
