@@ -953,6 +953,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
 // batch entry.  A's four and B's eight 32-row DMA blocks go to waves 0..7 and 0..3.  Each accumulator
 // receives the same MFMA sequence as in cgemm_b3_dma, so the results are identical.
 constexpr int WB_BM = 128, WB_BN = 256, WB_NS = 3, WB_BK = 16;
+#ifndef WB_MIN_K
+#define WB_MIN_K 256  // shortest K given to the wide tile
+#endif
 #ifndef WT_AH
 #define WT_AH 1  // Mc k steps requested ahead in the fused direct block
 #endif
@@ -1281,6 +1284,140 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
           *reinterpret_cast<float2*>(tl + 2 * (e * 64 + 32 * s + 16 * jb)) = make_float2(tR[jb][e], tI[jb][e]);
       vm_lds_barrier<0>();  // every wave is done with the slab before it is restaged
     }
+  }
+}
+
+// Short-K split products with a small A, on persistent blocks: the pair densities (A = psi rows of one k's
+// q batch, K = N_ao; B = that k's halves, N = n_band N_aux; the result written pre-split).  One block of
+// eight waves per CU keeps a 128-row block of A in LDS while it runs over the 256-column tiles of its batch
+// entry; each wave takes 32 columns and all 128 rows, reads its B fragments straight from global memory
+// PD_AHEAD k steps ahead (the first ones of the next tile during this tile's epilogue, so about 64 KiB per
+// CU stay in flight) and writes its 128 x 32 result through a private 4 KiB LDS buffer with 16-byte stores:
+// no block barrier separates one tile from the next.  Each accumulator receives the MFMA sequence of
+// cgemm_b3_dma over k in order, so the results are identical to those of the other split kernels.
+// A in LDS as [plane][128 rows][K], 16-byte chunk c of row r stored at c ^ (r % (K / 8)).
+constexpr int PD_BM = 128, PD_BN = 256, PD_KMAX = 128, PD_AHEAD = 2;
+constexpr size_t PD_LDS = (size_t)4 * PD_BM * PD_KMAX * sizeof(__bf16) + 8 * 4096;  // 160 KiB
+
+template <int NK>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void cgemm_b3_stream(GemmArgs g) {
+  constexpr int K = 16 * NK, CPR = K / 8;  // k, 16-byte chunks per A row
+  constexpr int APL = PD_BM * K;           // bf16 per A plane
+  static_assert(K <= PD_KMAX && (CPR & (CPR - 1)) == 0, "K of 64 or 128");
+  static_assert(NK % PD_AHEAD == 0, "the fragment ring restarts at slot 0 on every tile");
+  extern __shared__ __attribute__((aligned(1024))) __bf16 smem_s[];
+  __bf16* sA = smem_s;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __bf16* sE = smem_s + 4 * APL + wave * 2048;  // this wave's epilogue buffer [2][32][32]
+  const int h = lane >> 5, l32 = lane & 31;
+  const int gyn = (g.M + PD_BM - 1) / PD_BM, gxn = (g.N + PD_BN - 1) / PD_BN;
+  const long long items = (long long)g.batch * gyn * gxn;
+  const long long per = (items + gridDim.x - 1) / gridDim.x;
+  const long long it0 = (long long)blockIdx.x * per;
+  const long long it1 = it0 + per < items ? it0 + per : items;
+  if (it0 >= it1) return;  // uniform over the block
+  // B fragments of tile `it`, k step kt: column n0 + 32 wave + l32 (a valid column past the edge), k 16 kt + 8 h
+  auto bsrc = [&](long long it) -> const __bf16* {
+    const long long bm = it / gxn;
+    const int b = (int)(bm / gyn), n0 = (int)(it % gxn) * PD_BN;
+    const int col = n0 + 32 * wave + l32;
+    return (const __bf16*)g.B + off_of(g.b_tab, g.b_tab_pb, g.b_sb, g.b_sj, b, g.N, col < g.N ? col : g.N - 1) + 8 * h;
+  };
+  bf8v bq[PD_AHEAD][4];
+  auto load_b = [&](const __bf16* src, int kt, bf8v* dst) {
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) dst[pl] = *reinterpret_cast<const bf8v*>(src + pl * g.b_ps + 16 * kt);
+  };
+  const __bf16* bs = bsrc(it0);
+#pragma unroll
+  for (int s = 0; s < PD_AHEAD; ++s)
+    if (s < NK) load_b(bs, s, bq[s]);
+  long long cur_bm = -1;
+  for (long long it = it0; it < it1; ++it) {
+    const long long bm = it / gxn;
+    const int b = (int)(bm / gyn), m0 = (int)(bm % gyn) * PD_BM, n0 = (int)(it % gxn) * PD_BN;
+    if (bm != cur_bm) {
+      // restage A: rows m0 .. m0 + 127 of batch entry b (a valid row past the edge); every wave is past its
+      // last A read of the previous block of rows at the first barrier
+      __syncthreads();
+      constexpr int RPI = 64 / CPR;  // rows per DMA instruction (1 KiB)
+      for (int ins = wave; ins < 4 * PD_BM / RPI; ins += 8) {
+        const int pl = ins / (PD_BM / RPI), r = (ins % (PD_BM / RPI)) * RPI + lane / CPR;
+        const int ph = lane % CPR, lc = ph ^ (r % CPR);
+        const int arow = (m0 + r < g.M) ? m0 + r : g.M - 1;
+        const __bf16* src = (const __bf16*)g.A + off_of(g.a_tab, g.a_tab_pb, g.a_sb, g.a_si, b, g.M, arow) +
+                            pl * g.a_ps + 8 * lc;
+        __builtin_amdgcn_global_load_lds((const void*)src,
+                                         (__attribute__((address_space(3))) void*)(sA + pl * APL +
+                                                                                   (ins % (PD_BM / RPI)) * RPI * K),
+                                         16, 0, 0);
+      }
+      vm_lds_barrier<0>();
+      cur_bm = bm;
+    }
+    f16v accR[4], accI[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        accR[i][r] = 0.f;
+        accI[i][r] = 0.f;
+      }
+    // the next tile's fragments are requested as this tile's last k steps retire
+    const __bf16* bn = (it + 1 < it1) ? bsrc(it + 1) : bs;
+#pragma unroll
+    for (int kt = 0; kt < NK; ++kt) {
+      bf8v bb[4];
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) bb[pl] = bq[kt % PD_AHEAD][pl];
+      if (kt + PD_AHEAD < NK)
+        load_b(bs, kt + PD_AHEAD, bq[kt % PD_AHEAD]);
+      else if (it + 1 < it1)
+        load_b(bn, kt + PD_AHEAD - NK, bq[kt % PD_AHEAD]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 32 * i + l32;
+        const int o = row * K + 8 * ((2 * kt + h) ^ (row % CPR));
+        bf8v a[4];
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl) a[pl] = *reinterpret_cast<const bf8v*>(sA + pl * APL + o);
+        cmma_b3(a, neg8(a[2]), neg8(a[3]), bb, accR[i], accI[i]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    bs = bn;
+    // epilogue: per row sub-tile and part (Re, Im), hi and lo planes of 32 x 32 through the wave's buffer
+    const float al = (float)g.alpha;
+    const int col0 = n0 + 32 * wave;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int part = 0; part < 2; ++part) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = 8 * (r >> 2) + 4 * h + (r & 3);
+          __bf16 hh, ll;
+          split_bf16(al * (part ? accI[i][r] : accR[i][r]), hh, ll);
+          sE[row * 32 + l32] = hh;
+          sE[1024 + row * 32 + l32] = ll;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int id = lane + 64 * j;
+          const int pl = id >> 7, row = (id >> 2) & 31, c4 = id & 3;
+          const bf8v v = *reinterpret_cast<const bf8v*>(sE + pl * 1024 + row * 32 + c4 * 8);
+          const int grow = m0 + 32 * i + row, gcol = col0 + 8 * c4;
+          if (grow < g.M && gcol < g.N) {
+            const long long ro = off_of(g.c_tab, g.c_tab_pb, g.c_sb, g.c_si, b, g.M, grow);
+            __bf16* o = (__bf16*)g.C + (2 * part + pl) * g.c_ps + ro + gcol;
+            if (gcol + 8 <= g.N && ((ro + gcol) & 7) == 0) {
+              *reinterpret_cast<bf8v*>(o) = v;
+            } else {
+              for (int e = 0; e < 8 && gcol + e < g.N; ++e) o[e] = v[e];
+            }
+          }
+        }
+      }
   }
 }
 
@@ -1678,6 +1815,13 @@ bool wide_tiles_enabled() {
   return !(e && e[0] == '0');
 }
 
+// BSE_STREAM_PD=0 keeps the short-K split products on the tiled kernels (identical results; read at every
+// launch)
+bool stream_enabled() {
+  const char* e = std::getenv("BSE_STREAM_PD");
+  return !(e && e[0] == '0');
+}
+
 // the direct-to-LDS kernel needs unit k stride, whole K steps and 16-byte aligned operand rows
 bool dma_ok(const GemmArgs& g) {
   auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
@@ -1817,7 +1961,23 @@ bse_status cgemm_split(const GemmArgs& g, bool a_split, bool b_split, bool c_spl
         return BSE_OK;
       }
     }
-    if (c_split && g.K >= 256 && g.N >= 256 && g.M >= 128 && wide_tiles_enabled()) {
+    if (c_split && (g.K == 64 || g.K == 128) && g.M <= 2 * PD_BM && g.N >= 4 * PD_BN && !g.conjA && !g.conjB &&
+        stream_enabled()) {
+      // short K, few rows, many columns (the pair densities): persistent streaming blocks, one per CU
+      int dev = 0, ncu = 0;
+      BSE_HIP(hipGetDevice(&dev));
+      BSE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+      const long long items = (long long)g.batch * ((g.M + PD_BM - 1) / PD_BM) * ((g.N + PD_BN - 1) / PD_BN);
+      const unsigned grid = (unsigned)std::max<long long>(1, std::min<long long>(items, ncu));
+      auto go = [&](auto kern) -> bse_status {
+        BSE_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)PD_LDS));
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(512), PD_LDS, st, g);
+        BSE_CHECK_LAUNCH();
+        return BSE_OK;
+      };
+      return g.K == 64 ? go(cgemm_b3_stream<4>) : go(cgemm_b3_stream<8>);
+    }
+    if (c_split && g.K >= WB_MIN_K && g.N >= 256 && g.M >= 128 && wide_tiles_enabled()) {
       // long K and a wide B (the W step): 128 x 256 tiles, three LDS stages
       const long long tiles = (long long)((g.N + WB_BN - 1) / WB_BN) * ((g.M + WB_BM - 1) / WB_BM) * g.batch;
       if (tiles < (1LL << 31)) {

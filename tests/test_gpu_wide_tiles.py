@@ -1,9 +1,11 @@
-"""GPU parity of the long-K BF16x3 kernels: the 128 x 256 three-stage W-step tile and the fused W step +
-direct block (P kept on chip), against the oracle's explicit A and against the two-kernel path.
+"""GPU parity of the BF16x3 kernels for large shapes: the 128 x 256 three-stage W-step tile, the fused W
+step + direct block (P kept on chip) and the persistent streaming kernel of the pair densities, against the
+oracle's explicit A and against the kernels they replace.
 
-The wide tile gives results identical to the 64 x 128 tile (same MFMA sequence per accumulator); the fused
-kernel forms T = M_c P^T on 16x16x32 MFMA in another summation order, so it is held to the BF16x3 bound of
-the kernel part.  BSE_WIDE_TILES=0 / BSE_FUSED_WSTEP=0 select the previous kernels at the next apply.
+The wide tile and the streaming kernel give results identical to the tiled kernels (same MFMA sequence per
+accumulator); the fused kernel forms T = M_c P^T on 16x16x32 MFMA in another summation order, so it is held
+to the BF16x3 bound of the kernel part.  BSE_WIDE_TILES=0 / BSE_FUSED_WSTEP=0 / BSE_STREAM_PD=0 select the
+previous kernels at the next apply.
 """
 import os
 
@@ -21,6 +23,10 @@ pytestmark = pytest.mark.gpu
 FUSED_256 = dict(cfg_id=70, coarse=(2, 2, 2), dense=(2, 2, 2), n_ao=16, nv=8, nc=8, n_aux=256)
 FUSED_512 = dict(cfg_id=71, coarse=(2, 2, 2), dense=(2, 2, 2), n_ao=16, nv=8, nc=8, n_aux=512)
 # ragged wide tile: 18 k x 9 rows = 162 rows (128 + 34), N_aux = 272 (256 + 16)
+# streaming pair densities: K = N_ao of 64 and 128; rows q x n_band ragged (n_v = 3, n_c = 5), columns
+# n_band x N_aux of 1200 / 2000 (ragged 256-column tiles)
+STREAM_64 = dict(cfg_id=73, coarse=(2, 2, 2), dense=(2, 2, 3), n_ao=64, nv=3, nc=5, n_aux=400)
+STREAM_128 = dict(cfg_id=74, coarse=(2, 2, 2), dense=(2, 2, 3), n_ao=128, nv=3, nc=5, n_aux=400)
 WIDE_RAGGED = dict(cfg_id=72, coarse=(2, 2, 2), dense=(3, 3, 2), n_ao=16, nv=3, nc=4, n_aux=272)
 
 
@@ -95,5 +101,24 @@ def test_wide_tile_ragged_identical(B, all_pairs):
     print("[wide tile ragged, all pairs %s] kernel-part err %.2e, identical to the 64 x 128 tile: %s" %
           (all_pairs, err, np.array_equal(Yw, Yn)), flush=True)
     assert np.array_equal(Yw, Yn)
+    assert err < KERNEL_TOL["bf16x3"]
+    plan.close()
+
+
+@pytest.mark.parametrize("all_pairs", [False, True])
+@pytest.mark.parametrize("cfg", ["STREAM_64", "STREAM_128"])
+def test_stream_pair_densities_identical(B, cfg, all_pairs):
+    p = make_problem({"STREAM_64": STREAM_64, "STREAM_128": STREAM_128}[cfg], 3, "G2")
+    kq = dense_kmesh(p.nk)
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, kq)
+    plan = B.plan_from_problem(p, Wq, prec="bf16x3", max_nb=4, conduction="mc", all_pairs=all_pairs)
+    X = random_block(p.N, 4, seed=7)
+    Ys = _apply_with(plan, X, "BSE_STREAM_PD", "1")
+    Yt = _apply_with(plan, X, "BSE_STREAM_PD", "0")
+    H = O.build_H(p, O.interpolate_W_matmul(p.W_R, p.R, p.w_R, kq))
+    err = kernel_err(Ys, H @ X, diag_times(p, X))
+    print("[stream %s, all pairs %s] kernel-part err %.2e, identical to the tiled kernel: %s" %
+          (cfg, all_pairs, err, np.array_equal(Ys, Yt)), flush=True)
+    assert np.array_equal(Ys, Yt)
     assert err < KERNEL_TOL["bf16x3"]
     plan.close()
