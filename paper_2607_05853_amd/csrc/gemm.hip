@@ -956,6 +956,9 @@ constexpr int WB_BM = 128, WB_BN = 256, WB_NS = 3, WB_BK = 16;
 #ifndef WB_MIN_K
 #define WB_MIN_K 256  // shortest K given to the wide tile
 #endif
+#ifndef WB_PINGPONG
+#define WB_PINGPONG 1  // wide-tile main loop with the two wave groups taking turns on the matrix cores
+#endif
 #ifndef WT_AH
 #define WT_AH 1  // Mc k steps requested ahead in the fused direct block
 #endif
@@ -1028,21 +1031,10 @@ __device__ __forceinline__ void wide_tile_kloop(const GemmArgs& g, __bf16* smem,
   issue(0);
   if (nK > 1) issue(1);
   const int ch = lane >> 5;
-  for (int kt = 0; kt < nK; ++kt) {
-    // stage kt has landed once only the loads of stage kt + 1 (if issued) may be outstanding; the barrier
-    // also guarantees that every wave has finished reading stage kt - 1, whose buffer is refilled next
-    if (kt + 1 < nK) {
-      if (two)
-        vm_lds_barrier<8>();
-      else
-        vm_lds_barrier<4>();
-    } else {
-      vm_lds_barrier<0>();
-    }
-    if (kt + 2 < nK) issue(kt + 2);
+  bf8v a[2][4], bb[2][4];
+  auto frags = [&](int kt) {
     const __bf16* sa = smem + (kt % NS) * STAGE;
     const __bf16* sb = sa + 4 * PA;
-    bf8v a[2][4], bb[2][4];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int row = wm * 64 + i * 32 + (lane & 31);
@@ -1056,7 +1048,12 @@ __device__ __forceinline__ void wide_tile_kloop(const GemmArgs& g, __bf16* smem,
       const int o = col * BK + 8 * (ch ^ ((col >> 3) & 1));
 #pragma unroll
       for (int pl = 0; pl < 4; ++pl) bb[j][pl] = *reinterpret_cast<const bf8v*>(sb + pl * PB + o);
-      if (CJB) {
+    }
+  };
+  auto mma = [&]() {
+    if (CJB) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
         bb[j][2] = neg8(bb[j][2]);
         bb[j][3] = neg8(bb[j][3]);
       }
@@ -1084,7 +1081,54 @@ __device__ __forceinline__ void wide_tile_kloop(const GemmArgs& g, __bf16* smem,
         ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ih, bb[j][0], ci, 0, 0, 0);
       }
     }
+  };
+  // barrier after waiting until at most `n` of this wave's most recent stages are in flight
+  auto bar = [&](int n) {
+    if (two) {
+      if (n >= 2)
+        vm_lds_barrier<16>();
+      else if (n == 1)
+        vm_lds_barrier<8>();
+      else
+        vm_lds_barrier<0>();
+    } else {
+      if (n >= 2)
+        vm_lds_barrier<8>();
+      else if (n == 1)
+        vm_lds_barrier<4>();
+      else
+        vm_lds_barrier<0>();
+    }
+  };
+  auto last = [&](int kt) { return kt < nK - 1 ? kt : nK - 1; };  // last stage issued by step kt
+#if WB_PINGPONG
+  // Ping-pong: waves 0..3 and 4..7 (one of each per SIMD) take turns on the matrix cores.  Both groups run
+  // "barrier, fragments of stage kt, barrier, products" per step, the second group one barrier behind, so
+  // that between consecutive barriers one group reads LDS while the other multiplies.  With barriers
+  // B0, B1, ...: group 0 reads stage kt between B(2kt) and B(2kt+1), group 1 between B(2kt+1) and B(2kt+2),
+  // so every wave waits for its loads of stage kt before B(2kt), all reads of stage kt are done at
+  // B(2kt+2), and the loads of stage kt + 2 (into stage kt - 1's buffer) are issued after B(2kt).
+  const bool late = wave >= 4;
+  if (late) bar(last(1) - 0);
+  for (int kt = 0; kt < nK; ++kt) {
+    bar(last(kt + 1) - kt);  // stage kt has landed (group 0 reads it next)
+    if (kt + 2 < nK) issue(kt + 2);
+    frags(kt);
+    if (late)
+      bar(last(kt + 2) - (kt + 1));  // stage kt + 1 has landed (group 0 reads it after this barrier)
+    else
+      bar(last(kt + 2) - kt);
+    mma();
   }
+  if (!late) bar(0);
+#else
+  for (int kt = 0; kt < nK; ++kt) {
+    bar(last(kt + 1) - kt);  // stage kt has landed; every wave is done with stage kt - 1
+    if (kt + 2 < nK) issue(kt + 2);
+    frags(kt);
+    mma();
+  }
+#endif
   vm_lds_barrier<0>();  // every wave is done with the stages before the caller reuses LDS
 }
 
