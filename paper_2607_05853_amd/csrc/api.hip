@@ -461,7 +461,8 @@ bse_status build_plan(Plan* p, const bse_dims* d, const double* eps_qp, const vo
     BSE_TRY(plan_alloc(p, &p->psi, 8 * npsi));
     BSE_TRY(convert_c128_to_c64(p->psi64, (float*)p->psi, npsi, st));
     BSE_TRY(plan_alloc(p, &p->Wq, 8 * nw));
-    BSE_TRY(convert_c128_to_c64((const double*)W_q, (float*)p->Wq, nw, st));
+    // transposed per q (W[q][nu][mu]), as for BF16X3: the W step reads columns nu contiguous in mu
+    BSE_TRY(convert_c128_to_c64_T((const double*)W_q, (float*)p->Wq, Nk, na, na, st));
   }
 
   // halves B^mu_n(k) = psi_n(k)^H C^mu, computed in FP64; rho from the FP64 halves

@@ -845,8 +845,8 @@ bse_status apply_coupling_direct(Plan* p, const double* X, double* Y, int nb, hi
       } else {
         g.B = off_bytes(p->Wq, (long long)q0 * na * na, p->esz);
         g.b_sb = (long long)na * na;
-        g.b_sk = na;
-        g.b_sj = 1;
+        g.b_sk = f64 ? na : 1;  // FP32 plans store W(q) transposed
+        g.b_sj = f64 ? 1 : na;
         BSE_TRY(cgemm(g, ar, f64, f64, st));
       }
     }
@@ -1051,8 +1051,8 @@ bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t
       } else {
         g.B = off_bytes(p->Wq, (long long)q0 * na * na, p->esz);
         g.b_sb = (long long)na * na;
-        g.b_sk = na;
-        g.b_sj = 1;
+        g.b_sk = f64 ? na : 1;  // FP32 plans store W(q) transposed
+        g.b_sj = f64 ? 1 : na;
         BSE_TRY(cgemm(g, ar, f64, f64, st));
       }
     }

@@ -102,6 +102,8 @@ bse_status split_planes(const void* in, bool in_f64, __bf16* out, long long n, l
                         hipStream_t st);
 bse_status split_planes_T(const void* in, bool in_f64, __bf16* out, int batch, int rows, int cols,
                           long long plane_stride, hipStream_t st);
+// out[b][c][r] = complex64(in[b][r][c]) for batch complex128 rows x cols matrices
+bse_status convert_c128_to_c64_T(const double* in, float* out, int batch, int rows, int cols, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // plan

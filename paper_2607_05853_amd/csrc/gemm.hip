@@ -41,6 +41,13 @@ __device__ __forceinline__ f4v mma16(float a, float b, f4v c) {
 }
 
 
+// wait until at most N vector-memory ops of this wave are outstanding and its LDS
+// ops are done, then barrier
+template <int N>
+__device__ __forceinline__ void vm_lds_barrier() {
+  asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
 template <typename T>
 struct C2 {
   T x, y;
@@ -222,6 +229,166 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
       }
     }
   }
+}
+
+// ----------------------------------------------------------------------------
+// FP32, large tiles: interleaved c64 operands staged straight into LDS, 32x32x2 MFMA
+// ----------------------------------------------------------------------------
+// The wide tile (128 x 256 complex, eight waves of 64 x 64, three 48 KiB LDS stages of 16 complex k, the
+// ping-pong schedule of wide_tile_kloop) for FP32 plans, whose operands are interleaved complex64.  An LDS
+// row holds the 16 k of one operand row (128 bytes, eight 16-byte chunks of two complex values); chunk c of
+// row r is stored at c ^ ((r / 2) % 8), so the 16-byte fragment reads of 32 consecutive rows spread over
+// the banks.  A lane of half h (lane / 32) reads chunk 2 g + h for k group g (four complex k), i.e. k =
+// 4 g + 2 h + m for m = 0, 1 in its two complex values; one 32x32x2 product per (g, m) then sums the k of both
+// halves, the same split for A and B.  Each complex k step is four real products with FP32 accumulation:
+//   Cr += Ar Br - Ai Bi,  Ci += Ar Bi + Ai Br   (conj A / conj B negate Ai / Bi).
+// 256 FP32 products per k step per wave (8192 matrix-core cycles), so the 48 KiB of operands per stage are
+// far from limiting.  The result is written from the registers (each row of 32 lanes is 256 contiguous bytes).
+constexpr int FW_BM = 128, FW_BN = 256, FW_BK = 16, FW_NS = 3;
+constexpr int FW_STAGE = (FW_BM + FW_BN) * FW_BK * 2;  // floats per stage
+constexpr size_t FW_LDS = (size_t)FW_NS * FW_STAGE * sizeof(float);  // 144 KiB
+
+template <int CJA, int CJB, typename TC>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void cgemm_f32_dma_w(GemmArgs g) {
+  constexpr int BM = FW_BM, BN = FW_BN, BK = FW_BK, NS = FW_NS, STAGE = FW_STAGE;
+  constexpr int RBLK = (BM + BN) / 8;  // 8-row DMA blocks per stage: 16 of A, 32 of B
+  extern __shared__ __attribute__((aligned(1024))) float smem_f[];
+  float* smem = smem_f;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 2, wn = wave & 3;
+  const int h = lane >> 5, l32 = lane & 31;
+  const int nK = g.K / BK;
+  const int gxn = (g.N + BN - 1) / BN, gyn = (g.M + BM - 1) / BM;
+  const long long per_batch = (long long)gxn * gyn;
+  long long bl, t;
+  xcd_map(blockIdx.x, per_batch, g.batch, bl, t);
+  const int b = (int)bl;
+  int m0, n0;
+  tile_of(t, gxn, gyn, BM, BN, m0, n0);
+  // DMA: block rb (of 48) -> wave rb % 8; lane -> row 8 (rb') + lane / 8, stored chunk lane % 8, which holds
+  // source chunk (lane % 8) ^ ((row / 2) % 8); rows past the edge re-load a valid row (never stored)
+  const float* src[RBLK / 8];
+  int ldo[RBLK / 8];
+#pragma unroll
+  for (int u = 0; u < RBLK / 8; ++u) {
+    const int rb = wave + 8 * u;
+    const bool isA = rb < BM / 8;
+    const int r = 8 * (isA ? rb : rb - BM / 8) + (lane >> 3);
+    const int c = (lane & 7) ^ ((r >> 1) & 7);
+    if (isA) {
+      const int row = (m0 + r < g.M) ? m0 + r : m0;
+      src[u] = (const float*)g.A + 2 * off_of(g.a_tab, g.a_tab_pb, g.a_sb, g.a_si, b, g.M, row) + 4 * c;
+      ldo[u] = 8 * rb * BK * 2;
+    } else {
+      const int col = (n0 + r < g.N) ? n0 + r : n0;
+      src[u] = (const float*)g.B + 2 * off_of(g.b_tab, g.b_tab_pb, g.b_sb, g.b_sj, b, g.N, col) + 4 * c;
+      ldo[u] = BM * BK * 2 + 8 * (rb - BM / 8) * BK * 2;
+    }
+  }
+  auto issue = [&](int kt) {
+    if (kt >= nK) return;
+    float* st = smem + (kt % NS) * STAGE;
+#pragma unroll
+    for (int u = 0; u < RBLK / 8; ++u)
+      __builtin_amdgcn_global_load_lds((const void*)(src[u] + 2 * BK * kt),
+                                       (__attribute__((address_space(3))) void*)(st + ldo[u]), 16, 0, 0);
+  };
+  f16v accR[2][2], accI[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        accR[i][j][r] = 0.f;
+        accI[i][j][r] = 0.f;
+      }
+  issue(0);
+  issue(1);
+  f4v a[2][4], bb[2][4];
+  auto frags = [&](int kt) {
+    const float* sa = smem + (kt % NS) * STAGE;
+    const float* sb = sa + BM * BK * 2;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int row = wm * 64 + i * 32 + l32;
+#pragma unroll
+      for (int gk = 0; gk < 4; ++gk)
+        a[i][gk] = *reinterpret_cast<const f4v*>(sa + row * BK * 2 + 4 * ((2 * gk + h) ^ ((row >> 1) & 7)));
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = wn * 64 + j * 32 + l32;
+#pragma unroll
+      for (int gk = 0; gk < 4; ++gk)
+        bb[j][gk] = *reinterpret_cast<const f4v*>(sb + col * BK * 2 + 4 * ((2 * gk + h) ^ ((col >> 1) & 7)));
+    }
+  };
+  auto mma = [&]() {
+#pragma unroll
+    for (int gk = 0; gk < 4; ++gk)
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const float ar = a[i][gk][2 * m];
+          const float ai = CJA ? -a[i][gk][2 * m + 1] : a[i][gk][2 * m + 1];
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            const float br = bb[j][gk][2 * m];
+            const float bi = CJB ? -bb[j][gk][2 * m + 1] : bb[j][gk][2 * m + 1];
+            accR[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, accR[i][j], 0, 0, 0);
+            accR[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, bi, accR[i][j], 0, 0, 0);
+            accI[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bi, accI[i][j], 0, 0, 0);
+            accI[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, br, accI[i][j], 0, 0, 0);
+          }
+        }
+  };
+  // ping-pong as in wide_tile_kloop (six loads per wave per stage)
+  auto bar = [&](int n) {
+    if (n >= 2)
+      vm_lds_barrier<12>();
+    else if (n == 1)
+      vm_lds_barrier<6>();
+    else
+      vm_lds_barrier<0>();
+  };
+  auto last = [&](int kt) { return kt < nK - 1 ? kt : nK - 1; };
+  const bool late = wave >= 4;
+  if (late) bar(last(1) - 0);
+  for (int kt = 0; kt < nK; ++kt) {
+    bar(last(kt + 1) - kt);
+    issue(kt + 2);
+    frags(kt);
+    if (late)
+      bar(last(kt + 2) - (kt + 1));
+    else
+      bar(last(kt + 2) - kt);
+    mma();
+  }
+  if (!late) bar(0);
+  // result: register r of a 32 x 32 tile holds row 8 (r / 4) + 4 h + r % 4, column l32
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+      if (row >= g.M) continue;
+      const long long ro = off_of(g.c_tab, g.c_tab_pb, g.c_sb, g.c_si, b, g.M, row);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int col = n0 + wn * 64 + j * 32 + l32;
+        if (col >= g.N) continue;
+        TC* o = (TC*)g.C + 2 * (ro + (long long)col * g.c_sj);
+        double vr = g.alpha * (double)accR[i][j][r], vi = g.alpha * (double)accI[i][j][r];
+        if (g.beta) {
+          vr += (double)o[0];
+          vi += (double)o[1];
+        }
+        o[0] = (TC)vr;
+        o[1] = (TC)vi;
+      }
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -610,12 +777,6 @@ __global__ __launch_bounds__(256) void cgemm_b3_big(GemmArgs g) {
 // A split C is staged through LDS and written with 16-byte stores.
 // ----------------------------------------------------------------------------
 
-// wait until at most N vector-memory ops of this wave are outstanding and its LDS
-// ops are done, then barrier
-template <int N>
-__device__ __forceinline__ void vm_lds_barrier() {
-  asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
-}
 
 template <int CJA, int CJB, bool CS, typename TC>
 __global__ __launch_bounds__(256) void cgemm_b3_dma(GemmArgs g) {
@@ -1826,9 +1987,35 @@ Shape pick(const GemmArgs& g) {
   return SH_WIDE;
 }
 
+bool dma_ok(const GemmArgs& g);
+bool wide_tiles_enabled();
+
+template <typename TC>
+bse_status launch_f32_wide(const GemmArgs& g, hipStream_t st) {
+  const long long tiles = (long long)((g.N + FW_BN - 1) / FW_BN) * ((g.M + FW_BM - 1) / FW_BM) * g.batch;
+  const dim3 grid((unsigned)tiles), block(512);
+  auto go = [&](auto kern) -> bse_status {
+    BSE_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)FW_LDS));
+    hipLaunchKernelGGL(kern, grid, block, FW_LDS, st, g);
+    BSE_CHECK_LAUNCH();
+    return BSE_OK;
+  };
+  if (g.conjA && g.conjB) return go(cgemm_f32_dma_w<1, 1, TC>);
+  if (g.conjA) return go(cgemm_f32_dma_w<1, 0, TC>);
+  if (g.conjB) return go(cgemm_f32_dma_w<0, 1, TC>);
+  return go(cgemm_f32_dma_w<0, 0, TC>);
+}
+
 template <typename T, typename TC>
 bse_status run_real(const GemmArgs& g, hipStream_t st) {
   constexpr int BK = 16;  // 16 complex k per stage: the FP32 tile spills at two waves per SIMD with 32
+  if constexpr (sizeof(T) == 4) {
+    // FP32 products with enough rows and columns for the wide tile (direct-to-LDS operands)
+    const long long tiles = (long long)((g.N + FW_BN - 1) / FW_BN) * ((g.M + FW_BM - 1) / FW_BM) * g.batch;
+    if (g.M >= FW_BM && g.N >= FW_BN && g.K % FW_BK == 0 && dma_ok(g) && tiles < (1LL << 31) &&
+        wide_tiles_enabled())
+      return launch_f32_wide<TC>(g, st);
+  }
   switch (pick(g)) {
     case SH_NARROW_N:
       return launch(cgemm_real<T, TC, 4, 1, 1, 2, BK>, g, 64, 16, st);

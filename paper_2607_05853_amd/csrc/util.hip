@@ -62,7 +62,28 @@ __global__ void split_T_kernel(const T* __restrict__ in, __bf16* __restrict__ ou
   }
 }
 
+// out[b][c][r] = (complex64) in[b][r][c]: batch complex128 matrices rows x cols, transposed and rounded
+__global__ void cvt_T_kernel(const double* __restrict__ in, float* __restrict__ out, int batch, int rows, int cols) {
+  const long long per = (long long)rows * cols, n = per * batch;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long b = i / per, rc = i % per;
+    const int c = (int)(rc / rows), r = (int)(rc % rows);
+    const long long src = b * per + (long long)r * cols + c;
+    out[2 * i] = (float)in[2 * src];
+    out[2 * i + 1] = (float)in[2 * src + 1];
+  }
+}
+
 }  // namespace
+
+bse_status convert_c128_to_c64_T(const double* in, float* out, int batch, int rows, int cols, hipStream_t st) {
+  const long long n = (long long)batch * rows * cols;
+  if (n <= 0) return BSE_OK;
+  hipLaunchKernelGGL(cvt_T_kernel, dim3(grid_for(n)), dim3(256), 0, st, in, out, batch, rows, cols);
+  BSE_CHECK_LAUNCH();
+  return BSE_OK;
+}
 
 bse_status split_planes(const void* in, bool in_f64, __bf16* out, long long n, long long plane_stride,
                         hipStream_t st) {
