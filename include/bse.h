@@ -279,7 +279,9 @@ bse_status bse_density_start(const bse_plan* plan, const void* psi, void* P, voi
  * classical Gram-Schmidt done twice) from the start vectors P, in FP64:
  *   b_0 = |p|, q_1 = p / b_0;  w = A q_j;  a_j = Re q_j^H w;
  *   w -= a_j q_j + b_{j-1} q_{j-1};  w -= Q (Q^H w) twice;  b_j = |w|;
- *   breakdown when b_j <= 1e-12 b_0 (chain stops, steps_done = j);
+ *   breakdown when b_j <= 1e-12 max(|a_1|, .., |a_j|, b_1, .., b_{j-1}) (the
+ *   chain's own scale of A, so the test does not depend on |p|; the chain
+ *   stops, steps_done = j);
  * then the continued fraction
  *   S_b(w) = -(1/(pi N_k)) Im  b_0^2 / (z - a_1 - b_1^2 / (z - a_2 - ... - b_{m-1}^2/(z - a_m))),
  *   z = w + i eta
@@ -378,8 +380,10 @@ bse_status bse_lowest_excitons(bse_plan* plan, int32_t n_block, int32_t max_iter
  * 2 nb <= max_nb and 2 <= n_steps <= 2N.  S host f64 [nb][n_w]; a host f64
  * [nb][n_steps] (diagonal, zero up to rounding), b host f64 [nb][n_steps+1]
  * (b[0] = |[p; p*]|, then the off-diagonal); steps_done host int32 [nb].
- * Exact once the Krylov space is invariant; BSE_INFO_BREAKDOWN when a chain
- * stopped early (its spectrum uses the steps done).
+ * A chain stops when b_j <= 1e-12 max(|a_0|, .., |a_{j-1}|, b_1, .., b_{j-1})
+ * (scale of H seen by the chain, independent of |p|).  Exact once the Krylov
+ * space is invariant; BSE_INFO_BREAKDOWN when a chain stopped early (its
+ * spectrum uses the steps done).
  * ------------------------------------------------------------------------- */
 /* bse_full_lowest: the n_block smallest positive Omega_S of the full BSE with
  * right eigenvectors [X; Y] normalised X^H X - Y^H Y = 1 (Eqs. (right)/(left);

@@ -489,7 +489,10 @@ def haydock(apply, p, m, tol=1e-12):
     b_0 = |p|, q_1 = p / b_0, q_0 = 0.  For j = 1..m:
       w = H q_j;  a_j = Re q_j^H w;  w -= a_j q_j + b_{j-1} q_{j-1};
       full re-orthogonalisation against q_1..q_j, done twice (classical Gram-Schmidt);
-      b_j = |w|;  stop (breakdown) if b_j <= tol * b_0;  q_{j+1} = w / b_j.
+      b_j = |w|;  stop (breakdown) if b_j <= tol * s_j;  q_{j+1} = w / b_j,
+    s_j = max(|a_1|, .., |a_j|, b_1, .., b_{j-1}): the largest recurrence coefficient so far.  b_j has the
+    units of H (the q_j are unit vectors), so the test compares it with H's own scale as the chain has seen
+    it; b_0 = |p| carries the start vector's scale and does not enter.
     Returns a [m] (a_1..a_m), b [m+1] (b_0..b_m), steps done, basis [steps][N].
     """
     p = np.asarray(p, dtype=np.complex128)
@@ -509,7 +512,8 @@ def haydock(apply, p, m, tol=1e-12):
         for _ in range(2):
             w = w - Qm.T @ (Qm.conj() @ w)
         b[j] = np.linalg.norm(w)
-        if b[j] <= tol * b0:
+        scale = max(np.abs(a[:j]).max(), b[1:j].max(initial=0.0))
+        if b[j] <= tol * scale:
             steps = j
             break
         qprev = qj

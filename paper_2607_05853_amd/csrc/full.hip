@@ -193,9 +193,9 @@ __global__ void fb_three_term(long long L, int m, int j, const double* __restric
   r[2 * (bi * L + I) + 1] = vi;
 }
 
-// basis row j of Q and W: x / s and y / s per chain (s = b[bi][sidx]); a chain whose s is not above
-// tol * b[bi][0], or that stopped before, gets zero rows and records its step count once
-__global__ void fb_store(long long L, int nb, int m, int j, int sidx, double tol, const double* __restrict__ b,
+// basis row j of Q and W: x / s and y / s per chain (s = b[bi][sidx]); a chain that fb_mark stopped, now
+// or before, gets zero rows
+__global__ void fb_store(long long L, int nb, int m, int j, int sidx, const double* __restrict__ b,
                          const double* __restrict__ x, const double* __restrict__ y, double* __restrict__ Q,
                          double* __restrict__ W, const int* __restrict__ active) {
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < L * nb;
@@ -203,8 +203,7 @@ __global__ void fb_store(long long L, int nb, int m, int j, int sidx, double tol
     const int bi = (int)(t / L);
     const long long I = t % L;
     const double s = b[(long long)bi * (m + 1) + sidx];
-    const double b0 = b[(long long)bi * (m + 1)];
-    const bool ok = active[bi] != 0 && s > tol * b0 && s > 0.0;
+    const bool ok = active[bi] != 0 && s > 0.0;
     const double f = ok ? 1.0 / s : 0.0;
     const long long o = 2 * ((long long)bi * m * L + (long long)j * L + I);
     Q[o] = x[2 * t] * f;
@@ -214,13 +213,24 @@ __global__ void fb_store(long long L, int nb, int m, int j, int sidx, double tol
   }
 }
 
-__global__ void fb_mark(int nb, int m, int j, int sidx, double tol, const double* __restrict__ b,
-                        int* __restrict__ active, int* __restrict__ steps) {
+// breakdown test, one thread per chain.  sidx = 0: the start vector (its M-norm b_0 must be positive).
+// sidx >= 1: b_sidx <= tol * s with s = max(|a_0|, .., |a_{sidx-1}|, b_1, .., b_{sidx-1}), the largest
+// recurrence coefficient so far (kept in scale[bi]); the coefficients are in the units of H, b_0 carries the
+// start vector's size and does not enter.  A chain that stops records its step count j.
+__global__ void fb_mark(int nb, int m, int j, int sidx, double tol, const double* __restrict__ a,
+                        const double* __restrict__ b, double* __restrict__ scale, int* __restrict__ active,
+                        int* __restrict__ steps) {
   const int bi = blockIdx.x * blockDim.x + threadIdx.x;
-  if (bi >= nb) return;
+  if (bi >= nb || !active[bi]) return;
   const double s = b[(long long)bi * (m + 1) + sidx];
-  const double b0 = b[(long long)bi * (m + 1)];
-  if (active[bi] && !(s > tol * b0 && s > 0.0)) {
+  bool ok = s > 0.0;
+  if (sidx > 0) {
+    double sc = fmax(scale[bi], fabs(a[(long long)bi * m + sidx - 1]));
+    if (sidx > 1) sc = fmax(sc, b[(long long)bi * (m + 1) + sidx - 1]);
+    scale[bi] = sc;
+    ok = ok && s > tol * sc;
+  }
+  if (!ok) {
     active[bi] = 0;
     steps[bi] = j;
   }
@@ -321,9 +331,10 @@ bse_status bse_full_spectrum(bse_plan* plan, const void* P, int32_t nb, int32_t 
   const double tol = 1e-12;
   struct Bufs {
     double *Q = nullptr, *W = nullptr, *blk = nullptr, *hblk = nullptr, *r = nullptr, *hr = nullptr,
-           *da = nullptr, *db = nullptr, *h = nullptr;
+           *da = nullptr, *db = nullptr, *h = nullptr, *scl = nullptr;
     int *act = nullptr, *stp = nullptr;
     ~Bufs() {
+      dfree(scl);
       dfree(Q);
       dfree(W);
       dfree(blk);
@@ -346,10 +357,12 @@ bse_status bse_full_spectrum(bse_plan* plan, const void* P, int32_t nb, int32_t 
   BSE_TRY(dmalloc((void**)&B.da, 8 * (size_t)nb * m));
   BSE_TRY(dmalloc((void**)&B.db, 8 * (size_t)nb * (m + 1)));
   BSE_TRY(dmalloc((void**)&B.h, 16 * (size_t)nb * m));
+  BSE_TRY(dmalloc((void**)&B.scl, 8 * (size_t)nb));
   BSE_TRY(dmalloc((void**)&B.act, sizeof(int) * nb));
   BSE_TRY(dmalloc((void**)&B.stp, sizeof(int) * nb));
   BSE_TRY(zero_fill(B.da, 8 * (size_t)nb * m, st));
   BSE_TRY(zero_fill(B.db, 8 * (size_t)nb * (m + 1), st));
+  BSE_TRY(zero_fill(B.scl, 8 * (size_t)nb, st));
   {
     std::vector<int> one(nb, 1), full(nb, m);
     BSE_HIP(hipMemcpyAsync(B.act, one.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
@@ -364,8 +377,9 @@ bse_status bse_full_spectrum(bse_plan* plan, const void* P, int32_t nb, int32_t 
   BSE_TRY(bse_apply_full(plan, B.blk, B.hblk, nb, hip_stream));
   hipLaunchKernelGGL(fb_rows_from_block, dim3(gL), dim3(256), 0, st, L, nb, B.hblk, B.hr);
   hipLaunchKernelGGL(fb_jdot, dim3(nb), dim3(FB), 0, st, N, B.hr, L, B.r, L, B.db, (long long)(m + 1), 1);
-  hipLaunchKernelGGL(fb_mark, dim3((nb + 63) / 64), dim3(64), 0, st, nb, m, 0, 0, -1.0, B.db, B.act, B.stp);
-  hipLaunchKernelGGL(fb_store, dim3(gL), dim3(256), 0, st, L, nb, m, 0, 0, -1.0, B.db, B.r, B.hr, B.Q, B.W, B.act);
+  hipLaunchKernelGGL(fb_mark, dim3((nb + 63) / 64), dim3(64), 0, st, nb, m, 0, 0, tol, B.da, B.db, B.scl, B.act,
+                     B.stp);
+  hipLaunchKernelGGL(fb_store, dim3(gL), dim3(256), 0, st, L, nb, m, 0, 0, B.db, B.r, B.hr, B.Q, B.W, B.act);
   BSE_CHECK_LAUNCH();
   for (int j = 0; j < m; ++j) {
     {
@@ -389,10 +403,10 @@ bse_status bse_full_spectrum(bse_plan* plan, const void* P, int32_t nb, int32_t 
       hipLaunchKernelGGL(fb_rows_from_block, dim3(gL), dim3(256), 0, st, L, nb, B.hblk, B.hr);
       // b_{j+1} = |r|_M
       hipLaunchKernelGGL(fb_jdot, dim3(nb), dim3(FB), 0, st, N, B.hr, L, B.r, L, B.db + (j + 1), (long long)(m + 1), 1);
-      hipLaunchKernelGGL(fb_mark, dim3((nb + 63) / 64), dim3(64), 0, st, nb, m, j + 1, j + 1, tol, B.db, B.act,
-                         B.stp);
-      hipLaunchKernelGGL(fb_store, dim3(gL), dim3(256), 0, st, L, nb, m, j + 1, j + 1, tol, B.db, B.r, B.hr, B.Q,
-                         B.W, B.act);
+      hipLaunchKernelGGL(fb_mark, dim3((nb + 63) / 64), dim3(64), 0, st, nb, m, j + 1, j + 1, tol, B.da, B.db,
+                         B.scl, B.act, B.stp);
+      hipLaunchKernelGGL(fb_store, dim3(gL), dim3(256), 0, st, L, nb, m, j + 1, j + 1, B.db, B.r, B.hr, B.Q, B.W,
+                         B.act);
       BSE_CHECK_LAUNCH();
     }
   }

@@ -152,21 +152,36 @@ __global__ void lz_subtract(long long N, int m, int j, const double* __restrict_
   w[2 * (bi * N + I) + 1] -= si;
 }
 
-// breakdown test and q_{j+1} = w / b_j
-__global__ void lz_next(long long N, int nb, int m, int j, double tol, const double* __restrict__ b,
+// breakdown test of step j, one thread per chain: b_j <= tol * s_j with s_j = max(|a_1|, .., |a_j|,
+// b_1, .., b_{j-1}), the largest recurrence coefficient of the chain so far (kept in scale[bi]).  b_j is in
+// the units of A (the q_j are unit vectors); b_0 = |p| is the start vector's size and does not enter, so the
+// test does not depend on how p is scaled.  A chain that breaks down records steps = j and goes inactive.
+__global__ void lz_decide(int nb, int m, int j, double tol, const double* __restrict__ a,
+                          const double* __restrict__ b, double* __restrict__ scale, int* __restrict__ active,
+                          int* __restrict__ steps) {
+  const int bi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (bi >= nb || !active[bi]) return;
+  double sc = fmax(scale[bi], fabs(a[(long long)bi * m + j - 1]));
+  if (j > 1) sc = fmax(sc, b[(long long)bi * (m + 1) + j - 1]);
+  scale[bi] = sc;
+  const double bj = b[(long long)bi * (m + 1) + j];
+  if (!(bj > tol * sc)) {
+    active[bi] = 0;
+    steps[bi] = j;
+  }
+}
+
+// q_{j+1} = w / b_j on the chains still active after step j's test (zero on the others)
+__global__ void lz_next(long long N, int nb, int m, int j, const double* __restrict__ b,
                         const double* __restrict__ w, double* __restrict__ basis, double* __restrict__ Qcur,
-                        int* __restrict__ active, int* __restrict__ steps) {
+                        const int* __restrict__ active) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= N * nb) return;
   const long long I = t / nb;
   const int bi = (int)(t % nb);
-  const double b0 = b[(long long)bi * (m + 1)];
-  const double bj = b[(long long)bi * (m + 1) + j];
-  const bool alive = active[bi] != 0;
-  const bool brk = !(bj > tol * b0);
-  // every thread sees the same inputs; thread I == 0 records the state change
   double vr = 0, vi = 0;
-  if (alive && !brk) {
+  if (active[bi]) {
+    const double bj = b[(long long)bi * (m + 1) + j];
     vr = w[2 * (bi * N + I)] / bj;
     vi = w[2 * (bi * N + I) + 1] / bj;
   }
@@ -177,15 +192,6 @@ __global__ void lz_next(long long N, int nb, int m, int j, double tol, const dou
     row[0] = vr;
     row[1] = vi;
   }
-  if (I == 0 && alive && brk) steps[bi] = j;
-}
-
-__global__ void lz_mark(int nb, int m, int j, double tol, const double* __restrict__ b, int* __restrict__ active) {
-  const int bi = blockIdx.x * blockDim.x + threadIdx.x;
-  if (bi >= nb) return;
-  const double b0 = b[(long long)bi * (m + 1)];
-  const double bj = b[(long long)bi * (m + 1) + j];
-  if (active[bi] && !(bj > tol * b0)) active[bi] = 0;
 }
 
 // continued fraction, one thread per (chain, frequency)
@@ -247,7 +253,7 @@ extern "C" bse_status bse_haydock_spectrum(bse_plan* plan, const void* P, int32_
 
   struct Bufs {
     double *basis = nullptr, *Q = nullptr, *Wb = nullptr, *w = nullptr, *da = nullptr, *db = nullptr, *h = nullptr,
-           *part = nullptr, *dom = nullptr, *dS = nullptr;
+           *part = nullptr, *dom = nullptr, *dS = nullptr, *scl = nullptr;
     int *act = nullptr, *stp = nullptr;
     bool own_basis = false;
     ~Bufs() {
@@ -261,6 +267,7 @@ extern "C" bse_status bse_haydock_spectrum(bse_plan* plan, const void* P, int32_
       dfree(part);
       dfree(dom);
       dfree(dS);
+      dfree(scl);
       dfree(act);
       dfree(stp);
     }
@@ -280,10 +287,12 @@ extern "C" bse_status bse_haydock_spectrum(bse_plan* plan, const void* P, int32_
   BSE_TRY(dmalloc((void**)&B.part, 16 * (size_t)nb * nblk));
   BSE_TRY(dmalloc((void**)&B.dom, 8 * (size_t)n_w));
   BSE_TRY(dmalloc((void**)&B.dS, 8 * (size_t)nb * n_w));
+  BSE_TRY(dmalloc((void**)&B.scl, 8 * (size_t)nb));
   BSE_TRY(dmalloc((void**)&B.act, sizeof(int) * nb));
   BSE_TRY(dmalloc((void**)&B.stp, sizeof(int) * nb));
   BSE_TRY(zero_fill(B.da, 8 * (size_t)nb * m, st));
   BSE_TRY(zero_fill(B.db, 8 * (size_t)nb * (m + 1), st));
+  BSE_TRY(zero_fill(B.scl, 8 * (size_t)nb, st));
   BSE_HIP(hipMemcpyAsync(B.dom, omega, 8 * (size_t)n_w, hipMemcpyHostToDevice, st));
 
   const unsigned gN = (unsigned)((N * nb + 255) / 256);
@@ -310,9 +319,9 @@ extern "C" bse_status bse_haydock_spectrum(bse_plan* plan, const void* P, int32_
     }
     hipLaunchKernelGGL(dotc_partial, dim3(nblk, nb), dim3(RB), 0, st, N, B.w, N, B.w, N, B.part);
     hipLaunchKernelGGL(dot_finalize, dim3(nb), dim3(RB), 0, st, nblk, B.part, B.db + j, (long long)(m + 1), 1);
-    hipLaunchKernelGGL(lz_next, dim3(gN), dim3(256), 0, st, N, nb, m, j, tol, B.db, B.w, B.basis, B.Q, B.act,
+    hipLaunchKernelGGL(lz_decide, dim3((nb + 63) / 64), dim3(64), 0, st, nb, m, j, tol, B.da, B.db, B.scl, B.act,
                        B.stp);
-    hipLaunchKernelGGL(lz_mark, dim3((nb + 63) / 64), dim3(64), 0, st, nb, m, j, tol, B.db, B.act);
+    hipLaunchKernelGGL(lz_next, dim3(gN), dim3(256), 0, st, N, nb, m, j, B.db, B.w, B.basis, B.Q, B.act);
     BSE_CHECK_LAUNCH();
   }
   {

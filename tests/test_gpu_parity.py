@@ -327,6 +327,19 @@ def test_haydock_full_krylov_and_breakdown(B):
     te = O.transition_energies(p).ravel()
     ref = (0.1 / np.pi) / ((w - te[5]) ** 2 + 0.01) / p.Nk
     assert rel(out0["S"][0], ref) < 1e-13
+    # three entries with distinct energies: the Krylov space is invariant after three steps, and the chain
+    # stops there however large or small the start vector is (the test is against the chain's own scale of A)
+    idx = [1, 6, 11]
+    assert len(set(np.round(te[idx], 12))) == 3
+    v = np.zeros((p.N, 1), dtype=complex)
+    v[idx, 0] = [0.6, -0.3 + 0.2j, 0.5j]
+    runs = [plan0.haydock(T(sp * v), 10, w, 0.1) for sp in (1.0, 1e-20, 1e20)]
+    ref3 = (0.1 / np.pi) * sum(abs(v[i, 0]) ** 2 / ((w - te[i]) ** 2 + 0.01) for i in idx) / p.Nk
+    for sp, r in zip((1.0, 1e-20, 1e20), runs):
+        assert r["breakdown"] and r["steps"][0] == 3, (sp, r["steps"])
+        assert np.abs(r["a"][0, :3] - runs[0]["a"][0, :3]).max() < 1e-13 * te.max()
+        assert np.abs(r["b"][0, 1:3] - runs[0]["b"][0, 1:3]).max() < 1e-13 * te.max()
+        assert rel(r["S"][0] / sp ** 2, ref3) < 1e-12
 
 
 # ---------------------------------------------------------------------------

@@ -78,3 +78,28 @@ def test_c1_convergence_in_m():
     S200 = O.haydock_spectrum(lambda x: H @ x, P, 200, w, 0.1, p.Nk)[0]
     err = np.abs(S200 - Sref).max() / np.abs(Sref).max()
     assert err < 1e-8
+
+
+def test_breakdown_does_not_depend_on_the_scales(small_cfg):
+    # p supported on three distinct transition energies of a diagonal H: the Krylov space is invariant after
+    # three steps.  The chain must stop there whatever the size of p (b_0) or of H: a test against b_0 would
+    # run on into rounding noise for a tiny p, and stop at once for a huge one
+    p = make_problem(small_cfg, 0)
+    te = O.transition_energies(p).ravel()
+    idx = [3, 11, 20]
+    assert len(set(np.round(te[idx], 12))) == 3
+    v = np.zeros(p.N, dtype=complex)
+    v[idx] = [0.6, -0.3 + 0.2j, 0.5j]
+    ref = None
+    for sp in (1.0, 1e-20, 1e20):
+        for sh in (1.0, 1e-8, 1e8):
+            H = np.diag(sh * te).astype(complex)
+            a, b, st, _ = O.haydock(lambda x: H @ x, sp * v, 10)
+            assert st == 3, (sp, sh, st)
+            assert b[3] <= 1e-14 * sh * te.max()
+            # the recurrence coefficients scale with H alone, b_0 with p alone
+            assert abs(b[0] - sp * np.linalg.norm(v)) <= 1e-15 * b[0]
+            if ref is None:
+                ref = (a[:3].copy(), b[1:3].copy())
+            assert np.allclose(a[:3] / sh, ref[0], rtol=1e-13, atol=0)
+            assert np.allclose(b[1:3] / sh, ref[1], rtol=1e-12, atol=0)
