@@ -220,6 +220,16 @@ bse_status bse_plan_conduction(const bse_plan* plan, int32_t* forms_mc);
  * two GEMMs instead.  Host pointer. */
 bse_status bse_plan_fused(const bse_plan* plan, int32_t* fused);
 
+/* *frag = 1 when the plan stores its BF16X3 halves B^mu_n(k) in the fragment
+ * order of the pair-density kernel (BF16X3 with k-independent coefficients,
+ * N_ao = 128, N_aux a multiple of 32, n_v^2 a multiple of 8): per k and band
+ * side the [n_band N_aux][N_ao] matrix is laid out as 32-column by 16-k blocks
+ * of 1 KiB, each the operand of one matrix-core step, so that the streaming
+ * kernel reads whole KiB instead of 32-byte pieces of 32 rows.  The results are
+ * identical to those of the row layout.  BSE_FRAG_HALVES=0 in the environment
+ * at plan creation keeps the row layout.  Host pointer. */
+bse_status bse_plan_frag(const bse_plan* plan, int32_t* frag);
+
 /* Device bytes held by the plan (copies, halves and workspaces). */
 bse_status bse_plan_bytes(const bse_plan* plan, uint64_t* bytes);
 

@@ -54,6 +54,7 @@ _SIGS = {
     "bse_plan_pairs": [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
     "bse_plan_conduction": [_vp, ctypes.POINTER(ctypes.c_int32)],
     "bse_plan_fused": [_vp, ctypes.POINTER(ctypes.c_int32)],
+    "bse_plan_frag": [_vp, ctypes.POINTER(ctypes.c_int32)],
     "bse_offset_spectrum": [_vp, _vp, _vp, _i32, _i32, _i32, _vp, _i32, ctypes.c_double, _vp, _vp, _vp],
     "bse_offset_set": [ctypes.POINTER(ctypes.c_int32), _vp, _vp],
     "bse_apply": [_vp, _vp, _vp, _i32, _vp],
@@ -264,6 +265,13 @@ class Plan:
         """True when an apply forms the W step and the direct block in one kernel (P kept on chip)."""
         v = ctypes.c_int32()
         _check("bse_plan_fused", lib().bse_plan_fused(self._ptr, ctypes.byref(v)))
+        return bool(v.value)
+
+    @property
+    def frag(self):
+        """True when the plan keeps its BF16x3 halves in the pair-density kernel's fragment order."""
+        v = ctypes.c_int32()
+        _check("bse_plan_frag", lib().bse_plan_frag(self._ptr, ctypes.byref(v)))
         return bool(v.value)
 
     @property

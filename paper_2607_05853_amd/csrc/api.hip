@@ -471,6 +471,13 @@ bse_status build_plan(Plan* p, const bse_dims* d, const double* eps_qp, const vo
   p->ps_W = nw;
   p->ps_Bv = hv;
   p->ps_Bc = hc;
+  // BF16X3 halves in fragment order where every pair-density product of the plan runs on the streaming
+  // kernel: K = N_ao = 128, columns in whole 32-blocks, split results (k-independent coefficients, and the
+  // k-major adjoint's alignment)
+  p->frag_halves = (p->split && !tc && no == 128 && na % 32 == 0 && (nv * nv) % 8 == 0 && na % 8 == 0 &&
+                    frag_halves_enabled())
+                       ? 1
+                       : 0;
   BSE_TRY(plan_alloc(p, &p->Bv, p->esz * hv));
   BSE_TRY(plan_alloc(p, &p->Bc, p->esz * hc));
   if (p->split) BSE_TRY(plan_alloc(p, &p->BcT, 8 * hc));
@@ -589,7 +596,13 @@ bse_status build_plan(Plan* p, const bse_dims* d, const double* eps_qp, const vo
         break;
       }
     }
-    if (p->split) {
+    if (p->split && p->frag_halves) {
+      s = split_planes_frag(dv, (__bf16*)p->Bv + (long long)k0 * nv * na * no, kn, nv * na, no, hv, st);
+      if (s == BSE_OK)
+        s = split_planes_frag(dc, (__bf16*)p->Bc + (long long)k0 * nc * na * no, kn, nc * na, no, hc, st);
+      if (s == BSE_OK)
+        s = split_planes_T(dc, true, (__bf16*)p->BcT + (long long)k0 * nc * no * na, kn * nc, na, no, hc, st);
+    } else if (p->split) {
       s = split_planes(dv, true, (__bf16*)p->Bv + (long long)k0 * nv * na * no, (long long)kn * nv * na * no, hv, st);
       if (s == BSE_OK)
         s = split_planes(dc, true, (__bf16*)p->Bc + (long long)k0 * nc * na * no, (long long)kn * nc * na * no, hc,
@@ -981,6 +994,15 @@ bse_status bse_plan_fused(const bse_plan* plan, int32_t* fused) {
     return BSE_EINVAL;
   }
   *fused = (plan->impl.fused_wt && fused_wstep_enabled()) ? 1 : 0;
+  return BSE_OK;
+}
+
+bse_status bse_plan_frag(const bse_plan* plan, int32_t* frag) {
+  if (!plan || bad_ptr(frag)) {
+    set_error("bse_plan_frag: NULL argument");
+    return BSE_EINVAL;
+  }
+  *frag = plan->impl.frag_halves ? 1 : 0;
   return BSE_OK;
 }
 

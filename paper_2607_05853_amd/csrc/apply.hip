@@ -546,6 +546,7 @@ bse_status form_pair_densities(Plan* p, int q0, int nq, bool need_c, const int* 
       g.a_tab_pb = 1;
       g.a_sk = 1;
       g.B = p->Bv;
+      g.b_frag = p->frag_halves;
       g.b_sb = (long long)nv * na * no;
       g.b_sj = no;
       g.b_sk = 1;
@@ -575,6 +576,7 @@ bse_status form_pair_densities(Plan* p, int q0, int nq, bool need_c, const int* 
       g.a_tab_pb = 1;
       g.a_sk = 1;
       g.B = p->Bc;
+      g.b_frag = p->frag_halves;
       g.b_sb = (long long)nc * na * no;
       g.b_sj = no;
       g.b_sk = 1;
@@ -760,6 +762,7 @@ bse_status apply_coupling_direct(Plan* p, const double* X, double* Y, int nb, hi
         g.a_tab_pb = 1;
         g.a_sk = 1;
         g.B = p->Bv;
+        g.b_frag = p->frag_halves;
         g.b_sb = (long long)nv * na * no;
         g.b_sj = no;
         g.b_sk = 1;
@@ -788,6 +791,7 @@ bse_status apply_coupling_direct(Plan* p, const double* X, double* Y, int nb, hi
         g.a_tab_pb = 1;
         g.a_sk = 1;
         g.B = p->Bc;
+        g.b_frag = p->frag_halves;
         g.b_sb = (long long)nc * na * no;
         g.b_sj = no;
         g.b_sk = 1;

@@ -79,6 +79,9 @@ struct GemmArgs {
   int tab_aligned = 0;
   // k-major kernel with a c128 result: batch entry b of the product is stored at C batch c_bidx[b]
   const int* c_bidx = nullptr;
+  // B pre-split in fragment order (split_planes_frag; b_sb per batch entry, b_ps per plane, column j and
+  // k as that layout places them; b_sj and b_sk unused): only the streaming pair-density kernel reads it
+  int b_frag = 0;
 };
 
 // in_f64: A and B are c128 (else c64); out_f64: C is c128 (else c64).
@@ -96,6 +99,16 @@ bse_status wstep_dblock(const GemmArgs& g, const __bf16* mc, long long mc_sb, lo
                         hipStream_t st);
 // BSE_FUSED_WSTEP=0 in the environment selects the two GEMMs (read at every call)
 bool fused_wstep_enabled();
+// Fragment order of a pre-split B operand for the streaming pair-density kernel: each batch entry's
+// N x K matrix (N a multiple of 32, K of 16) as [N/32][K/16][64 lanes][8], lane 32 h + c of block (jb, s)
+// holding column 32 jb + c, k = 16 s + 8 h .. 16 s + 8 h + 7 -- the 16 bytes that lane passes to one 32x32x16
+// MFMA, so a wave reads each fragment as one contiguous KiB.  in: c128 [batch][N][K]; out: four planes of
+// batch * N * K bf16 at plane_stride.
+bse_status split_planes_frag(const double* in, __bf16* out, int batch, int N, int K, long long plane_stride,
+                             hipStream_t st);
+// the plan stores its BF16X3 halves in fragment order when its shape allows it; BSE_FRAG_HALVES=0 in the
+// environment at plan creation keeps the row order
+bool frag_halves_enabled();
 // split c64 / c128 arrays into four bf16 planes (util.hip); n complex elements,
 // optionally transposing each of `batch` rows x cols matrices
 bse_status split_planes(const void* in, bool in_f64, __bf16* out, long long n, long long plane_stride,
@@ -158,6 +171,7 @@ struct Plan {
   // conduction side: 1 = form M_cc' and T = M_c P^T (FP64 / FP32 always), 0 = B_c(k) contraction (BF16X3)
   int mc_direct = 1;
   int fused_wt = 0;  // the shape admits the fused W step + direct block (BF16X3, M_cc' route, n_v = n_c = 8)
+  int frag_halves = 0;  // BF16X3 halves Bv, Bc stored in fragment order (split_planes_frag)
   int* kqp = nullptr;
   int* kqm = nullptr;
   int* qord = nullptr;              // [Nk] dense-mesh index of the j-th q of that order

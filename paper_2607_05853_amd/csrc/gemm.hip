@@ -1500,11 +1500,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 // CU stay in flight) and writes its 128 x 32 result through a private 4 KiB LDS buffer with 16-byte stores:
 // no block barrier separates one tile from the next.  Each accumulator receives the MFMA sequence of
 // cgemm_b3_dma over k in order, so the results are identical to those of the other split kernels.
-// A in LDS as [plane][128 rows][K], 16-byte chunk c of row r stored at c ^ (r % (K / 8)).
+// A in LDS as [plane][128 rows][K], 16-byte chunk c of row r stored at c ^ (r % (K / 8)).  FRAG: B in fragment
+// order (split_planes_frag), so that each of a wave's fragment loads reads one contiguous KiB instead of 16
+// or 32 bytes of 32 different columns.
 constexpr int PD_BM = 128, PD_BN = 256, PD_KMAX = 128, PD_AHEAD = 2;
 constexpr size_t PD_LDS = (size_t)4 * PD_BM * PD_KMAX * sizeof(__bf16) + 8 * 4096;  // 160 KiB
 
-template <int NK>
+template <int NK, bool FRAG>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void cgemm_b3_stream(GemmArgs g) {
   constexpr int K = 16 * NK, CPR = K / 8;  // k, 16-byte chunks per A row
   constexpr int APL = PD_BM * K;           // bf16 per A plane
@@ -1522,16 +1524,24 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const long long it1 = it0 + per < items ? it0 + per : items;
   if (it0 >= it1) return;  // uniform over the block
   // B fragments of tile `it`, k step kt: column n0 + 32 wave + l32 (a valid column past the edge), k 16 kt + 8 h
+  // (FRAG: the wave's 32-column block, the last one past the edge)
   auto bsrc = [&](long long it) -> const __bf16* {
     const long long bm = it / gxn;
     const int b = (int)(bm / gyn), n0 = (int)(it % gxn) * PD_BN;
-    const int col = n0 + 32 * wave + l32;
-    return (const __bf16*)g.B + off_of(g.b_tab, g.b_tab_pb, g.b_sb, g.b_sj, b, g.N, col < g.N ? col : g.N - 1) + 8 * h;
+    if constexpr (FRAG) {
+      const int last = g.N / 32 - 1, jb = n0 / 32 + wave;
+      return (const __bf16*)g.B + (long long)b * g.b_sb + (long long)(jb < last ? jb : last) * (NK * 512) + 8 * lane;
+    } else {
+      const int col = n0 + 32 * wave + l32;
+      return (const __bf16*)g.B + off_of(g.b_tab, g.b_tab_pb, g.b_sb, g.b_sj, b, g.N, col < g.N ? col : g.N - 1) +
+             8 * h;
+    }
   };
   bf8v bq[PD_AHEAD][4];
+  constexpr int BSTEP = FRAG ? 512 : 16;  // bf16 between the fragments of consecutive k steps
   auto load_b = [&](const __bf16* src, int kt, bf8v* dst) {
 #pragma unroll
-    for (int pl = 0; pl < 4; ++pl) dst[pl] = *reinterpret_cast<const bf8v*>(src + pl * g.b_ps + 16 * kt);
+    for (int pl = 0; pl < 4; ++pl) dst[pl] = *reinterpret_cast<const bf8v*>(src + pl * g.b_ps + BSTEP * kt);
   };
   const __bf16* bs = bsrc(it0);
 #pragma unroll
@@ -2163,6 +2173,20 @@ bse_status wstep_dblock(const GemmArgs& g, const __bf16* mc, long long mc_sb, lo
   return BSE_OK;
 }
 
+template <int NK, bool FRAG>
+bse_status launch_stream(const GemmArgs& g, hipStream_t st) {
+  int dev = 0, ncu = 0;
+  BSE_HIP(hipGetDevice(&dev));
+  BSE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const long long items = (long long)g.batch * ((g.M + PD_BM - 1) / PD_BM) * ((g.N + PD_BN - 1) / PD_BN);
+  const unsigned grid = (unsigned)std::max<long long>(1, std::min<long long>(items, ncu));
+  BSE_HIP(hipFuncSetAttribute((const void*)cgemm_b3_stream<NK, FRAG>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)PD_LDS));
+  hipLaunchKernelGGL((cgemm_b3_stream<NK, FRAG>), dim3(grid), dim3(512), PD_LDS, st, g);
+  BSE_CHECK_LAUNCH();
+  return BSE_OK;
+}
+
 bse_status cgemm_split(const GemmArgs& g, bool a_split, bool b_split, bool c_split, bool out_f64, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return BSE_OK;
   if (g.K <= 0) {
@@ -2173,6 +2197,14 @@ bse_status cgemm_split(const GemmArgs& g, bool a_split, bool b_split, bool c_spl
     if (a_split && b_split && !c_split && out_f64 && !dma_ok(g) && tn_ok(g)) return launch_tn(g, false, st);
     set_error("cgemm_split: a batch index table needs the k-major kernel");
     return BSE_EINVAL;
+  }
+  if (g.b_frag) {  // a B operand in fragment order: only the streaming kernel reads that layout
+    if (!(a_split && b_split && c_split && dma_ok(g) && g.K == PD_KMAX && g.N % 32 == 0 && !g.conjA && !g.conjB &&
+          !g.b_tab)) {
+      set_error("cgemm_split: a fragment-order B needs split operands and result, K = 128, N a multiple of 32");
+      return BSE_EINVAL;
+    }
+    return launch_stream<8, true>(g, st);
   }
   if (a_split && b_split && dma_ok(g)) {
     if (!c_split && g.M <= 64 && g.N <= 64) {  // small per-pair products: quarter-size tiles
@@ -2195,18 +2227,7 @@ bse_status cgemm_split(const GemmArgs& g, bool a_split, bool b_split, bool c_spl
     if (c_split && (g.K == 64 || g.K == 128) && g.M <= 2 * PD_BM && g.N >= 4 * PD_BN && !g.conjA && !g.conjB &&
         stream_enabled()) {
       // short K, few rows, many columns (the pair densities): persistent streaming blocks, one per CU
-      int dev = 0, ncu = 0;
-      BSE_HIP(hipGetDevice(&dev));
-      BSE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-      const long long items = (long long)g.batch * ((g.M + PD_BM - 1) / PD_BM) * ((g.N + PD_BN - 1) / PD_BN);
-      const unsigned grid = (unsigned)std::max<long long>(1, std::min<long long>(items, ncu));
-      auto go = [&](auto kern) -> bse_status {
-        BSE_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)PD_LDS));
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(512), PD_LDS, st, g);
-        BSE_CHECK_LAUNCH();
-        return BSE_OK;
-      };
-      return g.K == 64 ? go(cgemm_b3_stream<4>) : go(cgemm_b3_stream<8>);
+      return g.K == 64 ? launch_stream<4, false>(g, st) : launch_stream<8, false>(g, st);
     }
     if (c_split && g.K >= WB_MIN_K && g.N >= 256 && g.M >= 128 && wide_tiles_enabled()) {
       // long K and a wide B (the W step): 128 x 256 tiles, three LDS stages

@@ -1,4 +1,6 @@
 // Small streaming kernels: precision conversion and fills.
+#include <cstdlib>
+
 #include "bse_internal.h"
 
 namespace bse {
@@ -62,6 +64,29 @@ __global__ void split_T_kernel(const T* __restrict__ in, __bf16* __restrict__ ou
   }
 }
 
+// fragment order (see split_planes_frag): output element i of batch entry b comes from column
+// 32 jb + (l % 32), k = 16 s + 8 (l / 32) + e of in[b], i = ((jb * (K / 16) + s) * 64 + l) * 8 + e
+__global__ void split_frag_kernel(const double* __restrict__ in, __bf16* __restrict__ out, int batch, int N, int K,
+                                  long long ps) {
+  const long long per = (long long)N * K, n = per * batch;
+  const int S = K / 16;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long b = i / per, r = i % per;
+    const int e = (int)(r & 7), l = (int)((r >> 3) & 63);
+    const long long f = r >> 9;  // jb * S + s
+    const int s = (int)(f % S), jb = (int)(f / S);
+    const int col = 32 * jb + (l & 31), kk = 16 * s + 8 * (l >> 5) + e;
+    const long long src = b * per + (long long)col * K + kk;
+    const float re = (float)in[2 * src], im = (float)in[2 * src + 1];
+    const __bf16 rh = (__bf16)re, ih = (__bf16)im;
+    out[i] = rh;
+    out[ps + i] = (__bf16)(re - (float)rh);
+    out[2 * ps + i] = ih;
+    out[3 * ps + i] = (__bf16)(im - (float)ih);
+  }
+}
+
 // out[b][c][r] = (complex64) in[b][r][c]: batch complex128 matrices rows x cols, transposed and rounded
 __global__ void cvt_T_kernel(const double* __restrict__ in, float* __restrict__ out, int batch, int rows, int cols) {
   const long long per = (long long)rows * cols, n = per * batch;
@@ -96,6 +121,24 @@ bse_status split_planes(const void* in, bool in_f64, __bf16* out, long long n, l
                        plane_stride);
   BSE_CHECK_LAUNCH();
   return BSE_OK;
+}
+
+bse_status split_planes_frag(const double* in, __bf16* out, int batch, int N, int K, long long plane_stride,
+                             hipStream_t st) {
+  if (N % 32 != 0 || K % 16 != 0) {
+    set_error("split_planes_frag: N must be a multiple of 32 and K of 16");
+    return BSE_ESHAPE;
+  }
+  const long long n = (long long)batch * N * K;
+  if (n <= 0) return BSE_OK;
+  hipLaunchKernelGGL(split_frag_kernel, dim3(grid_for(n)), dim3(256), 0, st, in, out, batch, N, K, plane_stride);
+  BSE_CHECK_LAUNCH();
+  return BSE_OK;
+}
+
+bool frag_halves_enabled() {
+  const char* e = std::getenv("BSE_FRAG_HALVES");
+  return !(e && e[0] == '0');
 }
 
 bse_status split_planes_T(const void* in, bool in_f64, __bf16* out, int batch, int rows, int cols,

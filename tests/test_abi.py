@@ -121,6 +121,8 @@ def test_null_plan_calls(L):
     assert L.bse_plan_pairs(None, ctypes.byref(a), ctypes.byref(b)) == 1
     c = ctypes.c_int32()
     assert L.bse_plan_conduction(None, ctypes.byref(c)) == 1
+    assert L.bse_plan_fused(None, ctypes.byref(c)) == 1
+    assert L.bse_plan_frag(None, ctypes.byref(c)) == 1
     # offset averaging: NULL arrays and empty offset lists are rejected before any HIP call
     w = (ctypes.c_double * 1)(1.0)
     om = (ctypes.c_double * 1)(2.0)

@@ -5,7 +5,7 @@ oracle's explicit A and against the kernels they replace.
 The wide tile and the streaming kernel give results identical to the tiled kernels (same MFMA sequence per
 accumulator); the fused kernel forms T = M_c P^T on 16x16x32 MFMA in another summation order, so it is held
 to the BF16x3 bound of the kernel part.  BSE_WIDE_TILES=0 / BSE_FUSED_WSTEP=0 / BSE_STREAM_PD=0 select the
-previous kernels at the next apply.
+previous kernels at the next apply; BSE_FRAG_HALVES=0 at plan creation keeps the halves in row order.
 """
 import os
 
@@ -28,6 +28,9 @@ FUSED_512 = dict(cfg_id=71, coarse=(2, 2, 2), dense=(2, 2, 2), n_ao=16, nv=8, nc
 STREAM_64 = dict(cfg_id=73, coarse=(2, 2, 2), dense=(2, 2, 3), n_ao=64, nv=3, nc=5, n_aux=400)
 STREAM_128 = dict(cfg_id=74, coarse=(2, 2, 2), dense=(2, 2, 3), n_ao=128, nv=3, nc=5, n_aux=400)
 WIDE_RAGGED = dict(cfg_id=72, coarse=(2, 2, 2), dense=(3, 3, 2), n_ao=16, nv=3, nc=4, n_aux=272)
+# halves in fragment order (N_ao = 128, N_aux a multiple of 32, n_v^2 a multiple of 8): columns
+# n_band x N_aux of 1664 / 2496, so the last 256-column tile holds 4 / 6 of the 8 waves' 32-column blocks
+FRAG_128 = dict(cfg_id=75, coarse=(2, 2, 2), dense=(2, 2, 3), n_ao=128, nv=4, nc=6, n_aux=416)
 
 
 def dev():
@@ -122,3 +125,58 @@ def test_stream_pair_densities_identical(B, cfg, all_pairs):
     assert np.array_equal(Ys, Yt)
     assert err < KERNEL_TOL["bf16x3"]
     plan.close()
+
+
+def _plan_with(B, p, Wq, frag, **kw):
+    old = os.environ.get("BSE_FRAG_HALVES")
+    os.environ["BSE_FRAG_HALVES"] = "1" if frag else "0"
+    try:
+        return B.plan_from_problem(p, Wq, prec="bf16x3", max_nb=4, **kw)
+    finally:
+        if old is None:
+            del os.environ["BSE_FRAG_HALVES"]
+        else:
+            os.environ["BSE_FRAG_HALVES"] = old
+
+
+@pytest.mark.parametrize("all_pairs", [False, True])
+def test_fragment_order_halves_identical(B, all_pairs):
+    # the streaming kernel on halves in fragment order against the row layout (streaming and tiled kernels):
+    # apply, adjoint (every pair-density product of the gradient) and the coupling block, bit for bit
+    p = make_problem(FRAG_128, 5, "G2")
+    kq = dense_kmesh(p.nk)
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, kq)
+    pf = _plan_with(B, p, Wq, True, conduction="mc", all_pairs=all_pairs)
+    pr = _plan_with(B, p, Wq, False, conduction="mc", all_pairs=all_pairs)
+    assert pf.frag and not pr.frag
+    X = random_block(p.N, 4, seed=11)
+    Yb = random_block(p.N, 4, seed=12)
+    Yf = H_(pf.apply(T(X)))
+    Yr = _apply_with(pr, X, "BSE_STREAM_PD", "1")
+    Yt = _apply_with(pr, X, "BSE_STREAM_PD", "0")
+    H = O.build_H(p, O.interpolate_W_matmul(p.W_R, p.R, p.w_R, kq))
+    err = kernel_err(Yf, H @ X, diag_times(p, X))
+    gf = pf.apply_adjoint(T(Yb), T(X), want_WR=False, want_Wq=True)
+    gr = pr.apply_adjoint(T(Yb), T(X), want_WR=False, want_Wq=True)
+    Bf = H_(pf.apply_coupling(T(X)))
+    Br = H_(pr.apply_coupling(T(X)))
+    print("[fragment-order halves, all pairs %s] kernel-part err %.2e; identical: apply %s / %s, g_W(q) %s, "
+          "g_eps %s, coupling %s" % (all_pairs, err, np.array_equal(Yf, Yr), np.array_equal(Yf, Yt),
+                                      torch.equal(gf["W_q"], gr["W_q"]), torch.equal(gf["eps"], gr["eps"]),
+                                      np.array_equal(Bf, Br)), flush=True)
+    assert err < KERNEL_TOL["bf16x3"]
+    assert np.array_equal(Yf, Yr) and np.array_equal(Yf, Yt)
+    assert torch.equal(gf["W_q"], gr["W_q"]) and torch.equal(gf["eps"], gr["eps"])
+    assert np.array_equal(Bf, Br)
+    pf.close()
+    pr.close()
+
+
+def test_fragment_order_only_where_it_applies(B):
+    # row layout for shapes the fragment order does not cover (N_ao = 64; n_v^2 odd) and for FP32
+    for cfg, prec in ((STREAM_64, "bf16x3"), (STREAM_128, "bf16x3"), (FRAG_128, "f32")):
+        p = make_problem(cfg, 3, "G2")
+        Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
+        pl = B.plan_from_problem(p, Wq, prec=prec, max_nb=2)
+        assert not pl.frag, (cfg, prec)
+        pl.close()
