@@ -1596,12 +1596,17 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         bf8v a[4];
 #pragma unroll
         for (int pl = 0; pl < 4; ++pl) a[pl] = *reinterpret_cast<const bf8v*>(sA + pl * APL + o);
-        cmma_b3(a, neg8(a[2]), neg8(a[3]), bb, accR[i], accI[i]);
+        // B fragments as the MFMA's first operand: the lane's registers 4 g .. 4 g + 3 hold four
+        // consecutive columns of one row, which the epilogue packs into 8-byte writes
+        cmma_b3_t(a, neg8(a[2]), neg8(a[3]), bb, accR[i], accI[i]);
         __builtin_amdgcn_sched_barrier(0);
       }
     }
     bs = bn;
-    // epilogue: per row sub-tile and part (Re, Im), hi and lo planes of 32 x 32 through the wave's buffer
+    // epilogue: per row sub-tile and part (Re, Im), hi and lo planes of 32 x 32 through the wave's buffer.
+    // Lane l holds row 32 i + l % 32, register 4 g + e column 8 g + 4 (l / 32) + e; the buffer keeps each
+    // row's 16-byte chunk c at c ^ ((row / 4) % 4), so the 8-byte writes of a wave meet every bank twice
+    // and the 16-byte reads once
     const float al = (float)g.alpha;
     const int col0 = n0 + 32 * wave;
 #pragma unroll
@@ -1609,18 +1614,22 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
       for (int part = 0; part < 2; ++part) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int row = 8 * (r >> 2) + 4 * h + (r & 3);
-          __bf16 hh, ll;
-          split_bf16(al * (part ? accI[i][r] : accR[i][r]), hh, ll);
-          sE[row * 32 + l32] = hh;
-          sE[1024 + row * 32 + l32] = ll;
+        for (int gq = 0; gq < 4; ++gq) {
+          f4v x;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) x[e] = al * (part ? accI[i][4 * gq + e] : accR[i][4 * gq + e]);
+          // split_bf16 on four values at once (pairs share one conversion instruction)
+          const bf4v hv = __builtin_convertvector(x, bf4v);
+          const bf4v lv = __builtin_convertvector(x - __builtin_convertvector(hv, f4v), bf4v);
+          const int o = l32 * 32 + 8 * (gq ^ ((l32 >> 2) & 3)) + 4 * h;
+          *reinterpret_cast<bf4v*>(sE + o) = hv;
+          *reinterpret_cast<bf4v*>(sE + 1024 + o) = lv;
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int id = lane + 64 * j;
           const int pl = id >> 7, row = (id >> 2) & 31, c4 = id & 3;
-          const bf8v v = *reinterpret_cast<const bf8v*>(sE + pl * 1024 + row * 32 + c4 * 8);
+          const bf8v v = *reinterpret_cast<const bf8v*>(sE + pl * 1024 + row * 32 + 8 * (c4 ^ ((row >> 2) & 3)));
           const int grow = m0 + 32 * i + row, gcol = col0 + 8 * c4;
           if (grow < g.M && gcol < g.N) {
             const long long ro = off_of(g.c_tab, g.c_tab_pb, g.c_sb, g.c_si, b, g.M, grow);

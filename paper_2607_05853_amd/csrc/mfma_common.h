@@ -12,6 +12,7 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef float f16v __attribute__((ext_vector_type(16)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef __bf16 bf4v __attribute__((ext_vector_type(4)));
 typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 
 // x = hi + lo + O(2^-16 |x|): hi = bf16_rn(x), lo = bf16_rn(x - hi)
@@ -80,6 +81,23 @@ __device__ __forceinline__ void cmma_b3(const bf8v* a, bf8v nih, bf8v nil, const
   ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[2], ci, 0, 0, 0);
   cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nih, b[2], cr, 0, 0, 0);
   ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[0], ci, 0, 0, 0);
+}
+
+// the same products with the roles of the operands exchanged: the fragments b give the rows of the
+// 32 x 32 result and a its columns (result transposed, each element summed exactly as by cmma_b3)
+__device__ __forceinline__ void cmma_b3_t(const bf8v* a, bf8v nih, bf8v nil, const bf8v* b, f16v& cr, f16v& ci) {
+  cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[0], a[1], cr, 0, 0, 0);
+  ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[2], a[1], ci, 0, 0, 0);
+  cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[1], a[0], cr, 0, 0, 0);
+  ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[3], a[0], ci, 0, 0, 0);
+  cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[2], nil, cr, 0, 0, 0);
+  ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[0], a[3], ci, 0, 0, 0);
+  cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[3], nih, cr, 0, 0, 0);
+  ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[1], a[2], ci, 0, 0, 0);
+  cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[0], a[0], cr, 0, 0, 0);
+  ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[2], a[0], ci, 0, 0, 0);
+  cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[2], nih, cr, 0, 0, 0);
+  ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[0], a[2], ci, 0, 0, 0);
 }
 
 }  // namespace bse
