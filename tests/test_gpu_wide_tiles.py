@@ -31,6 +31,10 @@ WIDE_RAGGED = dict(cfg_id=72, coarse=(2, 2, 2), dense=(3, 3, 2), n_ao=16, nv=3, 
 # halves in fragment order (N_ao = 128, N_aux a multiple of 32, n_v^2 a multiple of 8): columns
 # n_band x N_aux of 1664 / 2496, so the last 256-column tile holds 4 / 6 of the 8 waves' 32-column blocks
 FRAG_128 = dict(cfg_id=75, coarse=(2, 2, 2), dense=(2, 2, 3), n_ao=128, nv=4, nc=6, n_aux=416)
+# T.X with 16-row tiles: n_c n_v of 16, 32 and 64 (the last two with compile-time band counts)
+TX_16 = dict(cfg_id=76, coarse=(2, 2, 2), dense=(2, 3, 2), n_ao=16, nv=4, nc=4, n_aux=40)
+TX_32 = dict(cfg_id=77, coarse=(2, 2, 2), dense=(2, 3, 2), n_ao=16, nv=4, nc=8, n_aux=40)
+TX_64 = dict(cfg_id=78, coarse=(2, 2, 2), dense=(2, 2, 2), n_ao=16, nv=8, nc=8, n_aux=48)
 
 
 def dev():
@@ -180,3 +184,27 @@ def test_fragment_order_only_where_it_applies(B):
         pl = B.plan_from_problem(p, Wq, prec=prec, max_nb=2)
         assert not pl.frag, (cfg, prec)
         pl.close()
+
+
+@pytest.mark.parametrize("nb", [3, 8, 16])
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+@pytest.mark.parametrize("cfg", ["TX_16", "TX_32", "TX_64"])
+def test_tx_restaged_kernel(B, cfg, prec, nb):
+    # the restaged T.X kernel against the oracle and against the previous matrix-core kernel (BSE_TX2=0):
+    # both sum FP32 products per item in FP64, over k in another order, so they agree to FP32 rounding
+    p = make_problem({"TX_16": TX_16, "TX_32": TX_32, "TX_64": TX_64}[cfg], 4, "G2")
+    kq = dense_kmesh(p.nk)
+    Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, kq)
+    plan = B.plan_from_problem(p, Wq, prec=prec, max_nb=16)
+    X = random_block(p.N, nb, seed=13)
+    Y2 = _apply_with(plan, X, "BSE_TX2", "1")
+    Y1 = _apply_with(plan, X, "BSE_TX2", "0")
+    H = O.build_H(p, O.interpolate_W_matmul(p.W_R, p.R, p.w_R, kq))
+    DX = diag_times(p, X)
+    e2, e1 = kernel_err(Y2, H @ X, DX), kernel_err(Y1, H @ X, DX)
+    d = kernel_err(Y2, Y1, DX)
+    print("[T.X %s %s nb=%d] kernel-part err restaged %.2e, previous %.2e, between them %.2e" %
+          (cfg, prec, nb, e2, e1, d), flush=True)
+    assert e2 < KERNEL_TOL[prec]
+    assert d < 1e-6
+    plan.close()
