@@ -529,13 +529,17 @@ __global__ void adj_gmT_split_kernel(int Nk, int nq, int q0, int nv, int nc, int
   const int kp = kq[(long long)k * Nk + q0 + qi];
   const double* yg = Yb + 2 * (long long)(SWAP ? kp : k) * nt * nb;
   const double* xg = X + 2 * (long long)(SWAP ? k : kp) * nt * nb;
-  // both slices in LDS (2 nt nb complex, at most 64 KiB): every output reads n_b values of each
+  // both slices in LDS, each row of n_b complex padded by one (row stride 2 n_b + 2 doubles): a wave's outputs
+  // read a few distinct rows of each slice at once, which without the padding would all start in one bank
+  // when 16 n_b bytes is a multiple of the bank period
   extern __shared__ double gsm[];
+  const int rs = 2 * nb + 2;
   double* y = gsm;
-  double* x = gsm + 2 * nt * nb;
+  double* x = gsm + (long long)nt * rs;
   for (int i = threadIdx.x; i < 2 * nt * nb; i += blockDim.x) {
-    y[i] = yg[i];
-    x[i] = xg[i];
+    const int r = i / (2 * nb), o = i % (2 * nb);
+    y[r * rs + o] = yg[i];
+    x[r * rs + o] = xg[i];
   }
   __syncthreads();
   __bf16* out = G + ((long long)qi * Nk + k) * nt2;
@@ -543,8 +547,8 @@ __global__ void adj_gmT_split_kernel(int Nk, int nq, int q0, int nv, int nc, int
     const int col = e / nv2, row = e % nv2;  // col = (first c, second c), row = (first v, second v)
     const int cp = SWAP ? col % nc : col / nc, c = SWAP ? col / nc : col % nc;
     const int vp = SWAP ? row % nv : row / nv, v = SWAP ? row / nv : row % nv;
-    const double* yr = y + 2 * (long long)(c * nv + v) * nb;
-    const double* xr = x + 2 * (long long)(cp * nv + vp) * nb;
+    const double* yr = y + (long long)(c * nv + v) * rs;
+    const double* xr = x + (long long)(cp * nv + vp) * rs;
     double sr = 0, si = 0;
     for (int b = 0; b < nb; ++b) {
       const double ar = yr[2 * b], ai = yr[2 * b + 1], br = xr[2 * b], bi = -xr[2 * b + 1];
@@ -1305,7 +1309,16 @@ bse_status adjoint_tn_pass(Plan* p, int q0, int i0, int nq, bool swap, const int
   const long long pair_v = (long long)nv * nv * na, pair_c = (long long)nc * nc * na;
   const long long nt2 = (long long)nc * nc * nv * nv;
   __bf16* G = (__bf16*)p->T + (long long)i0 * Nk * nt2;
-  const size_t gsh = 2 * (size_t)nc * nv * nb * 16;  // <= 64 KiB since nv nc max_nb <= 2048
+  // two padded slices: 2 nt (nb + 1) complex, <= 64 KiB + 32 nt bytes since nv nc max_nb <= 2048
+  const size_t gsh = 2 * (size_t)nc * nv * (nb + 1) * 16;
+  static bool gsh_attr = false;
+  if (gsh > 64 * 1024 && !gsh_attr) {
+    BSE_HIP(hipFuncSetAttribute((const void*)adj_gmT_split_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                160 * 1024));
+    BSE_HIP(hipFuncSetAttribute((const void*)adj_gmT_split_kernel<false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    gsh_attr = true;
+  }
   if (swap)
     hipLaunchKernelGGL(adj_gmT_split_kernel<true>, dim3(nq * Nk), dim3(256), gsh, st, Nk, nq, q0 + i0, nv, nc, nb, kq,
                        Ybar, X, G, p->ps_T);
