@@ -14,6 +14,7 @@
 #include "mfma_common.h"
 
 #include <cstdlib>
+#include <type_traits>
 
 namespace bse {
 namespace {
@@ -275,59 +276,76 @@ __global__ __launch_bounds__(256) void direct_tx_mfma(int Nk, int nq, int q0, in
 
 // The same sums for 16-row tiles of T (n_c n_v a multiple of 16, at most 64) and 2 n_b <= 32, laid out so
 // that the product loop has no index arithmetic.  Per (q, pass) item the block stages T' as the interleaved
-// real matrix [n_t][2 n_t] (row stride 2 n_t + 4 floats) and X as its expanded transpose [2 n_b][2 n_t]
+// real matrix [n_t][2 n_t] (row stride 2 n_t + 16 bytes) and X as its expanded transpose [2 n_b][2 n_t]
 // (X'[2b][2j] = Re X_jb, [2b][2j+1] = -Im, [2b+1][2j] = Im, [2b+1][2j+1] = Re).  The real contraction index
-// kk runs over the lanes' four K groups as kk = (2 n_t / 4) l4 + ks, so a lane reads four consecutive k
-// steps of A and B with one 16-byte LDS read each.  The next item's T block is loaded into registers while
-// the current item is multiplied.  FP32 products per item, FP64 sums over the items, as in direct_tx_mfma.
+// kk runs over the lanes' four K groups as kk = (2 n_t / 4) l4 + ks, so a lane reads 16 / sizeof(TT)
+// consecutive k steps of A and B with one 16-byte LDS read each.  The next item's T block is loaded into
+// registers while the current item is multiplied.  TT = float: c64 T on 16x16x4 FP32 MFMA (FP32 products per
+// item, FP64 sums over the items, as in direct_tx_mfma); TT = double: c128 T on 16x16x4 FP64 MFMA.
 // NV, NC > 0 fix the band counts at compile time (the index arithmetic of the staging becomes shifts and
 // multiplications); 0 takes them from the arguments.
-constexpr int TX2_TREG = 8;  // 16-byte T chunks per thread (n_t = 64: 32 KiB over 256 threads)
+template <typename TT>
+struct Tx2 {
+  static constexpr int EPC = 16 / sizeof(TT);          // reals per 16-byte LDS read (k steps per read)
+  static constexpr int CPC = 8 / sizeof(TT);           // complex elements of T per 16-byte chunk
+  static constexpr int TREG = sizeof(TT) == 8 ? 16 : 8;  // 16-byte T chunks per thread (n_t = 64)
+  static constexpr int PAD = EPC;                      // row padding: 16 bytes
+};
 
-template <int NV, int NC>
+__device__ __forceinline__ f4v tx_mfma(float a, float b, f4v c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+__device__ __forceinline__ d4v tx_mfma(double a, double b, d4v c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename TT, int NV, int NC>
 __global__ __launch_bounds__(256) void direct_tx_mfma2(int Nk, int nq, int q0, int nv_, int nc_, int nb, int qlen,
                                                        const int* __restrict__ kqp, const int* __restrict__ kqm,
-                                                       int nself, const float* __restrict__ T,
+                                                       int nself, const TT* __restrict__ T,
                                                        const double* __restrict__ X, double* __restrict__ part) {
-  extern __shared__ __attribute__((aligned(16))) float sf[];
+  using C = Tx2<TT>;
+  using V4 = typename std::conditional<sizeof(TT) == 8, d4v, f4v>::type;
+  extern __shared__ __attribute__((aligned(16))) unsigned char sbytes2[];
+  TT* const sf = reinterpret_cast<TT*>(sbytes2);
   const int nv = NV > 0 ? NV : nv_, nc = NC > 0 ? NC : nc_;
   const int k = blockIdx.x, chunk = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nt = nc * nv, nt2 = nt * nt, nv2 = nv * nv, K2 = 2 * nt, RS = K2 + 4, KG = K2 / 4;
+  const int nt = nc * nv, nt2 = nt * nt, nv2 = nv * nv, K2 = 2 * nt, RS = K2 + C::PAD, KG = K2 / 4;
   const int CT = (2 * nb + 15) / 16, ntile = (nt / 16) * CT;
-  float* Ta = sf;            // [nt][RS]
-  float* Xs = Ta + nt * RS;  // [16 CT][RS], X' of the current item (rows from 2 nb on stay zero)
+  TT* Ta = sf;               // [nt][RS]
+  TT* Xs = Ta + nt * RS;     // [16 CT][RS], X' of the current item (rows from 2 nb on stay zero)
   const int l4 = lane >> 4, l16 = lane & 15;
   const int qa = chunk * qlen, qe = min(nq, qa + qlen);
   // X' of the slice at kx into Xd
-  auto stage_x = [&](int kx, float* Xd) {
+  auto stage_x = [&](int kx, TT* Xd) {
     const double* Xg = X + 2 * (long long)kx * nt * nb;
     for (int e = tid; e < nt * nb; e += 256) {
       const int j = e / nb, b = e % nb;
-      const float re = (float)Xg[2 * e], im = (float)Xg[2 * e + 1];
-      *reinterpret_cast<float2*>(Xd + (2 * b) * RS + 2 * j) = make_float2(re, -im);
-      *reinterpret_cast<float2*>(Xd + (2 * b + 1) * RS + 2 * j) = make_float2(im, re);
+      const TT re = (TT)Xg[2 * e], im = (TT)Xg[2 * e + 1];
+      Xd[(2 * b) * RS + 2 * j] = re;
+      Xd[(2 * b) * RS + 2 * j + 1] = -im;
+      Xd[(2 * b + 1) * RS + 2 * j] = im;
+      Xd[(2 * b + 1) * RS + 2 * j + 1] = re;
     }
   };
-  for (int e = tid; e < 16 * CT * RS; e += 256) Xs[e] = 0.f;
+  for (int e = tid; e < 16 * CT * RS; e += 256) Xs[e] = TT(0);
   double acc[2][4];
 #pragma unroll
   for (int s = 0; s < 2; ++s)
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[s][q] = 0.0;
   // items (qi, pass) in order: pass 1 only for q from nself on
-  auto tblock = [&](int qi, int pass) -> const float* {
+  auto tblock = [&](int qi, int pass) -> const TT* {
     const int j = q0 + qi;
     const int kb = pass == 0 ? k : kqm[(long long)k * Nk + j];
     return T + 2 * ((long long)qi * Nk + kb) * nt2;
   };
-  const int nchunk16 = nt2 / 2;  // 16-byte chunks (two complex) of a T block
-  float4 tr[TX2_TREG];
-  auto load_t = [&](const float* Tg) {
+  const int nchunk16 = nt2 / C::CPC;  // 16-byte chunks of a T block
+  uint4 tr[C::TREG];
+  auto load_t = [&](const TT* Tg) {
 #pragma unroll
-    for (int r = 0; r < TX2_TREG; ++r) {
+    for (int r = 0; r < C::TREG; ++r) {
       const int c = tid + 256 * r;
-      if (c < nchunk16) tr[r] = reinterpret_cast<const float4*>(Tg)[c];
+      if (c < nchunk16) tr[r] = reinterpret_cast<const uint4*>(Tg)[c];
     }
   };
   int qi = qa, pass = 0;
@@ -344,19 +362,19 @@ __global__ __launch_bounds__(256) void direct_tx_mfma2(int Nk, int nq, int q0, i
     // T' of this item from the registers: T element (c1 c2, v1 v2); first pass T'[(c2 v2)][(c1 v1)] =
     // T[(c1 c2)][(v1 v2)], partner pass T'[(c1 v1)][(c2 v2)] = conj T[(c1 c2)][(v1 v2)]
 #pragma unroll
-    for (int r = 0; r < TX2_TREG; ++r) {
+    for (int r = 0; r < C::TREG; ++r) {
       const int c = tid + 256 * r;
       if (c < nchunk16) {
-        const float v4[4] = {tr[r].x, tr[r].y, tr[r].z, tr[r].w};
+        const TT* v = reinterpret_cast<const TT*>(&tr[r]);
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int e = 2 * c + h;
+        for (int h = 0; h < C::CPC; ++h) {
+          const int e = C::CPC * c + h;
           const int r1 = e / nv2, r2 = e % nv2;
           const int c1 = r1 / nc, c2 = r1 % nc, v1 = r2 / nv, v2 = r2 % nv;
           const int row = pass == 0 ? c2 * nv + v2 : c1 * nv + v1;
           const int col = pass == 0 ? c1 * nv + v1 : c2 * nv + v2;
-          *reinterpret_cast<float2*>(Ta + row * RS + 2 * col) =
-              make_float2(v4[2 * h], pass == 0 ? v4[2 * h + 1] : -v4[2 * h + 1]);
+          Ta[row * RS + 2 * col] = v[2 * h];
+          Ta[row * RS + 2 * col + 1] = pass == 0 ? v[2 * h + 1] : -v[2 * h + 1];
         }
       }
     }
@@ -369,16 +387,16 @@ __global__ __launch_bounds__(256) void direct_tx_mfma2(int Nk, int nq, int q0, i
       const int t = wave + 4 * s;
       if (t >= ntile) break;
       const int rt = t / CT, ct = t % CT;
-      const float* pa = Ta + (16 * rt + l16) * RS + KG * l4;
-      const float* pb = Xs + (16 * ct + l16) * RS + KG * l4;
-      f4v a4 = {0, 0, 0, 0};
-      for (int m = 0; m < KG; m += 4) {
-        const float4 av = *reinterpret_cast<const float4*>(pa + m);
-        const float4 bv = *reinterpret_cast<const float4*>(pb + m);
-        a4 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, a4, 0, 0, 0);
-        a4 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, a4, 0, 0, 0);
-        a4 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv.z, a4, 0, 0, 0);
-        a4 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv.w, a4, 0, 0, 0);
+      const TT* pa = Ta + (16 * rt + l16) * RS + KG * l4;
+      const TT* pb = Xs + (16 * ct + l16) * RS + KG * l4;
+      V4 a4 = {0, 0, 0, 0};
+      for (int m = 0; m < KG; m += C::EPC) {
+        const uint4 au = *reinterpret_cast<const uint4*>(pa + m);
+        const uint4 bu = *reinterpret_cast<const uint4*>(pb + m);
+        const TT* av = reinterpret_cast<const TT*>(&au);
+        const TT* bv = reinterpret_cast<const TT*>(&bu);
+#pragma unroll
+        for (int e = 0; e < C::EPC; ++e) a4 = tx_mfma(av[e], bv[e], a4);
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) acc[s][q] += (double)a4[q];
@@ -386,7 +404,7 @@ __global__ __launch_bounds__(256) void direct_tx_mfma2(int Nk, int nq, int q0, i
     qi = nqi;
     pass = npass;
   }
-  // register q of a lane holds real column l16 of tile row 4 l4 + q
+  // register q of a lane holds real column l16 of tile row 4 l4 + q (FP32 instruction) or l4 + 4 q (FP64)
   const int nout = nt * nb;
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
@@ -397,18 +415,19 @@ __global__ __launch_bounds__(256) void direct_tx_mfma2(int Nk, int nq, int q0, i
     if (cc >= 2 * nb) continue;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int i = rt * 16 + 4 * l4 + q;
+      const int i = rt * 16 + (sizeof(TT) == 8 ? l4 + 4 * q : 4 * l4 + q);
       part[2 * (((long long)chunk * Nk + k) * nout + (long long)i * nb + (cc >> 1)) + (cc & 1)] = acc[s][q];
     }
   }
 }
 
-// LDS bytes of direct_tx_mfma2, 0 when its shape conditions do not hold
-size_t tx2_lds(int nv, int nc, int nb) {
+// LDS bytes of direct_tx_mfma2 for elements of esz bytes, 0 when its shape conditions do not hold
+size_t tx2_lds(int nv, int nc, int nb, size_t esz) {
   const int nt = nc * nv;
-  if (nt % 16 != 0 || nt > 64 || 2 * nb > 32 || nt * nt / 2 > 256 * TX2_TREG) return 0;
-  const int RS = 2 * nt + 4, CT = (2 * nb + 15) / 16;
-  return sizeof(float) * (size_t)RS * (nt + 16 * CT);
+  const int cpc = esz == 8 ? 1 : 2, treg = esz == 8 ? 16 : 8;  // as Tx2<TT>
+  if (nt % 16 != 0 || nt > 64 || 2 * nb > 32 || nt * nt / cpc > 256 * treg) return 0;
+  const int RS = 2 * nt + (int)(16 / esz), CT = (2 * nb + 15) / 16;
+  return esz * (size_t)RS * (nt + 16 * CT);
 }
 
 // Y[i] += scale * sum_chunk part[chunk][i] (complex, n = N * nb), chunks added in order
@@ -1262,21 +1281,32 @@ bse_status apply_direct(Plan* p, const double* X, double* Y, int nb, hipStream_t
       const dim3 grid((unsigned)Nk, (unsigned)nch);
       const int slots = (nt * nb + 255) / 256;
       const int ntile = ((nt + 15) / 16) * ((2 * nb + 15) / 16);
-      const size_t sh2 = f64 ? 0 : tx2_lds(nv, nc, nb);
-      if (sh2 > 0 && tx2_enabled()) {  // FP32 matrix cores, staged for 16-byte operand reads
-        auto go = [&](auto kern) -> bse_status {
+      const size_t sh2 = tx2_lds(nv, nc, nb, f64 ? 8 : 4);
+      if (sh2 > 0 && tx2_enabled()) {  // matrix cores, staged for 16-byte operand reads
+        auto go = [&](auto kern, auto tp) -> bse_status {
           BSE_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh2));
           hipLaunchKernelGGL(kern, grid, dim3(256), sh2, st, Nk, nq, q0, nv, nc, nb, qlen, kq, p->kqm, nself,
-                             (const float*)p->T, X, p->txp);
+                             (decltype(tp))p->T, X, p->txp);
           BSE_CHECK_LAUNCH();
           return BSE_OK;
         };
-        if (nv == 8 && nc == 8)
-          BSE_TRY(go(direct_tx_mfma2<8, 8>));
-        else if (nv == 4 && nc == 8)
-          BSE_TRY(go(direct_tx_mfma2<4, 8>));
-        else
-          BSE_TRY(go(direct_tx_mfma2<0, 0>));
+        if (f64) {
+          const double* tp = nullptr;
+          if (nv == 8 && nc == 8)
+            BSE_TRY(go(direct_tx_mfma2<double, 8, 8>, tp));
+          else if (nv == 4 && nc == 8)
+            BSE_TRY(go(direct_tx_mfma2<double, 4, 8>, tp));
+          else
+            BSE_TRY(go(direct_tx_mfma2<double, 0, 0>, tp));
+        } else {
+          const float* tp = nullptr;
+          if (nv == 8 && nc == 8)
+            BSE_TRY(go(direct_tx_mfma2<float, 8, 8>, tp));
+          else if (nv == 4 && nc == 8)
+            BSE_TRY(go(direct_tx_mfma2<float, 4, 8>, tp));
+          else
+            BSE_TRY(go(direct_tx_mfma2<float, 0, 0>, tp));
+        }
       } else if (!f64 && ntile <= 4 * TX_MAXT) {  // FP32 matrix cores for c64 T: one item staged at a time
         const size_t tb = ((size_t)nt * nt * p->esz + 15) & ~(size_t)15;
         const size_t shm = tb + (size_t)nt * nb * p->esz;
