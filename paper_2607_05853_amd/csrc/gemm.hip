@@ -391,6 +391,114 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     }
 }
 
+// The same products on 64 x 64 tiles for small per-pair matrices (the FP32 direct block T = M_c P^T has
+// n_c^2 x n_v^2 entries per pair, K = N_aux): four waves of one 32 x 32 tile each, three 16 KiB
+// direct-to-LDS stages (16 complex k of 64 rows of A and 64 of B, the chunk swizzle of the wide tile), loads
+// of stage kt + 2 in flight while stage kt is multiplied, three blocks per CU.
+constexpr int F64T_BM = 64, F64T_BN = 64, F64T_BK = 16, F64T_NS = 3;
+
+template <int CJA, int CJB, typename TC>
+__global__ __launch_bounds__(256) void cgemm_f32_dma64(GemmArgs g) {
+  constexpr int BM = F64T_BM, BN = F64T_BN, BK = F64T_BK, NS = F64T_NS;
+  constexpr int STAGE = (BM + BN) * BK * 2;  // floats per stage
+  constexpr int RBLK = (BM + BN) / 8;        // 8-row DMA blocks per stage: 8 of A, 8 of B
+  __shared__ __attribute__((aligned(1024))) float smem[NS * STAGE];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int h = lane >> 5, l32 = lane & 31;
+  const int nK = g.K / BK;
+  const int gxn = (g.N + BN - 1) / BN, gyn = (g.M + BM - 1) / BM;
+  const long long per_batch = (long long)gxn * gyn;
+  long long bl, t;
+  xcd_map(blockIdx.x, per_batch, g.batch, bl, t);
+  const int b = (int)bl;
+  int m0, n0;
+  tile_of(t, gxn, gyn, BM, BN, m0, n0);
+  // DMA: block rb (of 16) -> wave rb % 4; lane -> row 8 (rb') + lane / 8, stored chunk lane % 8, which holds
+  // source chunk (lane % 8) ^ ((row / 2) % 8); rows past the edge re-load a valid row (never stored)
+  const float* src[RBLK / 4];
+  int ldo[RBLK / 4];
+#pragma unroll
+  for (int u = 0; u < RBLK / 4; ++u) {
+    const int rb = wave + 4 * u;
+    const bool isA = rb < BM / 8;
+    const int r = 8 * (isA ? rb : rb - BM / 8) + (lane >> 3);
+    const int c = (lane & 7) ^ ((r >> 1) & 7);
+    if (isA) {
+      const int row = (m0 + r < g.M) ? m0 + r : m0;
+      src[u] = (const float*)g.A + 2 * off_of(g.a_tab, g.a_tab_pb, g.a_sb, g.a_si, b, g.M, row) + 4 * c;
+      ldo[u] = 8 * rb * BK * 2;
+    } else {
+      const int col = (n0 + r < g.N) ? n0 + r : n0;
+      src[u] = (const float*)g.B + 2 * off_of(g.b_tab, g.b_tab_pb, g.b_sb, g.b_sj, b, g.N, col) + 4 * c;
+      ldo[u] = BM * BK * 2 + 8 * (rb - BM / 8) * BK * 2;
+    }
+  }
+  auto issue = [&](int kt) {
+    if (kt >= nK) return;
+    float* st = smem + (kt % NS) * STAGE;
+#pragma unroll
+    for (int u = 0; u < RBLK / 4; ++u)
+      __builtin_amdgcn_global_load_lds((const void*)(src[u] + 2 * BK * kt),
+                                       (__attribute__((address_space(3))) void*)(st + ldo[u]), 16, 0, 0);
+  };
+  f16v accR, accI;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    accR[r] = 0.f;
+    accI[r] = 0.f;
+  }
+  issue(0);
+  issue(1);
+  for (int kt = 0; kt < nK; ++kt) {
+    // stage kt has landed (the four loads of stage kt + 1 may still be in flight) and every wave is done
+    // with stage kt - 1, whose slot the next issue overwrites
+    if (kt + 1 < nK)
+      vm_lds_barrier<RBLK / 4>();
+    else
+      vm_lds_barrier<0>();
+    issue(kt + 2);
+    const float* sa = smem + (kt % NS) * STAGE;
+    const float* sb = sa + BM * BK * 2;
+    f4v a[4], bb[4];
+    const int row = wm * 32 + l32, col = wn * 32 + l32;
+#pragma unroll
+    for (int gk = 0; gk < 4; ++gk) {
+      a[gk] = *reinterpret_cast<const f4v*>(sa + row * BK * 2 + 4 * ((2 * gk + h) ^ ((row >> 1) & 7)));
+      bb[gk] = *reinterpret_cast<const f4v*>(sb + col * BK * 2 + 4 * ((2 * gk + h) ^ ((col >> 1) & 7)));
+    }
+#pragma unroll
+    for (int gk = 0; gk < 4; ++gk)
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const float ar = a[gk][2 * m];
+        const float ai = CJA ? -a[gk][2 * m + 1] : a[gk][2 * m + 1];
+        const float br = bb[gk][2 * m];
+        const float bi = CJB ? -bb[gk][2 * m + 1] : bb[gk][2 * m + 1];
+        accR = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, accR, 0, 0, 0);
+        accR = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, bi, accR, 0, 0, 0);
+        accI = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bi, accI, 0, 0, 0);
+        accI = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, br, accI, 0, 0, 0);
+      }
+  }
+  // result: register r holds row 8 (r / 4) + 4 h + r % 4, column l32 of the wave's 32 x 32 tile
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = m0 + wm * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+    const int col = n0 + wn * 32 + l32;
+    if (row >= g.M || col >= g.N) continue;
+    const long long ro = off_of(g.c_tab, g.c_tab_pb, g.c_sb, g.c_si, b, g.M, row);
+    TC* o = (TC*)g.C + 2 * (ro + (long long)col * g.c_sj);
+    double vr = g.alpha * (double)accR[r], vi = g.alpha * (double)accI[r];
+    if (g.beta) {
+      vr += (double)o[0];
+      vi += (double)o[1];
+    }
+    o[0] = (TC)vr;
+    o[1] = (TC)vi;
+  }
+}
+
 // ----------------------------------------------------------------------------
 // BF16x3 kernel (c64 inputs, split into bf16 hi/lo when staged to LDS)
 // ----------------------------------------------------------------------------
@@ -2034,6 +2142,22 @@ bse_status run_real(const GemmArgs& g, hipStream_t st) {
     if (g.M >= FW_BM && g.N >= FW_BN && g.K % FW_BK == 0 && dma_ok(g) && tiles < (1LL << 31) &&
         wide_tiles_enabled())
       return launch_f32_wide<TC>(g, st);
+    // small per-pair products with a long K (the direct block): 64 x 64 tiles, one per batch entry, where
+    // they are at least a quarter full (narrower products keep the 64 x 16 tiles below)
+    if (g.M <= F64T_BM && g.N <= F64T_BN && g.M > 32 && g.N > 32 && g.K % F64T_BK == 0 &&
+        g.K >= 4 * F64T_BK && dma_ok(g) && wide_tiles_enabled()) {
+      const dim3 grid((unsigned)g.batch), block(256);
+      if (g.conjA && g.conjB)
+        hipLaunchKernelGGL((cgemm_f32_dma64<1, 1, TC>), grid, block, 0, st, g);
+      else if (g.conjA)
+        hipLaunchKernelGGL((cgemm_f32_dma64<1, 0, TC>), grid, block, 0, st, g);
+      else if (g.conjB)
+        hipLaunchKernelGGL((cgemm_f32_dma64<0, 1, TC>), grid, block, 0, st, g);
+      else
+        hipLaunchKernelGGL((cgemm_f32_dma64<0, 0, TC>), grid, block, 0, st, g);
+      BSE_CHECK_LAUNCH();
+      return BSE_OK;
+    }
   }
   switch (pick(g)) {
     case SH_NARROW_N:
