@@ -222,7 +222,7 @@ bse_status bse_plan_fused(const bse_plan* plan, int32_t* fused);
 
 /* *frag = 1 when the plan stores its BF16X3 halves B^mu_n(k) in the fragment
  * order of the pair-density kernel (BF16X3 with k-independent coefficients,
- * N_ao = 128, N_aux a multiple of 32, n_v^2 a multiple of 8): per k and band
+ * N_ao of 64 or 128, N_aux a multiple of 32, n_v^2 a multiple of 8): per k and band
  * side the [n_band N_aux][N_ao] matrix is laid out as 32-column by 16-k blocks
  * of 1 KiB, each the operand of one matrix-core step, so that the streaming
  * kernel reads whole KiB instead of 32-byte pieces of 32 rows.  The results are

@@ -472,10 +472,10 @@ bse_status build_plan(Plan* p, const bse_dims* d, const double* eps_qp, const vo
   p->ps_Bv = hv;
   p->ps_Bc = hc;
   // BF16X3 halves in fragment order where every pair-density product of the plan runs on the streaming
-  // kernel: K = N_ao = 128, columns in whole 32-blocks, split results (k-independent coefficients, and the
-  // k-major adjoint's alignment)
-  p->frag_halves = (p->split && !tc && no == 128 && na % 32 == 0 && (nv * nv) % 8 == 0 && na % 8 == 0 &&
-                    frag_halves_enabled())
+  // kernel: K = N_ao of 64 or 128, columns in whole 32-blocks, split results (k-independent coefficients,
+  // and the k-major adjoint's alignment)
+  p->frag_halves = (p->split && !tc && (no == 64 || no == 128) && na % 32 == 0 && (nv * nv) % 8 == 0 &&
+                    na % 8 == 0 && frag_halves_enabled())
                        ? 1
                        : 0;
   BSE_TRY(plan_alloc(p, &p->Bv, p->esz * hv));

@@ -2332,12 +2332,13 @@ bse_status cgemm_split(const GemmArgs& g, bool a_split, bool b_split, bool c_spl
     return BSE_EINVAL;
   }
   if (g.b_frag) {  // a B operand in fragment order: only the streaming kernel reads that layout
-    if (!(a_split && b_split && c_split && dma_ok(g) && g.K == PD_KMAX && g.N % 32 == 0 && !g.conjA && !g.conjB &&
-          !g.b_tab)) {
-      set_error("cgemm_split: a fragment-order B needs split operands and result, K = 128, N a multiple of 32");
+    if (!(a_split && b_split && c_split && dma_ok(g) && (g.K == 64 || g.K == 128) && g.N % 32 == 0 && !g.conjA &&
+          !g.conjB && !g.b_tab)) {
+      set_error("cgemm_split: a fragment-order B needs split operands and result, K of 64 or 128, N a multiple "
+                "of 32");
       return BSE_EINVAL;
     }
-    return launch_stream<8, true>(g, st);
+    return g.K == 64 ? launch_stream<4, true>(g, st) : launch_stream<8, true>(g, st);
   }
   if (a_split && b_split && dma_ok(g)) {
     if (!c_split && g.M <= 64 && g.N <= 64) {  // small per-pair products: quarter-size tiles

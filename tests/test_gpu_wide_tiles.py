@@ -31,6 +31,7 @@ WIDE_RAGGED = dict(cfg_id=72, coarse=(2, 2, 2), dense=(3, 3, 2), n_ao=16, nv=3, 
 # halves in fragment order (N_ao = 128, N_aux a multiple of 32, n_v^2 a multiple of 8): columns
 # n_band x N_aux of 1664 / 2496, so the last 256-column tile holds 4 / 6 of the 8 waves' 32-column blocks
 FRAG_128 = dict(cfg_id=75, coarse=(2, 2, 2), dense=(2, 2, 3), n_ao=128, nv=4, nc=6, n_aux=416)
+FRAG_64 = dict(cfg_id=79, coarse=(2, 2, 2), dense=(2, 2, 3), n_ao=64, nv=4, nc=6, n_aux=416)
 # T.X with 16-row tiles: n_c n_v of 16, 32 and 64 (the last two with compile-time band counts)
 TX_16 = dict(cfg_id=76, coarse=(2, 2, 2), dense=(2, 3, 2), n_ao=16, nv=4, nc=4, n_aux=40)
 TX_32 = dict(cfg_id=77, coarse=(2, 2, 2), dense=(2, 3, 2), n_ao=16, nv=4, nc=8, n_aux=40)
@@ -144,10 +145,11 @@ def _plan_with(B, p, Wq, frag, **kw):
 
 
 @pytest.mark.parametrize("all_pairs", [False, True])
-def test_fragment_order_halves_identical(B, all_pairs):
+@pytest.mark.parametrize("cfg", ["FRAG_128", "FRAG_64"])
+def test_fragment_order_halves_identical(B, cfg, all_pairs):
     # the streaming kernel on halves in fragment order against the row layout (streaming and tiled kernels):
     # apply, adjoint (every pair-density product of the gradient) and the coupling block, bit for bit
-    p = make_problem(FRAG_128, 5, "G2")
+    p = make_problem({"FRAG_128": FRAG_128, "FRAG_64": FRAG_64}[cfg], 5, "G2")
     kq = dense_kmesh(p.nk)
     Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, kq)
     pf = _plan_with(B, p, Wq, True, conduction="mc", all_pairs=all_pairs)
@@ -164,8 +166,8 @@ def test_fragment_order_halves_identical(B, all_pairs):
     gr = pr.apply_adjoint(T(Yb), T(X), want_WR=False, want_Wq=True)
     Bf = H_(pf.apply_coupling(T(X)))
     Br = H_(pr.apply_coupling(T(X)))
-    print("[fragment-order halves, all pairs %s] kernel-part err %.2e; identical: apply %s / %s, g_W(q) %s, "
-          "g_eps %s, coupling %s" % (all_pairs, err, np.array_equal(Yf, Yr), np.array_equal(Yf, Yt),
+    print("[fragment-order halves %s, all pairs %s] kernel-part err %.2e; identical: apply %s / %s, g_W(q) %s, "
+          "g_eps %s, coupling %s" % (cfg, all_pairs, err, np.array_equal(Yf, Yr), np.array_equal(Yf, Yt),
                                       torch.equal(gf["W_q"], gr["W_q"]), torch.equal(gf["eps"], gr["eps"]),
                                       np.array_equal(Bf, Br)), flush=True)
     assert err < KERNEL_TOL["bf16x3"]
@@ -177,7 +179,7 @@ def test_fragment_order_halves_identical(B, all_pairs):
 
 
 def test_fragment_order_only_where_it_applies(B):
-    # row layout for shapes the fragment order does not cover (N_ao = 64; n_v^2 odd) and for FP32
+    # row layout for shapes the fragment order does not cover (N_aux = 400; n_v^2 odd) and for FP32
     for cfg, prec in ((STREAM_64, "bf16x3"), (STREAM_128, "bf16x3"), (FRAG_128, "f32")):
         p = make_problem(cfg, 3, "G2")
         Wq = B.interpolate_W(T(p.W_R), p.R, p.w_R, dense_kmesh(p.nk))
