@@ -40,3 +40,27 @@ def test_source_digest_matches_committed_profiles():
     if stored != dig:
         pytest.skip("the HIP sources changed since the counter summary was taken (traffic is then null)")
     assert stored == dig
+
+
+def test_roofline_counts_of_the_fused_w_step():
+    # the dominant kernel at 16^3 (W step with the direct blocks, P on chip): its algorithmic flops per pair
+    # are the W term plus the direct-block term, and its bytes per launch read G_v and M_c once, W(q) once per
+    # q of the batch and write T once (16 q x 4096 k pairs per full batch)
+    from types import SimpleNamespace
+    p = SimpleNamespace(n_aux=512, n_ao=128, nv=8, nc=8, Nk=4096)
+    f = bench.kernel_flops_per_pair(p, "bf16x3", "fused")
+    assert f["wstep"] == 8 * 512 ** 2 * 64 + 8 * 512 * 64 * 64 == 150994944
+    assert "dblock" not in f
+    assert f["pairdens_v"] == f["pairdens_c"] == 8 * 512 * 128 * 64
+    b = bench.kernel_bytes_per_pair(p, "bf16x3", "fused")
+    per_pair = 8 * (64 * 512 + 64 * 512) + 8 * 512 * 512 / 4096 + 8 * 64 * 64
+    assert b["wstep"] == per_pair
+    assert abs(16 * 4096 * per_pair / 1e9 - 36.54) < 0.01
+    # the bench's per-launch figure averages over 128 batches of 16 q and one of 4 (65,155 pairs)
+    assert abs(2052 * 4096 / 129 * per_pair / 1e9 - 36.33) < 0.01
+    # the B_c route prices the conduction side at its own executed count (about twice the M_cc' count)
+    q = SimpleNamespace(n_aux=256, n_ao=64, nv=4, nc=8, Nk=512)
+    u = bench.kernel_flops_per_pair(q, "bf16x3", "u")["dblock"]
+    mc = bench.kernel_flops_per_pair(q, "bf16x3", "mc")
+    assert u == 8 * 8 * 64 * 256 * 16 + 8 * 64 * 64 * 16
+    assert 2.0 < u / (mc["pairdens_c"]) < 2.1
