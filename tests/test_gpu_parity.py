@@ -134,6 +134,26 @@ def test_apply_c1(B, wgen, prec):
     assert err < KERNEL_TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["f64", "bf16x3"])
+def test_apply_complex_hermitian_vbar(B, prec):
+    # the generators' Vbar is real symmetric (real auxiliary functions), but the ABI takes any Hermitian
+    # Vbar: with a complex one the orientation of the exchange term (mu on the density at k, nu on the one
+    # at k') is observable, and the apply must follow the oracle's (pinned by the AO-kernel brute force)
+    p = make_problem("mesh4_ao16", 0, "G2", coarse=(3, 3, 2))
+    A = np.random.default_rng(8).standard_normal((p.n_aux, p.n_aux))
+    p = dataclasses.replace(p, Vbar=p.Vbar + 0.1j * (A - A.T))
+    plan, Wq = _plan(B, p, prec, nb=3)
+    H = O.build_H(p, OW(p))
+    X = random_block(p.N, 3, seed=1)
+    DX = diag_times(p, X)
+    HT = O.build_H(dataclasses.replace(p, Vbar=p.Vbar.T), OW(p))
+    assert kernel_err(HT @ X, H @ X, DX) > 1e3 * KERNEL_TOL[prec]   # the transposed Vbar is far outside
+    err = kernel_err(H_(plan.apply(T(X))), H @ X, DX)
+    plan.close()
+    print("[complex Vbar %s] kernel-part err %.3e" % (prec, err), flush=True)
+    assert err < KERNEL_TOL[prec]
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
 def test_apply_ragged_and_triplet(B, prec):
     # sizes that are not multiples of any tile: 30 k, 3+5 bands, 40 aux, 12 AOs, 5 vectors

@@ -1,4 +1,5 @@
 """Pins of the oracle's explicit TDA Hamiltonian (Eq. (Hamiltonian) through Eq. (W_LRI))."""
+import dataclasses
 import json
 import os
 
@@ -104,9 +105,20 @@ def _ao_bruteforce_H(p, Wq):
     return H
 
 
+@pytest.mark.parametrize("complex_vbar", [False, True])
+@pytest.mark.parametrize("dense", [(2, 2, 1), (3, 2, 1)])
 @pytest.mark.parametrize("wgen", ["G1", "G2"])
-def test_bruteforce_ao_kernel(wgen):
-    p = make_problem(dict(cfg_id=92, coarse=(3, 3, 2), dense=(2, 2, 1), n_ao=4, nv=2, nc=2, n_aux=6), 1, wgen)
+def test_bruteforce_ao_kernel(wgen, dense, complex_vbar):
+    # On the 2x2x1 mesh every q is its own negative, so W(q) = W(-q) = W(q)^T even for G2 and the mu <-> nu
+    # orientation of W in the direct term is invisible; the 3x2x1 mesh has q != -q, where G2's W(q) is not
+    # symmetric and the brute force fixes which pair density carries mu (the valence one) and which nu.
+    # The generators' Vbar is real symmetric (real auxiliary functions); a complex Hermitian Vbar fixes the
+    # orientation of the exchange term the same way (mu on the density at k, nu on the one at k').
+    p = make_problem(dict(cfg_id=92, coarse=(3, 3, 2), dense=dense, n_ao=4, nv=2, nc=2, n_aux=6), 1, wgen)
+    if complex_vbar:
+        A = np.random.default_rng(8).standard_normal((p.n_aux, p.n_aux))
+        p = dataclasses.replace(p, Vbar=p.Vbar + 0.1j * (A - A.T))
+        assert np.abs(p.Vbar.imag).max() > 1e-2
     Wq = _Wq(p)
     H = O.build_H(p, Wq)
     Hb = _ao_bruteforce_H(p, Wq)

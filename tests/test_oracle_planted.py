@@ -1,0 +1,216 @@
+"""Planted mistakes in the oracle: each plausible slip in the explicit Hamiltonian (Eq. (Hamiltonian) with
+the kernels of Eq. (W_LRI)), the interpolation of W (Sec. III.B), the velocity-form start vector
+(Eq. (abs_vel)), the continued fraction of the Haydock spectrum and the binding energy (Sec. IV.B.3) -- a
+dropped term, a wrong sign, a transposed operand, a wrong index or orientation, a missing normalisation --
+is planted in a copy of that oracle function for the duration of one test, and at least one of the pins
+that tie the function to the paper and the mathematics (hand-derived cases, the AO-kernel brute force,
+closed forms, library routines, invariants) must fail.  The unmutated oracle passes every pin (the
+"none" cases), so a failure here is the pin catching the planted slip, not the harness."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle.bse_ref as R
+import test_oracle_binding as TB
+import test_oracle_hamiltonian as TH
+import test_oracle_haydock as TY
+import test_oracle_interp as TI
+from conftest import SMALL, TINY
+from synth import dense_kmesh, make_problem
+
+
+# ---------------------------------------------------------------------------------------------------------
+# mutated copies of the oracle functions (same arithmetic as the oracle except for the planted slip)
+# ---------------------------------------------------------------------------------------------------------
+def _block_with(kind):
+    """hamiltonian_block with one planted slip."""
+    def blk(prob, W_q, alpha, k, kp, cache=None):
+        val, con = R._bands(prob)
+        Nk, nc, nv = prob.Nk, prob.nc, prob.nv
+        Mcv = R._pairs(prob, k, con, k, val)
+        Mvc = R._pairs(prob, kp, val, kp, con)
+        if kind == "valence_density_unconjugated":
+            Mvv = np.transpose(R._pairs(prob, k, val, kp, val), (0, 2, 1))   # M_vv'(k,k') where conj is due
+        else:
+            Mvv = R._pairs(prob, kp, val, k, val)
+        if kind == "conduction_density_reversed":
+            Mcc = np.transpose(R._pairs(prob, kp, con, k, con), (0, 2, 1))   # M_c'c(k',k) read as [c][c']
+        else:
+            Mcc = R._pairs(prob, k, con, kp, con)
+        qi = R.q_index(prob.nk, kp, k) if kind == "W_of_minus_q" else R.q_index(prob.nk, k, kp)
+        Wq = W_q[qi].T if kind == "W_transposed" else W_q[qi]
+        Vb = prob.Vbar.T if kind == "Vbar_transposed" else prob.Vbar
+        out = "vcpd" if kind == "transition_order" else "cvdp"
+        t1 = np.einsum("mcv,mn->ncv", Mcv, Vb)
+        Xb = (alpha / Nk) * np.einsum("ncv,npd->" + out, t1, Mvc)
+        t2 = np.einsum("mpv,mn->npv", Mvv, Wq)
+        Db = -(1.0 / Nk) * np.einsum("npv,ncd->" + out, t2, Mcc)
+        if kind == "exchange_sign":
+            Xb = -Xb
+        elif kind == "direct_sign":
+            Db = -Db
+        elif kind == "dropped_exchange":
+            Xb = 0.0 * Xb
+        elif kind == "dropped_direct":
+            Db = 0.0 * Db
+        elif kind == "direct_without_1_over_Nk":
+            Db = Nk * Db
+        b = (Xb + Db).reshape(nc * nv, nc * nv)
+        if k == kp:
+            te = R.transition_energies(prob)[k]
+            b = b + np.diag(-te if kind == "diagonal_sign" else te)
+        return b
+    return blk
+
+
+def _interp_with(kind):
+    def interp(W_R, Rv, w_R, q_frac):
+        W_R = np.asarray(W_R, dtype=np.complex128)
+        q_frac = np.atleast_2d(np.asarray(q_frac, dtype=np.float64))
+        out = np.zeros((len(q_frac),) + W_R.shape[1:], dtype=np.complex128)
+        sign = -1.0 if kind == "fourier_sign" else 1.0
+        two_pi = 1.0 if kind == "missing_2pi" else 2.0 * np.pi
+        for iq, q in enumerate(q_frac):
+            for r in range(len(Rv)):
+                w = 1.0 if kind == "weights_dropped" else w_R[r]
+                out[iq] += w * np.exp(sign * 1j * two_pi * np.dot(q, Rv[r])) * W_R[r]
+        return out
+    return interp
+
+
+def _velocity_with(kind):
+    def vel(prob, pol):
+        pol = np.atleast_2d(pol)
+        nv, nc = prob.nv, prob.nc
+        eps = prob.eps_qp if kind == "quasiparticle_denominator" else prob.eps_ks
+        out = np.zeros((prob.N, len(pol)), dtype=np.complex128)
+        for b, e in enumerate(pol):
+            for k in range(prob.Nk):
+                for c in range(nc):
+                    for v in range(nv):
+                        amp = sum(e[a] * prob.vel[a, k, c, v] for a in range(3))
+                        if kind == "conjugated_amplitude":
+                            amp = np.conj(amp)
+                        out[(k * nc + c) * nv + v, b] = amp / (eps[k, nv + c] - eps[k, v])
+        return out
+    return vel
+
+
+def _cf_with(kind):
+    def cf(a, b, steps, omega, eta, Nk):
+        z = np.asarray(omega, dtype=np.float64) + (-1j if kind == "eta_sign" else 1j) * eta
+        sh = 1 if kind == "coefficient_shift" else 0
+        g = z - a[steps - 1]
+        for j in range(steps - 1, 0, -1):
+            g = z - a[j - 1] - b[min(j + sh, steps - 1)] ** 2 / g
+        f = (b[0] if kind == "b0_unsquared" else b[0] ** 2) / g
+        return -np.imag(f) / (np.pi * (1 if kind == "missing_1_over_Nk" else Nk))
+    return cf
+
+
+def _eb_with(kind):
+    def eb(prob, Omega1):
+        nv = prob.nv
+        e = prob.eps_ks if kind == "kohn_sham_energies" else prob.eps_qp
+        if kind == "indirect_gap":
+            gap = e[:, nv].min() - e[:, nv - 1].max()
+        elif kind == "max_for_min":
+            gap = (e[:, nv] - e[:, nv - 1]).max()
+        elif kind == "wrong_bands":
+            gap = (e[:, nv + 1] - e[:, nv - 2]).min()
+        else:
+            gap = (e[:, nv] - e[:, nv - 1]).min()
+        return Omega1 - gap if kind == "wrong_sign" else gap - Omega1
+    return eb
+
+
+# ---------------------------------------------------------------------------------------------------------
+# the pins each family of functions answers to (the tests of the oracle modules, called with their inputs)
+# ---------------------------------------------------------------------------------------------------------
+HAMILTONIAN_PINS = {
+    "hand_one_k": TH.test_hand_one_k,
+    "hand_three_k": TH.test_hand_three_k_phase_orientation,
+    "ao_bruteforce_G1": lambda: TH.test_bruteforce_ao_kernel("G1", (2, 2, 1), False),
+    "ao_bruteforce_G2": lambda: TH.test_bruteforce_ao_kernel("G2", (2, 2, 1), False),
+    "ao_bruteforce_G2_q_ne_minus_q": lambda: TH.test_bruteforce_ao_kernel("G2", (3, 2, 1), False),
+    "ao_bruteforce_complex_vbar": lambda: TH.test_bruteforce_ao_kernel("G1", (2, 2, 1), True),
+    "hermitian_G2": lambda: TH.test_hermitian(dict(TINY), "G2"),
+    "zero_kernel": lambda: TH.test_zero_kernel_is_transition_energies(dict(SMALL)),
+    "exchange_psd_alpha": lambda: TH.test_exchange_psd_low_rank_and_alpha(dict(SMALL)),
+}
+INTERP_PINS = {
+    "single_R_closed_form": TI.test_single_R_closed_form,
+    "R0_constant": TI.test_R0_only_gives_constant,
+    "numpy_fft": lambda: TI.test_matches_numpy_fft_of_padded_box((3, 3, 2), (6, 6, 5)),
+    "coarse_round_trip": lambda: TI.test_coarse_round_trip_exact((3, 2, 2)),
+    "hand_three_k": TH.test_hand_three_k_phase_orientation,
+}
+VELOCITY_PINS = {"velocity_hand_case": TH.test_velocity_start_hand_case}
+SPECTRUM_PINS = {
+    "full_krylov_vs_eigh": lambda: TY.test_full_krylov_equals_eigh(dict(TINY)),
+    "diagonal_closed_form": lambda: TY.test_diagonal_closed_form_and_breakdown(dict(SMALL)),
+}
+BINDING_PINS = {
+    "binding_hand_case": TB.test_binding_energy_hand_case,
+    "zero_kernel_zero_EB": TB.test_zero_kernel_has_zero_binding_energy,
+}
+
+FAMILIES = {
+    "hamiltonian_block": (_block_with, HAMILTONIAN_PINS,
+                          ["exchange_sign", "direct_sign", "dropped_exchange", "dropped_direct",
+                           "direct_without_1_over_Nk", "W_of_minus_q", "W_transposed", "Vbar_transposed",
+                           "valence_density_unconjugated", "conduction_density_reversed", "transition_order",
+                           "diagonal_sign"]),
+    "interpolate_W": (_interp_with, INTERP_PINS, ["fourier_sign", "missing_2pi", "weights_dropped"]),
+    "velocity_start": (_velocity_with, VELOCITY_PINS, ["quasiparticle_denominator", "conjugated_amplitude"]),
+    "continued_fraction": (_cf_with, SPECTRUM_PINS,
+                           ["eta_sign", "coefficient_shift", "b0_unsquared", "missing_1_over_Nk"]),
+    "binding_energy": (_eb_with, BINDING_PINS,
+                       ["kohn_sham_energies", "indirect_gap", "max_for_min", "wrong_bands", "wrong_sign"]),
+}
+
+CASES = [(fam, kind) for fam, (_, _, kinds) in FAMILIES.items() for kind in ["none"] + kinds]
+
+
+def _run_pins(pins):
+    failed = []
+    for name, pin in pins.items():
+        try:
+            pin()
+        except AssertionError:
+            failed.append(name)
+    return failed
+
+
+@pytest.mark.parametrize("fam,kind", CASES, ids=["%s-%s" % c for c in CASES])
+def test_planted_mistake_fails_a_pin(monkeypatch, fam, kind):
+    make, pins, _ = FAMILIES[fam]
+    fn = make(kind)
+    # the oracle's own calls resolve through its module, the pins' calls through the package
+    monkeypatch.setattr(R, fam, fn)
+    monkeypatch.setattr(oracle, fam, fn)
+    failed = _run_pins(pins)
+    print("[planted %s / %s] pins failing: %s" % (fam, kind, ", ".join(failed) or "none"))
+    if kind == "none":
+        assert failed == []      # the copy without a slip is the oracle: every pin holds
+    else:
+        assert failed, "planted mistake %s in %s passes every pin" % (kind, fam)
+
+
+def test_the_copies_without_a_slip_match_the_oracle():
+    # the mutated copies differ from the oracle only by the slip: without one they give the oracle's values
+    p = make_problem(dict(TINY), 0, "G2", coarse=(3, 3, 2))
+    Wq = R.interpolate_W(p.W_R, p.R, p.w_R, dense_kmesh(p.nk))
+    assert np.array_equal(_interp_with("none")(p.W_R, p.R, p.w_R, dense_kmesh(p.nk)), Wq)
+    for k, kp in [(0, 0), (1, 5), (6, 2)]:
+        assert np.array_equal(_block_with("none")(p, Wq, p.alpha, k, kp), R.hamiltonian_block(p, Wq, p.alpha, k, kp))
+    P = R.velocity_start(p, np.eye(3))
+    assert np.array_equal(_velocity_with("none")(p, np.eye(3)), P)
+    H = R.build_H(p, Wq)
+    a, b, st, _ = R.haydock(lambda x: H @ x, P[:, 0], 12)
+    w = np.linspace(1.0, 5.0, 31)
+    assert np.array_equal(_cf_with("none")(a, b, st, w, 0.1, p.Nk), R.continued_fraction(a, b, st, w, 0.1, p.Nk))
+    q = dataclasses.replace(p)
+    assert _eb_with("none")(q, 1.5) == R.binding_energy(q, 1.5)
