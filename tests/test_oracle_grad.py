@@ -30,9 +30,19 @@ def _admissible_dWR(p, seed):
 
 
 def test_apply_gradient_is_exact_linear_response(tiny_cfg):
+    _linear_response(tiny_cfg)
+
+
+def test_apply_gradient_linear_response_where_q_differs_from_minus_q(small_cfg):
+    # on the 2x2x2 mesh every q is its own negative, so the phase sign of the W(R) gradient and which of
+    # q, -q a pair's contribution goes to are invisible there; the 3x2x2 mesh shows both
+    _linear_response(small_cfg)
+
+
+def _linear_response(cfg):
     # L = Re <Ybar, H(W) X> is linear in W(R) and eps: its derivative along any direction
     # equals the difference quotient exactly (up to rounding)
-    p, kq = _setup(tiny_cfg)
+    p, kq = _setup(cfg)
     rng = np.random.default_rng(1)
     Yb = rng.standard_normal((p.N, 2)) + 1j * rng.standard_normal((p.N, 2))
     X = rng.standard_normal((p.N, 2)) + 1j * rng.standard_normal((p.N, 2))

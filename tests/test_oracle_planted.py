@@ -14,6 +14,7 @@ import pytest
 import oracle
 import oracle.bse_ref as R
 import test_oracle_binding as TB
+import test_oracle_grad as TG
 import test_oracle_hamiltonian as TH
 import test_oracle_haydock as TY
 import test_oracle_interp as TI
@@ -126,6 +127,53 @@ def _eb_with(kind):
     return eb
 
 
+def _grad_with(kind):
+    """grad_apply with one planted slip."""
+    def grad(prob, W_q, Ybar, X, alpha=None):
+        nv, nc, Nk = prob.nv, prob.nc, prob.Nk
+        nt = nc * nv
+        val, con = R._bands(prob)
+        Ybar = np.asarray(Ybar).reshape(prob.N, -1)
+        X = np.asarray(X).reshape(prob.N, -1)
+        g_eps = np.zeros((Nk, nv + nc))
+        for k in range(Nk):
+            for c in range(nc):
+                for v in range(nv):
+                    s = np.real(np.vdot(Ybar[(k * nc + c) * nv + v], X[(k * nc + c) * nv + v]))
+                    sg = -1.0 if kind == "eps_signs_swapped" else 1.0
+                    g_eps[k, nv + c] += sg * s
+                    g_eps[k, v] -= sg * s
+        g_Wq = np.zeros((Nk, prob.n_aux, prob.n_aux), dtype=np.complex128)
+        for k in range(Nk):
+            for kp in range(Nk):
+                Mvv = R._pairs(prob, kp, val, k, val)
+                Mcc = R._pairs(prob, k, con, kp, con)
+                G = (Ybar[k * nt:(k + 1) * nt] @ X[kp * nt:(kp + 1) * nt].conj().T).reshape(nc, nv, nc, nv)
+                out = "nm" if kind == "W_gradient_transposed" else "mn"
+                a = Mvv if kind == "valence_conjugate_dropped" else Mvv.conj()
+                term = np.einsum("mpv,ncd,cvdp->" + out, a, Mcc.conj(), G)
+                scale = -1.0 if kind != "W_gradient_sign" else 1.0
+                if kind != "W_gradient_without_1_over_Nk":
+                    scale /= Nk
+                qi = R.q_index(prob.nk, kp, k) if kind == "W_gradient_at_minus_q" else R.q_index(prob.nk, k, kp)
+                g_Wq[qi] += scale * term
+        return g_eps, g_Wq
+    return grad
+
+
+def _gwr_with(kind):
+    def gwr(g_Wq, Rv, w_R, q_frac):
+        out = np.zeros((len(Rv),) + g_Wq.shape[1:], dtype=np.complex128)
+        sign = 1.0 if kind == "phase_sign" else -1.0
+        for r in range(len(Rv)):
+            for iq, q in enumerate(q_frac):
+                out[r] += np.exp(sign * 2j * np.pi * np.dot(q, Rv[r])) * g_Wq[iq]
+            if kind != "weights_dropped":
+                out[r] *= w_R[r]
+        return out
+    return gwr
+
+
 # ---------------------------------------------------------------------------------------------------------
 # the pins each family of functions answers to (the tests of the oracle modules, called with their inputs)
 # ---------------------------------------------------------------------------------------------------------
@@ -152,6 +200,14 @@ SPECTRUM_PINS = {
     "full_krylov_vs_eigh": lambda: TY.test_full_krylov_equals_eigh(dict(TINY)),
     "diagonal_closed_form": lambda: TY.test_diagonal_closed_form_and_breakdown(dict(SMALL)),
 }
+GRADIENT_PINS = {
+    "linear_response": lambda: TG.test_apply_gradient_is_exact_linear_response(dict(TINY)),
+    "linear_response_q_ne_minus_q": lambda: TG.test_apply_gradient_linear_response_where_q_differs_from_minus_q(
+        dict(SMALL)),
+    "first_moment": lambda: TG.test_first_moment_identity(dict(TINY)),
+    "lowest_exciton_fd": lambda: TG.test_lowest_exciton_gradient_fd(dict(SMALL)),
+    "spectrum_fd": lambda: TG.test_spectrum_gradient_fd(dict(TINY)),
+}
 BINDING_PINS = {
     "binding_hand_case": TB.test_binding_energy_hand_case,
     "zero_kernel_zero_EB": TB.test_zero_kernel_has_zero_binding_energy,
@@ -167,6 +223,10 @@ FAMILIES = {
     "velocity_start": (_velocity_with, VELOCITY_PINS, ["quasiparticle_denominator", "conjugated_amplitude"]),
     "continued_fraction": (_cf_with, SPECTRUM_PINS,
                            ["eta_sign", "coefficient_shift", "b0_unsquared", "missing_1_over_Nk"]),
+    "grad_apply": (_grad_with, GRADIENT_PINS,
+                   ["eps_signs_swapped", "W_gradient_transposed", "valence_conjugate_dropped", "W_gradient_sign",
+                    "W_gradient_without_1_over_Nk", "W_gradient_at_minus_q"]),
+    "grad_WR_from_Wq": (_gwr_with, GRADIENT_PINS, ["phase_sign", "weights_dropped"]),
     "binding_energy": (_eb_with, BINDING_PINS,
                        ["kohn_sham_energies", "indirect_gap", "max_for_min", "wrong_bands", "wrong_sign"]),
 }
