@@ -192,6 +192,28 @@ def test_gauge_covariance(small_cfg):
     assert np.abs(S - S2).max() < 1e-11 * np.abs(S).max()
 
 
+def test_lowest_exciton_is_the_lowest_eigenpair(small_cfg):
+    # (Omega_1, x) is an eigenpair of A with |x| = 1, and A - Omega_1 is positive semi-definite (a Cholesky
+    # factorisation of A - Omega_1 + 1e-9 succeeds, of A - Omega_1 - 1e-9 fails)
+    p = make_problem(small_cfg, 0, "G2", coarse=(3, 3, 2))
+    H = O.build_H(p, _Wq(p))
+    Om, x = O.lowest_exciton(H)
+    assert x.shape == (p.N,)
+    assert abs(np.linalg.norm(x) - 1.0) < 1e-13
+    assert np.abs(H @ x - Om * x).max() < 1e-12 * np.abs(H).max()
+    eye = np.eye(p.N)
+
+    def positive_definite(M):
+        try:
+            np.linalg.cholesky(M)
+            return True
+        except np.linalg.LinAlgError:
+            return False
+
+    assert positive_definite(H - (Om - 1e-9) * eye)
+    assert not positive_definite(H - (Om + 1e-9) * eye)
+
+
 def test_apply_rows_match_explicit(small_cfg):
     p = make_problem(small_cfg, 0, "G2", coarse=(3, 3, 2))
     Wq = _Wq(p)

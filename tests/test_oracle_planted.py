@@ -18,6 +18,7 @@ import test_oracle_grad as TG
 import test_oracle_hamiltonian as TH
 import test_oracle_haydock as TY
 import test_oracle_interp as TI
+import test_oracle_momentum as TM
 from conftest import SMALL, TINY
 from synth import dense_kmesh, make_problem
 
@@ -174,6 +175,76 @@ def _gwr_with(kind):
     return gwr
 
 
+def _pd_with(kind):
+    """pair_density with one planted slip."""
+    def pd(psi, C, ki, bi, kj, bj):
+        a = psi[ki][list(bi)]
+        b = psi[kj][list(bj)]
+        if kind == "conjugate_on_the_right":
+            a, b = a.conj(), b.conj()
+        Cm = np.transpose(C, (0, 2, 1)) if kind == "C_transposed" else C
+        if kind == "k_of_the_left_band":
+            b = psi[ki][list(bj)]
+        return np.matmul(a.conj()[None], np.matmul(Cm, b.T))
+    return pd
+
+
+def _spec_with(kind):
+    def spec(Omega, Z, P, omega, eta, Nk):
+        amp = np.abs((Z.T if kind == "eigenvectors_unconjugated" else Z.conj().T) @ P) ** 2
+        if kind == "amplitude_unsquared":
+            amp = np.sqrt(amp)
+        L = R.lorentzian(np.asarray(omega)[None, :] - np.asarray(Omega)[:, None], eta)
+        return (amp.T @ L) / (1 if kind == "missing_1_over_Nk" else Nk)
+    return spec
+
+
+def _lor_with(kind):
+    def lor(x, eta):
+        if kind == "full_width_for_half_width":
+            eta = eta / 2
+        num = eta if kind != "missing_1_over_pi" else eta * np.pi
+        return (num / np.pi) / (x * x + (eta if kind == "eta_unsquared" else eta * eta))
+    return lor
+
+
+def _lowest_with(kind):
+    def lowest(H):
+        Om, Z = np.linalg.eigh(H)
+        i = -1 if kind == "largest_eigenvalue" else 0
+        return Om[i], (Z[i] if kind == "eigenvector_row" else Z[:, i])
+    return lowest
+
+
+def _c2r_with(kind):
+    def c2r(W_qc, coarse, Rv):
+        qc = R.coarse_mesh(coarse)
+        out = np.zeros((len(Rv),) + W_qc.shape[1:], dtype=np.complex128)
+        sign = 1.0 if kind == "phase_sign" else -1.0
+        for r in range(len(Rv)):
+            for iq in range(len(qc)):
+                out[r] += np.exp(sign * 2j * np.pi * np.dot(qc[iq], Rv[r])) * W_qc[iq]
+        return out if kind == "missing_1_over_Nc" else out / len(qc)
+    return c2r
+
+
+def _ds_with(kind):
+    def ds(prob):
+        nv, nc = prob.nv, prob.nc
+        out = np.zeros((prob.N, 1), dtype=np.complex128)
+        for k in range(prob.Nk):
+            for c in range(nc):
+                for v in range(nv):
+                    if kind == "conjugated_element":
+                        out[(k * nc + c) * nv + v, 0] = np.vdot(prob.psi[k, v], prob.psi[k, nv + c])
+                    elif kind == "same_band_twice":
+                        out[(k * nc + c) * nv + v, 0] = np.vdot(prob.psi[k, nv + c], prob.psi[k, nv + c])
+                    else:
+                        out[(k * nc + c) * nv + v, 0] = np.vdot(prob.psi[k, nv + c], prob.psi[k, v])
+        return out
+    return ds
+
+
 # ---------------------------------------------------------------------------------------------------------
 # the pins each family of functions answers to (the tests of the oracle modules, called with their inputs)
 # ---------------------------------------------------------------------------------------------------------
@@ -208,6 +279,25 @@ GRADIENT_PINS = {
     "lowest_exciton_fd": lambda: TG.test_lowest_exciton_gradient_fd(dict(SMALL)),
     "spectrum_fd": lambda: TG.test_spectrum_gradient_fd(dict(TINY)),
 }
+PAIR_PINS = {k: HAMILTONIAN_PINS[k] for k in ("hand_one_k", "hand_three_k", "ao_bruteforce_G1",
+                                                 "ao_bruteforce_G2", "ao_bruteforce_G2_q_ne_minus_q")}
+SPECTRUM_EXACT_PINS = {
+    "ipa_closed_form": lambda: TH.test_zero_kernel_is_transition_energies(dict(SMALL)),
+    "full_krylov_vs_eigh": lambda: TY.test_full_krylov_equals_eigh(dict(TINY)),
+    "gauge_covariance": lambda: TH.test_gauge_covariance(dict(SMALL)),
+}
+LOWEST_PINS = {
+    "zero_kernel_zero_EB": TB.test_zero_kernel_has_zero_binding_energy,
+    "lowest_exciton_fd": lambda: TG.test_lowest_exciton_gradient_fd(dict(SMALL)),
+    "lowest_eigenpair": lambda: TH.test_lowest_exciton_is_the_lowest_eigenpair(dict(SMALL)),
+}
+COARSE_PINS = {"coarse_round_trip_322": lambda: TI.test_coarse_round_trip_exact((3, 2, 2)),
+               "coarse_round_trip_222": lambda: TI.test_coarse_round_trip_exact((2, 2, 2))}
+DENSITY_PINS = {
+    "vanishes_at_Q0": TM.test_density_start_vanishes_at_zero_momentum,
+    "completeness_bound": TM.test_density_start_bounded_by_completeness,
+    "long_wavelength_limit": TM.test_density_start_long_wavelength_limit_is_the_velocity_form,
+}
 BINDING_PINS = {
     "binding_hand_case": TB.test_binding_energy_hand_case,
     "zero_kernel_zero_EB": TB.test_zero_kernel_has_zero_binding_energy,
@@ -227,6 +317,14 @@ FAMILIES = {
                    ["eps_signs_swapped", "W_gradient_transposed", "valence_conjugate_dropped", "W_gradient_sign",
                     "W_gradient_without_1_over_Nk", "W_gradient_at_minus_q"]),
     "grad_WR_from_Wq": (_gwr_with, GRADIENT_PINS, ["phase_sign", "weights_dropped"]),
+    "pair_density": (_pd_with, PAIR_PINS, ["conjugate_on_the_right", "C_transposed", "k_of_the_left_band"]),
+    "spectrum_exact": (_spec_with, SPECTRUM_EXACT_PINS,
+                       ["eigenvectors_unconjugated", "amplitude_unsquared", "missing_1_over_Nk"]),
+    "lorentzian": (_lor_with, SPECTRUM_EXACT_PINS, ["full_width_for_half_width", "missing_1_over_pi",
+                                                    "eta_unsquared"]),
+    "lowest_exciton": (_lowest_with, LOWEST_PINS, ["largest_eigenvalue", "eigenvector_row"]),
+    "coarse_to_R": (_c2r_with, COARSE_PINS, ["phase_sign", "missing_1_over_Nc"]),
+    "density_start": (_ds_with, DENSITY_PINS, ["conjugated_element", "same_band_twice"]),
     "binding_energy": (_eb_with, BINDING_PINS,
                        ["kohn_sham_energies", "indirect_gap", "max_for_min", "wrong_bands", "wrong_sign"]),
 }
