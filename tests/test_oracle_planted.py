@@ -19,6 +19,7 @@ import test_oracle_hamiltonian as TH
 import test_oracle_haydock as TY
 import test_oracle_interp as TI
 import test_oracle_momentum as TM
+import test_oracle_rows as TR
 from conftest import SMALL, TINY
 from synth import dense_kmesh, make_problem
 
@@ -245,6 +246,114 @@ def _ds_with(kind):
     return ds
 
 
+def _allpairs_with(kind):
+    """apply_H_rows_allpairs with one planted slip."""
+    def rows_fn(prob, W_q, X, rows, alpha=None, chunk=64):
+        alpha = prob.alpha if alpha is None else alpha
+        nv, nc, Nk, na, no = prob.nv, prob.nc, prob.Nk, prob.n_aux, prob.n_ao
+        nt = nc * nv
+        val, con = R._bands(prob)
+        pv, pc = prob.psi[:, val, :], prob.psi[:, con, :]
+        C = prob.C
+        X = np.asarray(X).reshape(Nk, nt, -1)
+        nb = X.shape[2]
+        Xr = X.reshape(Nk, nc, nv, nb)
+        last = Nk - chunk + 1 if kind == "ragged_chunk_dropped" else Nk
+        t = np.zeros((na, nb), dtype=np.complex128)
+        for k0 in range(0, max(last, 1), chunk):
+            ks = slice(k0, min(Nk, k0 + chunk))
+            K = ks.stop - ks.start
+            Cpc = np.transpose(np.tensordot(C, pc[ks], axes=([2], [2])), (2, 1, 0, 3)).reshape(K, no, -1)
+            left = pv[ks] if kind == "exchange_density_unconjugated" else pv[ks].conj()
+            Mvc = np.transpose(np.matmul(left, Cpc).reshape(K, nv, na, nc), (0, 2, 1, 3))
+            t += np.transpose(Mvc, (1, 0, 2, 3)).reshape(na, -1) @ np.transpose(Xr[ks], (0, 2, 1, 3)).reshape(-1, nb)
+        u = (prob.Vbar.T if kind == "Vbar_transposed" else prob.Vbar) @ t
+        qtab = np.array([[R.q_index(prob.nk, kp, k) if kind == "q_reversed" else R.q_index(prob.nk, k, kp)
+                          for kp in range(Nk)] for k in rows])
+        eps_t = R.transition_energies(prob)
+        out = np.zeros((len(rows), nt, nb), dtype=np.complex128)
+        for i, k in enumerate(rows):
+            Mcv = R.pair_density(prob.psi, C, k, con, k, val)
+            out[i] += (alpha / Nk) * np.einsum("mcv,mb->cvb", Mcv, u).reshape(nt, nb)
+            out[i] += eps_t[k][:, None] * X[k]
+            Cv = np.matmul(C, pv[k].T)
+            Bc = np.matmul(pc[k].conj()[None], C)
+            for k0 in range(0, max(last, 1), chunk):
+                ks = slice(k0, min(Nk, k0 + chunk))
+                K = ks.stop - ks.start
+                Mvv = np.transpose(np.tensordot(pv[ks].conj(), Cv, axes=([2], [1])), (0, 2, 1, 3)).reshape(K, na, nv * nv)
+                Mcc = np.transpose(np.tensordot(Bc, pc[ks], axes=([2], [2])), (2, 1, 3, 0)).reshape(K, nc * nc, na)
+                W = W_q[qtab[i, ks]]
+                t2 = np.matmul(W if kind == "W_transposed" else np.transpose(W, (0, 2, 1)), Mvv)
+                D = -(1.0 / Nk) * np.matmul(Mcc, t2)
+                D = np.transpose(D.reshape(K, nc, nc, nv, nv),
+                                 (0, 2, 3, 1, 4) if kind == "block_transposed" else (0, 1, 4, 2, 3)).reshape(K, nt, nt)
+                out[i] += np.transpose(D, (1, 0, 2)).reshape(nt, K * nt) @ X[ks].reshape(K * nt, nb)
+        return out.reshape(len(rows) * nt, nb)
+    return rows_fn
+
+
+def _wmm_with(kind):
+    def wmm(W_R, Rv, w_R, q_frac):
+        W_R = np.asarray(W_R, dtype=np.complex128)
+        q_frac = np.atleast_2d(np.asarray(q_frac, dtype=np.float64))
+        sign = -1.0 if kind == "phase_sign" else 1.0
+        w = np.ones(len(Rv)) if kind == "weights_dropped" else np.asarray(w_R)
+        ph = w[None, :] * np.exp(sign * 2j * np.pi * (q_frac @ np.asarray(Rv, dtype=np.float64).T))
+        out = (ph @ W_R.reshape(len(Rv), -1)).reshape((len(q_frac),) + W_R.shape[1:])
+        return np.transpose(out, (0, 2, 1)) if kind == "result_transposed" else out
+    return wmm
+
+
+def _geps_with(kind):
+    def geps(prob, Ybar, X):
+        nv, nc, Nk = prob.nv, prob.nc, prob.Nk
+        yb = np.asarray(Ybar) if kind == "conjugate_dropped" else np.conj(np.asarray(Ybar))
+        s = np.real(np.sum(yb * np.asarray(X), axis=1)).reshape(Nk, nc, nv)
+        sg = -1.0 if kind == "signs_swapped" else 1.0
+        g = np.zeros((Nk, nv + nc))
+        g[:, nv:] = sg * s.sum(axis=2)
+        g[:, :nv] = -sg * s.sum(axis=1)
+        return g
+    return geps
+
+
+def _gwq_with(kind):
+    """grad_Wq_at with one planted slip."""
+    def gwq(prob, Ybar, X, qs, chunk=64):
+        nv, nc, Nk, na, no = prob.nv, prob.nc, prob.Nk, prob.n_aux, prob.n_ao
+        nt = nc * nv
+        val, con = R._bands(prob)
+        pv, pc = prob.psi[:, val, :], prob.psi[:, con, :]
+        C = prob.C
+        Ybar = np.asarray(Ybar).reshape(Nk, nt, -1)
+        X = np.asarray(X).reshape(Nk, nt, -1)
+        out = np.zeros((len(qs), na, na), dtype=np.complex128)
+        n = np.array(prob.nk)
+        kidx = np.array(np.unravel_index(np.arange(Nk), prob.nk)).T
+        for i, q in enumerate(qs):
+            sq = -1 if kind == "pairs_at_minus_q" else 1
+            kps = np.ravel_multi_index(tuple(((kidx + sq * np.array(np.unravel_index(q, prob.nk))) % n).T), prob.nk)
+            for k0 in range(0, Nk, chunk):
+                ks = np.arange(k0, min(Nk, k0 + chunk))
+                kp = kps[ks]
+                K = len(ks)
+                Cv = np.transpose(np.tensordot(C, pv[ks], axes=([2], [2])), (2, 1, 0, 3)).reshape(K, no, -1)
+                Mvv = np.transpose(np.matmul(pv[kp].conj(), Cv).reshape(K, nv, na, nv), (0, 2, 1, 3))
+                Cc = np.transpose(np.tensordot(C, pc[kp], axes=([2], [2])), (2, 1, 0, 3)).reshape(K, no, -1)
+                Mcc = np.transpose(np.matmul(pc[ks].conj(), Cc).reshape(K, nc, na, nc), (0, 2, 1, 3))
+                xk = X[kp] if kind == "X_unconjugated" else X[kp].conj()
+                G = np.matmul(Ybar[ks], np.transpose(xk, (0, 2, 1)))
+                G = np.transpose(G.reshape(K, nc, nv, nc, nv), (0, 1, 3, 4, 2)).reshape(K, nc * nc, nv * nv)
+                Z = np.matmul(Mcc.conj().reshape(K, na, nc * nc), G)
+                A = np.transpose(Mvv.conj().reshape(K, na, nv * nv), (1, 0, 2)).reshape(na, -1)
+                Bz = np.transpose(Z, (1, 0, 2)).reshape(na, -1)
+                term = -(1.0 / Nk) * (A @ Bz.T)
+                out[i] += term.T if kind == "result_transposed" else term
+        return out
+    return gwq
+
+
 # ---------------------------------------------------------------------------------------------------------
 # the pins each family of functions answers to (the tests of the oracle modules, called with their inputs)
 # ---------------------------------------------------------------------------------------------------------
@@ -298,6 +407,20 @@ DENSITY_PINS = {
     "completeness_bound": TM.test_density_start_bounded_by_completeness,
     "long_wavelength_limit": TM.test_density_start_long_wavelength_limit_is_the_velocity_form,
 }
+ROW_PINS = {
+    "allpairs_vs_blocks_ragged": lambda: TR.test_allpairs_rows_match_blocks("RAGGED", 7, 2.0),
+    "allpairs_vs_blocks_wide_v": lambda: TR.test_allpairs_rows_match_blocks("WIDE_V", 5, 2.0),
+    "allpairs_vs_explicit_H": TR.test_allpairs_rows_match_explicit_H,
+}
+MATMUL_PINS = {
+    "matmul_vs_direct_sum": lambda: TR.test_interpolate_matmul_matches_direct_sum("RAGGED"),
+    "matmul_single_R": TR.test_interpolate_matmul_single_R_closed_form,
+}
+GEPS_PINS = {"grad_eps_vs_grad_apply": TR.test_grad_eps_matches_grad_apply}
+GWQ_PINS = {
+    "grad_Wq_at_vs_grad_apply_ragged": lambda: TR.test_grad_Wq_at_matches_grad_apply("RAGGED", 7),
+    "grad_Wq_at_vs_grad_apply_wide_v": lambda: TR.test_grad_Wq_at_matches_grad_apply("WIDE_V", 64),
+}
 BINDING_PINS = {
     "binding_hand_case": TB.test_binding_energy_hand_case,
     "zero_kernel_zero_EB": TB.test_zero_kernel_has_zero_binding_energy,
@@ -325,6 +448,12 @@ FAMILIES = {
     "lowest_exciton": (_lowest_with, LOWEST_PINS, ["largest_eigenvalue", "eigenvector_row"]),
     "coarse_to_R": (_c2r_with, COARSE_PINS, ["phase_sign", "missing_1_over_Nc"]),
     "density_start": (_ds_with, DENSITY_PINS, ["conjugated_element", "same_band_twice"]),
+    "apply_H_rows_allpairs": (_allpairs_with, ROW_PINS,
+                              ["ragged_chunk_dropped", "exchange_density_unconjugated", "Vbar_transposed",
+                               "q_reversed", "W_transposed", "block_transposed"]),
+    "interpolate_W_matmul": (_wmm_with, MATMUL_PINS, ["phase_sign", "weights_dropped", "result_transposed"]),
+    "grad_eps": (_geps_with, GEPS_PINS, ["conjugate_dropped", "signs_swapped"]),
+    "grad_Wq_at": (_gwq_with, GWQ_PINS, ["pairs_at_minus_q", "X_unconjugated", "result_transposed"]),
     "binding_energy": (_eb_with, BINDING_PINS,
                        ["kohn_sham_energies", "indirect_gap", "max_for_min", "wrong_bands", "wrong_sign"]),
 }
