@@ -139,6 +139,13 @@ def test_zero_kernel_is_transition_energies(small_cfg):
     H = O.build_H(p, _Wq(p))
     te = O.transition_energies(p).ravel()
     assert np.abs(H - np.diag(te)).max() == 0.0
+    # the diagonal is E^QP_ck - E^QP_vk in the row order (k, c, v), written out here without the oracle; the
+    # scissor makes the Kohn-Sham differences another diagonal, and n_c != n_v another (v, c) order
+    nv = p.nv
+    te_ref = np.array([p.eps_qp[k, nv + c] - p.eps_qp[k, v]
+                       for k in range(p.Nk) for c in range(p.nc) for v in range(nv)])
+    assert np.array_equal(np.diag(H).real, te_ref)
+    assert np.abs((p.eps_qp - p.eps_ks)[:, nv:]).min() > 0.1 and p.nc != p.nv
     # IPA limit of the spectrum: peaks at e_c - e_v with weight |p_I|^2 / N_k
     P = O.velocity_start(p, np.eye(3))
     w = np.linspace(1.0, 6.0, 101)
@@ -190,6 +197,20 @@ def test_gauge_covariance(small_cfg):
     S2, Om2, _ = O.eig_spectrum(O.build_H(p, Wq), O.velocity_start(p, np.eye(3)), w, 0.1, p.Nk)
     assert np.abs(Om - Om2).max() < 1e-12
     assert np.abs(S - S2).max() < 1e-11 * np.abs(S).max()
+
+
+def test_q_index_is_the_mesh_index_of_the_difference():
+    # q_index(k, k') is the position in the mesh of k' - k (mod 1), found here by coordinates on a mesh with
+    # three different sizes, so that a swapped axis or a reversed difference shows; the oracle's mesh is the
+    # one the inputs are generated on
+    nk = (3, 2, 5)
+    km = O.kmesh(nk)
+    assert np.array_equal(km, dense_kmesh(nk))
+    for i in range(len(km)):
+        for j in range(len(km)):
+            d = (km[j] - km[i]) % 1.0
+            hit = np.flatnonzero(np.all(np.abs(((km - d) + 0.5) % 1.0 - 0.5) < 1e-12, axis=1))
+            assert len(hit) == 1 and O.q_index(nk, i, j) == hit[0]
 
 
 def test_lowest_exciton_is_the_lowest_eigenpair(small_cfg):

@@ -24,6 +24,19 @@ def test_full_krylov_equals_eigh(tiny_cfg):
     assert np.abs(S - Sref).max() < 1e-11 * np.abs(Sref).max()
 
 
+def test_full_krylov_indefinite_operator(tiny_cfg):
+    # the recurrence is that of any Hermitian operator: shifted so that its spectrum has both signs (and
+    # Rayleigh quotients of both signs occur), the full-Krylov continued fraction is still the resolvent
+    p, H, P = _setup(tiny_cfg)
+    ev = np.linalg.eigvalsh(H)
+    Hs = H - np.median(ev) * np.eye(p.N)
+    w = np.linspace(-3.0, 3.0, 201)
+    Sref, _, _ = O.eig_spectrum(Hs, P, w, 0.1, p.Nk)
+    S, a, b, st = O.haydock_spectrum(lambda x: Hs @ x, P, p.N, w, 0.1, p.Nk)
+    assert (a < 0).any() and (a > 0).any()
+    assert np.abs(S - Sref).max() < 1e-11 * np.abs(Sref).max()
+
+
 def test_moment_identities(small_cfg):
     # p^H H^n p = b_0^2 (T_m^n)_{11} for n <= 2m - 1, at every m
     p, H, P = _setup(small_cfg)

@@ -354,6 +354,101 @@ def _gwq_with(kind):
     return gwq
 
 
+def _haydock_with(kind):
+    """haydock with one planted slip."""
+    def hay(apply, p, m, tol=1e-12):
+        p = np.asarray(p, dtype=np.complex128)
+        b0 = np.linalg.norm(p)
+        a = np.zeros(m)
+        b = np.zeros(m + 1)
+        b[0] = b0
+        Q = [p if kind == "start_unnormalised" else p / b0]
+        qprev = np.zeros_like(p)
+        steps = m
+        for j in range(1, m + 1):
+            qj = Q[-1]
+            w = apply(qj)
+            a[j - 1] = np.abs(np.vdot(qj, w)) if kind == "a_modulus" else np.real(np.vdot(qj, w))
+            if kind != "a_not_subtracted":
+                w = w - a[j - 1] * qj
+            w = w - (b[j - 1] if j > 1 else 0.0) * qprev
+            Qm = np.array(Q)
+            for _ in range(2):
+                w = w - Qm.T @ (Qm.conj() @ w)
+            b[j] = np.linalg.norm(w) ** (2 if kind == "b_squared" else 1)
+            scale = max(np.abs(a[:j]).max(), b[1:j].max(initial=0.0))
+            if b[j] <= tol * scale:
+                steps = j
+                break
+            qprev = qj
+            if j < m:
+                Q.append(w / b[j])
+        return a, b, steps, np.array(Q[:steps])
+    return hay
+
+
+def _gspec_with(kind):
+    def gspec(prob, W_q, P, omega, eta, gamma, H=None, alpha=None):
+        if H is None:
+            H = R.build_H(prob, W_q, alpha)
+        Om, U = np.linalg.eigh(H)
+        Nk = prob.Nk
+        Ys, Xs = [], []
+        for e in range(P.shape[1]):
+            c = U.conj().T @ P[:, e]
+            for iw, w in enumerate(omega):
+                z = w + 1j * eta
+                y = U @ (c / (z - Om))
+                yt = y if kind == "same_resolvent_both_sides" else U @ (c / (np.conj(z) - Om))
+                f = -1.0 if kind == "missing_i" else -1j
+                Ys.append((f * gamma[e][iw] / (np.pi * Nk)) * yt)
+                Xs.append(y)
+        return R.grad_apply(prob, W_q, np.array(Ys).T, np.array(Xs).T, alpha)
+    return gspec
+
+
+def _glow_with(kind):
+    def glow(prob, W_q, H=None, alpha=None):
+        if H is None:
+            H = R.build_H(prob, W_q, alpha)
+        Om, Z = np.linalg.eigh(H)
+        x = Z[:, 1:2] if kind == "second_eigenvector" else Z[:, :1]
+        if kind == "eigenvector_conjugated":
+            x = x.conj()
+        g_eps, g_Wq = R.grad_apply(prob, W_q, x, x, alpha)
+        return Om[0], g_eps, g_Wq
+    return glow
+
+
+def _te_with(kind):
+    def te(prob, eps=None):
+        e = prob.eps_qp if eps is None else eps
+        if kind == "kohn_sham" and eps is None:
+            e = prob.eps_ks
+        nv, nc = prob.nv, prob.nc
+        out = np.empty((len(e), nc * nv))
+        for k in range(len(e)):
+            for c in range(nc):
+                for v in range(nv):
+                    d = e[k, nv + c] - e[k, v]
+                    out[k, (v * nc + c) if kind == "valence_major" else (c * nv + v)] = -d if kind == "reversed" else d
+        return out
+    return te
+
+
+def _qi_with(kind):
+    def qi(nk, ik, jk):
+        n1, n2, n3 = nk
+        a1, a2, a3 = ik // (n2 * n3), (ik // n3) % n2, ik % n3
+        b1, b2, b3 = jk // (n2 * n3), (jk // n3) % n2, jk % n3
+        if kind == "k_minus_kprime":
+            a1, a2, a3, b1, b2, b3 = b1, b2, b3, a1, a2, a3
+        if kind == "axes_swapped":
+            return (((b3 - a3) % n3) * n2 + (b2 - a2) % n2) * n1 + (b1 - a1) % n1
+        return (((b1 - a1) % n1) * n2 + (b2 - a2) % n2) * n3 + (b3 - a3) % n3
+    return qi
+
+
 # ---------------------------------------------------------------------------------------------------------
 # the pins each family of functions answers to (the tests of the oracle modules, called with their inputs)
 # ---------------------------------------------------------------------------------------------------------
@@ -421,6 +516,19 @@ GWQ_PINS = {
     "grad_Wq_at_vs_grad_apply_ragged": lambda: TR.test_grad_Wq_at_matches_grad_apply("RAGGED", 7),
     "grad_Wq_at_vs_grad_apply_wide_v": lambda: TR.test_grad_Wq_at_matches_grad_apply("WIDE_V", 64),
 }
+LANCZOS_PINS = {
+    "full_krylov_vs_eigh": lambda: TY.test_full_krylov_equals_eigh(dict(TINY)),
+    "moment_identities": lambda: TY.test_moment_identities(dict(SMALL)),
+    "diagonal_closed_form": lambda: TY.test_diagonal_closed_form_and_breakdown(dict(SMALL)),
+    "full_krylov_indefinite": lambda: TY.test_full_krylov_indefinite_operator(dict(TINY)),
+}
+GSPEC_PINS = {"spectrum_fd": lambda: TG.test_spectrum_gradient_fd(dict(TINY))}
+GLOW_PINS = {"lowest_exciton_fd": lambda: TG.test_lowest_exciton_gradient_fd(dict(SMALL))}
+TE_PINS = {k: HAMILTONIAN_PINS[k] for k in ("hand_one_k", "hand_three_k")}
+TE_PINS["ipa_closed_form"] = lambda: TH.test_zero_kernel_is_transition_energies(dict(SMALL))
+TE_PINS["binding_hand_case"] = TB.test_binding_energy_hand_case
+QI_PINS = {k: HAMILTONIAN_PINS[k] for k in ("hand_three_k", "ao_bruteforce_G2_q_ne_minus_q")}
+QI_PINS["mesh_index_of_the_difference"] = TH.test_q_index_is_the_mesh_index_of_the_difference
 BINDING_PINS = {
     "binding_hand_case": TB.test_binding_energy_hand_case,
     "zero_kernel_zero_EB": TB.test_zero_kernel_has_zero_binding_energy,
@@ -454,6 +562,12 @@ FAMILIES = {
     "interpolate_W_matmul": (_wmm_with, MATMUL_PINS, ["phase_sign", "weights_dropped", "result_transposed"]),
     "grad_eps": (_geps_with, GEPS_PINS, ["conjugate_dropped", "signs_swapped"]),
     "grad_Wq_at": (_gwq_with, GWQ_PINS, ["pairs_at_minus_q", "X_unconjugated", "result_transposed"]),
+    "haydock": (_haydock_with, LANCZOS_PINS, ["start_unnormalised", "a_modulus", "a_not_subtracted",
+                                              "b_squared"]),
+    "grad_spectrum": (_gspec_with, GSPEC_PINS, ["same_resolvent_both_sides", "missing_i"]),
+    "grad_lowest": (_glow_with, GLOW_PINS, ["second_eigenvector", "eigenvector_conjugated"]),
+    "transition_energies": (_te_with, TE_PINS, ["reversed", "kohn_sham", "valence_major"]),
+    "q_index": (_qi_with, QI_PINS, ["k_minus_kprime", "axes_swapped"]),
     "binding_energy": (_eb_with, BINDING_PINS,
                        ["kohn_sham_energies", "indirect_gap", "max_for_min", "wrong_bands", "wrong_sign"]),
 }
