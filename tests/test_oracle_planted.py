@@ -1,11 +1,14 @@
-"""Planted mistakes in the oracle: each plausible slip in the explicit Hamiltonian (Eq. (Hamiltonian) with
-the kernels of Eq. (W_LRI)), the interpolation of W (Sec. III.B), the velocity-form start vector
-(Eq. (abs_vel)), the continued fraction of the Haydock spectrum and the binding energy (Sec. IV.B.3) -- a
-dropped term, a wrong sign, a transposed operand, a wrong index or orientation, a missing normalisation --
-is planted in a copy of that oracle function for the duration of one test, and at least one of the pins
-that tie the function to the paper and the mathematics (hand-derived cases, the AO-kernel brute force,
-closed forms, library routines, invariants) must fail.  The unmutated oracle passes every pin (the
-"none" cases), so a failure here is the pin catching the planted slip, not the harness."""
+"""Planted mistakes in the oracle.  Each plausible slip (a dropped term, a wrong sign, a transposed or
+unconjugated operand, a wrong index, orientation or band, a missing normalisation, a dropped ragged chunk)
+is planted in a copy of one oracle function for the duration of one test, and at least one of the pins
+that tie that function to the paper and the mathematics (hand-derived cases, the AO-kernel brute force,
+closed forms, library routines, invariants, finite differences) must then fail.  Covered: the explicit
+Hamiltonian (Eq. (Hamiltonian) with the kernels of Eq. (W_LRI)), its diagonal and q indexing, the pair
+densities (C-tilde of Sec. III.A), the interpolation of W and its inverse (Sec. III.B), the velocity and
+finite-momentum start vectors (Eq. (abs_vel)), the exact spectrum and the Lorentzian, the Lanczos
+recurrence and continued fraction, the lowest exciton and the binding energy (Sec. IV.B.3), the gradients,
+and the row-at-a-time forms the large-mesh parity tests use.  The copies without a slip reproduce the
+oracle and pass every pin (the "none" cases), so a failure is the pin catching the slip."""
 import dataclasses
 
 import numpy as np
@@ -603,15 +606,49 @@ def test_planted_mistake_fails_a_pin(monkeypatch, fam, kind):
 def test_the_copies_without_a_slip_match_the_oracle():
     # the mutated copies differ from the oracle only by the slip: without one they give the oracle's values
     p = make_problem(dict(TINY), 0, "G2", coarse=(3, 3, 2))
-    Wq = R.interpolate_W(p.W_R, p.R, p.w_R, dense_kmesh(p.nk))
-    assert np.array_equal(_interp_with("none")(p.W_R, p.R, p.w_R, dense_kmesh(p.nk)), Wq)
-    for k, kp in [(0, 0), (1, 5), (6, 2)]:
-        assert np.array_equal(_block_with("none")(p, Wq, p.alpha, k, kp), R.hamiltonian_block(p, Wq, p.alpha, k, kp))
+    s3 = make_problem(dict(SMALL), 0, "G2", coarse=(3, 3, 2))
+    kq = dense_kmesh(p.nk)
+    Wq = R.interpolate_W(p.W_R, p.R, p.w_R, kq)
     P = R.velocity_start(p, np.eye(3))
-    assert np.array_equal(_velocity_with("none")(p, np.eye(3)), P)
     H = R.build_H(p, Wq)
     a, b, st, _ = R.haydock(lambda x: H @ x, P[:, 0], 12)
+    rng = np.random.default_rng(0)
+    Yb = rng.standard_normal((p.N, 2)) + 1j * rng.standard_normal((p.N, 2))
+    X = rng.standard_normal((p.N, 2)) + 1j * rng.standard_normal((p.N, 2))
     w = np.linspace(1.0, 5.0, 31)
-    assert np.array_equal(_cf_with("none")(a, b, st, w, 0.1, p.Nk), R.continued_fraction(a, b, st, w, 0.1, p.Nk))
-    q = dataclasses.replace(p)
-    assert _eb_with("none")(q, 1.5) == R.binding_energy(q, 1.5)
+    Om, Z = np.linalg.eigh(H)
+    gq = R.grad_apply(p, Wq, Yb, X)[1]
+    calls = {
+        "hamiltonian_block": [(p, Wq, p.alpha, k, kp) for k, kp in [(0, 0), (1, 5), (6, 2)]],
+        "interpolate_W": [(p.W_R, p.R, p.w_R, kq)],
+        "velocity_start": [(p, np.eye(3))],
+        "continued_fraction": [(a, b, st, w, 0.1, p.Nk)],
+        "binding_energy": [(p, 1.5)],
+        "grad_apply": [(p, Wq, Yb, X)],
+        "grad_WR_from_Wq": [(gq, p.R, p.w_R, kq)],
+        "pair_density": [(p.psi, p.C, 1, [0, 1], 3, [2, 3])],
+        "spectrum_exact": [(Om, Z, P, w, 0.1, p.Nk)],
+        "lorentzian": [(w - 2.5, 0.1)],
+        "lowest_exciton": [(H,)],
+        "coarse_to_R": [(Wq[:8], (2, 2, 2), p.R)],
+        "density_start": [(p,)],
+        "apply_H_rows_allpairs": [(s3, R.interpolate_W(s3.W_R, s3.R, s3.w_R, dense_kmesh(s3.nk)),
+                                   rng.standard_normal((s3.N, 2)) + 0j, [0, 7], 2.0, 5)],
+        "interpolate_W_matmul": [(p.W_R, p.R, p.w_R, kq)],
+        "grad_eps": [(p, Yb, X)],
+        "grad_Wq_at": [(p, Yb, X, [0, 3, 5], 3)],
+        "haydock": [(lambda x: H @ x, P[:, 0], 12)],
+        "grad_spectrum": [(p, Wq, P[:, :1], w[:4], 0.1, rng.standard_normal((1, 4)))],
+        "grad_lowest": [(p, Wq)],
+        "transition_energies": [(s3,)],
+        "q_index": [((3, 2, 5), i, j) for i, j in [(0, 29), (7, 11), (13, 2)]],
+    }
+    assert set(calls) == set(FAMILIES)
+    for fam, arglists in calls.items():
+        make = FAMILIES[fam][0]
+        for args in arglists:
+            got, ref = make("none")(*args), getattr(R, fam)(*args)
+            got, ref = (got if isinstance(got, tuple) else (got,)), (ref if isinstance(ref, tuple) else (ref,))
+            assert len(got) == len(ref), fam
+            for g, r in zip(got, ref):
+                assert np.array_equal(np.asarray(g), np.asarray(r)), fam
