@@ -1,5 +1,7 @@
 """Pins of the oracle's full BSE (coupling block B of Eq. (Hamiltonian), the paired eigenproblem of
 Eqs. (right)/(left) and the spectrum of Eq. (full_BSE_epsilon2))."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -50,9 +52,17 @@ def _ao_bruteforce_B(p, Wq):
     return B
 
 
+@pytest.mark.parametrize("complex_vbar", [False, True])
+@pytest.mark.parametrize("dense", [(2, 2, 1), (3, 2, 1)])
 @pytest.mark.parametrize("wgen", ["G1", "G2"])
-def test_coupling_block_bruteforce(wgen):
-    p = make_problem(dict(cfg_id=82, coarse=(3, 3, 2), dense=(2, 2, 1), n_ao=4, nv=2, nc=2, n_aux=6), 1, wgen)
+def test_coupling_block_bruteforce(wgen, dense, complex_vbar):
+    # the 3x2x1 mesh has q != -q, where G2's W(q) is not symmetric, so which of W(q), W(-q) = W(q)^T the
+    # direct term takes shows; a complex Hermitian Vbar shows the orientation of the exchange term (the
+    # generators' Vbar is real symmetric)
+    p = make_problem(dict(cfg_id=82, coarse=(3, 3, 2), dense=dense, n_ao=4, nv=2, nc=2, n_aux=6), 1, wgen)
+    if complex_vbar:
+        A = np.random.default_rng(8).standard_normal((p.n_aux, p.n_aux))
+        p = dataclasses.replace(p, Vbar=p.Vbar + 0.1j * (A - A.T))
     Wq = _Wq(p)
     B = O.build_B(p, Wq)
     Bb = _ao_bruteforce_B(p, Wq)

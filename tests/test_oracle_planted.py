@@ -17,6 +17,7 @@ import pytest
 import oracle
 import oracle.bse_ref as R
 import test_oracle_binding as TB
+import test_oracle_full_bse as TF
 import test_oracle_grad as TG
 import test_oracle_hamiltonian as TH
 import test_oracle_haydock as TY
@@ -452,6 +453,32 @@ def _qi_with(kind):
     return qi
 
 
+def _cb_with(kind):
+    """coupling_block with one planted slip."""
+    def cb(prob, W_q, alpha, k, kp):
+        val, con = R._bands(prob)
+        nc, nv = prob.nc, prob.nv
+        Mcv = R._pairs(prob, k, con, k, val)
+        Mcv2 = R._pairs(prob, kp, con, kp, val)
+        if kind == "exchange_density_conjugated":
+            Mcv2 = np.transpose(R._pairs(prob, kp, val, kp, con), (0, 2, 1))     # M_v'c'(k',k') read as [c'][v']
+        Mcpv = R._pairs(prob, kp, con, k, val)
+        Mcvp = R._pairs(prob, k, con, kp, val)
+        if kind == "direct_densities_swapped":
+            Mcpv, Mcvp = R._pairs(prob, k, con, kp, val), R._pairs(prob, kp, con, k, val)
+        qi = R.q_index(prob.nk, kp, k) if kind == "W_of_minus_q" else R.q_index(prob.nk, k, kp)
+        Wq = W_q[qi].T if kind == "W_transposed" else W_q[qi]
+        Vb = prob.Vbar.T if kind == "Vbar_transposed" else prob.Vbar
+        Xb = (alpha / prob.Nk) * np.einsum("mcv,mn,ndp->cvdp", Mcv, Vb, Mcv2)
+        Db = -(1.0 / prob.Nk) * np.einsum("mdv,mn,ncp->cvdp", Mcpv, Wq, Mcvp)
+        if kind == "direct_sign":
+            Db = -Db
+        elif kind == "exchange_sign":
+            Xb = -Xb
+        return (Xb + Db).reshape(nc * nv, nc * nv)
+    return cb
+
+
 # ---------------------------------------------------------------------------------------------------------
 # the pins each family of functions answers to (the tests of the oracle modules, called with their inputs)
 # ---------------------------------------------------------------------------------------------------------
@@ -532,6 +559,14 @@ TE_PINS["ipa_closed_form"] = lambda: TH.test_zero_kernel_is_transition_energies(
 TE_PINS["binding_hand_case"] = TB.test_binding_energy_hand_case
 QI_PINS = {k: HAMILTONIAN_PINS[k] for k in ("hand_three_k", "ao_bruteforce_G2_q_ne_minus_q")}
 QI_PINS["mesh_index_of_the_difference"] = TH.test_q_index_is_the_mesh_index_of_the_difference
+COUPLING_PINS = {
+    "coupling_bruteforce_G1": lambda: TF.test_coupling_block_bruteforce("G1", (2, 2, 1), False),
+    "coupling_bruteforce_G2": lambda: TF.test_coupling_block_bruteforce("G2", (2, 2, 1), False),
+    "coupling_bruteforce_G2_q_ne_minus_q": lambda: TF.test_coupling_block_bruteforce("G2", (3, 2, 1), False),
+    "coupling_bruteforce_complex_vbar": lambda: TF.test_coupling_block_bruteforce("G1", (2, 2, 1), True),
+    "coupling_symmetric_G2": lambda: TF.test_coupling_block_is_symmetric("G2", False),
+    "paired_eigenproblem": TF.test_paired_eigenproblem,
+}
 BINDING_PINS = {
     "binding_hand_case": TB.test_binding_energy_hand_case,
     "zero_kernel_zero_EB": TB.test_zero_kernel_has_zero_binding_energy,
@@ -571,6 +606,9 @@ FAMILIES = {
     "grad_lowest": (_glow_with, GLOW_PINS, ["second_eigenvector", "eigenvector_conjugated"]),
     "transition_energies": (_te_with, TE_PINS, ["reversed", "kohn_sham", "valence_major"]),
     "q_index": (_qi_with, QI_PINS, ["k_minus_kprime", "axes_swapped"]),
+    "coupling_block": (_cb_with, COUPLING_PINS, ["exchange_density_conjugated", "direct_densities_swapped",
+                                                 "W_of_minus_q", "W_transposed", "Vbar_transposed", "direct_sign",
+                                                 "exchange_sign"]),
     "binding_energy": (_eb_with, BINDING_PINS,
                        ["kohn_sham_energies", "indirect_gap", "max_for_min", "wrong_bands", "wrong_sign"]),
 }
@@ -642,6 +680,7 @@ def test_the_copies_without_a_slip_match_the_oracle():
         "grad_lowest": [(p, Wq)],
         "transition_energies": [(s3,)],
         "q_index": [((3, 2, 5), i, j) for i, j in [(0, 29), (7, 11), (13, 2)]],
+        "coupling_block": [(p, Wq, p.alpha, k, kp) for k, kp in [(0, 0), (1, 5), (6, 2)]],
     }
     assert set(calls) == set(FAMILIES)
     for fam, arglists in calls.items():
