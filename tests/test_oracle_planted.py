@@ -479,6 +479,44 @@ def _cb_with(kind):
     return cb
 
 
+def _feig_with(kind):
+    """full_bse_eig with one planted slip."""
+    def feig(A, B):
+        import scipy.linalg
+        N = A.shape[0]
+        Bl = B if kind == "lower_block_unconjugated" else B.conj()
+        M = np.block([[A, B], [Bl, A.conj()]])
+        J = np.diag(np.r_[np.ones(N), -np.ones(N)]).astype(np.complex128)
+        lam, Z = scipy.linalg.eigh(J, M)
+        pos = lam < 0 if kind == "negative_branch" else lam > 0
+        Om = 1.0 / np.abs(lam[pos])
+        Z = Z[:, pos] * (np.sqrt(Om)[None, :] if kind != "normalised_in_M" else 1.0)
+        order = np.argsort(Om)
+        Om, Z = Om[order], Z[:, order]
+        return Om, Z[:N], Z[N:]
+    return feig
+
+
+def _famp_with(kind):
+    def famp(prob, pol, X, Y):
+        pol = np.atleast_2d(pol)
+        nv, nc = prob.nv, prob.nc
+        eps = prob.eps_qp if kind == "quasiparticle_denominator" else prob.eps_ks
+        out = np.zeros((X.shape[1], len(pol)), dtype=np.complex128)
+        for b, e in enumerate(pol):
+            for k in range(prob.Nk):
+                for c in range(nc):
+                    for v in range(nv):
+                        I = (k * nc + c) * nv + v
+                        d = eps[k, nv + c] - eps[k, v]
+                        m = sum(e[a] * prob.vel[a, k, c, v] for a in range(3))
+                        my = np.conj(m) if kind == "Y_element_conjugated" else m
+                        dy = d if kind == "Y_denominator_sign" else -d
+                        out[:, b] += np.conj(m) / d * X[I] + my / dy * Y[I]
+        return out
+    return famp
+
+
 # ---------------------------------------------------------------------------------------------------------
 # the pins each family of functions answers to (the tests of the oracle modules, called with their inputs)
 # ---------------------------------------------------------------------------------------------------------
@@ -567,6 +605,15 @@ COUPLING_PINS = {
     "coupling_symmetric_G2": lambda: TF.test_coupling_block_is_symmetric("G2", False),
     "paired_eigenproblem": TF.test_paired_eigenproblem,
 }
+FULL_EIG_PINS = {
+    "paired_eigenproblem": TF.test_paired_eigenproblem,
+    "no_coupling_is_tda": TF.test_no_coupling_is_tda,
+    "two_level_closed_form": lambda: TF.test_two_level_closed_form(0.2 + 0.5j),
+}
+FULL_AMP_PINS = {
+    "resolvent_identity": TF.test_spectrum_resolvent_identity,
+    "no_coupling_is_tda": TF.test_no_coupling_is_tda,
+}
 BINDING_PINS = {
     "binding_hand_case": TB.test_binding_energy_hand_case,
     "zero_kernel_zero_EB": TB.test_zero_kernel_has_zero_binding_energy,
@@ -609,6 +656,9 @@ FAMILIES = {
     "coupling_block": (_cb_with, COUPLING_PINS, ["exchange_density_conjugated", "direct_densities_swapped",
                                                  "W_of_minus_q", "W_transposed", "Vbar_transposed", "direct_sign",
                                                  "exchange_sign"]),
+    "full_bse_eig": (_feig_with, FULL_EIG_PINS, ["lower_block_unconjugated", "negative_branch", "normalised_in_M"]),
+    "full_bse_amplitudes": (_famp_with, FULL_AMP_PINS, ["quasiparticle_denominator", "Y_element_conjugated",
+                                                        "Y_denominator_sign"]),
     "binding_energy": (_eb_with, BINDING_PINS,
                        ["kohn_sham_energies", "indirect_gap", "max_for_min", "wrong_bands", "wrong_sign"]),
 }
@@ -681,6 +731,8 @@ def test_the_copies_without_a_slip_match_the_oracle():
         "transition_energies": [(s3,)],
         "q_index": [((3, 2, 5), i, j) for i, j in [(0, 29), (7, 11), (13, 2)]],
         "coupling_block": [(p, Wq, p.alpha, k, kp) for k, kp in [(0, 0), (1, 5), (6, 2)]],
+        "full_bse_eig": [(H, R.build_B(p, Wq))],
+        "full_bse_amplitudes": [(p, np.eye(3), Z[:, :5], 0.1 * Z[:, 5:10])],
     }
     assert set(calls) == set(FAMILIES)
     for fam, arglists in calls.items():
