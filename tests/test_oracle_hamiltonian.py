@@ -10,7 +10,8 @@ import oracle as O
 from synth import make_problem, dense_kmesh
 from synth.crystal import Problem
 
-GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "hand_cases.json")))
+with open(os.path.join(os.path.dirname(__file__), "golden", "hand_cases.json")) as _f:
+    GOLD = json.load(_f)
 
 
 def _Wq(p):
