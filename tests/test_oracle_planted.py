@@ -517,6 +517,88 @@ def _famp_with(kind):
     return famp
 
 
+def _twosided_with(kind):
+    """apply_rows_twosided with one planted slip."""
+    def rows_fn(prob, W_q, X, rows, block="A", alpha=None, chunk=64):
+        alpha = prob.alpha if alpha is None else alpha
+        nv, nc, Nk = prob.nv, prob.nc, prob.Nk
+        nt = nc * nv
+        pv, pc = R._psi_sets(prob)
+        Fv, Fc, two = R._F_sets(prob)
+        X = np.asarray(X).reshape(Nk, nt, -1)
+        nb = X.shape[2]
+        allk = np.arange(Nk)
+        rho = R._pairs_rows(pc, Fc, allk, pv, Fv, allk, two)
+        Xr = X.reshape(Nk, nc, nv, nb)
+        if block == "A" or kind == "B_exchange_with_the_A_density":
+            Mvc = R._pairs_rows(pv, Fv, allk, pc, Fc, allk, two)
+            t = np.einsum("knvc,kcvb->nb", Mvc, Xr, optimize=True)
+        else:
+            t = np.einsum("kncv,kcvb->nb", rho, Xr, optimize=True)
+        u = prob.Vbar @ t
+        qtab = np.array([[R.q_index(prob.nk, kp, k) if kind == "q_reversed" else R.q_index(prob.nk, k, kp)
+                          for kp in range(Nk)] for k in rows])
+        eps_t = R.transition_energies(prob)
+        out = np.zeros((len(rows), nt, nb), dtype=np.complex128)
+        for i, k in enumerate(rows):
+            out[i] += (alpha / Nk) * np.einsum("mcv,mb->cvb", rho[k], u).reshape(nt, nb)
+            if block == "A" or kind == "diagonal_in_B":
+                out[i] += eps_t[k][:, None] * X[k]
+            for k0 in range(0, Nk, chunk):
+                ks = np.arange(k0, min(Nk, k0 + chunk))
+                kk = np.full(len(ks), k)
+                W = W_q[qtab[i, ks]]
+                if kind == "W_transposed":
+                    W = np.transpose(W, (0, 2, 1))
+                if block == "A":
+                    L = R._pairs_rows(pv, Fv, ks, pv, Fv, kk, two)
+                    Rt = R._pairs_rows(pc, Fc, kk, pc, Fc, ks, two)
+                    D = -(1.0 / Nk) * np.einsum("xmpv,xmn,xncd->xcvdp", L, W, Rt, optimize=True)
+                else:
+                    L = R._pairs_rows(pc, Fc, ks, pv, Fv, kk, two)
+                    Rt = R._pairs_rows(pc, Fc, kk, pv, Fv, ks, two)
+                    if kind == "B_direct_densities_swapped":
+                        L, Rt = R._pairs_rows(pc, Fc, kk, pv, Fv, ks, two), R._pairs_rows(pc, Fc, ks, pv, Fv, kk, two)
+                    D = -(1.0 / Nk) * np.einsum("xmdv,xmn,xncp->xcvdp", L, W, Rt, optimize=True)
+                out[i] += np.einsum("xcvdp,xdpb->cvb", D, Xr[ks], optimize=True).reshape(nt, nb)
+        return out.reshape(len(rows) * nt, nb)
+    return rows_fn
+
+
+def _pairs_rows_with(kind):
+    def pr(pa, Fa, ka, pb, Fb, kb, two):
+        M = np.einsum("xis,xmsj->xmij", pa[ka].conj(), Fb[kb], optimize=True)
+        if two and kind != "second_centre_dropped":
+            Fak = Fa[ka] if kind == "second_centre_unconjugated" else Fa[ka].conj()
+            M = M + np.einsum("xmti,xjt->xmij", Fak, pb[kb], optimize=True)
+        return M
+    return pr
+
+
+def _fsets_with(kind):
+    def fs(prob):
+        pv, pc = R._psi_sets(prob)
+        if getattr(prob, "C_R", None) is None:
+            Cm = np.transpose(prob.C, (0, 2, 1)) if kind == "C_transposed" else prob.C
+            Fv = np.transpose(np.tensordot(Cm, pv, axes=([2], [2])), (2, 0, 1, 3))
+            Fc = np.transpose(np.tensordot(Cm, pc, axes=([2], [2])), (2, 0, 1, 3))
+            return Fv, Fc, False
+        kv, kc = prob.band_k()
+        RC = np.asarray(prob.RC, dtype=np.float64)
+        sign = -1.0 if kind == "phase_sign" else 1.0
+        out = []
+        for psi_n, kn in ((pv, kv), (pc, kc)):
+            F = np.zeros((prob.Nk, prob.n_aux, prob.n_ao, psi_n.shape[1]), dtype=np.complex128)
+            for r in range(len(RC)):
+                ph = np.exp(sign * 2j * np.pi * (kn @ RC[r]))
+                G = np.tensordot(np.transpose(prob.C_R[r], (0, 2, 1)) if kind == "C_transposed" else prob.C_R[r],
+                                 psi_n, axes=([2], [2]))
+                F += ph[:, None, None, None] * np.transpose(G, (2, 0, 1, 3))
+            out.append(F)
+        return out[0], out[1], True
+    return fs
+
+
 # ---------------------------------------------------------------------------------------------------------
 # the pins each family of functions answers to (the tests of the oracle modules, called with their inputs)
 # ---------------------------------------------------------------------------------------------------------
@@ -614,6 +696,14 @@ FULL_AMP_PINS = {
     "resolvent_identity": TF.test_spectrum_resolvent_identity,
     "no_coupling_is_tda": TF.test_no_coupling_is_tda,
 }
+TWOSIDED_PINS = {
+    "twosided_A": lambda: TR.test_twosided_rows_match_blocks("A", False, {}),
+    "twosided_B": lambda: TR.test_twosided_rows_match_blocks("B", False, {}),
+    "twosided_A_two_centre": lambda: TR.test_twosided_rows_match_blocks("A", True, {}),
+    "twosided_B_two_centre": lambda: TR.test_twosided_rows_match_blocks("B", True, {}),
+    "twosided_A_two_centre_momentum": lambda: TR.test_twosided_rows_match_blocks("A", True,
+                                                                                 dict(momentum=(0.5, 0.25, 0.0))),
+}
 BINDING_PINS = {
     "binding_hand_case": TB.test_binding_energy_hand_case,
     "zero_kernel_zero_EB": TB.test_zero_kernel_has_zero_binding_energy,
@@ -659,6 +749,11 @@ FAMILIES = {
     "full_bse_eig": (_feig_with, FULL_EIG_PINS, ["lower_block_unconjugated", "negative_branch", "normalised_in_M"]),
     "full_bse_amplitudes": (_famp_with, FULL_AMP_PINS, ["quasiparticle_denominator", "Y_element_conjugated",
                                                         "Y_denominator_sign"]),
+    "apply_rows_twosided": (_twosided_with, TWOSIDED_PINS,
+                            ["B_exchange_with_the_A_density", "diagonal_in_B", "W_transposed", "q_reversed",
+                             "B_direct_densities_swapped"]),
+    "_pairs_rows": (_pairs_rows_with, TWOSIDED_PINS, ["second_centre_dropped", "second_centre_unconjugated"]),
+    "_F_sets": (_fsets_with, TWOSIDED_PINS, ["phase_sign", "C_transposed"]),
     "binding_energy": (_eb_with, BINDING_PINS,
                        ["kohn_sham_energies", "indirect_gap", "max_for_min", "wrong_bands", "wrong_sign"]),
 }
@@ -683,7 +778,8 @@ def test_planted_mistake_fails_a_pin(monkeypatch, fam, kind):
     fn = make(kind)
     # the oracle's own calls resolve through its module, the pins' calls through the package
     monkeypatch.setattr(R, fam, fn)
-    monkeypatch.setattr(oracle, fam, fn)
+    if hasattr(oracle, fam):      # private helpers are not re-exported by the package
+        monkeypatch.setattr(oracle, fam, fn)
     failed = _run_pins(pins)
     print("[planted %s / %s] pins failing: %s" % (fam, kind, ", ".join(failed) or "none"))
     if kind == "none":
@@ -707,6 +803,9 @@ def test_the_copies_without_a_slip_match_the_oracle():
     w = np.linspace(1.0, 5.0, 31)
     Om, Z = np.linalg.eigh(H)
     gq = R.grad_apply(p, Wq, Yb, X)[1]
+    t2 = make_problem(dict(SMALL), 0, "G2", coarse=(3, 3, 2), two_centre=True)
+    pv2, pc2 = R._psi_sets(t2)
+    Fv2, Fc2, _ = R._F_sets(t2)
     calls = {
         "hamiltonian_block": [(p, Wq, p.alpha, k, kp) for k, kp in [(0, 0), (1, 5), (6, 2)]],
         "interpolate_W": [(p.W_R, p.R, p.w_R, kq)],
@@ -734,6 +833,10 @@ def test_the_copies_without_a_slip_match_the_oracle():
         "coupling_block": [(p, Wq, p.alpha, k, kp) for k, kp in [(0, 0), (1, 5), (6, 2)]],
         "full_bse_eig": [(H, R.build_B(p, Wq))],
         "full_bse_amplitudes": [(p, np.eye(3), Z[:, :5], 0.1 * Z[:, 5:10])],
+        "apply_rows_twosided": [(t2, R.interpolate_W(t2.W_R, t2.R, t2.w_R, dense_kmesh(t2.nk)),
+                                 rng.standard_normal((t2.N, 2)) + 0j, [0, 5], blk, None, 4) for blk in "AB"],
+        "_pairs_rows": [(pv2, Fv2, np.arange(t2.Nk), pc2, Fc2, np.arange(t2.Nk)[::-1], True)],
+        "_F_sets": [(t2,), (p,)],
     }
     assert set(calls) == set(FAMILIES)
     for fam, arglists in calls.items():
