@@ -23,7 +23,9 @@ import test_oracle_hamiltonian as TH
 import test_oracle_haydock as TY
 import test_oracle_interp as TI
 import test_oracle_momentum as TM
+import test_oracle_offsets as TO
 import test_oracle_rows as TR
+import test_oracle_two_centre as TC
 from conftest import SMALL, TINY
 from synth import dense_kmesh, make_problem
 
@@ -599,6 +601,75 @@ def _fsets_with(kind):
     return fs
 
 
+def _hrows_with(kind):
+    """hamiltonian_rows with one planted slip."""
+    def hrows(prob, W_q, rows, alpha=None, chunk=64):
+        alpha = prob.alpha if alpha is None else alpha
+        nv, nc, Nk, na, no = prob.nv, prob.nc, prob.Nk, prob.n_aux, prob.n_ao
+        nt = nc * nv
+        val, con = R._bands(prob)
+        pv, pc = R._psi_sets(prob)
+        C = prob.C
+        Mvc = np.empty((Nk, na, nv, nc), dtype=np.complex128)
+        for k0 in range(0, Nk, chunk):
+            ks = slice(k0, min(Nk, k0 + chunk))
+            K = ks.stop - ks.start
+            Cpc = np.transpose(np.tensordot(C, pc[ks], axes=([2], [2])), (2, 1, 0, 3)).reshape(K, no, -1)
+            Mvc[ks] = np.transpose(np.matmul(pv[ks].conj(), Cpc).reshape(K, nv, na, nc), (0, 2, 1, 3))
+        qtab = np.array([[R.q_index(prob.nk, kp, k) if kind == "q_reversed" else R.q_index(prob.nk, k, kp)
+                          for kp in range(Nk)] for k in rows])
+        eps_t = R.transition_energies(prob)
+        out = np.zeros((len(rows), nt, Nk, nt), dtype=np.complex128)
+        for i, k in enumerate(rows):
+            Mcv = R.pair_density(prob.psi, C, k, con, k, val)
+            t1 = np.einsum("mcv,mn->ncv", Mcv, prob.Vbar)
+            out[i] += ((alpha / Nk) * np.einsum("ncv,knpd->cvkdp", t1, Mvc)).reshape(nt, Nk, nt)
+            if kind != "diagonal_dropped":
+                out[i, :, k, :] += np.diag(eps_t[k])
+            Cv = np.matmul(C, pv[k].T)
+            Bc = np.matmul(pc[k].conj()[None], C)
+            for k0 in range(0, Nk, chunk):
+                ks = slice(k0, min(Nk, k0 + chunk))
+                K = ks.stop - ks.start
+                Mvv = np.transpose(np.tensordot(pv[ks].conj(), Cv, axes=([2], [1])), (0, 2, 1, 3)).reshape(K, na, nv * nv)
+                Mcc = np.transpose(np.tensordot(Bc, pc[ks], axes=([2], [2])), (2, 1, 3, 0)).reshape(K, nc * nc, na)
+                W = W_q[qtab[i, ks]]
+                t2 = np.matmul(W if kind == "W_transposed" else np.transpose(W, (0, 2, 1)), Mvv)
+                D = -(1.0 / Nk) * np.matmul(Mcc, t2)
+                perm = (1, 3, 0, 2, 4) if kind == "column_order_swapped" else (1, 4, 0, 2, 3)
+                out[i, :, ks, :] += np.transpose(D.reshape(K, nc, nc, nv, nv), perm).reshape(nt, K, nt)
+        return out.reshape(len(rows) * nt, Nk * nt)
+    return hrows
+
+
+def _bfull_with(kind):
+    def bfull(prob, W_q, alpha=None):
+        A = R.build_H(prob, W_q, alpha)
+        B = R.build_B(prob, W_q, alpha)
+        lower_left = B.conj() if kind == "lower_left_sign" else -B.conj()
+        lower_right = -A if kind == "lower_right_unconjugated" else -A.conj()
+        return np.block([[A, B], [lower_left, lower_right]])
+    return bfull
+
+
+def _oavg_with(kind):
+    def oavg(spectra, weights):
+        out = np.zeros_like(np.asarray(spectra[0], dtype=np.float64))
+        for S, w in zip(spectra, weights):
+            out = out + (1.0 if kind == "weights_dropped" else w) * np.asarray(S, dtype=np.float64)
+        return out
+    return oavg
+
+
+def _lrik_with(kind):
+    def lrik(C_R, RC, k):
+        sign = -1.0 if kind == "phase_sign" else 1.0
+        ph = np.exp(sign * 2j * np.pi * (np.asarray(RC, dtype=np.float64) @ np.asarray(k, dtype=np.float64)))
+        out = np.tensordot(ph, C_R, axes=(0, 0))
+        return np.transpose(out, (0, 2, 1)) if kind == "transposed" else out
+    return lrik
+
+
 # ---------------------------------------------------------------------------------------------------------
 # the pins each family of functions answers to (the tests of the oracle modules, called with their inputs)
 # ---------------------------------------------------------------------------------------------------------
@@ -704,6 +775,16 @@ TWOSIDED_PINS = {
     "twosided_A_two_centre_momentum": lambda: TR.test_twosided_rows_match_blocks("A", True,
                                                                                  dict(momentum=(0.5, 0.25, 0.0))),
 }
+HROWS_PINS = {
+    "hrows_vs_blocks": lambda: TR.test_hamiltonian_rows_match_blocks("RAGGED", 7, 2.0),
+    "hrows_give_build_H": TR.test_hamiltonian_rows_give_build_H,
+}
+BFULL_PINS = {"paired_eigenproblem": TF.test_paired_eigenproblem,
+              "resolvent_identity": TF.test_spectrum_resolvent_identity}
+OAVG_PINS = {"equal_spectra": TO.test_offset_average_of_equal_spectra_is_that_spectrum,
+             "zero_kernel_closed_form": TO.test_zero_kernel_offset_average_closed_form}
+LRIK_PINS = {"real_space_%d" % i: (lambda a=a, b=b: TC.test_two_centre_coefficient_from_real_space(a, b))
+             for i, (a, b) in enumerate(TC.KPAIRS)}
 BINDING_PINS = {
     "binding_hand_case": TB.test_binding_energy_hand_case,
     "zero_kernel_zero_EB": TB.test_zero_kernel_has_zero_binding_energy,
@@ -754,6 +835,11 @@ FAMILIES = {
                              "B_direct_densities_swapped"]),
     "_pairs_rows": (_pairs_rows_with, TWOSIDED_PINS, ["second_centre_dropped", "second_centre_unconjugated"]),
     "_F_sets": (_fsets_with, TWOSIDED_PINS, ["phase_sign", "C_transposed"]),
+    "hamiltonian_rows": (_hrows_with, HROWS_PINS, ["q_reversed", "diagonal_dropped", "W_transposed",
+                                                   "column_order_swapped"]),
+    "build_full": (_bfull_with, BFULL_PINS, ["lower_left_sign", "lower_right_unconjugated"]),
+    "offset_average": (_oavg_with, OAVG_PINS, ["weights_dropped"]),
+    "lri_coeff_k": (_lrik_with, LRIK_PINS, ["phase_sign", "transposed"]),
     "binding_energy": (_eb_with, BINDING_PINS,
                        ["kohn_sham_energies", "indirect_gap", "max_for_min", "wrong_bands", "wrong_sign"]),
 }
@@ -837,6 +923,10 @@ def test_the_copies_without_a_slip_match_the_oracle():
                                  rng.standard_normal((t2.N, 2)) + 0j, [0, 5], blk, None, 4) for blk in "AB"],
         "_pairs_rows": [(pv2, Fv2, np.arange(t2.Nk), pc2, Fc2, np.arange(t2.Nk)[::-1], True)],
         "_F_sets": [(t2,), (p,)],
+        "hamiltonian_rows": [(s3, R.interpolate_W(s3.W_R, s3.R, s3.w_R, dense_kmesh(s3.nk)), [0, 7], 2.0, 5)],
+        "build_full": [(p, Wq)],
+        "offset_average": [([w, 2 * w, 3 * w, 4 * w], R.PAPER_OFFSET_WEIGHTS)],
+        "lri_coeff_k": [(t2.C_R, t2.RC, [0.25, -0.5, 1.0 / 3])],
     }
     assert set(calls) == set(FAMILIES)
     for fam, arglists in calls.items():
