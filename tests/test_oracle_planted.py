@@ -670,6 +670,59 @@ def _lrik_with(kind):
     return lrik
 
 
+def _bh_with(kind):
+    def bh(prob, W_q, alpha=None):
+        alpha = prob.alpha if alpha is None else alpha
+        Nk, nt = prob.Nk, prob.nc * prob.nv
+        H = np.zeros((Nk * nt, Nk * nt), dtype=np.complex128)
+        for k in range(Nk):
+            for kp in range(Nk):
+                r, c = (kp, k) if kind == "blocks_placed_transposed" else (k, kp)
+                H[r * nt:(r + 1) * nt, c * nt:(c + 1) * nt] = R.hamiltonian_block(prob, W_q, alpha, k, kp)
+        return H
+    return bh
+
+
+def _ahr_with(kind):
+    def ahr(prob, W_q, X, rows, alpha=None):
+        alpha = prob.alpha if alpha is None else alpha
+        nt = prob.nc * prob.nv
+        X = np.asarray(X).reshape(prob.Nk * nt, -1)
+        out = np.zeros((len(rows) * nt, X.shape[1]), dtype=np.complex128)
+        for i, k in enumerate(rows):
+            for kp in range(prob.Nk):
+                blk = R.hamiltonian_block(prob, W_q, alpha, k, kp)
+                xs = X[k * nt:(k + 1) * nt] if kind == "own_row_of_X" else X[kp * nt:(kp + 1) * nt]
+                out[i * nt:(i + 1) * nt] += blk @ xs
+        return out
+    return ahr
+
+
+def _hs_with(kind):
+    def hs(apply, P, m, omega, eta, Nk, tol=1e-12):
+        S, A, B, st = [], [], [], []
+        for col in range(P.shape[1]):
+            a, b, n, _ = R.haydock(apply, P[:, 0 if kind == "first_column_only" else col], m, tol)
+            S.append(R.continued_fraction(a, b, n, omega, eta, Nk))
+            A.append(a)
+            B.append(b)
+            st.append(n)
+        return np.array(S), np.array(A), np.array(B), np.array(st)
+    return hs
+
+
+def _fspec_with(kind):
+    def fspec(prob, pol, Omega, X, Y, omega, eta):
+        amp = np.abs(R.full_bse_amplitudes(prob, pol, X, Y)) ** 2
+        if kind == "both_branches":
+            Lw = R.lorentzian(np.asarray(omega)[None, :] - np.asarray(Omega)[:, None], eta) + \
+                R.lorentzian(np.asarray(omega)[None, :] + np.asarray(Omega)[:, None], eta)
+        else:
+            Lw = R.lorentzian(np.asarray(omega)[None, :] - np.asarray(Omega)[:, None], eta)
+        return (amp.T @ Lw) / (1 if kind == "missing_1_over_Nk" else prob.Nk)
+    return fspec
+
+
 # ---------------------------------------------------------------------------------------------------------
 # the pins each family of functions answers to (the tests of the oracle modules, called with their inputs)
 # ---------------------------------------------------------------------------------------------------------
@@ -785,6 +838,12 @@ OAVG_PINS = {"equal_spectra": TO.test_offset_average_of_equal_spectra_is_that_sp
              "zero_kernel_closed_form": TO.test_zero_kernel_offset_average_closed_form}
 LRIK_PINS = {"real_space_%d" % i: (lambda a=a, b=b: TC.test_two_centre_coefficient_from_real_space(a, b))
              for i, (a, b) in enumerate(TC.KPAIRS)}
+BUILD_H_PINS = {k: HAMILTONIAN_PINS[k] for k in ("hand_three_k", "hermitian_G2", "ao_bruteforce_G2_q_ne_minus_q")}
+APPLY_ROWS_PINS = {"rows_match_explicit": lambda: TH.test_apply_rows_match_explicit(dict(SMALL)),
+                   "allpairs_vs_blocks_ragged": lambda: TR.test_allpairs_rows_match_blocks("RAGGED", 7, 2.0)}
+HSPEC_PINS = {"full_krylov_vs_eigh": lambda: TY.test_full_krylov_equals_eigh(dict(TINY))}
+FSPEC_PINS = {"resolvent_identity": TF.test_spectrum_resolvent_identity,
+              "no_coupling_is_tda": TF.test_no_coupling_is_tda}
 BINDING_PINS = {
     "binding_hand_case": TB.test_binding_energy_hand_case,
     "zero_kernel_zero_EB": TB.test_zero_kernel_has_zero_binding_energy,
@@ -840,6 +899,10 @@ FAMILIES = {
     "build_full": (_bfull_with, BFULL_PINS, ["lower_left_sign", "lower_right_unconjugated"]),
     "offset_average": (_oavg_with, OAVG_PINS, ["weights_dropped"]),
     "lri_coeff_k": (_lrik_with, LRIK_PINS, ["phase_sign", "transposed"]),
+    "build_H": (_bh_with, BUILD_H_PINS, ["blocks_placed_transposed"]),
+    "apply_H_rows": (_ahr_with, APPLY_ROWS_PINS, ["own_row_of_X"]),
+    "haydock_spectrum": (_hs_with, HSPEC_PINS, ["first_column_only"]),
+    "full_bse_spectrum": (_fspec_with, FSPEC_PINS, ["both_branches", "missing_1_over_Nk"]),
     "binding_energy": (_eb_with, BINDING_PINS,
                        ["kohn_sham_energies", "indirect_gap", "max_for_min", "wrong_bands", "wrong_sign"]),
 }
@@ -927,6 +990,10 @@ def test_the_copies_without_a_slip_match_the_oracle():
         "build_full": [(p, Wq)],
         "offset_average": [([w, 2 * w, 3 * w, 4 * w], R.PAPER_OFFSET_WEIGHTS)],
         "lri_coeff_k": [(t2.C_R, t2.RC, [0.25, -0.5, 1.0 / 3])],
+        "build_H": [(p, Wq)],
+        "apply_H_rows": [(p, Wq, X, [0, 5])],
+        "haydock_spectrum": [(lambda x: H @ x, P, 10, w, 0.1, p.Nk)],
+        "full_bse_spectrum": [(p, np.eye(3), Om[:5], Z[:, :5], 0.1 * Z[:, 5:10], w, 0.1)],
     }
     assert set(calls) == set(FAMILIES)
     for fam, arglists in calls.items():
