@@ -30,6 +30,17 @@ def test_f_apply_formula():
     assert F - Fx == 8 * 512 * (512 - 260) * (256 * 64 * (8 ** 2 + 4 ** 2) + 256 ** 2 * 4 ** 2)
 
 
+@pytest.mark.parametrize("dims,total", [
+    ((64, 16, 4, 4, 64, 3), 4.030e9),            # 4x4x4 mesh, N_ao 16, 4 + 4 bands, N_aux 64, 3 vectors
+    ((512, 64, 4, 8, 256, 4), 5.773e12),         # 8x8x8 mesh, LOBPCG block of 4
+    ((1728, 96, 6, 10, 384, 8), 317.02e12),      # 12x12x12 mesh, N_ao 96, 6 + 10 bands, N_aux 384
+    ((4096, 128, 8, 8, 512, 16), 4503.6e12),     # 16x16x16 mesh, N_ao 128, 8 + 8 bands, N_aux 512, 16 vectors
+])
+def test_f_apply_at_the_workloads(dims, total):
+    # the algorithmic count of one apply at each workload (the GFLOP/s of every record divides it by time)
+    assert abs(bench.f_apply(*dims) / total - 1) < 2e-4
+
+
 def test_source_digest_matches_committed_profiles():
     # the traffic figure is reported only when the committed counter summary was taken on the apply's sources
     dig = bench.source_digest()
