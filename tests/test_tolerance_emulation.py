@@ -7,11 +7,13 @@ kernel's error).  This module emulates, in numpy, the dataflow of the direct ter
 with every stored operand rounded as the GPU stores it, and shows that
 
 * rounding each operand to one bf16 (8 significant bits: a product of the hi parts only) misses the
-  BF16x3 bound by a wide margin, and
+  BF16x3 bound by a wide margin, and so does dropping the lo part of any single operand (the halves, the
+  bands, W(q), G_v, P or M_c) while the others stay split, and
 * rounding to the two-term split hi + lo of BF16x3 and to FP32 meets the bounds with room,
 
 so the bounds reject a kernel that drops the lo terms, while the split kernels pass them."""
 import numpy as np
+import pytest
 
 import oracle as O
 from synth import dense_kmesh, make_problem, random_block
@@ -42,26 +44,31 @@ def _round(z, mode):
     return r(z.real) + 1j * r(z.imag)
 
 
-def _emulated_kernel_apply(p, Wq, X, mode):
+OPERANDS = ("Bv", "Bc", "psi", "W", "Gv", "P", "Mc")   # every operand a BF16x3 kernel stores split
+
+
+def _emulated_kernel_apply(p, Wq, X, mode, hi_only=None):
     """Direct + exchange terms of A X with the pair densities formed from stored (rounded) halves and bands,
     P = conj(G_v) W(q) from rounded G_v and W(q), T = M_c P^T from rounded M_c and P, and FP64 for the
-    exchange and the accumulation over k' (as on the GPU)."""
+    exchange and the accumulation over k' (as on the GPU).  hi_only: the one operand (of OPERANDS) stored
+    as its bf16 hi part alone, as a kernel that drops that operand's lo plane would."""
     nv, nc, Nk, na = p.nv, p.nc, p.Nk, p.n_aux
     nt = nc * nv
+    md = lambda name: "bf16_hi" if name == hi_only else mode
     psi_v, psi_c = p.psi[:, :nv], p.psi[:, nv:]
-    Bv = _round(np.einsum("kvs,mst->kvmt", psi_v.conj(), p.C), mode)          # psi_v(k)^H C^mu
-    Bc = _round(np.einsum("kcs,mst->kcmt", psi_c.conj(), p.C), mode)
-    pv, pc = _round(psi_v, mode), _round(psi_c, mode)
-    W = _round(Wq, mode)
+    Bv = _round(np.einsum("kvs,mst->kvmt", psi_v.conj(), p.C), md("Bv"))     # psi_v(k)^H C^mu
+    Bc = _round(np.einsum("kcs,mst->kcmt", psi_c.conj(), p.C), md("Bc"))
+    pv, pc = _round(psi_v, md("psi")), _round(psi_c, md("psi"))
+    W = _round(Wq, md("W"))
     q = O.q_index_table(p.nk)
     Xk = X.reshape(Nk, nc, nv, -1)
     Y = np.zeros((Nk, nc, nv, X.shape[1]), dtype=complex)
     for k in range(Nk):
         kp = np.arange(Nk)
         # G_v[k'][v][v'][mu] = B_v(k)[v][mu] . psi_v'(k')  = M^mu_vv'(k, k');  conj gives M^mu_v'v(k', k)
-        Gv = _round(np.einsum("vmt,kpt->kvpm", Bv[k], pv[kp]), mode)
-        P = _round(np.einsum("kvpm,kmn->kvpn", Gv.conj(), W[q[k, kp]]), mode)
-        Mc = _round(np.einsum("cmt,kdt->kcdm", Bc[k], pc[kp]), mode)          # M^nu_cc'(k, k')
+        Gv = _round(np.einsum("vmt,kpt->kvpm", Bv[k], pv[kp]), md("Gv"))
+        P = _round(np.einsum("kvpm,kmn->kvpn", Gv.conj(), W[q[k, kp]]), md("P"))
+        Mc = _round(np.einsum("cmt,kdt->kcdm", Bc[k], pc[kp]), md("Mc"))          # M^nu_cc'(k, k')
         T = np.einsum("kcdn,kvpn->kcvdp", Mc, P)                               # [k'][c][v][c'][v']
         Y[k] = -(1.0 / Nk) * np.einsum("kcvdp,kdpb->cvb", T, Xk)
     rho = np.einsum("kcs,mst,kvt->kcvm", psi_c.conj(), p.C, psi_v)            # FP64, as the plan keeps it
@@ -70,10 +77,10 @@ def _emulated_kernel_apply(p, Wq, X, mode):
     return Y.reshape(Nk * nt, -1)
 
 
-def _kernel_err(p, Wq, X, mode):
+def _kernel_err(p, Wq, X, mode, hi_only=None):
     H = O.build_H(p, Wq)
     ref = H @ X - O.transition_energies(p).reshape(-1)[:, None] * X
-    got = _emulated_kernel_apply(p, Wq, X, mode)
+    got = _emulated_kernel_apply(p, Wq, X, mode, hi_only)
     return np.abs(got - ref).max() / np.abs(ref).max()
 
 
@@ -98,3 +105,14 @@ def test_bounds_reject_hi_only_and_accept_split():
     assert e_32 < 0.2 * KERNEL_TOL["f32"]
     # and an FP32 bound would also reject the split product (its 16 bits are not FP32's 24)
     assert e_b3 > KERNEL_TOL["f32"]
+
+
+@pytest.mark.parametrize("operand", OPERANDS)
+def test_bound_rejects_one_operand_without_its_lo_part(operand):
+    # a BF16x3 kernel that loads only the hi plane of one operand (the others split) still misses the bound
+    p = make_problem("mesh4_ao16", 0, "G2", coarse=(3, 3, 2))
+    Wq = O.interpolate_W(p.W_R, p.R, p.w_R, dense_kmesh(p.nk))
+    X = random_block(p.N, 3, seed=1)
+    e = _kernel_err(p, Wq, X, "bf16x3", hi_only=operand)
+    print("[emulation] %s hi only: kernel-part error %.2e" % (operand, e))
+    assert e > 3 * KERNEL_TOL["bf16x3"]
